@@ -1,0 +1,183 @@
+/*
+ * ibmg.h -- C ABI of the MI355X (gfx950) implicit immersed-boundary
+ * multigrid library.
+ *
+ * The library advances the implicit-time immersed boundary method of
+ * Guy, Philip and Griffith, "Geometric multigrid for an implicit-time
+ * immersed boundary method" (arXiv 1311.5614): at each time step it solves
+ * the coupled Stokes-structure system (Sec. 2.3.2, eliminated to the
+ * Eulerian saddle system of Sec. 3) with FGMRES right-preconditioned by the
+ * geometric multigrid V-cycle of Algorithm 1 (Sec. 3), hybrid coarse
+ * operators (Sec. 3.2) and (big-)box relaxation (Sec. 5-6), then moves the
+ * structure with the lagged interpolation operator.
+ *
+ * Problem (periodic unit square, N x N cells, h = 1/N, MAC layout):
+ *   (rho/dt) u - mu Lap_h u + G p + M_0 u = (rho/dt) u^n + S_0 (K L X^n) + g
+ *   -D u = 0,   M_0 = -dt K S_0 L S^*,   X^{n+1} = X^n + dt S^* u^{n+1}
+ * with S_0 spreading through the 4-point regularised delta (Sec. 2.2),
+ * S^* = h^2 S_0^T its adjoint, L the closed-fibre second difference
+ * (nodal springs, force G = K L X).  This is the unsteady form the paper
+ * gives in its discussion (operator I - dt Lap - dt^2 gamma S A_f S^*,
+ * Sec. 8), divided by dt.
+ *
+ * Memory and ownership
+ *   - Every array argument is DEVICE memory owned by the caller, FP64 unless
+ *     stated, except fiber_offsets (host).
+ *   - Eulerian fields are N x N row-major, x fastest: u[j][i] at
+ *     (i h, (j+1/2) h), v[j][i] at ((i+1/2) h, j h), p[j][i] at the cell
+ *     centre.  A stacked vector w = [u; v; p] has 3 N_l^2 entries on level l
+ *     (N_l = N / 2^l).
+ *   - Lagrangian positions X are M x 2 (x, y interleaved), not wrapped; the
+ *     kernels wrap them internally.
+ *   - The library never allocates device memory: the caller queries
+ *     ibmg_workspace_bytes() and binds one device buffer it owns with
+ *     ibmg_bind_workspace().  The handle keeps only host-side bookkeeping.
+ *   - All work is enqueued on the stream given at creation (a hipStream_t
+ *     passed as void*; NULL = default stream).  Calls that return stats, or
+ *     that read device scalars for control flow (solve, step, setup),
+ *     synchronise that stream before returning.
+ *   - One handle per host thread; handles are independent.
+ *
+ * Errors: every call returns an ibmg_status.  Negative values are errors;
+ * on an error the caller's output buffers are left untouched (results are
+ * formed in the workspace and copied out last).  IBMG_NOT_CONVERGED (> 0)
+ * is a warning: outputs hold the best iterate.
+ */
+#ifndef IBMG_H
+#define IBMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibmg_handle ibmg_handle;
+
+typedef enum {
+  IBMG_OK = 0,
+  IBMG_NOT_CONVERGED = 1,   /* iteration cap reached; outputs hold the last iterate */
+  IBMG_EINVAL = -1,         /* null pointer, bad enum, bad size                    */
+  IBMG_ESHAPE = -2,         /* N not a power of two, box does not tile a level     */
+  IBMG_EHIP = -3,           /* a HIP runtime call failed                           */
+  IBMG_ENOMEM = -4,         /* bound workspace too small / not bound               */
+  IBMG_ENONFINITE = -5,     /* NaN or Inf met in the inputs or the iteration       */
+  IBMG_ESTATE = -6          /* call order violated (e.g. solve before setup)       */
+} ibmg_status;
+
+enum { IBMG_DELTA_IB4 = 0,  /* Peskin's standard 4-point kernel                    */
+       IBMG_DELTA_COS4 = 1  /* cosine 4-point kernel printed in Sec. 2.2           */ };
+enum { IBMG_FP64 = 0, IBMG_FP32 = 1 };
+enum { IBMG_GUESS_ZERO = 0, IBMG_GUESS_PREV = 1 };
+
+typedef struct {
+  int32_t N;                     /* cells per side, power of two >= 4               */
+  double rho, mu;                /* density and viscosity, rho > 0, mu > 0          */
+  int32_t n_points;              /* M, total Lagrangian points (may be 0)           */
+  int32_t n_fibers;              /* closed fibres                                   */
+  const int32_t* fiber_offsets;  /* HOST, n_fibers + 1 CSR offsets into [0, M]      */
+  double K;                      /* nodal spring stiffness, force G = K L X         */
+  int32_t delta;                 /* IBMG_DELTA_IB4 or IBMG_DELTA_COS4               */
+} ibmg_problem;
+
+typedef struct {
+  int32_t levels;      /* multigrid levels, coarsest N / 2^(levels-1) >= 2          */
+  int32_t box;         /* box edge n in cells: 1, 2 or 4; every smoothed level needs
+                          N_l >= max(4, 2n) (colour classes of boxes stay disjoint)  */
+  int32_t nu1, nu2;    /* pre- and post-smoothing sweeps (Algorithm 1)              */
+  int32_t maxit;       /* FGMRES iteration cap (no restart below it), 1..200        */
+  double rtol;         /* stop when ||b - A w||_2 <= rtol ||b||_2                   */
+  int32_t vcycle_prec; /* IBMG_FP64 or IBMG_FP32 (V-cycle fields and stencils)      */
+  int32_t guess;       /* IBMG_GUESS_ZERO or IBMG_GUESS_PREV (step only)            */
+} ibmg_opts;
+
+typedef struct {
+  int32_t iters;          /* preconditioner applications                          */
+  int32_t converged;      /* 1 if the true residual met rtol                      */
+  double rel_resid_est;   /* Arnoldi estimate |g_{j+1}| / ||b||                   */
+  double rel_resid_true;  /* ||b - A w|| / ||b|| of the returned iterate          */
+  double bnorm;           /* ||b||_2                                              */
+  double t_setup_ms, t_solve_ms, t_step_ms;  /* host wall clock around the phases */
+} ibmg_stats;
+
+/* Create a handle.  Validates shapes (box tiling, power-of-two N, levels) and
+ * stores the fibre topology.  No device work, no allocation on the device.
+ * Errors: EINVAL, ESHAPE. */
+int ibmg_create(ibmg_handle** out, const ibmg_problem* prob, const ibmg_opts* opts,
+                void* hip_stream);
+/* Bytes of device workspace the handle needs (256-byte aligned pointer). */
+int ibmg_workspace_bytes(const ibmg_handle* h, size_t* bytes);
+/* Bind caller-owned device memory (>= ibmg_workspace_bytes).  Errors: ENOMEM. */
+int ibmg_bind_workspace(ibmg_handle* h, void* dev_ptr, size_t bytes);
+int ibmg_destroy(ibmg_handle* h);
+const char* ibmg_status_string(int status);
+/* Kernel timing of the box-relaxation phase kernel with HIP events on the
+ * handle's stream (1 = on).  ibmg_phase_timing reads the accumulated total
+ * (ms), the number of launches timed and their algorithmic bytes. */
+int ibmg_set_timing(ibmg_handle* h, int on);
+int ibmg_phase_timing(ibmg_handle* h, double* total_ms, int64_t* launches, double* bytes);
+
+/* Operator setup at positions X (Sec. 2.3.2 lags S at X^n; Sec. 3.2 builds the
+ * coarse elasticity operators by Galerkin products; Sec. 8 notes the box
+ * factors are re-formed near the structure each step): fibre forces, delta
+ * weights, restricted/prolonged per-point patches on every level, point-to-box
+ * binning, box factors and the bordered coarsest inverse, for time step dt.
+ * X: M x 2.  Synchronises.  Errors: EINVAL, ENOMEM, EHIP, ENONFINITE. */
+int ibmg_setup(ibmg_handle* h, double dt, const double* X);
+
+/* One implicit IB time step (Sec. 2.3.2): setup at X^n, right-hand side,
+ * FGMRES solve, zero-mean pressure, X^{n+1} = X^n + dt S^{n*} u^{n+1}.
+ * u, v, p: N x N in = state n (p only used as part of the initial guess when
+ * guess = PREV), out = state n+1.  X: M x 2 in/out.  g_u, g_v: body force on
+ * u and v faces, nullable.  out: host stats, nullable. */
+int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X,
+              const double* g_u, const double* g_v, ibmg_stats* out);
+
+/* Right-hand side of the step system at the current setup (Sec. 2.3.2 with
+ * the stiffness factor restored): b = [(rho/dt) u + S_0 G + g_u;
+ * (rho/dt) v + S_0 G + g_v; 0].  b: 3 N^2. */
+int ibmg_rhs(ibmg_handle* h, const double* u, const double* v, const double* g_u,
+             const double* g_v, double* b);
+
+/* Solve A w = b with the operator of the current setup (Sec. 3.3, FGMRES with
+ * the multigrid right preconditioner).  w: 3 N^2, in = initial guess x0,
+ * out = solution.  b: 3 N^2. */
+int ibmg_solve(ibmg_handle* h, const double* b, double* w, ibmg_stats* out);
+
+/* --- single operations, exported for parity checks (same kernels as the
+ *     solve uses, FP64 arguments; on an FP32 handle they run the FP32
+ *     kernels with conversion at entry and exit).  All need a setup. --- */
+/* y = A_l w on level l (Sec. 3 matrix; level > 0 uses the hybrid operator of Sec. 3.2). */
+int ibmg_apply(ibmg_handle* h, int level, const double* w, double* y);
+/* r = b - A_l w. */
+int ibmg_residual(ibmg_handle* h, int level, const double* b, const double* w, double* r);
+/* `sweeps` box-relaxation sweeps on level l (Sec. 5-6) in place on w, colours
+ * (0,0),(1,0),(0,1),(1,1), each colour from the residual at its start. */
+int ibmg_smooth(ibmg_handle* h, int level, const double* b, double* w, int sweeps);
+/* coarse = I_{2h<-h} fine, level l -> l+1 (Sec. 3.1: R_u, R_v, R_p). */
+int ibmg_restrict(ibmg_handle* h, int level, const double* fine, double* coarse);
+/* fine += I_{h<-2h} coarse, level l+1 -> l (Sec. 3.1: bilinear, constant). */
+int ibmg_prolong_add(ibmg_handle* h, int level, const double* coarse, double* fine);
+/* Exact coarsest solve, bordered with zero-mean pressure (Algorithm 1). */
+int ibmg_coarse_solve(ibmg_handle* h, const double* b, double* w);
+/* z = MGV(0, r) on level 0 (Algorithm 1 with nu1, nu2 of the handle). */
+int ibmg_vcycle(ibmg_handle* h, const double* r, double* z);
+/* Dense box matrix A_l[box, box] (elasticity included) of box (bx, by) on
+ * level l as assembled for factorisation; out: ndof x ndof row-major,
+ * ndof = 2n(n+1) + n^2, local order u faces, v faces, pressures, x fastest. */
+int ibmg_box_matrix(ibmg_handle* h, int level, int bx, int by, double* out);
+
+/* --- Lagrangian-Eulerian coupling at arbitrary positions (Sec. 2.2).  These
+ *     rebuild the finest-level point data for X and invalidate the setup. --- */
+/* G = K L X (closed fibres).  G: M x 2. */
+int ibmg_fiber_force(ibmg_handle* h, const double* X, double* G);
+/* f = S_0 G on u and v faces (deterministic gather over binned points). */
+int ibmg_spread(ibmg_handle* h, const double* X, const double* G, double* f_u, double* f_v);
+/* U = S^* (u, v) = h^2 S_0^T (u, v).  U: M x 2. */
+int ibmg_interp(ibmg_handle* h, const double* X, const double* u, const double* v, double* U);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBMG_H */

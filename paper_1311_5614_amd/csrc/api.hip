@@ -1,0 +1,888 @@
+// Host side of the C ABI (include/ibmg.h): validation, workspace layout, the
+// per-step setup sequence, the V-cycle schedule (Algorithm 1), FGMRES and the
+// implicit time step.  Every arithmetic step runs in the gfx950 kernels of
+// ib_setup.hip, mg.hip, dense.hip and krylov.hip; the host only sequences
+// launches on the handle's stream and reads back scalars for control flow.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ibmg.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int kPW = 16;          // panel width of the coarse Gauss-Jordan (dense.hip)
+constexpr int kDotBlocks = 256;  // workgroups of the deterministic dot products
+constexpr int kMaxTimed = 8192;  // timed phase launches per solve
+
+struct Buf {
+  size_t off = 0, bytes = 0;
+};
+
+struct LevelBufs {
+  int N = 0, nb = 0;
+  Buf w, b, r;               // V-cycle vectors in the V-cycle precision
+  Buf orgB, wB, orgC, wC;    // per-point patches (FP64)
+  Buf wBf, wCf;              // FP32 copies of the patch weights
+  Buf t;                     // gathered values, V-cycle precision
+  Buf cnt, start, cursor, list, ib_index, ib_boxes, info;
+  Buf ainv_plain, ainv_plain_f, ainv_ib;
+  int max_ib = 0, max_list = 0;
+};
+
+}  // namespace
+
+struct ibmg_handle {
+  // problem and options
+  int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 2, nu2 = 2, maxit = 100, prec = 0, guess = 0;
+  double rho = 1, mu = 1, K = 0, rtol = 1e-8;
+  std::vector<int> prev, next;
+  hipStream_t stream = nullptr;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0, need = 0;
+  LevelBufs L[IBMG_MAX_LEVELS];
+  Buf X0, G, prev_d, next_d, U;
+  Buf V, Z, H, g, cs, sn, y, flags, partial, scal, hc;
+  Buf bvec, xvec, rvec, w0f, b0f;
+  Buf aug, cm, cpiv, crowpos, cused, cY, cainv;
+  int nr = 0, ndof = 0;
+  // state
+  bool setup_ok = false, has_ib = false;
+  double dt = 0;
+  int n_ib[IBMG_MAX_LEVELS][5] = {};
+  // timing of the box-relaxation phase kernel
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  std::vector<double> ev_bytes;
+  double t_total_ms = 0, t_bytes = 0;
+  int64_t t_launches = 0;
+
+  template <typename T> T* p(const Buf& b) const { return reinterpret_cast<T*>(ws + b.off); }
+  size_t n0() const { return 3 * (size_t)N * N; }
+};
+
+namespace {
+
+using namespace ibmg;
+
+void take(size_t& cur, Buf& b, size_t bytes) {
+  cur = (cur + 255) & ~(size_t)255;
+  b.off = cur;
+  b.bytes = bytes;
+  cur += bytes;
+}
+
+int boxes_per_point(int n) {
+  const int a = (4 + n - 1) / n + 2;
+  return a * a;
+}
+
+void layout(ibmg_handle* h) {
+  size_t cur = 0;
+  const size_t rs = h->prec == IBMG_FP32 ? sizeof(float) : sizeof(double);
+  const int M = h->M, bpp = boxes_per_point(h->n);
+  h->ndof = 2 * h->n * (h->n + 1) + h->n * h->n;
+  const size_t nd2 = (size_t)h->ndof * h->ndof;
+  for (int l = 0; l < h->levels; ++l) {
+    LevelBufs& B = h->L[l];
+    B.N = h->N >> l;
+    B.nb = B.N / h->n;
+    const size_t NN = (size_t)B.N * B.N;
+    const bool fine = (l == 0);
+    if (!fine || h->prec == IBMG_FP32) {
+      take(cur, B.w, 3 * NN * rs);
+      take(cur, B.b, 3 * NN * rs);
+    }
+    take(cur, B.r, 3 * NN * rs);
+    if (M > 0) {
+      take(cur, B.orgB, 4 * (size_t)M * sizeof(int));
+      take(cur, B.orgC, 4 * (size_t)M * sizeof(int));
+      take(cur, B.wB, 2 * (size_t)M * IBMG_PATCH * sizeof(double));
+      take(cur, B.wC, 2 * (size_t)M * IBMG_PATCH * sizeof(double));
+      if (h->prec == IBMG_FP32) {
+        take(cur, B.wBf, 2 * (size_t)M * IBMG_PATCH * sizeof(float));
+        take(cur, B.wCf, 2 * (size_t)M * IBMG_PATCH * sizeof(float));
+      }
+      take(cur, B.t, 2 * (size_t)M * rs);
+    }
+    const size_t nbox = (size_t)B.nb * B.nb;
+    B.max_list = std::max(1, M * bpp);
+    take(cur, B.cnt, nbox * sizeof(int));
+    take(cur, B.start, (nbox + 1) * sizeof(int));
+    take(cur, B.cursor, nbox * sizeof(int));
+    take(cur, B.list, (size_t)B.max_list * sizeof(int));
+    take(cur, B.info, 8 * sizeof(int));
+    if (l < h->levels - 1) {
+      take(cur, B.ib_index, nbox * sizeof(int));
+      take(cur, B.ib_boxes, nbox * sizeof(int));
+      take(cur, B.ainv_plain, nd2 * sizeof(double));
+      take(cur, B.ainv_plain_f, nd2 * sizeof(float));
+      B.max_ib = M > 0 ? (int)std::min<size_t>(nbox, (size_t)M * bpp) : 0;
+      take(cur, B.ainv_ib, std::max<size_t>(1, (size_t)B.max_ib) * nd2 * sizeof(double));
+    }
+  }
+  const int Nc = h->N >> (h->levels - 1);
+  h->nr = 3 * Nc * Nc + 1;
+  const size_t nr = h->nr;
+  take(cur, h->aug, nr * 2 * nr * sizeof(double));
+  take(cur, h->cm, nr * kPW * sizeof(double));
+  take(cur, h->cpiv, nr * sizeof(int));
+  take(cur, h->crowpos, nr * sizeof(int));
+  take(cur, h->cused, nr * sizeof(int));
+  take(cur, h->cY, (size_t)kPW * 2 * nr * sizeof(double));
+  take(cur, h->cainv, nr * nr * sizeof(double));
+  const size_t Mx = std::max(1, M);
+  take(cur, h->X0, 2 * Mx * sizeof(double));
+  take(cur, h->G, 2 * Mx * sizeof(double));
+  take(cur, h->U, 2 * Mx * sizeof(double));
+  take(cur, h->prev_d, Mx * sizeof(int));
+  take(cur, h->next_d, Mx * sizeof(int));
+  const size_t n0 = h->n0(), m = h->maxit;
+  take(cur, h->V, (m + 1) * n0 * sizeof(double));
+  take(cur, h->Z, m * n0 * sizeof(double));
+  take(cur, h->H, (m + 1) * (m + 1) * sizeof(double));
+  take(cur, h->g, (m + 2) * sizeof(double));
+  take(cur, h->cs, (m + 1) * sizeof(double));
+  take(cur, h->sn, (m + 1) * sizeof(double));
+  take(cur, h->y, (m + 1) * sizeof(double));
+  take(cur, h->hc, (m + 2) * sizeof(double));
+  take(cur, h->flags, 8 * sizeof(double));
+  take(cur, h->scal, 16 * sizeof(double));
+  take(cur, h->partial, (size_t)kDotBlocks * (m + 2) * sizeof(double));
+  take(cur, h->bvec, n0 * sizeof(double));
+  take(cur, h->xvec, n0 * sizeof(double));
+  take(cur, h->rvec, n0 * sizeof(double));
+  if (h->prec == IBMG_FP32) {
+    take(cur, h->w0f, n0 * sizeof(float));
+    take(cur, h->b0f, n0 * sizeof(float));
+  }
+  h->need = cur + 256;
+}
+
+template <typename T>
+LevelView<T> view(const ibmg_handle* h, int l) {
+  const LevelBufs& B = h->L[l];
+  LevelView<T> v{};
+  v.N = B.N;
+  v.nb = B.nb;
+  v.n = h->n;
+  v.ndof = h->ndof;
+  const double hl = 1.0 / B.N, h0 = 1.0 / h->N;
+  v.c = (T)(h->rho / h->dt);
+  v.muh2 = (T)(h->mu / (hl * hl));
+  v.invh = (T)(1.0 / hl);
+  v.kappa = (T)(-h->dt * h->K / (h0 * h0));
+  v.M = h->M;
+  v.prev = h->p<int>(h->prev_d);
+  v.next = h->p<int>(h->next_d);
+  if (h->M > 0) {
+    v.orgB = h->p<int>(B.orgB);
+    v.orgC = h->p<int>(B.orgC);
+    if (sizeof(T) == sizeof(float)) {
+      v.wB = reinterpret_cast<const T*>(h->p<float>(B.wBf));
+      v.wC = reinterpret_cast<const T*>(h->p<float>(B.wCf));
+    } else {
+      v.wB = reinterpret_cast<const T*>(h->p<double>(B.wB));
+      v.wC = reinterpret_cast<const T*>(h->p<double>(B.wC));
+    }
+    v.t = h->p<T>(B.t);
+  }
+  v.box_start = h->p<int>(B.start);
+  v.box_list = h->p<int>(B.list);
+  if (l < h->levels - 1) {
+    v.ib_index = h->p<int>(B.ib_index);
+    v.ainv_plain = sizeof(T) == sizeof(float) ? reinterpret_cast<const T*>(h->p<float>(B.ainv_plain_f))
+                                              : reinterpret_cast<const T*>(h->p<double>(B.ainv_plain));
+    v.ainv_ib = h->p<double>(B.ainv_ib);
+  }
+  return v;
+}
+
+int sync(ibmg_handle* h) {
+  IBMG_HIP(hipStreamSynchronize(h->stream));
+  return IBMG_OK;
+}
+
+int read_doubles(ibmg_handle* h, const double* dev, double* host, int n) {
+  IBMG_HIP(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  IBMG_HIP(hipStreamSynchronize(h->stream));
+  return IBMG_OK;
+}
+
+// ---------------------------------------------------------------- V-cycle schedule
+
+template <typename T>
+void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, int colour) {
+  const bool t = h->timing && h->ev_used + 2 <= (int)h->ev.size();
+  if (t) (void)hipEventRecord(h->ev[h->ev_used], h->stream);
+  launch_phase<T>(h->stream, v, b, w, colour, h->has_ib);
+  if (t) {
+    (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+    const double NN = (double)v.N * v.N;
+    // algorithmic bytes: 9 words per cell per sweep (read w and b, write w),
+    // a quarter of the level per colour, plus the box inverses read
+    double bytes = 9.0 * sizeof(T) * NN / 4.0 + (double)v.ndof * v.ndof * sizeof(T);
+    if (h->has_ib) bytes += (double)h->n_ib[l][colour] * v.ndof * v.ndof * sizeof(double);
+    h->ev_bytes[h->ev_used / 2] = bytes;
+    h->ev_used += 2;
+  }
+}
+
+template <typename T>
+void sweep(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w) {
+  for (int c = 0; c < 4; ++c) {
+    if (h->has_ib) launch_gather<T>(h->stream, v, w);
+    phase_timed<T>(h, v, l, b, w, c);
+  }
+}
+
+// z = MGV(0, r) on level 0 (Algorithm 1), vectors in precision T.
+template <typename T>
+void vcycle(ibmg_handle* h, const T* b0, T* w0) {
+  const int Lv = h->levels;
+  hipStream_t s = h->stream;
+  T* w[IBMG_MAX_LEVELS];
+  const T* b[IBMG_MAX_LEVELS];
+  T* r[IBMG_MAX_LEVELS];
+  LevelView<T> v[IBMG_MAX_LEVELS];
+  for (int l = 0; l < Lv; ++l) {
+    v[l] = view<T>(h, l);
+    w[l] = l == 0 ? w0 : h->p<T>(h->L[l].w);
+    b[l] = l == 0 ? b0 : h->p<T>(h->L[l].b);
+    r[l] = h->p<T>(h->L[l].r);
+  }
+  for (int l = 0; l + 1 < Lv; ++l) {
+    const size_t n3 = 3 * (size_t)v[l].N * v[l].N;
+    k_fill<T><<<nblk(n3), 256, 0, s>>>(w[l], n3, T(0));
+    for (int q = 0; q < h->nu1; ++q) sweep<T>(h, v[l], l, b[l], w[l]);
+    if (h->has_ib) launch_gather<T>(s, v[l], w[l]);
+    launch_residual<T>(s, v[l], b[l], w[l], r[l], h->has_ib);
+    launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b));
+  }
+  launch_coarse_apply<T>(s, h->p<double>(h->cainv), h->nr, b[Lv - 1], w[Lv - 1]);
+  for (int l = Lv - 2; l >= 0; --l) {
+    launch_prolong_add<T>(s, v[l].N, w[l + 1], w[l]);
+    for (int q = 0; q < h->nu2; ++q) sweep<T>(h, v[l], l, b[l], w[l]);
+  }
+}
+
+// z = M^{-1} r in FP64 at the ABI, dispatching on the V-cycle precision.
+void precond(ibmg_handle* h, const double* r, double* z) {
+  if (h->prec == IBMG_FP32) {
+    const size_t n0 = h->n0();
+    k_convert<double, float><<<nblk(n0), 256, 0, h->stream>>>(r, h->p<float>(h->b0f), n0);
+    vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f));
+    k_convert<float, double><<<nblk(n0), 256, 0, h->stream>>>(h->p<float>(h->w0f), z, n0);
+  } else {
+    vcycle<double>(h, r, z);
+  }
+}
+
+// y = A_0 w (FP64, the outer operator of FGMRES).
+void apply0(ibmg_handle* h, const double* w, double* y, const double* b = nullptr) {
+  LevelView<double> v = view<double>(h, 0);
+  if (h->has_ib) launch_gather<double>(h->stream, v, w);
+  launch_residual<double>(h->stream, v, b, w, y, h->has_ib);
+}
+
+// <a, b> into dev[0]
+void dot(ibmg_handle* h, const double* a, const double* b, double* dev) {
+  launch_multidot(h->stream, a, 0, 1, b, h->n0(), h->p<double>(h->partial), kDotBlocks);
+  launch_reduce(h->stream, h->p<double>(h->partial), kDotBlocks, 1, dev, 0);
+}
+
+// ---------------------------------------------------------------- setup
+
+int do_setup(ibmg_handle* h, double dt, const double* X) {
+  if (!h->ws) return IBMG_ENOMEM;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return IBMG_EINVAL;
+  hipStream_t s = h->stream;
+  h->dt = dt;
+  h->setup_ok = false;
+  const int M = h->M, Lv = h->levels;
+  h->has_ib = M > 0 && h->K != 0.0;
+  if (M > 0) {
+    if (!X) return IBMG_EINVAL;
+    IBMG_HIP(hipMemcpyAsync(h->p<double>(h->X0), X, 2 * (size_t)M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_fiber_force(s, M, h->p<int>(h->prev_d), h->p<int>(h->next_d), h->K, h->p<double>(h->X0),
+                       h->p<double>(h->G));
+    launch_weights0(s, M, h->N, h->kind, h->p<double>(h->X0), h->p<int>(h->L[0].orgB), h->p<double>(h->L[0].wB));
+    launch_weights0(s, M, h->N, h->kind, h->p<double>(h->X0), h->p<int>(h->L[0].orgC), h->p<double>(h->L[0].wC));
+    int* oB[IBMG_MAX_LEVELS];
+    int* oC[IBMG_MAX_LEVELS];
+    double* wB[IBMG_MAX_LEVELS];
+    double* wC[IBMG_MAX_LEVELS];
+    int Ns[IBMG_MAX_LEVELS];
+    for (int l = 0; l < Lv; ++l) {
+      oB[l] = h->p<int>(h->L[l].orgB);
+      oC[l] = h->p<int>(h->L[l].orgC);
+      wB[l] = h->p<double>(h->L[l].wB);
+      wC[l] = h->p<double>(h->L[l].wC);
+      Ns[l] = h->L[l].N;
+    }
+    launch_coarsen(s, M, Lv, oB, wB, oC, wC, Ns);
+    if (h->prec == IBMG_FP32)
+      for (int l = 0; l < Lv; ++l) {
+        const size_t nw = 2 * (size_t)M * IBMG_PATCH;
+        k_convert<double, float><<<nblk(nw), 256, 0, s>>>(wB[l], h->p<float>(h->L[l].wBf), nw);
+        k_convert<double, float><<<nblk(nw), 256, 0, s>>>(wC[l], h->p<float>(h->L[l].wCf), nw);
+      }
+  }
+  for (int l = 0; l < Lv; ++l) {
+    LevelBufs& B = h->L[l];
+    const bool smoothed = l < Lv - 1;
+    launch_box_lists(s, M, M > 0 ? h->p<int>(B.orgB) : nullptr, h->n, B.N, B.nb, h->p<int>(B.cnt),
+                     h->p<int>(B.start), h->p<int>(B.cursor), h->p<int>(B.list), B.max_list,
+                     smoothed ? h->p<int>(B.ib_index) : nullptr, smoothed ? h->p<int>(B.ib_boxes) : nullptr,
+                     h->p<int>(B.info));
+  }
+  // box counts per colour drive the factor launches
+  std::vector<int> info(8 * Lv, 0);
+  for (int l = 0; l + 1 < Lv; ++l)
+    IBMG_HIP(hipMemcpyAsync(&info[8 * l], h->p<int>(h->L[l].info), 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+  {
+    int last = 0;
+    IBMG_HIP(hipMemcpyAsync(&last, h->p<int>(h->L[0].start) + (size_t)h->L[0].nb * h->L[0].nb, sizeof(int),
+                            hipMemcpyDeviceToHost, s));
+    IBMG_HIP(hipStreamSynchronize(s));
+    if (M > 0 && last > h->L[0].max_list) return IBMG_ENOMEM;
+  }
+  for (int l = 0; l + 1 < Lv; ++l) {
+    for (int c = 0; c < 5; ++c) h->n_ib[l][c] = h->has_ib ? info[8 * l + c] : 0;
+    if (h->n_ib[l][4] > h->L[l].max_ib) return IBMG_ENOMEM;
+    LevelView<double> v = view<double>(h, l);
+    launch_box_factor(s, v, h->p<int>(h->L[l].ib_boxes), h->n_ib[l][4], h->p<double>(h->L[l].ainv_plain),
+                      h->p<float>(h->L[l].ainv_plain_f), h->p<double>(h->L[l].ainv_ib));
+  }
+  {
+    LevelView<double> v = view<double>(h, Lv - 1);
+    if (!h->has_ib) v.M = 0;
+    launch_coarse_assemble(s, v, h->p<double>(h->aug), h->nr);
+    if (coarse_factor(s, h->p<double>(h->aug), h->nr, h->p<double>(h->cm), h->p<int>(h->cpiv), nullptr,
+                      h->p<int>(h->crowpos), h->p<int>(h->cused), h->p<double>(h->cY), h->p<double>(h->cainv)) != 0)
+      return IBMG_EHIP;
+  }
+  IBMG_HIP(hipGetLastError());
+  IBMG_HIP(hipStreamSynchronize(s));
+  h->setup_ok = true;
+  return IBMG_OK;
+}
+
+// ---------------------------------------------------------------- FGMRES
+
+int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
+  hipStream_t s = h->stream;
+  const size_t n0 = h->n0();
+  const int m = h->maxit, ldh = m + 1;
+  double* V = h->p<double>(h->V);
+  double* Z = h->p<double>(h->Z);
+  double* H = h->p<double>(h->H);
+  double* g = h->p<double>(h->g);
+  double* scal = h->p<double>(h->scal);
+  double* partial = h->p<double>(h->partial);
+  double* hc = h->p<double>(h->hc);
+  double hs[4];
+  h->ev_used = 0;
+  dot(h, b, b, scal);
+  int rc = read_doubles(h, scal, hs, 1);
+  if (rc) return rc;
+  const double bnorm = std::sqrt(hs[0]);
+  if (!std::isfinite(bnorm)) return IBMG_ENONFINITE;
+  st->bnorm = bnorm;
+  st->iters = 0;
+  st->converged = 0;
+  st->rel_resid_est = 0;
+  st->rel_resid_true = 0;
+  if (bnorm == 0.0) {
+    k_fill<double><<<nblk(n0), 256, 0, s>>>(x, n0, 0.0);
+    st->converged = 1;
+    return sync(h);
+  }
+  const double target = h->rtol * bnorm;
+  int total = 0;
+  double est = INFINITY;
+  for (;;) {
+    apply0(h, x, V, b);            // V[0] = b - A x
+    dot(h, V, V, scal);
+    if ((rc = read_doubles(h, scal, hs, 1))) return rc;
+    const double beta = std::sqrt(hs[0]);
+    if (!std::isfinite(beta)) return IBMG_ENONFINITE;
+    st->rel_resid_true = beta / bnorm;
+    if (beta <= target) { st->converged = 1; break; }
+    if (total >= m) break;
+    launch_scale(s, V, V, n0, scal);
+    k_fill<double><<<nblk(m + 2), 256, 0, s>>>(g, m + 2, 0.0);
+    IBMG_HIP(hipMemcpyAsync(g, &beta, sizeof(double), hipMemcpyHostToDevice, s));
+    int k = 0;
+    for (int j = 0; j < m && total < m; ++j) {
+      double* vj = V + (size_t)j * n0;
+      double* vn = V + (size_t)(j + 1) * n0;
+      double* zj = Z + (size_t)j * n0;
+      double* colj = H + (size_t)j * ldh;
+      precond(h, vj, zj);
+      apply0(h, zj, vn);
+      ++total;
+      // classical Gram-Schmidt, twice
+      launch_multidot(s, V, n0, j + 1, vn, n0, partial, kDotBlocks);
+      launch_reduce(s, partial, kDotBlocks, j + 1, colj, 0);
+      launch_update(s, V, n0, j + 1, colj, vn, n0, -1.0);
+      launch_multidot(s, V, n0, j + 1, vn, n0, partial, kDotBlocks);
+      launch_reduce(s, partial, kDotBlocks, j + 1, hc, 0);
+      launch_update(s, V, n0, j + 1, hc, vn, n0, -1.0);
+      launch_reduce(s, partial, kDotBlocks, j + 1, colj, 1);
+      // H(j+1, j)^2, normalise, rotate
+      launch_multidot(s, vn, 0, 1, vn, n0, partial, kDotBlocks);
+      launch_reduce(s, partial, kDotBlocks, 1, colj + j + 1, 0);
+      launch_scale(s, vn, vn, n0, colj + j + 1);
+      launch_givens(s, H, ldh, g, h->p<double>(h->cs), h->p<double>(h->sn), j, h->p<double>(h->flags), target);
+      if ((rc = read_doubles(h, h->p<double>(h->flags), hs, 3))) return rc;
+      k = j + 1;
+      est = hs[0] / bnorm;
+      if (hs[2] != 0.0) return IBMG_ENONFINITE;
+      if (hs[1] != 0.0) break;
+    }
+    launch_backsolve(s, H, ldh, g, k, h->p<double>(h->y));
+    launch_update(s, Z, n0, k, h->p<double>(h->y), x, n0, 1.0);
+  }
+  st->iters = total;
+  st->rel_resid_est = std::isfinite(est) ? est : st->rel_resid_true;
+  // phase timings
+  if (h->timing && h->ev_used > 0) {
+    IBMG_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q + 1 < h->ev_used; q += 2) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, h->ev[q], h->ev[q + 1]) == hipSuccess) {
+        h->t_total_ms += ms;
+        h->t_bytes += h->ev_bytes[q / 2];
+        h->t_launches += 1;
+      }
+    }
+  }
+  return st->converged ? IBMG_OK : IBMG_NOT_CONVERGED;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool ready(const ibmg_handle* h) { return h && h->ws; }
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* ibmg_status_string(int s) {
+  switch (s) {
+    case IBMG_OK: return "ok";
+    case IBMG_NOT_CONVERGED: return "not converged (iteration cap)";
+    case IBMG_EINVAL: return "invalid argument";
+    case IBMG_ESHAPE: return "unsupported shape (N, levels or box size)";
+    case IBMG_EHIP: return "HIP runtime error";
+    case IBMG_ENOMEM: return "workspace too small or not bound";
+    case IBMG_ENONFINITE: return "non-finite value";
+    case IBMG_ESTATE: return "call order violated (setup missing)";
+    default: return "unknown status";
+  }
+}
+
+int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, void* stream) {
+  if (!out || !pr || !op) return IBMG_EINVAL;
+  *out = nullptr;
+  const int N = pr->N;
+  if (N < 4 || (N & (N - 1)) != 0) return IBMG_ESHAPE;
+  if (!(pr->rho > 0) || !(pr->mu > 0) || !std::isfinite(pr->K) || pr->K < 0) return IBMG_EINVAL;
+  if (pr->delta != IBMG_DELTA_IB4 && pr->delta != IBMG_DELTA_COS4) return IBMG_EINVAL;
+  if (op->box != 1 && op->box != 2 && op->box != 4) return IBMG_ESHAPE;
+  if (op->levels < 1 || op->levels > IBMG_MAX_LEVELS) return IBMG_ESHAPE;
+  const int Nc = N >> (op->levels - 1);
+  if (Nc < 4 || Nc > 16) return IBMG_ESHAPE;
+  for (int l = 0; l + 1 < op->levels; ++l) {
+    const int Nl = N >> l;
+    if (Nl < 4 || Nl < 2 * op->box) return IBMG_ESHAPE;
+  }
+  if (op->nu1 < 0 || op->nu2 < 0 || op->maxit < 1 || op->maxit > 200 || !(op->rtol > 0)) return IBMG_EINVAL;
+  if (op->vcycle_prec != IBMG_FP64 && op->vcycle_prec != IBMG_FP32) return IBMG_EINVAL;
+  if (op->guess != IBMG_GUESS_ZERO && op->guess != IBMG_GUESS_PREV) return IBMG_EINVAL;
+  if (pr->n_points < 0 || pr->n_fibers < 0) return IBMG_EINVAL;
+  if (pr->n_points > 0 && (!pr->fiber_offsets || pr->n_fibers < 1)) return IBMG_EINVAL;
+  ibmg_handle* h = new (std::nothrow) ibmg_handle();
+  if (!h) return IBMG_EINVAL;
+  h->N = N; h->M = pr->n_points; h->nfib = pr->n_fibers; h->kind = pr->delta;
+  h->rho = pr->rho; h->mu = pr->mu; h->K = pr->K;
+  h->levels = op->levels; h->n = op->box; h->nu1 = op->nu1; h->nu2 = op->nu2; h->maxit = op->maxit;
+  h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess;
+  h->stream = (hipStream_t)stream;
+  h->prev.assign(h->M, 0);
+  h->next.assign(h->M, 0);
+  if (h->M > 0) {
+    const int* o = pr->fiber_offsets;
+    if (o[0] != 0 || o[pr->n_fibers] != h->M) { delete h; return IBMG_EINVAL; }
+    for (int f = 0; f < pr->n_fibers; ++f) {
+      const int a = o[f], b = o[f + 1];
+      if (b < a) { delete h; return IBMG_EINVAL; }
+      const int nf = b - a;
+      for (int k = a; k < b; ++k) {
+        h->prev[k] = a + (k - a - 1 + nf) % nf;
+        h->next[k] = a + (k - a + 1) % nf;
+      }
+    }
+  }
+  layout(h);
+  *out = h;
+  return IBMG_OK;
+}
+
+int ibmg_workspace_bytes(const ibmg_handle* h, size_t* bytes) {
+  if (!h || !bytes) return IBMG_EINVAL;
+  *bytes = h->need;
+  return IBMG_OK;
+}
+
+int ibmg_bind_workspace(ibmg_handle* h, void* dev, size_t bytes) {
+  if (!h || !dev) return IBMG_EINVAL;
+  char* base = (char*)(((uintptr_t)dev + 255) & ~(uintptr_t)255);
+  if (bytes < h->need || (size_t)(base - (char*)dev) + h->need - 256 > bytes) return IBMG_ENOMEM;
+  h->ws = base;
+  h->ws_bytes = bytes;
+  h->setup_ok = false;
+  if (h->M > 0) {
+    IBMG_HIP(hipMemcpyAsync(h->p<int>(h->prev_d), h->prev.data(), h->M * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+    IBMG_HIP(hipMemcpyAsync(h->p<int>(h->next_d), h->next.data(), h->M * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+    IBMG_HIP(hipStreamSynchronize(h->stream));
+  }
+  return IBMG_OK;
+}
+
+int ibmg_destroy(ibmg_handle* h) {
+  if (!h) return IBMG_EINVAL;
+  for (auto e : h->ev) (void)hipEventDestroy(e);
+  delete h;
+  return IBMG_OK;
+}
+
+int ibmg_set_timing(ibmg_handle* h, int on) {
+  if (!h) return IBMG_EINVAL;
+  h->timing = on != 0;
+  if (h->timing && h->ev.empty()) {
+    h->ev.resize(2 * kMaxTimed);
+    for (auto& e : h->ev) IBMG_HIP(hipEventCreate(&e));
+    h->ev_bytes.assign(kMaxTimed, 0.0);
+  }
+  h->t_total_ms = 0;
+  h->t_bytes = 0;
+  h->t_launches = 0;
+  return IBMG_OK;
+}
+
+int ibmg_phase_timing(ibmg_handle* h, double* total_ms, int64_t* launches, double* bytes) {
+  if (!h) return IBMG_EINVAL;
+  if (total_ms) *total_ms = h->t_total_ms;
+  if (launches) *launches = h->t_launches;
+  if (bytes) *bytes = h->t_bytes;
+  return IBMG_OK;
+}
+
+int ibmg_setup(ibmg_handle* h, double dt, const double* X) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  return do_setup(h, dt, X);
+}
+
+int ibmg_rhs(ibmg_handle* h, const double* u, const double* v, const double* gu, const double* gv, double* b) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!h->setup_ok) return IBMG_ESTATE;
+  if (!b) return IBMG_EINVAL;
+  LevelView<double> v0 = view<double>(h, 0);
+  const double inv_h2 = (double)h->N * h->N;
+  launch_rhs(h->stream, v0, inv_h2, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr, b);
+  IBMG_HIP(hipGetLastError());
+  return IBMG_OK;
+}
+
+int ibmg_solve(ibmg_handle* h, const double* b, double* w, ibmg_stats* out) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!h->setup_ok) return IBMG_ESTATE;
+  if (!b || !w) return IBMG_EINVAL;
+  ibmg_stats st{};
+  const double t0 = now_ms();
+  const size_t n0 = h->n0();
+  double* x = h->p<double>(h->xvec);
+  IBMG_HIP(hipMemcpyAsync(x, w, n0 * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  int rc = do_solve(h, b, x, &st);
+  if (rc >= 0) {
+    IBMG_HIP(hipMemcpyAsync(w, x, n0 * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    IBMG_HIP(hipStreamSynchronize(h->stream));
+  }
+  st.t_solve_ms = now_ms() - t0;
+  if (out) *out = st;
+  return rc;
+}
+
+int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X, const double* gu,
+              const double* gv, ibmg_stats* out) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!u || !v || !p || (h->M > 0 && !X)) return IBMG_EINVAL;
+  ibmg_stats st{};
+  const double t0 = now_ms();
+  int rc = do_setup(h, dt, X);
+  if (rc) return rc;
+  const double t1 = now_ms();
+  hipStream_t s = h->stream;
+  const size_t NN = (size_t)h->N * h->N, n0 = h->n0();
+  double* b = h->p<double>(h->bvec);
+  double* x = h->p<double>(h->xvec);
+  LevelView<double> v0 = view<double>(h, 0);
+  launch_rhs(s, v0, (double)h->N * h->N, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr, b);
+  if (h->guess == IBMG_GUESS_PREV) {
+    IBMG_HIP(hipMemcpyAsync(x, u, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(x + NN, v, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(x + 2 * NN, p, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    k_fill<double><<<nblk(n0), 256, 0, s>>>(x, n0, 0.0);
+  }
+  rc = do_solve(h, b, x, &st);
+  const double t2 = now_ms();
+  if (rc < 0) return rc;
+  // zero-mean pressure, then move the structure with the lagged S^n
+  double* part = h->p<double>(h->partial);
+  double* scal = h->p<double>(h->scal);
+  launch_sum(s, x + 2 * NN, NN, part, kDotBlocks);
+  launch_reduce(s, part, kDotBlocks, 1, scal, 0);
+  launch_mean_shift(s, x + 2 * NN, NN, scal);
+  if (h->M > 0) launch_interp(s, v0, x, x + NN, h->p<double>(h->U), h->p<double>(h->X0), dt);
+  IBMG_HIP(hipMemcpyAsync(u, x, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  IBMG_HIP(hipMemcpyAsync(v, x + NN, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  IBMG_HIP(hipMemcpyAsync(p, x + 2 * NN, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (h->M > 0)
+    IBMG_HIP(hipMemcpyAsync(X, h->p<double>(h->X0), 2 * (size_t)h->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  IBMG_HIP(hipGetLastError());
+  IBMG_HIP(hipStreamSynchronize(s));
+  h->setup_ok = false;   // the operator belongs to X^n
+  st.t_setup_ms = t1 - t0;
+  st.t_solve_ms = t2 - t1;
+  st.t_step_ms = now_ms() - t0;
+  if (out) *out = st;
+  return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- single operations
+
+namespace {
+
+template <typename T>
+int single_op(ibmg_handle* h, int which, int level, const double* a, const double* b, double* out, int sweeps) {
+  hipStream_t s = h->stream;
+  if (level < 0 || level >= h->levels) return IBMG_EINVAL;
+  LevelView<T> v = view<T>(h, level);
+  const size_t n3 = 3 * (size_t)v.N * v.N;
+  const bool f32 = sizeof(T) == sizeof(float);
+  // staging: FP32 handles convert through the level's r and w buffers (level 0: w0f, b0f)
+  auto stage = [&](const double* src, const Buf& bf) -> T* {
+    T* d = h->p<T>(bf);
+    k_convert<double, T><<<nblk(n3), 256, 0, s>>>(src, d, n3);
+    return d;
+  };
+  const Buf& wb = level == 0 ? h->w0f : h->L[level].w;
+  const Buf& bb = level == 0 ? h->b0f : h->L[level].b;
+  switch (which) {
+    case 0: {  // apply
+      const T* w = f32 ? stage(a, wb) : (const T*)a;
+      T* y = f32 ? h->p<T>(h->L[level].r) : (T*)out;
+      if (h->has_ib) launch_gather<T>(s, v, w);
+      launch_residual<T>(s, v, nullptr, w, y, h->has_ib);
+      if (f32) k_convert<T, double><<<nblk(n3), 256, 0, s>>>(y, out, n3);
+      break;
+    }
+    case 1: {  // residual r = b - A w
+      const T* w = f32 ? stage(a, wb) : (const T*)a;
+      const T* bv = f32 ? stage(b, bb) : (const T*)b;
+      T* y = f32 ? h->p<T>(h->L[level].r) : (T*)out;
+      if (h->has_ib) launch_gather<T>(s, v, w);
+      launch_residual<T>(s, v, bv, w, y, h->has_ib);
+      if (f32) k_convert<T, double><<<nblk(n3), 256, 0, s>>>(y, out, n3);
+      break;
+    }
+    case 2: {  // smooth in place on out, rhs b
+      if (level >= h->levels - 1) return IBMG_EINVAL;
+      T* w = f32 ? stage(out, wb) : (T*)out;
+      const T* bv = f32 ? stage(b, bb) : (const T*)b;
+      for (int q = 0; q < sweeps; ++q) sweep<T>(h, v, level, bv, w);
+      if (f32) k_convert<T, double><<<nblk(n3), 256, 0, s>>>(w, out, n3);
+      break;
+    }
+    case 3: {  // restrict a (level) -> out (level+1)
+      if (level >= h->levels - 1) return IBMG_EINVAL;
+      if (f32) {
+        T* f = stage(a, h->L[level].r);
+        T* c = h->p<T>(h->L[level + 1].b);
+        launch_restrict<T>(s, v.N, f, c);
+        const size_t nc3 = n3 / 4;
+        k_convert<T, double><<<nblk(nc3), 256, 0, s>>>(c, out, nc3);
+      } else {
+        launch_restrict<T>(s, v.N, (const T*)a, (T*)out);
+      }
+      break;
+    }
+    case 4: {  // out (level) += P a (level+1)
+      if (level >= h->levels - 1) return IBMG_EINVAL;
+      if (f32) {
+        const size_t nc3 = n3 / 4;
+        T* c = h->p<T>(h->L[level + 1].w);
+        k_convert<double, T><<<nblk(nc3), 256, 0, s>>>(a, c, nc3);
+        T* f = stage(out, wb);
+        launch_prolong_add<T>(s, v.N, c, f);
+        k_convert<T, double><<<nblk(n3), 256, 0, s>>>(f, out, n3);
+      } else {
+        launch_prolong_add<T>(s, v.N, (const T*)a, (T*)out);
+      }
+      break;
+    }
+    case 5: {  // coarsest solve
+      const int lc = h->levels - 1;
+      LevelView<T> vc = view<T>(h, lc);
+      const size_t nc3 = 3 * (size_t)vc.N * vc.N;
+      if (f32) {
+        T* bb2 = h->p<T>(lc == 0 ? h->b0f : h->L[lc].b);
+        T* ww = h->p<T>(lc == 0 ? h->w0f : h->L[lc].w);
+        k_convert<double, T><<<nblk(nc3), 256, 0, s>>>(a, bb2, nc3);
+        launch_coarse_apply<T>(s, h->p<double>(h->cainv), h->nr, bb2, ww);
+        k_convert<T, double><<<nblk(nc3), 256, 0, s>>>(ww, out, nc3);
+      } else {
+        launch_coarse_apply<T>(s, h->p<double>(h->cainv), h->nr, (const T*)a, (T*)out);
+      }
+      break;
+    }
+    default: return IBMG_EINVAL;
+  }
+  IBMG_HIP(hipGetLastError());
+  return sync(h);
+}
+
+int single(ibmg_handle* h, int which, int level, const double* a, const double* b, double* out, int sweeps) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!h->setup_ok) return IBMG_ESTATE;
+  return h->prec == IBMG_FP32 ? single_op<float>(h, which, level, a, b, out, sweeps)
+                              : single_op<double>(h, which, level, a, b, out, sweeps);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibmg_apply(ibmg_handle* h, int level, const double* w, double* y) {
+  if (!w || !y) return IBMG_EINVAL;
+  return single(h, 0, level, w, nullptr, y, 0);
+}
+int ibmg_residual(ibmg_handle* h, int level, const double* b, const double* w, double* r) {
+  if (!w || !b || !r) return IBMG_EINVAL;
+  return single(h, 1, level, w, b, r, 0);
+}
+int ibmg_smooth(ibmg_handle* h, int level, const double* b, double* w, int sweeps) {
+  if (!w || !b || sweeps < 0) return IBMG_EINVAL;
+  return single(h, 2, level, nullptr, b, w, sweeps);
+}
+int ibmg_restrict(ibmg_handle* h, int level, const double* fine, double* coarse) {
+  if (!fine || !coarse) return IBMG_EINVAL;
+  return single(h, 3, level, fine, nullptr, coarse, 0);
+}
+int ibmg_prolong_add(ibmg_handle* h, int level, const double* coarse, double* fine) {
+  if (!fine || !coarse) return IBMG_EINVAL;
+  return single(h, 4, level, coarse, nullptr, fine, 0);
+}
+int ibmg_coarse_solve(ibmg_handle* h, const double* b, double* w) {
+  if (!b || !w) return IBMG_EINVAL;
+  return single(h, 5, 0, b, nullptr, w, 0);
+}
+
+int ibmg_vcycle(ibmg_handle* h, const double* r, double* z) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!h->setup_ok) return IBMG_ESTATE;
+  if (!r || !z) return IBMG_EINVAL;
+  precond(h, r, z);
+  IBMG_HIP(hipGetLastError());
+  return sync(h);
+}
+
+int ibmg_box_matrix(ibmg_handle* h, int level, int bx, int by, double* out) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!h->setup_ok) return IBMG_ESTATE;
+  if (!out || level < 0 || level >= h->levels - 1) return IBMG_EINVAL;
+  const LevelBufs& B = h->L[level];
+  if (bx < 0 || by < 0 || bx >= B.nb || by >= B.nb) return IBMG_EINVAL;
+  LevelView<double> v = view<double>(h, level);
+  if (!h->has_ib) v.M = 0;
+  launch_box_matrix(h->stream, v, bx, by, out);
+  IBMG_HIP(hipGetLastError());
+  return sync(h);
+}
+
+int ibmg_fiber_force(ibmg_handle* h, const double* X, double* G) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (h->M == 0) return IBMG_OK;
+  if (!X || !G) return IBMG_EINVAL;
+  launch_fiber_force(h->stream, h->M, h->p<int>(h->prev_d), h->p<int>(h->next_d), h->K, X, G);
+  IBMG_HIP(hipGetLastError());
+  return sync(h);
+}
+
+}  // extern "C"
+
+namespace {
+// Finest-level point data (weights and box lists) for arbitrary X.
+int fine_points(ibmg_handle* h, const double* X) {
+  hipStream_t s = h->stream;
+  LevelBufs& B = h->L[0];
+  h->setup_ok = false;
+  launch_weights0(s, h->M, h->N, h->kind, X, h->p<int>(B.orgB), h->p<double>(B.wB));
+  launch_weights0(s, h->M, h->N, h->kind, X, h->p<int>(B.orgC), h->p<double>(B.wC));
+  launch_box_lists(s, h->M, h->p<int>(B.orgB), h->n, B.N, B.nb, h->p<int>(B.cnt), h->p<int>(B.start),
+                   h->p<int>(B.cursor), h->p<int>(B.list), B.max_list, nullptr, nullptr, h->p<int>(B.info));
+  IBMG_HIP(hipGetLastError());
+  return IBMG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ibmg_spread(ibmg_handle* h, const double* X, const double* G, double* fu, double* fv) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!fu || !fv || (h->M > 0 && (!X || !G))) return IBMG_EINVAL;
+  const size_t NN = (size_t)h->N * h->N;
+  double* b = h->p<double>(h->bvec);
+  if (h->M > 0) {
+    int rc = fine_points(h, X);
+    if (rc) return rc;
+  }
+  LevelView<double> v0 = view<double>(h, 0);
+  v0.c = 0.0;
+  launch_rhs(h->stream, v0, (double)h->N * h->N, nullptr, nullptr, nullptr, nullptr, h->M > 0 ? G : nullptr, b);
+  IBMG_HIP(hipMemcpyAsync(fu, b, NN * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  IBMG_HIP(hipMemcpyAsync(fv, b + NN, NN * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  IBMG_HIP(hipGetLastError());
+  return sync(h);
+}
+
+int ibmg_interp(ibmg_handle* h, const double* X, const double* u, const double* v, double* U) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (h->M == 0) return IBMG_OK;
+  if (!X || !u || !v || !U) return IBMG_EINVAL;
+  int rc = fine_points(h, X);
+  if (rc) return rc;
+  LevelView<double> v0 = view<double>(h, 0);
+  launch_interp(h->stream, v0, u, v, U, nullptr, 0.0);
+  IBMG_HIP(hipGetLastError());
+  return sync(h);
+}
+
+}  // extern "C"

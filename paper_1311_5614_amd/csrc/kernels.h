@@ -1,0 +1,70 @@
+// Launch wrappers and small utility kernels shared by the translation units.
+#pragma once
+#include "common.h"
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill(T* __restrict__ x, size_t n, T v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+__global__ void __launch_bounds__(256) static k_fill_i32(int* __restrict__ x, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(256) k_convert(const S* __restrict__ a, D* __restrict__ b, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (D)a[i];
+}
+
+namespace ibmg {
+
+inline unsigned nblk(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// ib_setup.hip
+void launch_fiber_force(hipStream_t s, int M, const int* prev, const int* next, double K,
+                        const double* X, double* G);
+void launch_weights0(hipStream_t s, int M, int N, int kind, const double* X, int* org, double* w);
+void launch_coarsen(hipStream_t s, int M, int levels, int* const* orgB, double* const* wB,
+                    int* const* orgC, double* const* wC, const int* Ns);
+void launch_box_lists(hipStream_t s, int M, const int* orgB, int n, int N, int nb, int* cnt, int* start,
+                      int* cursor, int* list, int max_list, int* ib_index, int* ib_boxes, int* info);
+void launch_box_factor(hipStream_t s, const LevelView<double>& L, const int* ib_boxes, int n_ib,
+                       double* ainv_plain, float* ainv_plain_f, double* ainv_ib);
+void launch_box_matrix(hipStream_t s, const LevelView<double>& L, int bx, int by, double* out);
+
+// mg.hip (T = double or float)
+template <typename T> void launch_gather(hipStream_t s, const LevelView<T>& L, const T* w);
+template <typename T> void launch_residual(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r,
+                                           bool ib);
+template <typename T> void launch_phase(hipStream_t s, const LevelView<T>& L, const T* b, T* w, int colour,
+                                        bool ib);
+template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc);
+template <typename T> void launch_prolong_add(hipStream_t s, int Nf, const T* ec, T* wf);
+void launch_rhs(hipStream_t s, const LevelView<double>& L0, double inv_h2, const double* u, const double* v,
+                const double* gu, const double* gv, const double* G, double* b);
+void launch_interp(hipStream_t s, const LevelView<double>& L0, const double* u, const double* v, double* U,
+                   double* X, double dt);
+
+// dense.hip: bordered coarsest system
+void launch_coarse_assemble(hipStream_t s, const LevelView<double>& L, double* aug, int nr);
+int coarse_factor(hipStream_t s, double* aug, int nr, double* m, int* piv, double* dpiv, int* rowpos,
+                  int* used, double* Y, double* ainv);
+template <typename T> void launch_coarse_apply(hipStream_t s, const double* ainv, int nr, const T* b, T* w);
+
+// krylov.hip
+void launch_multidot(hipStream_t s, const double* V, size_t ldv, int nvec, const double* w, size_t n,
+                     double* partial, int nblocks);
+void launch_reduce(hipStream_t s, const double* partial, int nblocks, int nvec, double* out, int accumulate);
+void launch_update(hipStream_t s, const double* V, size_t ldv, int nvec, const double* coef, double* w,
+                   size_t n, double sign);
+void launch_scale(hipStream_t s, const double* w, double* out, size_t n, const double* norm2);
+void launch_givens(hipStream_t s, double* H, int ldh, double* g, double* cs, double* sn, int j, double* flags,
+                   double target);
+void launch_backsolve(hipStream_t s, const double* H, int ldh, const double* g, int k, double* y);
+void launch_mean_shift(hipStream_t s, double* p, size_t n, const double* sum);
+void launch_sum(hipStream_t s, const double* x, size_t n, double* partial, int nblocks);
+
+}  // namespace ibmg

@@ -1,0 +1,271 @@
+"""Thin ctypes binding of libibmg.so (include/ibmg.h).
+
+Argument marshalling only: every arithmetic step runs in the gfx950 kernels
+of the library.  PyTorch supplies device memory (the workspace and the
+caller's tensors) and the HIP stream.  The functions keep the C names; the
+`Solver` class bundles a handle with its workspace tensor.
+
+The library must be built (python -m paper_1311_5614_amd.build); importing
+this module raises if libibmg.so is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibmg.so")
+
+IBMG_OK, IBMG_NOT_CONVERGED = 0, 1
+IBMG_EINVAL, IBMG_ESHAPE, IBMG_EHIP, IBMG_ENOMEM, IBMG_ENONFINITE, IBMG_ESTATE = -1, -2, -3, -4, -5, -6
+IBMG_DELTA_IB4, IBMG_DELTA_COS4 = 0, 1
+IBMG_FP64, IBMG_FP32 = 0, 1
+IBMG_GUESS_ZERO, IBMG_GUESS_PREV = 0, 1
+
+EXPORTS = [
+    "ibmg_create", "ibmg_workspace_bytes", "ibmg_bind_workspace", "ibmg_destroy",
+    "ibmg_status_string", "ibmg_set_timing", "ibmg_phase_timing", "ibmg_setup", "ibmg_step",
+    "ibmg_rhs", "ibmg_solve", "ibmg_apply", "ibmg_residual", "ibmg_smooth", "ibmg_restrict",
+    "ibmg_prolong_add", "ibmg_coarse_solve", "ibmg_vcycle", "ibmg_box_matrix",
+    "ibmg_fiber_force", "ibmg_spread", "ibmg_interp",
+]
+
+
+class ibmg_problem(C.Structure):
+    _fields_ = [("N", C.c_int32), ("rho", C.c_double), ("mu", C.c_double),
+                ("n_points", C.c_int32), ("n_fibers", C.c_int32),
+                ("fiber_offsets", C.POINTER(C.c_int32)), ("K", C.c_double), ("delta", C.c_int32)]
+
+
+class ibmg_opts(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("box", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("maxit", C.c_int32), ("rtol", C.c_double), ("vcycle_prec", C.c_int32),
+                ("guess", C.c_int32)]
+
+
+class ibmg_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_resid_est", C.c_double),
+                ("rel_resid_true", C.c_double), ("bnorm", C.c_double), ("t_setup_ms", C.c_double),
+                ("t_solve_ms", C.c_double), ("t_step_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1311_5614_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, dbl, sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    sig = {
+        "ibmg_create": [C.POINTER(vp), C.POINTER(ibmg_problem), C.POINTER(ibmg_opts), vp],
+        "ibmg_workspace_bytes": [vp, C.POINTER(sz)],
+        "ibmg_bind_workspace": [vp, vp, sz],
+        "ibmg_destroy": [vp],
+        "ibmg_status_string": [i32],
+        "ibmg_set_timing": [vp, i32],
+        "ibmg_phase_timing": [vp, C.POINTER(dbl), C.POINTER(C.c_int64), C.POINTER(dbl)],
+        "ibmg_setup": [vp, dbl, vp],
+        "ibmg_step": [vp, dbl, vp, vp, vp, vp, vp, vp, C.POINTER(ibmg_stats)],
+        "ibmg_rhs": [vp, vp, vp, vp, vp, vp],
+        "ibmg_solve": [vp, vp, vp, C.POINTER(ibmg_stats)],
+        "ibmg_apply": [vp, i32, vp, vp],
+        "ibmg_residual": [vp, i32, vp, vp, vp],
+        "ibmg_smooth": [vp, i32, vp, vp, i32],
+        "ibmg_restrict": [vp, i32, vp, vp],
+        "ibmg_prolong_add": [vp, i32, vp, vp],
+        "ibmg_coarse_solve": [vp, vp, vp],
+        "ibmg_vcycle": [vp, vp, vp],
+        "ibmg_box_matrix": [vp, i32, i32, i32, vp],
+        "ibmg_fiber_force": [vp, vp, vp],
+        "ibmg_spread": [vp, vp, vp, vp, vp],
+        "ibmg_interp": [vp, vp, vp, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_char_p if name == "ibmg_status_string" else C.c_int
+    return lib
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+class IBMGError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {lib().ibmg_status_string(code).decode()} ({code})")
+
+
+def _check(code, where, allow_not_converged=True):
+    if code < 0 or (code > 0 and not allow_not_converged):
+        raise IBMGError(code, where)
+    return code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("contiguous float64 tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Config:
+    N: int
+    levels: int
+    K: float = 0.0
+    rho: float = 1.0
+    mu: float = 1.0
+    delta: int = IBMG_DELTA_IB4
+    box: int = 4
+    nu1: int = 2
+    nu2: int = 2
+    maxit: int = 100
+    rtol: float = 1e-8
+    prec: int = IBMG_FP64
+    guess: int = IBMG_GUESS_ZERO
+
+
+class Solver:
+    """One handle plus its torch-owned workspace on `device`."""
+
+    def __init__(self, cfg: Config, fiber_offsets, device="cuda:0", stream=None):
+        L = lib()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        offs = [int(x) for x in (fiber_offsets if fiber_offsets is not None else [0])]
+        self.M = offs[-1] if len(offs) > 1 else 0
+        self._offs = (C.c_int32 * len(offs))(*offs)
+        prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, self.M, max(0, len(offs) - 1),
+                            C.cast(self._offs, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
+        opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
+                         cfg.guess)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.ibmg_create(C.byref(h), C.byref(prob), C.byref(opts),
+                             C.c_void_p(self.stream.cuda_stream)), "ibmg_create")
+        self.h = h
+        nbytes = C.c_size_t()
+        _check(L.ibmg_workspace_bytes(h, C.byref(nbytes)), "ibmg_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        _check(L.ibmg_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value),
+               "ibmg_bind_workspace")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ibmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- thin wrappers (same names as the C ABI without the prefix)
+    def setup(self, dt, X):
+        return _check(lib().ibmg_setup(self.h, float(dt), _ptr(X)), "ibmg_setup")
+
+    def step(self, dt, u, v, p, X, g_u=None, g_v=None):
+        st = ibmg_stats()
+        code = _check(lib().ibmg_step(self.h, float(dt), _ptr(u), _ptr(v), _ptr(p), _ptr(X),
+                                      _ptr(g_u), _ptr(g_v), C.byref(st)), "ibmg_step")
+        d = st.as_dict()
+        d["status"] = code
+        return d
+
+    def rhs(self, u, v, g_u=None, g_v=None):
+        N = self.cfg.N
+        b = torch.empty(3 * N * N, dtype=torch.float64, device=self.device)
+        _check(lib().ibmg_rhs(self.h, _ptr(u), _ptr(v), _ptr(g_u), _ptr(g_v), _ptr(b)), "ibmg_rhs")
+        return b
+
+    def solve(self, b, w):
+        st = ibmg_stats()
+        code = _check(lib().ibmg_solve(self.h, _ptr(b), _ptr(w), C.byref(st)), "ibmg_solve")
+        d = st.as_dict()
+        d["status"] = code
+        return d
+
+    def _n3(self, level):
+        Nl = self.cfg.N >> level
+        return 3 * Nl * Nl
+
+    def apply(self, level, w):
+        y = torch.empty(self._n3(level), dtype=torch.float64, device=self.device)
+        _check(lib().ibmg_apply(self.h, level, _ptr(w), _ptr(y)), "ibmg_apply")
+        return y
+
+    def residual(self, level, b, w):
+        r = torch.empty(self._n3(level), dtype=torch.float64, device=self.device)
+        _check(lib().ibmg_residual(self.h, level, _ptr(b), _ptr(w), _ptr(r)), "ibmg_residual")
+        return r
+
+    def smooth(self, level, b, w, sweeps=1):
+        _check(lib().ibmg_smooth(self.h, level, _ptr(b), _ptr(w), sweeps), "ibmg_smooth")
+        return w
+
+    def restrict(self, level, fine):
+        c = torch.empty(self._n3(level + 1), dtype=torch.float64, device=self.device)
+        _check(lib().ibmg_restrict(self.h, level, _ptr(fine), _ptr(c)), "ibmg_restrict")
+        return c
+
+    def prolong_add(self, level, coarse, fine):
+        _check(lib().ibmg_prolong_add(self.h, level, _ptr(coarse), _ptr(fine)), "ibmg_prolong_add")
+        return fine
+
+    def coarse_solve(self, b):
+        w = torch.empty_like(b)
+        _check(lib().ibmg_coarse_solve(self.h, _ptr(b), _ptr(w)), "ibmg_coarse_solve")
+        return w
+
+    def vcycle(self, r):
+        z = torch.empty_like(r)
+        _check(lib().ibmg_vcycle(self.h, _ptr(r), _ptr(z)), "ibmg_vcycle")
+        return z
+
+    def box_matrix(self, level, bx, by):
+        n = self.cfg.box
+        nd = 2 * n * (n + 1) + n * n
+        out = torch.empty(nd * nd, dtype=torch.float64, device=self.device)
+        _check(lib().ibmg_box_matrix(self.h, level, bx, by, _ptr(out)), "ibmg_box_matrix")
+        return out.view(nd, nd)
+
+    def fiber_force(self, X):
+        G = torch.empty_like(X)
+        _check(lib().ibmg_fiber_force(self.h, _ptr(X), _ptr(G)), "ibmg_fiber_force")
+        return G
+
+    def spread(self, X, G):
+        N = self.cfg.N
+        fu = torch.empty(N, N, dtype=torch.float64, device=self.device)
+        fv = torch.empty(N, N, dtype=torch.float64, device=self.device)
+        _check(lib().ibmg_spread(self.h, _ptr(X), _ptr(G), _ptr(fu), _ptr(fv)), "ibmg_spread")
+        return fu, fv
+
+    def interp(self, X, u, v):
+        U = torch.empty_like(X)
+        _check(lib().ibmg_interp(self.h, _ptr(X), _ptr(u), _ptr(v), _ptr(U)), "ibmg_interp")
+        return U
+
+    def set_timing(self, on=True):
+        _check(lib().ibmg_set_timing(self.h, 1 if on else 0), "ibmg_set_timing")
+
+    def phase_timing(self):
+        ms, n, by = C.c_double(), C.c_int64(), C.c_double()
+        _check(lib().ibmg_phase_timing(self.h, C.byref(ms), C.byref(n), C.byref(by)), "ibmg_phase_timing")
+        return dict(total_ms=ms.value, launches=n.value, bytes=by.value)

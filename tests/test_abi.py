@@ -1,0 +1,99 @@
+"""The C ABI without a GPU: the library loads, exports every symbol the header
+declares, the ctypes structs match the C layout, and host-side validation
+(shapes, options, fibre offsets) behaves as documented.  No compute call."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ibmg.h")
+
+
+def _lib():
+    from paper_1311_5614_amd import ibmg
+    return ibmg, ibmg.lib()
+
+
+def header_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(ibmg_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    ibmg, L = _lib()
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(ibmg.EXPORTS) == syms
+    out = subprocess.run(["nm", "-D", "--defined-only", ibmg.LIB_PATH], capture_output=True, text=True).stdout
+    for s in syms:
+        assert re.search(rf"\bT {s}$", out, re.M), s
+
+
+def test_struct_layout_matches_c():
+    ibmg, _ = _lib()
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "ibmg.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
+         offsetof(ibmg_problem, fiber_offsets), offsetof(ibmg_problem, K), offsetof(ibmg_opts, rtol),
+         offsetof(ibmg_stats, t_step_ms));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        got = list(map(int, subprocess.run([exe], capture_output=True, text=True).stdout.split()))
+    want = [C.sizeof(ibmg.ibmg_problem), C.sizeof(ibmg.ibmg_opts), C.sizeof(ibmg.ibmg_stats),
+            ibmg.ibmg_problem.fiber_offsets.offset, ibmg.ibmg_problem.K.offset, ibmg.ibmg_opts.rtol.offset,
+            ibmg.ibmg_stats.t_step_ms.offset]
+    assert got == want
+
+
+def _create(N=32, levels=3, box=4, offs=(0, 40), **kw):
+    ibmg, L = _lib()
+    o = (C.c_int32 * len(offs))(*offs)
+    prob = ibmg.ibmg_problem(N, kw.get("rho", 1.0), kw.get("mu", 1.0), offs[-1], len(offs) - 1,
+                             C.cast(o, C.POINTER(C.c_int32)), kw.get("K", 1e3), kw.get("delta", 0))
+    opts = ibmg.ibmg_opts(levels, box, kw.get("nu1", 2), kw.get("nu2", 2), kw.get("maxit", 100),
+                          kw.get("rtol", 1e-8), kw.get("prec", 0), kw.get("guess", 0))
+    h = C.c_void_p()
+    rc = L.ibmg_create(C.byref(h), C.byref(prob), C.byref(opts), None)
+    return rc, h, L
+
+
+def test_create_validates_shapes_without_gpu():
+    rc, h, L = _create()
+    assert rc == 0
+    n = C.c_size_t()
+    assert L.ibmg_workspace_bytes(h, C.byref(n)) == 0 and n.value > 0
+    # unbound workspace -> ENOMEM on every device call, before touching the GPU
+    assert L.ibmg_setup(h, 0.1, None) == -4
+    assert L.ibmg_vcycle(h, None, None) == -4
+    assert L.ibmg_destroy(h) == 0
+    assert _create(N=48)[0] == -2                     # not a power of two
+    assert _create(N=32, levels=5)[0] == -2           # coarsest 2x2
+    assert _create(N=16, levels=2, box=8)[0] == -2    # unsupported box
+    assert _create(N=8, levels=2, box=4)[0] == 0      # 8x8 holds two 4x4 boxes per side
+    assert _create(N=64, levels=2)[0] == -2           # coarsest 32 > 16
+    assert _create(offs=(0, 30, 20))[0] == -1         # decreasing offsets
+    assert _create(offs=(5, 40))[0] == -1             # offsets must start at 0
+    assert _create(rho=0.0)[0] == -1
+    assert _create(maxit=0)[0] == -1
+    assert _create(prec=3)[0] == -1
+
+
+def test_status_strings():
+    _, L = _lib()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, 99):
+        assert L.ibmg_status_string(code).decode()
