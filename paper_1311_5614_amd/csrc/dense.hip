@@ -161,7 +161,9 @@ k_coarse_panel(const double* __restrict__ aug, int nr, int k0, double* __restric
   }
 }
 
-// a[i][c] -= sum_s m[i][s] Y[s][c] for non-pivot rows, a[p_s][c] = Y[s][c].
+// Applies the panel's PW Gauss-Jordan steps to column c:
+// a[i][c] -= sum_s m[i][s] Y[s][c] for non-pivot rows,
+// a[p_s][c] = Y[s][c] - sum_{t>s} m[p_s][t] Y[t][c] for the pivot rows.
 __global__ void __launch_bounds__(256)
 k_coarse_update(double* __restrict__ aug, int nr, int k0, int pw, const double* __restrict__ m,
                 const int* __restrict__ rowpos, const double* __restrict__ Y) {
@@ -172,11 +174,15 @@ k_coarse_update(double* __restrict__ aug, int nr, int k0, int pw, const double* 
   double y[PW];
   for (int s = 0; s < pw; ++s) y[s] = Y[(size_t)s * ld + c];
   for (int i = r0; i < nr; i += gridDim.y * 4) {
+    // pivot row p_s: y_s, then eliminated by the later pivots t > s of the
+    // panel; any other row: eliminated by every pivot of the panel
     const int rp = rowpos[i];
     double* a = aug + (size_t)i * ld + c;
-    if (rp >= 0) { *a = y[rp]; continue; }
-    double v = *a;
-    for (int s = 0; s < pw; ++s) v -= m[(size_t)i * PW + s] * y[s];
+    double v = rp >= 0 ? 0.0 : *a;
+    for (int s = 0; s < pw; ++s) {
+      if (s == rp) v += y[s];
+      else if (s > rp) v -= m[(size_t)i * PW + s] * y[s];
+    }
     *a = v;
   }
 }
