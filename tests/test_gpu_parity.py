@@ -285,3 +285,48 @@ def test_errors_are_reported():
     s = ibmg.Solver(ibmg.Config(N=32, levels=3), None, DEV)
     with pytest.raises(ibmg.IBMGError):
         s.vcycle(torch.zeros(3 * 1024, dtype=torch.float64, device=DEV))   # before setup
+
+
+# ---------------------------------------------------------------- precision form: FP32 V-cycle
+
+def test_fp32_vcycle_error_statement():
+    """FP32 V-cycle fields and stencils (boxes with points and the coarsest
+    solve stay FP64): one V-cycle differs from the FP64 oracle V-cycle by
+    <= 1e-5 relative (measured value printed)."""
+    w, dt, s = make(N=64, levels=4, M=150, K=1e4, dt_factor=50.0, prec=1)
+    _setup(s, w, dt)
+    lv = oracle_levels(w, dt, 4, 1e4)
+    V = mg.VCycle(lv, 4, 2, 2)
+    r = np.random.default_rng(9).standard_normal(3 * 64 * 64)
+    r[2 * 4096:] -= r[2 * 4096:].mean()
+    z = tnp(s.vcycle(tdev(r)))
+    zo = V(r)
+    e = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    print(f"fp32 V-cycle relative error {e:.2e}")
+    assert e < 1e-5
+    x = np.random.default_rng(1).standard_normal(3 * 64 * 64)
+    y = tnp(s.apply(0, tdev(x)))
+    ey = np.max(np.abs(y - lv[0].A @ x)) / np.max(np.abs(lv[0].A @ x))
+    print(f"fp32 apply relative error {ey:.2e}")
+    assert ey < 1e-6
+
+
+@pytest.mark.parametrize("K,fac", [(1e4, 100.0), (1e8, 1000.0)])
+def test_fp32_solve_meets_fp64_tolerance(K, fac):
+    w, dt, s = make(N=64, levels=4, M=160, K=K, dt_factor=fac, prec=1, rtol=1e-10)
+    _, _, s64 = make(N=64, levels=4, M=160, K=K, dt_factor=fac, prec=0, rtol=1e-10)
+    _setup(s, w, dt)
+    _setup(s64, w, dt)
+    rng = np.random.default_rng(11)
+    u = rng.standard_normal((64, 64))
+    b = s.rhs(tdev(u), tdev(u.T.copy()))
+    x = torch.zeros_like(b)
+    st = s.solve(b, x)
+    x64 = torch.zeros_like(b)
+    st64 = s64.solve(b, x64)
+    lv = oracle_levels(w, dt, 1, K)
+    bo = tnp(b)
+    rr = np.linalg.norm(bo - lv[0].A @ tnp(x)) / np.linalg.norm(bo)
+    print(f"K={K:g}: fp32 iters {st['iters']} fp64 iters {st64['iters']} true residual {rr:.2e}")
+    assert st["converged"] == 1 and rr <= 1e-10
+    assert st["iters"] <= st64["iters"] + 3
