@@ -57,7 +57,7 @@ class Run:
         from paper_1311_5614_amd import ibmg
         self.w, self.dt = w, dt
         cfg = ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
-                          nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec)
+                          nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2))
         self.s = ibmg.Solver(cfg, w.fiber_offsets, dev)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
         self.X0 = t(w.X)
@@ -78,6 +78,9 @@ class Run:
 
 
 def timed(runs, steps, warmup, timing=False):
+    """Warm up, reset every trajectory, then time `steps` steps of all of them.
+    With timing set, the box kernels are event-timed (eager launches instead of
+    the replayed V-cycle graph)."""
     import torch
     for r in runs:
         r.reset()
@@ -86,8 +89,7 @@ def timed(runs, steps, warmup, timing=False):
             r.step()
     for r in runs:
         r.reset()
-        if timing:
-            r.s.set_timing(True)
+        r.s.set_timing(timing)
     torch.cuda.synchronize()
     its, conv = [], []
     t0 = time.perf_counter()
@@ -135,6 +137,9 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="plain,fp32")
+    ap.add_argument("--levels", type=int, default=0, help="override the workload's level count")
+    ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
+    ap.add_argument("--colours", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -144,17 +149,27 @@ def main():
     from paper_1311_5614_amd import ibmg
     dev = "cuda:0"
     cases, dts = workloads(args.workload)
+    for c in cases:
+        if args.levels:
+            c.levels = args.levels
+        if args.nu:
+            c.nu1, c.nu2 = (int(x) for x in args.nu.split(","))
+        c.colours = args.colours
     forms = args.forms.split(",")
     res = {}
     for form in forms:
         prec = ibmg.IBMG_FP32 if form == "fp32" else ibmg.IBMG_FP64
         runs = [Run(w, dt, prec, dev) for w, dt in zip(cases, dts)]
-        t, its, conv, ph = timed(runs, args.steps, args.warmup, timing=True)
+        t, its, conv, _ = timed(runs, args.steps, args.warmup, timing=False)
+        # roofline of the box kernel: the same trajectories, one more (untimed)
+        # step with every box launch bracketed by HIP events on its stream
+        _, _, _, ph = timed(runs, 1, 0, timing=True)
         n = args.steps * len(runs)
         res[form] = dict(time_s=t, timesteps=n, rate=n / t, iters_mean=sum(its) / len(its), iters_max=max(its),
                          converged=sum(conv), phase=ph)
         print(f"[bench] {form}: {n} steps in {t:.3f} s -> {n / t:.2f} steps/s, iters mean "
-              f"{res[form]['iters_mean']:.2f} max {max(its)}, converged {sum(conv)}/{n}", file=sys.stderr,
+              f"{res[form]['iters_mean']:.2f} max {max(its)}, converged {sum(conv)}/{n}; per case "
+              f"{[round(sum(its[c::len(runs)]) / args.steps, 1) for c in range(len(runs))]}", file=sys.stderr,
               flush=True)
         del runs
         torch.cuda.empty_cache()

@@ -90,6 +90,10 @@ typedef struct {
   double rtol;         /* stop when ||b - A w||_2 <= rtol ||b||_2                   */
   int32_t vcycle_prec; /* IBMG_FP64 or IBMG_FP32 (V-cycle fields and stencils)      */
   int32_t guess;       /* IBMG_GUESS_ZERO or IBMG_GUESS_PREV (step only)            */
+  int32_t colours;     /* box order of a sweep: 2 = checkerboard (bx + by) mod 2,
+                          4 = (bx mod 2, by mod 2) in the order (0,0),(1,0),(0,1),(1,1);
+                          within a colour every box solves from the residual at
+                          the start of that colour                                  */
 } ibmg_opts;
 
 typedef struct {
@@ -152,8 +156,8 @@ int ibmg_solve(ibmg_handle* h, const double* b, double* w, ibmg_stats* out);
 int ibmg_apply(ibmg_handle* h, int level, const double* w, double* y);
 /* r = b - A_l w. */
 int ibmg_residual(ibmg_handle* h, int level, const double* b, const double* w, double* r);
-/* `sweeps` box-relaxation sweeps on level l (Sec. 5-6) in place on w, colours
- * (0,0),(1,0),(0,1),(1,1), each colour from the residual at its start. */
+/* `sweeps` box-relaxation sweeps on level l (Sec. 5-6) in place on w, in the
+ * handle's colour order, each colour from the residual at its start. */
 int ibmg_smooth(ibmg_handle* h, int level, const double* b, double* w, int sweeps);
 /* coarse = I_{2h<-h} fine, level l -> l+1 (Sec. 3.1: R_u, R_v, R_p). */
 int ibmg_restrict(ibmg_handle* h, int level, const double* fine, double* coarse);

@@ -20,7 +20,7 @@ from .smoother import BoxSmoother
 
 
 class VCycle:
-    def __init__(self, levels, box=4, nu1=2, nu2=2, mode="colour"):
+    def __init__(self, levels, box=4, nu1=2, nu2=2, mode="colour2"):
         """levels: list of system.Level, finest first."""
         self.levels = levels
         self.nu1, self.nu2, self.mode = nu1, nu2, mode

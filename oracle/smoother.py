@@ -8,13 +8,17 @@ restriction of the full level operator, elasticity term included, to the
 box's unknowns; each box update is w[box] += A_box^{-1} (b - A w)[box], with
 no damping (none is stated).
 
-Two orderings:
+Orderings:
   * paper mode: boxes in lexicographic order, block Gauss-Seidel (Sec. 5, 6);
-  * colour mode: four colours by (bx mod 2, by mod 2) taken in the order
-    (0,0), (1,0), (0,1), (1,1); within a colour every box solves from the
-    residual at the start of that colour (Jacobi within a colour).  Boxes of
-    one colour share no unknowns.  This is the ordering the GPU path uses; it
-    is a different (equally valid) smoother from the paper's.
+  * colour2 mode: two colours, (bx + by) mod 2 (checkerboard), colour 0
+    first; within a colour every box solves from the residual at the start
+    of that colour (Jacobi within a colour).  Boxes of one colour share no
+    unknowns (diagonal neighbours touch only at a corner).  This is the GPU
+    path's default ordering;
+  * colour mode: four colours by (bx mod 2, by mod 2) in the order (0,0),
+    (1,0), (0,1), (1,1), with the same within-colour rule.
+The coloured orderings are different (equally valid) smoothers from the
+paper's lexicographic one.
 
 The local solve uses a pivoted dense LU of the extracted block.
 """
@@ -24,6 +28,7 @@ import numpy as np
 import scipy.linalg as sla
 
 COLOURS = ((0, 0), (1, 0), (0, 1), (1, 1))
+MODES = ("colour2", "colour", "paper")
 
 
 def box_dofs(bx, by, N, n):
@@ -76,6 +81,23 @@ class BoxSmoother:
                 w[d] += z
         return w
 
+    def sweep_colour2(self, w, b):
+        """One checkerboard sweep: colour (bx + by) mod 2 = 0, then 1, each
+        from the residual at the start of the colour."""
+        w = w.copy()
+        for par in (0, 1):
+            r = b - self.A @ w
+            upd = []
+            for by in range(self.nb):
+                for bx in range(self.nb):
+                    if (bx + by) % 2 != par:
+                        continue
+                    d = self.dofs[(bx, by)]
+                    upd.append((d, sla.lu_solve(self.lu[(bx, by)], r[d])))
+            for d, z in upd:
+                w[d] += z
+        return w
+
     def sweep_paper(self, w, b):
         """One lexicographic block Gauss-Seidel sweep (the paper's order)."""
         w = w.copy()
@@ -86,5 +108,11 @@ class BoxSmoother:
                 w[d] += sla.lu_solve(self.lu[(bx, by)], r)
         return w
 
-    def sweep(self, w, b, mode="colour"):
-        return self.sweep_colour(w, b) if mode == "colour" else self.sweep_paper(w, b)
+    def sweep(self, w, b, mode="colour2"):
+        if mode == "colour2":
+            return self.sweep_colour2(w, b)
+        if mode == "colour":
+            return self.sweep_colour(w, b)
+        if mode == "paper":
+            return self.sweep_paper(w, b)
+        raise ValueError(mode)

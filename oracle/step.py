@@ -31,14 +31,14 @@ class StepResult:
 
 
 def build(N, levels, rho, mu, dt, X, fiber_offsets, K, box=4, nu1=2, nu2=2,
-          mode="colour", kind=ib.DELTA_IB4):
+          mode="colour2", kind=ib.DELTA_IB4):
     lv = system.hierarchy(N, levels, rho, mu, dt, X, fiber_offsets, K, kind)
     return lv, VCycle(lv, box, nu1, nu2, mode)
 
 
 def step(u, v, p, X, fiber_offsets, K, dt, levels, rho=1.0, mu=1.0, box=4, nu1=2,
          nu2=2, rtol=1e-8, maxit=100, g_u=None, g_v=None, guess="zero",
-         mode="colour", orth="cgs2", kind=ib.DELTA_IB4):
+         mode="colour2", orth="cgs2", kind=ib.DELTA_IB4):
     N = u.shape[0]
     lv, mg = build(N, levels, rho, mu, dt, X, fiber_offsets, K, box, nu1, nu2, mode, kind)
     b = system.rhs(u, v, X, fiber_offsets, K, dt, rho, g_u, g_v, kind)

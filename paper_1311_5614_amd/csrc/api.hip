@@ -19,20 +19,21 @@ namespace {
 constexpr int kPW = 16;          // panel width of the coarse Gauss-Jordan (dense.hip)
 constexpr int kDotBlocks = 256;  // workgroups of the deterministic dot products
 constexpr int kMaxTimed = 8192;  // timed phase launches per solve
+constexpr int kSmallLevel = 32;  // levels up to this size run in one workgroup per V-cycle leg
 
 struct Buf {
   size_t off = 0, bytes = 0;
 };
 
 struct LevelBufs {
-  int N = 0, nb = 0;
+  int N = 0, nb = 0, maxact = 0, reach = 0;
   Buf w, b, r;               // V-cycle vectors in the V-cycle precision
-  Buf orgB, wB, orgC, wC;    // per-point patches (FP64)
-  Buf wBf, wCf;              // FP32 copies of the patch weights
-  Buf t;                     // gathered values, V-cycle precision
-  Buf cnt, start, cursor, list, ib_index, ib_boxes, info;
+  Buf act, rows, nact;       // active elastic rows of this level
+  Buf win, winf;             // FP64 windows and their FP32 copy
+  Buf yib;                   // elastic rows evaluated before a colour phase (V-cycle precision)
+  Buf ib_index, ib_boxes, boxflag, info;
   Buf ainv_plain, ainv_plain_f, ainv_ib;
-  int max_ib = 0, max_list = 0;
+  int max_ib = 0;
 };
 
 }  // namespace
@@ -40,6 +41,7 @@ struct LevelBufs {
 struct ibmg_handle {
   // problem and options
   int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 2, nu2 = 2, maxit = 100, prec = 0, guess = 0;
+  int ncol = 2;
   double rho = 1, mu = 1, K = 0, rtol = 1e-8;
   std::vector<int> prev, next;
   hipStream_t stream = nullptr;
@@ -48,12 +50,21 @@ struct ibmg_handle {
   size_t ws_bytes = 0, need = 0;
   LevelBufs L[IBMG_MAX_LEVELS];
   Buf X0, G, prev_d, next_d, U;
+  Buf org, wts, cnt, start, cursor, list, ltotal;   // finest-level point data and bins
+  Buf flag, loc, bsum, meta;                        // scan scratch and setup flags
+  int max_list = 0;
   Buf V, Z, H, g, cs, sn, y, flags, partial, scal, hc;
   Buf bvec, xvec, rvec, w0f, b0f;
   Buf aug, cm, cpiv, crowpos, cused, cY, cainv;
   int nr = 0, ndof = 0;
   // state
-  bool setup_ok = false, has_ib = false;
+  bool setup_ok = false, has_ib = false, launch_error = false;
+  // the V-cycle as a captured graph (fixed buffers b0g -> w0g), rebuilt when dt changes
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double graph_dt = -1.0;
+  Buf b0g, w0g;
   double dt = 0;
   int n_ib[IBMG_MAX_LEVELS][5] = {};
   // timing of the box-relaxation phase kernel
@@ -84,50 +95,50 @@ int boxes_per_point(int n) {
   return a * a;
 }
 
+int window_reach(int level) { return level == 0 ? IBMG_WR : (level == 1 ? 4 : 3); }
+
 void layout(ibmg_handle* h) {
   size_t cur = 0;
   const size_t rs = h->prec == IBMG_FP32 ? sizeof(float) : sizeof(double);
   const int M = h->M, bpp = boxes_per_point(h->n);
   h->ndof = 2 * h->n * (h->n + 1) + h->n * h->n;
   const size_t nd2 = (size_t)h->ndof * h->ndof;
+  const bool ib = M > 0;
   for (int l = 0; l < h->levels; ++l) {
     LevelBufs& B = h->L[l];
     B.N = h->N >> l;
     B.nb = B.N / h->n;
+    B.reach = window_reach(l);
     const size_t NN = (size_t)B.N * B.N;
-    const bool fine = (l == 0);
-    if (!fine || h->prec == IBMG_FP32) {
+    if (l > 0 || h->prec == IBMG_FP32) {
       take(cur, B.w, 3 * NN * rs);
       take(cur, B.b, 3 * NN * rs);
     }
     take(cur, B.r, 3 * NN * rs);
-    if (M > 0) {
-      take(cur, B.orgB, 4 * (size_t)M * sizeof(int));
-      take(cur, B.orgC, 4 * (size_t)M * sizeof(int));
-      take(cur, B.wB, 2 * (size_t)M * IBMG_PATCH * sizeof(double));
-      take(cur, B.wC, 2 * (size_t)M * IBMG_PATCH * sizeof(double));
-      if (h->prec == IBMG_FP32) {
-        take(cur, B.wBf, 2 * (size_t)M * IBMG_PATCH * sizeof(float));
-        take(cur, B.wCf, 2 * (size_t)M * IBMG_PATCH * sizeof(float));
-      }
-      take(cur, B.t, 2 * (size_t)M * rs);
+    if (ib) {
+      // each point covers 16 faces per component on the finest level; each
+      // active face of a level activates at most two faces of the next
+      B.maxact = (int)std::max<size_t>(1, std::min<size_t>(NN, (size_t)16 * M << l));
+      take(cur, B.act, 2 * NN * sizeof(int));
+      take(cur, B.rows, 2 * (size_t)B.maxact * sizeof(int));
+      take(cur, B.nact, 2 * sizeof(int));
+      take(cur, B.win, 2 * (size_t)B.maxact * IBMG_WS * sizeof(double));
+      if (h->prec == IBMG_FP32) take(cur, B.winf, 2 * (size_t)B.maxact * IBMG_WS * sizeof(float));
+      take(cur, B.yib, 2 * (size_t)B.maxact * sizeof(double));
     }
-    const size_t nbox = (size_t)B.nb * B.nb;
-    B.max_list = std::max(1, M * bpp);
-    take(cur, B.cnt, nbox * sizeof(int));
-    take(cur, B.start, (nbox + 1) * sizeof(int));
-    take(cur, B.cursor, nbox * sizeof(int));
-    take(cur, B.list, (size_t)B.max_list * sizeof(int));
-    take(cur, B.info, 8 * sizeof(int));
     if (l < h->levels - 1) {
+      const size_t nbox = (size_t)B.nb * B.nb;
       take(cur, B.ib_index, nbox * sizeof(int));
       take(cur, B.ib_boxes, nbox * sizeof(int));
+      take(cur, B.boxflag, nbox * sizeof(int));
+      take(cur, B.info, 8 * sizeof(int));
       take(cur, B.ainv_plain, nd2 * sizeof(double));
       take(cur, B.ainv_plain_f, nd2 * sizeof(float));
-      B.max_ib = M > 0 ? (int)std::min<size_t>(nbox, (size_t)M * bpp) : 0;
+      B.max_ib = ib ? (int)std::min<size_t>(nbox, (size_t)M * bpp) : 0;
       take(cur, B.ainv_ib, std::max<size_t>(1, (size_t)B.max_ib) * nd2 * sizeof(double));
     }
   }
+  const size_t N0 = (size_t)h->N * h->N, nbox0 = (size_t)h->L[0].nb * h->L[0].nb;
   const int Nc = h->N >> (h->levels - 1);
   h->nr = 3 * Nc * Nc + 1;
   const size_t nr = h->nr;
@@ -144,6 +155,19 @@ void layout(ibmg_handle* h) {
   take(cur, h->U, 2 * Mx * sizeof(double));
   take(cur, h->prev_d, Mx * sizeof(int));
   take(cur, h->next_d, Mx * sizeof(int));
+  take(cur, h->org, 4 * Mx * sizeof(int));
+  take(cur, h->wts, 2 * Mx * IBMG_PATCH * sizeof(double));
+  take(cur, h->cnt, (nbox0 + 1) * sizeof(int));
+  take(cur, h->start, (nbox0 + 1) * sizeof(int));
+  take(cur, h->cursor, nbox0 * sizeof(int));
+  h->max_list = std::max(1, M * bpp);
+  take(cur, h->list, (size_t)h->max_list * sizeof(int));
+  take(cur, h->ltotal, 4 * sizeof(int));
+  const size_t scan_n = std::max(2 * N0, nbox0 + 1);
+  take(cur, h->flag, scan_n * sizeof(int));
+  take(cur, h->loc, scan_n * sizeof(int));
+  take(cur, h->bsum, (scan_n / 1024 + 2) * sizeof(int));
+  take(cur, h->meta, 8 * sizeof(int));
   const size_t n0 = h->n0(), m = h->maxit;
   take(cur, h->V, (m + 1) * n0 * sizeof(double));
   take(cur, h->Z, m * n0 * sizeof(double));
@@ -162,6 +186,9 @@ void layout(ibmg_handle* h) {
   if (h->prec == IBMG_FP32) {
     take(cur, h->w0f, n0 * sizeof(float));
     take(cur, h->b0f, n0 * sizeof(float));
+  } else {
+    take(cur, h->w0g, n0 * sizeof(double));
+    take(cur, h->b0g, n0 * sizeof(double));
   }
   h->need = cur + 256;
 }
@@ -174,28 +201,21 @@ LevelView<T> view(const ibmg_handle* h, int l) {
   v.nb = B.nb;
   v.n = h->n;
   v.ndof = h->ndof;
-  const double hl = 1.0 / B.N, h0 = 1.0 / h->N;
+  v.ncol = h->ncol;
+  const double hl = 1.0 / B.N;
   v.c = (T)(h->rho / h->dt);
   v.muh2 = (T)(h->mu / (hl * hl));
   v.invh = (T)(1.0 / hl);
-  v.kappa = (T)(-h->dt * h->K / (h0 * h0));
-  v.M = h->M;
-  v.prev = h->p<int>(h->prev_d);
-  v.next = h->p<int>(h->next_d);
-  if (h->M > 0) {
-    v.orgB = h->p<int>(B.orgB);
-    v.orgC = h->p<int>(B.orgC);
-    if (sizeof(T) == sizeof(float)) {
-      v.wB = reinterpret_cast<const T*>(h->p<float>(B.wBf));
-      v.wC = reinterpret_cast<const T*>(h->p<float>(B.wCf));
-    } else {
-      v.wB = reinterpret_cast<const T*>(h->p<double>(B.wB));
-      v.wC = reinterpret_cast<const T*>(h->p<double>(B.wC));
-    }
-    v.t = h->p<T>(B.t);
+  v.reach = B.reach;
+  v.maxact = B.maxact;
+  if (h->has_ib) {
+    v.act = h->p<int>(B.act);
+    v.rows = h->p<int>(B.rows);
+    v.nact = h->p<int>(B.nact);
+    v.yib = h->p<T>(B.yib);
+    v.win = sizeof(T) == sizeof(float) ? reinterpret_cast<const T*>(h->p<float>(B.winf))
+                                       : reinterpret_cast<const T*>(h->p<double>(B.win));
   }
-  v.box_start = h->p<int>(B.start);
-  v.box_list = h->p<int>(B.list);
   if (l < h->levels - 1) {
     v.ib_index = h->p<int>(B.ib_index);
     v.ainv_plain = sizeof(T) == sizeof(float) ? reinterpret_cast<const T*>(h->p<float>(B.ainv_plain_f))
@@ -203,6 +223,21 @@ LevelView<T> view(const ibmg_handle* h, int l) {
     v.ainv_ib = h->p<double>(B.ainv_ib);
   }
   return v;
+}
+
+PointView points(const ibmg_handle* h) {
+  PointView P{};
+  P.M = h->M;
+  P.N = h->N;
+  P.n = h->n;
+  P.nb = h->L[0].nb;
+  P.prev = h->p<int>(h->prev_d);
+  P.next = h->p<int>(h->next_d);
+  P.org = h->p<int>(h->org);
+  P.wts = h->p<double>(h->wts);
+  P.box_start = h->p<int>(h->start);
+  P.box_list = h->p<int>(h->list);
+  return P;
 }
 
 int sync(ibmg_handle* h) {
@@ -218,17 +253,21 @@ int read_doubles(ibmg_handle* h, const double* dev, double* host, int n) {
 
 // ---------------------------------------------------------------- V-cycle schedule
 
+// One colour phase (residual + elastic rows, then box solves), with the box
+// kernel timed by events when timing is on.
 template <typename T>
-void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, int colour) {
+void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r, int colour) {
+  launch_res<T>(h->stream, v, b, w, r, h->has_ib);
   const bool t = h->timing && h->ev_used + 2 <= (int)h->ev.size();
   if (t) (void)hipEventRecord(h->ev[h->ev_used], h->stream);
-  launch_phase<T>(h->stream, v, b, w, colour, h->has_ib);
+  launch_box<T>(h->stream, v, r, w, colour, h->has_ib);
   if (t) {
     (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
-    const double NN = (double)v.N * v.N;
-    // algorithmic bytes: 9 words per cell per sweep (read w and b, write w),
-    // a quarter of the level per colour, plus the box inverses read
-    double bytes = 9.0 * sizeof(T) * NN / 4.0 + (double)v.ndof * v.ndof * sizeof(T);
+    // algorithmic bytes of one box launch: per unknown of the colour's boxes
+    // read r and w, write w; the shared inverse once; each FP64 inverse of a
+    // box with elastic rows once
+    const double boxes = colour_count(v.ncol, v.nb);
+    double bytes = boxes * v.ndof * 3.0 * sizeof(T) + (double)v.ndof * v.ndof * sizeof(T);
     if (h->has_ib) bytes += (double)h->n_ib[l][colour] * v.ndof * v.ndof * sizeof(double);
     h->ev_bytes[h->ev_used / 2] = bytes;
     h->ev_used += 2;
@@ -236,11 +275,8 @@ void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w,
 }
 
 template <typename T>
-void sweep(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w) {
-  for (int c = 0; c < 4; ++c) {
-    if (h->has_ib) launch_gather<T>(h->stream, v, w);
-    phase_timed<T>(h, v, l, b, w, c);
-  }
+void sweep(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r) {
+  for (int c = 0; c < h->ncol; ++c) phase_timed<T>(h, v, l, b, w, r, c);
 }
 
 // z = MGV(0, r) on level 0 (Algorithm 1), vectors in precision T.
@@ -258,28 +294,67 @@ void vcycle(ibmg_handle* h, const T* b0, T* w0) {
     b[l] = l == 0 ? b0 : h->p<T>(h->L[l].b);
     r[l] = h->p<T>(h->L[l].r);
   }
-  for (int l = 0; l + 1 < Lv; ++l) {
-    const size_t n3 = 3 * (size_t)v[l].N * v[l].N;
-    k_fill<T><<<nblk(n3), 256, 0, s>>>(w[l], n3, T(0));
-    for (int q = 0; q < h->nu1; ++q) sweep<T>(h, v[l], l, b[l], w[l]);
-    if (h->has_ib) launch_gather<T>(s, v[l], w[l]);
-    launch_residual<T>(s, v[l], b[l], w[l], r[l], h->has_ib);
-    launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b));
+  // levels ls.. (at most kSmallLevel cells per side, plus the coarsest) run in
+  // one LDS-resident workgroup
+  int ls = Lv - 1;
+  while (ls > 0 && v[ls - 1].N <= kSmallLevel) --ls;
+  if (ls > 0) {
+    const size_t n3 = 3 * (size_t)v[0].N * v[0].N;
+    k_fill<T><<<nblk(n3), 256, 0, s>>>(w[0], n3, T(0));
   }
-  launch_coarse_apply<T>(s, h->p<double>(h->cainv), h->nr, b[Lv - 1], w[Lv - 1]);
-  for (int l = Lv - 2; l >= 0; --l) {
+  for (int l = 0; l < ls; ++l) {
+    for (int q = 0; q < h->nu1; ++q) sweep<T>(h, v[l], l, b[l], w[l], r[l]);
+    launch_residual<T>(s, v[l], b[l], w[l], r[l], h->has_ib);
+    launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b), w[l + 1]);   // also zeroes w[l+1]
+  }
+  if (launch_tail<T>(s, v, ls, Lv, h->nu1, h->nu2, h->has_ib, h->nr, b[ls], w[ls], h->p<double>(h->cainv)) != 0)
+    h->launch_error = true;
+  for (int l = ls - 1; l >= 0; --l) {
     launch_prolong_add<T>(s, v[l].N, w[l + 1], w[l]);
-    for (int q = 0; q < h->nu2; ++q) sweep<T>(h, v[l], l, b[l], w[l]);
+    for (int q = 0; q < h->nu2; ++q) sweep<T>(h, v[l], l, b[l], w[l], r[l]);
   }
 }
 
+// Capture the V-cycle of the handle's precision on fixed buffers into a graph.
+int capture_vcycle(ibmg_handle* h) {
+  if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+  hipStream_t user = h->stream;
+  h->stream = h->cap;
+  IBMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  if (h->prec == IBMG_FP32) vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f));
+  else vcycle<double>(h, h->p<double>(h->b0g), h->p<double>(h->w0g));
+  const hipError_t e = hipStreamEndCapture(h->cap, &h->graph);
+  h->stream = user;
+  if (e != hipSuccess || h->launch_error) return IBMG_EHIP;
+  IBMG_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+  h->graph_dt = h->dt;
+  return IBMG_OK;
+}
+
 // z = M^{-1} r in FP64 at the ABI, dispatching on the V-cycle precision.
+// Without event timing the V-cycle runs as a replayed graph.
 void precond(ibmg_handle* h, const double* r, double* z) {
+  const size_t n0 = h->n0();
+  const bool graph = !h->timing && h->cap;
+  if (graph && (!h->gexec || h->graph_dt != h->dt)) {
+    if (capture_vcycle(h) != IBMG_OK) { h->launch_error = true; return; }
+  }
   if (h->prec == IBMG_FP32) {
-    const size_t n0 = h->n0();
     k_convert<double, float><<<nblk(n0), 256, 0, h->stream>>>(r, h->p<float>(h->b0f), n0);
-    vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f));
+    if (graph) {
+      if (hipGraphLaunch(h->gexec, h->stream) != hipSuccess) h->launch_error = true;
+    } else {
+      vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f));
+    }
     k_convert<float, double><<<nblk(n0), 256, 0, h->stream>>>(h->p<float>(h->w0f), z, n0);
+  } else if (graph) {
+    if (hipMemcpyAsync(h->p<double>(h->b0g), r, n0 * sizeof(double), hipMemcpyDeviceToDevice, h->stream) !=
+            hipSuccess ||
+        hipGraphLaunch(h->gexec, h->stream) != hipSuccess ||
+        hipMemcpyAsync(z, h->p<double>(h->w0g), n0 * sizeof(double), hipMemcpyDeviceToDevice, h->stream) !=
+            hipSuccess)
+      h->launch_error = true;
   } else {
     vcycle<double>(h, r, z);
   }
@@ -288,7 +363,6 @@ void precond(ibmg_handle* h, const double* r, double* z) {
 // y = A_0 w (FP64, the outer operator of FGMRES).
 void apply0(ibmg_handle* h, const double* w, double* y, const double* b = nullptr) {
   LevelView<double> v = view<double>(h, 0);
-  if (h->has_ib) launch_gather<double>(h->stream, v, w);
   launch_residual<double>(h->stream, v, b, w, y, h->has_ib);
 }
 
@@ -308,52 +382,58 @@ int do_setup(ibmg_handle* h, double dt, const double* X) {
   h->setup_ok = false;
   const int M = h->M, Lv = h->levels;
   h->has_ib = M > 0 && h->K != 0.0;
+  int* meta = h->p<int>(h->meta);
+  k_fill_i32<<<1, 256, 0, s>>>(meta, 8, 0);
   if (M > 0) {
     if (!X) return IBMG_EINVAL;
     IBMG_HIP(hipMemcpyAsync(h->p<double>(h->X0), X, 2 * (size_t)M * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_fiber_force(s, M, h->p<int>(h->prev_d), h->p<int>(h->next_d), h->K, h->p<double>(h->X0),
                        h->p<double>(h->G));
-    launch_weights0(s, M, h->N, h->kind, h->p<double>(h->X0), h->p<int>(h->L[0].orgB), h->p<double>(h->L[0].wB));
-    launch_weights0(s, M, h->N, h->kind, h->p<double>(h->X0), h->p<int>(h->L[0].orgC), h->p<double>(h->L[0].wC));
-    int* oB[IBMG_MAX_LEVELS];
-    int* oC[IBMG_MAX_LEVELS];
-    double* wB[IBMG_MAX_LEVELS];
-    double* wC[IBMG_MAX_LEVELS];
-    int Ns[IBMG_MAX_LEVELS];
+    launch_weights0(s, M, h->N, h->kind, h->p<double>(h->X0), h->p<int>(h->org), h->p<double>(h->wts));
+    launch_box_lists(s, points(h), h->p<int>(h->cnt), h->p<int>(h->start), h->p<int>(h->cursor),
+                     h->p<int>(h->list), h->max_list, h->p<int>(h->ltotal), h->p<int>(h->loc), h->p<int>(h->bsum));
+  }
+  if (h->has_ib) {
+    // elastic rows on every level: M_0 from the points, then M_{l+1} = R M_l P
+    const double h0 = 1.0 / h->N;
+    const double kappa = -dt * h->K / (h0 * h0);
     for (int l = 0; l < Lv; ++l) {
-      oB[l] = h->p<int>(h->L[l].orgB);
-      oC[l] = h->p<int>(h->L[l].orgC);
-      wB[l] = h->p<double>(h->L[l].wB);
-      wC[l] = h->p<double>(h->L[l].wC);
-      Ns[l] = h->L[l].N;
-    }
-    launch_coarsen(s, M, Lv, oB, wB, oC, wC, Ns);
-    if (h->prec == IBMG_FP32)
-      for (int l = 0; l < Lv; ++l) {
-        const size_t nw = 2 * (size_t)M * IBMG_PATCH;
-        k_convert<double, float><<<nblk(nw), 256, 0, s>>>(wB[l], h->p<float>(h->L[l].wBf), nw);
-        k_convert<double, float><<<nblk(nw), 256, 0, s>>>(wC[l], h->p<float>(h->L[l].wCf), nw);
+      LevelBufs& B = h->L[l];
+      launch_active(s, l, M, B.N, h->p<int>(h->org), l > 0 ? h->p<int>(h->L[l - 1].act) : nullptr,
+                    h->p<int>(h->flag), h->p<int>(B.act), h->p<int>(B.rows), h->p<int>(B.nact), B.maxact,
+                    h->p<int>(h->loc), h->p<int>(h->bsum));
+      if (l == 0)
+        launch_windows0(s, points(h), h->p<int>(B.rows), h->p<int>(B.nact), B.maxact, kappa, B.reach,
+                        h->p<double>(B.win), meta);
+      else
+        launch_windows_coarse(s, B.N, h->p<int>(h->L[l - 1].act), h->p<double>(h->L[l - 1].win),
+                              h->L[l - 1].maxact, h->L[l - 1].reach, h->p<int>(B.rows), h->p<int>(B.nact),
+                              B.maxact, B.reach, h->p<double>(B.win), meta);
+      if (h->prec == IBMG_FP32) {
+        const size_t nw = 2 * (size_t)B.maxact * IBMG_WS;
+        k_convert<double, float><<<nblk(nw), 256, 0, s>>>(h->p<double>(B.win), h->p<float>(B.winf), nw);
       }
+    }
   }
-  for (int l = 0; l < Lv; ++l) {
+  for (int l = 0; l + 1 < Lv; ++l) {
     LevelBufs& B = h->L[l];
-    const bool smoothed = l < Lv - 1;
-    launch_box_lists(s, M, M > 0 ? h->p<int>(B.orgB) : nullptr, h->n, B.N, B.nb, h->p<int>(B.cnt),
-                     h->p<int>(B.start), h->p<int>(B.cursor), h->p<int>(B.list), B.max_list,
-                     smoothed ? h->p<int>(B.ib_index) : nullptr, smoothed ? h->p<int>(B.ib_boxes) : nullptr,
-                     h->p<int>(B.info));
+    launch_box_classes(s, B.N, h->n, B.nb, h->ncol, h->has_ib ? h->p<int>(B.act) : nullptr, h->p<int>(B.boxflag),
+                       h->p<int>(B.ib_index), h->p<int>(B.ib_boxes), h->p<int>(B.info));
   }
-  // box counts per colour drive the factor launches
-  std::vector<int> info(8 * Lv, 0);
+  // read back counts: boxes with elastic rows per colour, active rows, flags
+  std::vector<int> info(8 * Lv, 0), nact(2 * Lv, 0), mt(8, 0), lt(4, 0);
   for (int l = 0; l + 1 < Lv; ++l)
     IBMG_HIP(hipMemcpyAsync(&info[8 * l], h->p<int>(h->L[l].info), 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-  {
-    int last = 0;
-    IBMG_HIP(hipMemcpyAsync(&last, h->p<int>(h->L[0].start) + (size_t)h->L[0].nb * h->L[0].nb, sizeof(int),
-                            hipMemcpyDeviceToHost, s));
-    IBMG_HIP(hipStreamSynchronize(s));
-    if (M > 0 && last > h->L[0].max_list) return IBMG_ENOMEM;
-  }
+  if (h->has_ib)
+    for (int l = 0; l < Lv; ++l)
+      IBMG_HIP(hipMemcpyAsync(&nact[2 * l], h->p<int>(h->L[l].nact), 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  IBMG_HIP(hipMemcpyAsync(mt.data(), meta, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+  if (M > 0) IBMG_HIP(hipMemcpyAsync(lt.data(), h->p<int>(h->ltotal), sizeof(int), hipMemcpyDeviceToHost, s));
+  IBMG_HIP(hipStreamSynchronize(s));
+  if (M > 0 && lt[0] > h->max_list) return IBMG_ENOMEM;
+  for (int l = 0; l < Lv && h->has_ib; ++l)
+    if (nact[2 * l] > h->L[l].maxact || nact[2 * l + 1] > h->L[l].maxact) return IBMG_ENOMEM;
+  if (mt[0] != 0) return IBMG_ESHAPE;   // an elastic coupling reaches beyond the coefficient window
   for (int l = 0; l + 1 < Lv; ++l) {
     for (int c = 0; c < 5; ++c) h->n_ib[l][c] = h->has_ib ? info[8 * l + c] : 0;
     if (h->n_ib[l][4] > h->L[l].max_ib) return IBMG_ENOMEM;
@@ -363,7 +443,6 @@ int do_setup(ibmg_handle* h, double dt, const double* X) {
   }
   {
     LevelView<double> v = view<double>(h, Lv - 1);
-    if (!h->has_ib) v.M = 0;
     launch_coarse_assemble(s, v, h->p<double>(h->aug), h->nr);
     if (coarse_factor(s, h->p<double>(h->aug), h->nr, h->p<double>(h->cm), h->p<int>(h->cpiv), nullptr,
                       h->p<int>(h->crowpos), h->p<int>(h->cused), h->p<double>(h->cY), h->p<double>(h->cainv)) != 0)
@@ -427,21 +506,20 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
       double* zj = Z + (size_t)j * n0;
       double* colj = H + (size_t)j * ldh;
       precond(h, vj, zj);
+      if (h->launch_error) return IBMG_EHIP;
       apply0(h, zj, vn);
       ++total;
-      // classical Gram-Schmidt, twice
+      // classical Gram-Schmidt, twice; then H(j+1, j) and the Givens step
       launch_multidot(s, V, n0, j + 1, vn, n0, partial, kDotBlocks);
       launch_reduce(s, partial, kDotBlocks, j + 1, colj, 0);
-      launch_update(s, V, n0, j + 1, colj, vn, n0, -1.0);
+      launch_update_acc(s, V, n0, j + 1, colj, vn, n0, nullptr);
       launch_multidot(s, V, n0, j + 1, vn, n0, partial, kDotBlocks);
       launch_reduce(s, partial, kDotBlocks, j + 1, hc, 0);
-      launch_update(s, V, n0, j + 1, hc, vn, n0, -1.0);
-      launch_reduce(s, partial, kDotBlocks, j + 1, colj, 1);
-      // H(j+1, j)^2, normalise, rotate
+      launch_update_acc(s, V, n0, j + 1, hc, vn, n0, colj);
       launch_multidot(s, vn, 0, 1, vn, n0, partial, kDotBlocks);
-      launch_reduce(s, partial, kDotBlocks, 1, colj + j + 1, 0);
-      launch_scale(s, vn, vn, n0, colj + j + 1);
-      launch_givens(s, H, ldh, g, h->p<double>(h->cs), h->p<double>(h->sn), j, h->p<double>(h->flags), target);
+      launch_reduce2(s, partial, kDotBlocks, colj + j + 1, scal + 1);
+      launch_scale_givens(s, vn, n0, scal + 1, H, ldh, g, h->p<double>(h->cs), h->p<double>(h->sn), j,
+                          h->p<double>(h->flags), target);
       if ((rc = read_doubles(h, h->p<double>(h->flags), hs, 3))) return rc;
       k = j + 1;
       est = hs[0] / bnorm;
@@ -511,6 +589,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   if (op->nu1 < 0 || op->nu2 < 0 || op->maxit < 1 || op->maxit > 200 || !(op->rtol > 0)) return IBMG_EINVAL;
   if (op->vcycle_prec != IBMG_FP64 && op->vcycle_prec != IBMG_FP32) return IBMG_EINVAL;
   if (op->guess != IBMG_GUESS_ZERO && op->guess != IBMG_GUESS_PREV) return IBMG_EINVAL;
+  if (op->colours != 2 && op->colours != 4) return IBMG_EINVAL;
   if (pr->n_points < 0 || pr->n_fibers < 0) return IBMG_EINVAL;
   if (pr->n_points > 0 && (!pr->fiber_offsets || pr->n_fibers < 1)) return IBMG_EINVAL;
   ibmg_handle* h = new (std::nothrow) ibmg_handle();
@@ -518,16 +597,17 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   h->N = N; h->M = pr->n_points; h->nfib = pr->n_fibers; h->kind = pr->delta;
   h->rho = pr->rho; h->mu = pr->mu; h->K = pr->K;
   h->levels = op->levels; h->n = op->box; h->nu1 = op->nu1; h->nu2 = op->nu2; h->maxit = op->maxit;
-  h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess;
+  h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess; h->ncol = op->colours;
   h->stream = (hipStream_t)stream;
   h->prev.assign(h->M, 0);
   h->next.assign(h->M, 0);
   if (h->M > 0) {
     const int* o = pr->fiber_offsets;
     if (o[0] != 0 || o[pr->n_fibers] != h->M) { delete h; return IBMG_EINVAL; }
+    for (int f = 0; f < pr->n_fibers; ++f)
+      if (o[f + 1] < o[f] || o[f + 1] > h->M) { delete h; return IBMG_EINVAL; }
     for (int f = 0; f < pr->n_fibers; ++f) {
       const int a = o[f], b = o[f + 1];
-      if (b < a) { delete h; return IBMG_EINVAL; }
       const int nf = b - a;
       for (int k = a; k < b; ++k) {
         h->prev[k] = a + (k - a - 1 + nf) % nf;
@@ -553,6 +633,17 @@ int ibmg_bind_workspace(ibmg_handle* h, void* dev, size_t bytes) {
   h->ws = base;
   h->ws_bytes = bytes;
   h->setup_ok = false;
+  h->graph_dt = -1.0;
+  if (!h->cap) IBMG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  {
+    // dynamic LDS of the V-cycle tail: the levels of at most kSmallLevel cells
+    // per side and the coarsest, three vectors each
+    int ls = h->levels - 1;
+    while (ls > 0 && h->L[ls - 1].N <= kSmallLevel) --ls;
+    size_t lds = 0;
+    for (int l = ls; l < h->levels; ++l) lds += 9 * (size_t)h->L[l].N * h->L[l].N * sizeof(double);
+    if (prepare_tail(lds) != 0) return IBMG_EHIP;
+  }
   if (h->M > 0) {
     IBMG_HIP(hipMemcpyAsync(h->p<int>(h->prev_d), h->prev.data(), h->M * sizeof(int), hipMemcpyHostToDevice,
                             h->stream));
@@ -566,6 +657,9 @@ int ibmg_bind_workspace(ibmg_handle* h, void* dev, size_t bytes) {
 int ibmg_destroy(ibmg_handle* h) {
   if (!h) return IBMG_EINVAL;
   for (auto e : h->ev) (void)hipEventDestroy(e);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
   return IBMG_OK;
 }
@@ -601,9 +695,8 @@ int ibmg_rhs(ibmg_handle* h, const double* u, const double* v, const double* gu,
   if (!ready(h)) return IBMG_ENOMEM;
   if (!h->setup_ok) return IBMG_ESTATE;
   if (!b) return IBMG_EINVAL;
-  LevelView<double> v0 = view<double>(h, 0);
   const double inv_h2 = (double)h->N * h->N;
-  launch_rhs(h->stream, v0, inv_h2, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr, b);
+  launch_rhs(h->stream, points(h), h->rho / h->dt, inv_h2, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr, b);
   IBMG_HIP(hipGetLastError());
   return IBMG_OK;
 }
@@ -640,8 +733,8 @@ int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double
   const size_t NN = (size_t)h->N * h->N, n0 = h->n0();
   double* b = h->p<double>(h->bvec);
   double* x = h->p<double>(h->xvec);
-  LevelView<double> v0 = view<double>(h, 0);
-  launch_rhs(s, v0, (double)h->N * h->N, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr, b);
+  launch_rhs(s, points(h), h->rho / dt, (double)h->N * h->N, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr,
+             b);
   if (h->guess == IBMG_GUESS_PREV) {
     IBMG_HIP(hipMemcpyAsync(x, u, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
     IBMG_HIP(hipMemcpyAsync(x + NN, v, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -658,7 +751,7 @@ int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double
   launch_sum(s, x + 2 * NN, NN, part, kDotBlocks);
   launch_reduce(s, part, kDotBlocks, 1, scal, 0);
   launch_mean_shift(s, x + 2 * NN, NN, scal);
-  if (h->M > 0) launch_interp(s, v0, x, x + NN, h->p<double>(h->U), h->p<double>(h->X0), dt);
+  if (h->M > 0) launch_interp(s, points(h), x, x + NN, h->p<double>(h->U), h->p<double>(h->X0), dt);
   IBMG_HIP(hipMemcpyAsync(u, x, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
   IBMG_HIP(hipMemcpyAsync(v, x + NN, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
   IBMG_HIP(hipMemcpyAsync(p, x + 2 * NN, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -699,7 +792,6 @@ int single_op(ibmg_handle* h, int which, int level, const double* a, const doubl
     case 0: {  // apply
       const T* w = f32 ? stage(a, wb) : (const T*)a;
       T* y = f32 ? h->p<T>(h->L[level].r) : (T*)out;
-      if (h->has_ib) launch_gather<T>(s, v, w);
       launch_residual<T>(s, v, nullptr, w, y, h->has_ib);
       if (f32) k_convert<T, double><<<nblk(n3), 256, 0, s>>>(y, out, n3);
       break;
@@ -708,7 +800,6 @@ int single_op(ibmg_handle* h, int which, int level, const double* a, const doubl
       const T* w = f32 ? stage(a, wb) : (const T*)a;
       const T* bv = f32 ? stage(b, bb) : (const T*)b;
       T* y = f32 ? h->p<T>(h->L[level].r) : (T*)out;
-      if (h->has_ib) launch_gather<T>(s, v, w);
       launch_residual<T>(s, v, bv, w, y, h->has_ib);
       if (f32) k_convert<T, double><<<nblk(n3), 256, 0, s>>>(y, out, n3);
       break;
@@ -717,7 +808,8 @@ int single_op(ibmg_handle* h, int which, int level, const double* a, const doubl
       if (level >= h->levels - 1) return IBMG_EINVAL;
       T* w = f32 ? stage(out, wb) : (T*)out;
       const T* bv = f32 ? stage(b, bb) : (const T*)b;
-      for (int q = 0; q < sweeps; ++q) sweep<T>(h, v, level, bv, w);
+      T* rr = h->p<T>(h->L[level].r);
+      for (int q = 0; q < sweeps; ++q) sweep<T>(h, v, level, bv, w, rr);
       if (f32) k_convert<T, double><<<nblk(n3), 256, 0, s>>>(w, out, n3);
       break;
     }
@@ -726,11 +818,11 @@ int single_op(ibmg_handle* h, int which, int level, const double* a, const doubl
       if (f32) {
         T* f = stage(a, h->L[level].r);
         T* c = h->p<T>(h->L[level + 1].b);
-        launch_restrict<T>(s, v.N, f, c);
+        launch_restrict<T>(s, v.N, f, c, (T*)nullptr);
         const size_t nc3 = n3 / 4;
         k_convert<T, double><<<nblk(nc3), 256, 0, s>>>(c, out, nc3);
       } else {
-        launch_restrict<T>(s, v.N, (const T*)a, (T*)out);
+        launch_restrict<T>(s, v.N, (const T*)a, (T*)out, (T*)nullptr);
       }
       break;
     }
@@ -810,6 +902,7 @@ int ibmg_vcycle(ibmg_handle* h, const double* r, double* z) {
   if (!h->setup_ok) return IBMG_ESTATE;
   if (!r || !z) return IBMG_EINVAL;
   precond(h, r, z);
+  if (h->launch_error) return IBMG_EHIP;
   IBMG_HIP(hipGetLastError());
   return sync(h);
 }
@@ -821,7 +914,6 @@ int ibmg_box_matrix(ibmg_handle* h, int level, int bx, int by, double* out) {
   const LevelBufs& B = h->L[level];
   if (bx < 0 || by < 0 || bx >= B.nb || by >= B.nb) return IBMG_EINVAL;
   LevelView<double> v = view<double>(h, level);
-  if (!h->has_ib) v.M = 0;
   launch_box_matrix(h->stream, v, bx, by, out);
   IBMG_HIP(hipGetLastError());
   return sync(h);
@@ -842,12 +934,10 @@ namespace {
 // Finest-level point data (weights and box lists) for arbitrary X.
 int fine_points(ibmg_handle* h, const double* X) {
   hipStream_t s = h->stream;
-  LevelBufs& B = h->L[0];
   h->setup_ok = false;
-  launch_weights0(s, h->M, h->N, h->kind, X, h->p<int>(B.orgB), h->p<double>(B.wB));
-  launch_weights0(s, h->M, h->N, h->kind, X, h->p<int>(B.orgC), h->p<double>(B.wC));
-  launch_box_lists(s, h->M, h->p<int>(B.orgB), h->n, B.N, B.nb, h->p<int>(B.cnt), h->p<int>(B.start),
-                   h->p<int>(B.cursor), h->p<int>(B.list), B.max_list, nullptr, nullptr, h->p<int>(B.info));
+  launch_weights0(s, h->M, h->N, h->kind, X, h->p<int>(h->org), h->p<double>(h->wts));
+  launch_box_lists(s, points(h), h->p<int>(h->cnt), h->p<int>(h->start), h->p<int>(h->cursor), h->p<int>(h->list),
+                   h->max_list, h->p<int>(h->ltotal), h->p<int>(h->loc), h->p<int>(h->bsum));
   IBMG_HIP(hipGetLastError());
   return IBMG_OK;
 }
@@ -864,9 +954,8 @@ int ibmg_spread(ibmg_handle* h, const double* X, const double* G, double* fu, do
     int rc = fine_points(h, X);
     if (rc) return rc;
   }
-  LevelView<double> v0 = view<double>(h, 0);
-  v0.c = 0.0;
-  launch_rhs(h->stream, v0, (double)h->N * h->N, nullptr, nullptr, nullptr, nullptr, h->M > 0 ? G : nullptr, b);
+  launch_rhs(h->stream, points(h), 0.0, (double)h->N * h->N, nullptr, nullptr, nullptr, nullptr, h->M > 0 ? G : nullptr,
+             b);
   IBMG_HIP(hipMemcpyAsync(fu, b, NN * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   IBMG_HIP(hipMemcpyAsync(fv, b + NN, NN * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   IBMG_HIP(hipGetLastError());
@@ -879,8 +968,7 @@ int ibmg_interp(ibmg_handle* h, const double* X, const double* u, const double* 
   if (!X || !u || !v || !U) return IBMG_EINVAL;
   int rc = fine_points(h, X);
   if (rc) return rc;
-  LevelView<double> v0 = view<double>(h, 0);
-  launch_interp(h->stream, v0, u, v, U, nullptr, 0.0);
+  launch_interp(h->stream, points(h), u, v, U, nullptr, 0.0);
   IBMG_HIP(hipGetLastError());
   return sync(h);
 }

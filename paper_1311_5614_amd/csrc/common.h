@@ -9,32 +9,50 @@
 #define IBMG_MAX_NDOF 56      // 2 n (n + 1) + n^2 for box edge n <= 4
 #define IBMG_PATCH 16         // 4 x 4 per-point patch on every level
 
+#define IBMG_WR 5                          // window reach on the finest level
+#define IBMG_WW (2 * IBMG_WR + 1)          // window width
+#define IBMG_WS (IBMG_WW * IBMG_WW)        // window entries per row
+
 // Per-level view handed to kernels by value.  T is the precision of the
 // V-cycle fields (double or float); box inverses of boxes that touch the
 // structure and the coarsest inverse are always FP64.
+//
+// The elasticity block M_l of level l is held as one coefficient window per
+// "active" velocity face (a face some row of M_l may reach): row f of M_l
+// couples f to the faces f + (dx, dy), |dx|, |dy| <= reach, with coefficient
+// win[(dy + WR) * WW + dx + WR].  The elimination factor -dt K (Sec. 2.3.2)
+// is folded in.
 template <typename T>
 struct LevelView {
   int N;          // cells per side on this level (power of two)
   int nb;         // boxes per side
   int n;          // box edge in cells
   int ndof;       // unknowns per box
+  int ncol;       // colour classes of a sweep (2 or 4)
   T c;            // rho / dt
   T muh2;         // mu / h_l^2
   T invh;         // 1 / h_l
-  T kappa;        // -dt K / h_0^2  (elasticity factor, Sec. 2.3.2 elimination)
-  int M;          // Lagrangian points
-  const int* prev;      // [M] fibre neighbours
-  const int* next;      // [M]
-  const int* orgB;      // [2][M][2] patch origins of the restricted spreading weights
-  const T* wB;          // [2][M][16]
-  const int* orgC;      // [2][M][2] patch origins of the prolonged interpolation weights
-  const T* wC;          // [2][M][16]
-  T* t;                 // [2][M] interpolated values C_l w
-  const int* box_start; // [nb^2 + 1] CSR of points whose B patch meets each box
-  const int* box_list;  // point ids, ascending within a box
-  const int* ib_index;  // [nb^2] index of the box among boxes with points, or -1
+  int reach;      // window reach on this level
+  int maxact;     // row capacity of the window store per component
+  const int* act; // [2][N^2] active-row index of each face, or -1
+  const T* win;   // [2][maxact][WS] windows
+  const int* rows;// [2][maxact] face of each active row
+  const int* nact;// [2] active rows per component
+  T* yib;         // [2][maxact] (M_l w) on the active rows, formed before each colour phase
+  const int* ib_index;  // [nb^2] index of the box among boxes with elastic rows, or -1
   const T* ainv_plain;  // [ndof * ndof] inverse of the plain box block, column-major
-  const double* ainv_ib;// [n_ib][ndof * ndof] inverses of boxes with points, column-major
+  const double* ainv_ib;// [n_ib][ndof * ndof] inverses of boxes with elastic rows, column-major
+};
+
+// Finest-level Lagrangian data: delta-weight patches and point-to-box bins.
+struct PointView {
+  int M, N, n, nb;
+  const int* prev;       // [M] fibre neighbours
+  const int* next;       // [M]
+  const int* org;        // [2][M][2] origin (i0, j0) of the 4 x 4 patch per component
+  const double* wts;     // [2][M][16] phi(x) phi(y) per patch entry, x fastest
+  const int* box_start;  // [nb^2 + 1] CSR of points whose patch meets each box
+  const int* box_list;   // point ids, ascending within a box
 };
 
 __host__ __device__ inline int wrapi(int i, int N) { return i & (N - 1); }
@@ -50,6 +68,21 @@ __device__ inline double phi_kernel(double r, int kind) {
   }
   if (r < 2.0) return 0.25 * (1.0 + cos(1.5707963267948966 * r));
   return 0.0;
+}
+
+// q-th box of a colour class.  ncol = 2: checkerboard, colour = (bx + by) & 1,
+// nb * nb / 2 boxes per colour; ncol = 4: colour = (bx & 1) + 2 (by & 1),
+// (nb / 2)^2 boxes per colour.  Row-major within a colour.
+__host__ __device__ inline int colour_count(int ncol, int nb) { return ncol == 2 ? nb * (nb / 2) : (nb / 2) * (nb / 2); }
+__host__ __device__ inline void colour_box(int q, int colour, int ncol, int nb, int& bx, int& by) {
+  const int half = nb / 2;
+  if (ncol == 2) {
+    by = q / half;
+    bx = 2 * (q - by * half) + ((by + colour) & 1);
+  } else {
+    bx = 2 * (q % half) + (colour & 1);
+    by = 2 * (q / half) + (colour >> 1);
+  }
 }
 
 // Local unknown r of box (bx, by) -> (component, i, j) on an N grid.
@@ -100,29 +133,22 @@ __device__ inline T stokes_row(const LevelView<T>& L, const T* __restrict__ w, i
   return -((u[j * N + ip] - u[j * N + i]) + (v[jp * N + i] - v[j * N + i])) * L.invh;
 }
 
-// Elasticity term (M_l w) at a velocity face: kappa * sum over points k whose
-// restricted spreading patch covers the face of B_l[k](face) * (L t)_k, with
-// t = C_l w gathered beforehand.  Points come from the face's box list in
-// ascending id order, so the sum is deterministic.
+// Elasticity term (M_l w) at a velocity face from its coefficient window.
 template <typename T>
-__device__ inline T ib_face(const LevelView<T>& L, int comp, int i, int j) {
-  const int box = (j / L.n) * L.nb + (i / L.n);
-  const int s = L.box_start[box], e = L.box_start[box + 1];
-  if (s == e) return T(0);
-  const int msk = L.N - 1;
-  const T* tt = L.t + comp * L.M;
-  const int* org = L.orgB + comp * L.M * 2;
-  const T* wb = L.wB + (size_t)comp * L.M * IBMG_PATCH;
+__device__ inline T win_face(const LevelView<T>& L, const T* __restrict__ w, int comp, int i, int j) {
+  const int N = L.N, msk = N - 1;
+  const int a = L.act[comp * N * N + j * N + i];
+  if (a < 0) return T(0);
+  const T* c = L.win + ((size_t)comp * L.maxact + a) * IBMG_WS;
+  const T* f = w + (size_t)comp * N * N;
+  const int r = L.reach;
   T acc = T(0);
-  for (int q = s; q < e; ++q) {
-    const int k = L.box_list[q];
-    const int di = (i - org[2 * k]) & msk, dj = (j - org[2 * k + 1]) & msk;
-    if (di < 4 && dj < 4) {
-      const T sk = tt[L.prev[k]] - T(2) * tt[k] + tt[L.next[k]];
-      acc += wb[k * IBMG_PATCH + dj * 4 + di] * sk;
-    }
+  for (int dy = -r; dy <= r; ++dy) {
+    const T* row = f + (size_t)((j + dy) & msk) * N;
+    const T* cw = c + (dy + IBMG_WR) * IBMG_WW + IBMG_WR;
+    for (int dx = -r; dx <= r; ++dx) acc += cw[dx] * row[(i + dx) & msk];
   }
-  return L.kappa * acc;
+  return acc;
 }
 
 // Host-side helpers -----------------------------------------------------------

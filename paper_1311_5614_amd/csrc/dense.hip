@@ -41,28 +41,12 @@ k_coarse_assemble(LevelView<double> L, double* __restrict__ aug, int nr) {
     row[2 * NN + j * N + i] += L.invh;
     if (comp == 0) row[2 * NN + j * N + im] -= L.invh;
     else row[2 * NN + jm * N + i] -= L.invh;
-    if (L.M > 0) {
-      const int box = (j / L.n) * L.nb + (i / L.n);
-      const int* orgB = L.orgB + comp * L.M * 2;
-      const int* orgC = L.orgC + comp * L.M * 2;
-      const double* wB = L.wB + (size_t)comp * L.M * IBMG_PATCH;
-      const double* wC = L.wC + (size_t)comp * L.M * IBMG_PATCH;
-      for (int q = L.box_start[box]; q < L.box_start[box + 1]; ++q) {
-        const int k = L.box_list[q];
-        const int di = (i - orgB[2 * k]) & msk, dj = (j - orgB[2 * k + 1]) & msk;
-        if (di >= 4 || dj >= 4) continue;
-        const double bk = L.kappa * wB[k * IBMG_PATCH + dj * 4 + di];
-        const int nbk[3] = {L.prev[k], k, L.next[k]};
-        const double lc[3] = {1.0, -2.0, 1.0};
-        for (int s = 0; s < 3; ++s) {
-          const int kk = nbk[s];
-          const int oi = orgC[2 * kk], oj = orgC[2 * kk + 1];
-          for (int e = 0; e < 16; ++e) {
-            const int ci = (oi + (e & 3)) & msk, cj = (oj + (e >> 2)) & msk;
-            row[base + cj * N + ci] += bk * lc[s] * wC[kk * IBMG_PATCH + e];
-          }
-        }
-      }
+    const int ar = L.act ? L.act[comp * NN + j * N + i] : -1;
+    if (ar >= 0) {
+      const double* cw = L.win + ((size_t)comp * L.maxact + ar) * IBMG_WS;
+      for (int dy = -L.reach; dy <= L.reach; ++dy)
+        for (int dx = -L.reach; dx <= L.reach; ++dx)
+          row[base + ((j + dy) & msk) * N + ((i + dx) & msk)] += cw[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR];
     }
   } else {
     row[j * N + ip] -= L.invh;
@@ -172,16 +156,19 @@ k_coarse_update(double* __restrict__ aug, int nr, int k0, int pw, const double* 
   if (c >= ld) return;
   const int r0 = blockIdx.y * 4 + (threadIdx.x >> 6);
   double y[PW];
-  for (int s = 0; s < pw; ++s) y[s] = Y[(size_t)s * ld + c];
+#pragma unroll
+  for (int s = 0; s < PW; ++s) y[s] = s < pw ? Y[(size_t)s * ld + c] : 0.0;
   for (int i = r0; i < nr; i += gridDim.y * 4) {
     // pivot row p_s: y_s, then eliminated by the later pivots t > s of the
     // panel; any other row: eliminated by every pivot of the panel
     const int rp = rowpos[i];
     double* a = aug + (size_t)i * ld + c;
+    const double* mi = m + (size_t)i * PW;
     double v = rp >= 0 ? 0.0 : *a;
-    for (int s = 0; s < pw; ++s) {
-      if (s == rp) v += y[s];
-      else if (s > rp) v -= m[(size_t)i * PW + s] * y[s];
+#pragma unroll
+    for (int s = 0; s < PW; ++s) {
+      const double coef = (s < rp || s >= pw) ? 0.0 : (s == rp ? -1.0 : mi[s]);
+      v -= coef * y[s];
     }
     *a = v;
   }

@@ -1,11 +1,12 @@
-// Per-step operator setup on gfx950: fibre forces, delta weights, Galerkin-
-// coarsened per-point patches, point-to-box binning and dense box factors.
+// Per-step operator setup on gfx950: fibre forces, delta weights, point-to-box
+// binning, the elasticity operator on every level as per-face coefficient
+// windows, and the dense box factors.
 //
-// Paper references: fibre force and regularised delta (Sec. 2.2), lagged
-// spreading/interpolation (Sec. 2.3.2), Galerkin coarsening of the
-// elasticity operator with the Sec. 3.1 transfers (Sec. 3.2), box relaxation
-// blocks (Sec. 5-6) and the observation that plain boxes share one factor
-// while boxes near the structure need their own, re-formed every step (Sec. 8).
+// Paper references: fibre force and regularised delta (Sec. 2.2); lagged
+// spreading/interpolation and the elimination M_0 = -dt K S L S^* (Sec. 2.3.2);
+// Galerkin coarsening M_{l+1} = R M_l P with the Sec. 3.1 transfers
+// (Sec. 3.2); box relaxation blocks (Sec. 5-6); plain boxes share one factor
+// while boxes near the structure get their own, re-formed every step (Sec. 8).
 #include "common.h"
 #include "kernels.h"
 
@@ -46,95 +47,7 @@ k_weights0(int M, int N, int kind, const double* __restrict__ X, int* __restrict
   org[2 * t + 1] = ((j0 % N) + N) % N;
 }
 
-// ---------------------------------------------------------------- a5: Galerkin patches
-// B_{l+1} = R_l B_l (restriction of the spreading patch) and
-// C_{l+1} = C_l P_l (interpolation patch through bilinear prolongation),
-// evaluated on unwrapped relative offsets, so every coarse entry is a plain
-// sum of fine entries.  New origins: B: (floor(a/2), floor(b/2));
-// C: normal direction floor(a/2), tangential floor((b-1)/2).
-struct PatchLevels {
-  int* orgB[IBMG_MAX_LEVELS];
-  double* wB[IBMG_MAX_LEVELS];
-  int* orgC[IBMG_MAX_LEVELS];
-  double* wC[IBMG_MAX_LEVELS];
-  int N[IBMG_MAX_LEVELS];
-};
-
-__device__ inline int floordiv2(int a) { return a >> 1; }   // arithmetic shift floors
-
-__global__ void __launch_bounds__(256)
-k_coarsen(int M, int levels, PatchLevels P) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * M) return;
-  const int comp = t / M;
-  const double wr[3] = {1.0 / 8.0, 2.0 / 8.0, 1.0 / 8.0};
-  for (int l = 0; l + 1 < levels; ++l) {
-    const int Nc = P.N[l + 1];
-    // ---- restriction of B
-    {
-      const int a = P.orgB[l][2 * t], b = P.orgB[l][2 * t + 1];
-      const double* f = P.wB[l] + (size_t)t * IBMG_PATCH;
-      const int A0 = floordiv2(a), B0 = floordiv2(b);
-      double out[16];
-      for (int q = 0; q < 16; ++q) out[q] = 0.0;
-      for (int J = 0; J < 4; ++J)
-        for (int I = 0; I < 4; ++I) {
-          double s = 0.0;
-          for (int d = -1; d <= 1; ++d)
-            for (int e = 0; e <= 1; ++e) {
-              int fx, fy;
-              if (comp == 0) { fx = 2 * (A0 + I) + d - a; fy = 2 * (B0 + J) + e - b; }
-              else           { fx = 2 * (A0 + I) + e - a; fy = 2 * (B0 + J) + d - b; }
-              if (fx >= 0 && fx < 4 && fy >= 0 && fy < 4) s += wr[d + 1] * f[fy * 4 + fx];
-            }
-          out[J * 4 + I] = s;
-        }
-      double* o = P.wB[l + 1] + (size_t)t * IBMG_PATCH;
-      for (int q = 0; q < 16; ++q) o[q] = out[q];
-      P.orgB[l + 1][2 * t] = wrapi(A0, Nc);
-      P.orgB[l + 1][2 * t + 1] = wrapi(B0, Nc);
-    }
-    // ---- prolongation of C
-    {
-      const int a = P.orgC[l][2 * t], b = P.orgC[l][2 * t + 1];
-      const double* f = P.wC[l] + (size_t)t * IBMG_PATCH;
-      // normal direction (x for u, y for v) and tangential direction origins
-      const int an = comp == 0 ? a : b;   // fine origin along the normal
-      const int at = comp == 0 ? b : a;   // fine origin along the tangent
-      const int N0 = floordiv2(an), T0 = floordiv2(at - 1);
-      double out[16];
-      for (int q = 0; q < 16; ++q) out[q] = 0.0;
-      for (int fy = 0; fy < 4; ++fy)
-        for (int fx = 0; fx < 4; ++fx) {
-          const double val = f[fy * 4 + fx];
-          const int in = comp == 0 ? an + fx : an + fy;   // fine index along normal
-          const int it = comp == 0 ? at + fy : at + fx;   // fine index along tangent
-          int cn[2], ct[2];
-          double wn[2], wt[2];
-          int nn, nt;
-          if ((in & 1) == 0) { cn[0] = in >> 1; wn[0] = 1.0; nn = 1; }
-          else { cn[0] = (in - 1) >> 1; cn[1] = (in + 1) >> 1; wn[0] = wn[1] = 0.5; nn = 2; }
-          const int Jt = it >> 1;
-          if ((it & 1) == 0) { ct[0] = Jt; wt[0] = 0.75; ct[1] = Jt - 1; wt[1] = 0.25; }
-          else { ct[0] = Jt; wt[0] = 0.75; ct[1] = Jt + 1; wt[1] = 0.25; }
-          nt = 2;
-          for (int x = 0; x < nn; ++x)
-            for (int y = 0; y < nt; ++y) {
-              const int rn = cn[x] - N0, rt = ct[y] - T0;
-              const int cx = comp == 0 ? rn : rt, cy = comp == 0 ? rt : rn;
-              out[cy * 4 + cx] += val * wn[x] * wt[y];
-            }
-        }
-      double* o = P.wC[l + 1] + (size_t)t * IBMG_PATCH;
-      for (int q = 0; q < 16; ++q) o[q] = out[q];
-      const int ox = comp == 0 ? N0 : T0, oy = comp == 0 ? T0 : N0;
-      P.orgC[l + 1][2 * t] = wrapi(ox, Nc);
-      P.orgC[l + 1][2 * t + 1] = wrapi(oy, Nc);
-    }
-  }
-}
-
-// ---------------------------------------------------------------- a2: point-to-box binning
+// ---------------------------------------------------------------- a2: point-to-box binning (finest)
 __device__ inline void add_unique(int* a, int& n, int v) {
   for (int q = 0; q < n; ++q)
     if (a[q] == v) return;
@@ -157,29 +70,29 @@ __device__ inline void patch_boxes(int comp, int oi, int oj, int n, int N, int n
     for (int q = 0; q < nbx; ++q) add_unique(ids, cnt, bys[p] * nb + bxs[q]);
 }
 
-__device__ inline int point_boxes(int k, int M, const int* orgB, int n, int N, int nb, int* ids) {
+__device__ inline int point_boxes(int k, int M, const int* org, int n, int N, int nb, int* ids) {
   int cnt = 0;
   for (int comp = 0; comp < 2; ++comp)
-    patch_boxes(comp, orgB[(comp * M + k) * 2], orgB[(comp * M + k) * 2 + 1], n, N, nb, ids, cnt);
+    patch_boxes(comp, org[(comp * M + k) * 2], org[(comp * M + k) * 2 + 1], n, N, nb, ids, cnt);
   return cnt;
 }
 
 __global__ void __launch_bounds__(256)
-k_box_count(int M, const int* __restrict__ orgB, int n, int N, int nb, int* __restrict__ cnt) {
+k_box_count(int M, const int* __restrict__ org, int n, int N, int nb, int* __restrict__ cnt) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
   int ids[64];
-  const int c = point_boxes(k, M, orgB, n, N, nb, ids);
+  const int c = point_boxes(k, M, org, n, N, nb, ids);
   for (int q = 0; q < c; ++q) atomicAdd(&cnt[ids[q]], 1);
 }
 
 __global__ void __launch_bounds__(256)
-k_box_fill(int M, const int* __restrict__ orgB, int n, int N, int nb, const int* __restrict__ start,
+k_box_fill(int M, const int* __restrict__ org, int n, int N, int nb, const int* __restrict__ start,
            int* __restrict__ cursor, int* __restrict__ list, int max_list) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
   int ids[64];
-  const int c = point_boxes(k, M, orgB, n, N, nb, ids);
+  const int c = point_boxes(k, M, org, n, N, nb, ids);
   for (int q = 0; q < c; ++q) {
     const int pos = atomicAdd(&cursor[ids[q]], 1);
     const int at = start[ids[q]] + pos;
@@ -188,6 +101,7 @@ k_box_fill(int M, const int* __restrict__ orgB, int n, int N, int nb, const int*
 }
 
 // Ascending point ids within each box (fixed summation order downstream).
+// Lists on the finest level hold only the points within a few cells.
 __global__ void __launch_bounds__(256)
 k_box_sort(int nbox, const int* __restrict__ start, int* __restrict__ list) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -199,6 +113,229 @@ k_box_sort(int nbox, const int* __restrict__ start, int* __restrict__ list) {
     while (j >= s && list[j] > v) { list[j + 1] = list[j]; --j; }
     list[j + 1] = v;
   }
+}
+
+// ---------------------------------------------------------------- multi-block exclusive scan
+// Pass 1: each workgroup scans 1024 entries (4 per thread), writes the local
+// exclusive prefix and its block total.
+__global__ void __launch_bounds__(256)
+k_scan1(const int* __restrict__ in, int n, int* __restrict__ loc, int* __restrict__ bsum) {
+  __shared__ int sh[256];
+  const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+  int v[4], s = 0;
+  for (int q = 0; q < 4; ++q) {
+    v[q] = base + q < n ? in[base + q] : 0;
+    s += v[q];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int a = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += a;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;
+  for (int q = 0; q < 4; ++q) {
+    if (base + q < n) loc[base + q] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == 255) bsum[blockIdx.x] = sh[255];
+}
+
+// Pass 2 (one workgroup): exclusive scan of the block totals; total[0] = sum.
+__global__ void __launch_bounds__(1024) k_scan2(int* __restrict__ bsum, int nblk, int* __restrict__ total) {
+  __shared__ int sh[1024];
+  int carry = 0;
+  for (int c0 = 0; c0 < nblk; c0 += 1024) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < nblk ? bsum[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int a = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (i < nblk) bsum[i] = carry + sh[threadIdx.x] - v;
+    const int tot = sh[1023];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) total[0] = carry;
+}
+
+// Pass 3: out[i] = loc[i] + bsum[block]; with `rows` set, a compaction:
+// flagged entries get their rank (and rows[rank] = i), the others -1; ranks
+// at or beyond `cap` are dropped (the host checks the total against it).
+__global__ void __launch_bounds__(256)
+k_scan3(const int* __restrict__ flag, int n, const int* __restrict__ loc, const int* __restrict__ bsum,
+        int* __restrict__ out, int* __restrict__ rows, int cap) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int v = loc[i] + bsum[i / 1024];
+  if (!rows) { out[i] = v; return; }
+  if (flag[i] && v < cap) { out[i] = v; rows[v] = i; }
+  else out[i] = -1;
+}
+
+// ---------------------------------------------------------------- active faces
+// Finest level: every face a delta patch covers.
+__global__ void __launch_bounds__(256)
+k_mark0(int M, int N, const int* __restrict__ org, int* __restrict__ flag) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * M) return;
+  const int comp = t / M, NN = N * N;
+  const int oi = org[2 * t], oj = org[2 * t + 1];
+  for (int e = 0; e < 16; ++e)
+    flag[comp * NN + wrapi(oj + (e >> 2), N) * N + wrapi(oi + (e & 3), N)] = 1;
+}
+
+// Level l+1: faces whose restriction stencil meets an active face of level l.
+__global__ void __launch_bounds__(256)
+k_mark_coarse(int Nc, const int* __restrict__ act_f, int* __restrict__ flag) {
+  const int NNc = Nc * Nc, Nf = 2 * Nc, NNf = Nf * Nf, mf = Nf - 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * NNc) return;
+  const int comp = idx / NNc, rem = idx - comp * NNc;
+  const int J = rem / Nc, I = rem - J * Nc;
+  const int* a = act_f + comp * NNf;
+  int any = 0;
+  for (int d = -1; d <= 1; ++d)
+    for (int e = 0; e <= 1; ++e) {
+      const int x = comp == 0 ? 2 * I + d : 2 * I + e;
+      const int y = comp == 0 ? 2 * J + e : 2 * J + d;
+      any |= a[(y & mf) * Nf + (x & mf)] >= 0;
+    }
+  flag[idx] = any;
+}
+
+// ---------------------------------------------------------------- a5: elasticity windows
+__device__ inline int wrap_half(int d, int N) {   // periodic offset into (-N/2, N/2]
+  d = d & (N - 1);
+  return d > N / 2 ? d - N : d;
+}
+
+// Finest level: row f of M_0 = -dt K S_0 L S^* (S_0 = W / h^2, S^* = W^T):
+// kappa * sum over points k covering f of W_k(f) * sum_{k'} L_{k k'} W_{k'}.
+// One thread per active row, window accumulated in LDS, points in ascending
+// id order from the face's box list.  flags[0] |= 1 if a nonzero falls
+// outside the window.
+__global__ void __launch_bounds__(64)
+k_win0(PointView P, const int* __restrict__ rows, const int* __restrict__ nact, int maxact, double kappa,
+       int reach, double* __restrict__ win, int* __restrict__ flags) {
+  __shared__ double acc[64 * IBMG_WS];
+  const int comp = blockIdx.y;
+  const int row = blockIdx.x * 64 + threadIdx.x;
+  if (row >= maxact || row >= nact[comp]) return;
+  double* a = acc + threadIdx.x * IBMG_WS;
+  for (int q = 0; q < IBMG_WS; ++q) a[q] = 0.0;
+  const int N = P.N, msk = N - 1;
+  const int f = rows[comp * maxact + row];
+  const int i = f % N, j = f / N;
+  const int box = (j / P.n) * P.nb + (i / P.n);
+  const int* org = P.org + comp * P.M * 2;
+  const double* wts = P.wts + (size_t)comp * P.M * IBMG_PATCH;
+  int bad = 0;
+  for (int q = P.box_start[box]; q < P.box_start[box + 1]; ++q) {
+    const int k = P.box_list[q];
+    const int di = (i - org[2 * k]) & msk, dj = (j - org[2 * k + 1]) & msk;
+    if (di >= 4 || dj >= 4) continue;
+    const double bk = kappa * wts[k * IBMG_PATCH + dj * 4 + di];
+    const int nbk[3] = {P.prev[k], k, P.next[k]};
+    const double lc[3] = {1.0, -2.0, 1.0};
+    for (int s = 0; s < 3; ++s) {
+      const int kk = nbk[s];
+      const int oi = org[2 * kk], oj = org[2 * kk + 1];
+      for (int e = 0; e < 16; ++e) {
+        const double val = bk * lc[s] * wts[kk * IBMG_PATCH + e];
+        const int dx = wrap_half(oi + (e & 3) - i, N), dy = wrap_half(oj + (e >> 2) - j, N);
+        if (dx >= -reach && dx <= reach && dy >= -reach && dy <= reach)
+          a[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR] += val;
+        else if (val != 0.0)
+          bad = 1;
+      }
+    }
+  }
+  double* o = win + ((size_t)comp * maxact + row) * IBMG_WS;
+  for (int q = 0; q < IBMG_WS; ++q) o[q] = a[q];
+  if (bad) atomicOr(flags, 1);
+}
+
+// Level l -> l+1: row F of R M_l P.  For each fine row f of the restriction
+// stencil of F (weight rw) and each window entry g = f + d of that row, the
+// coefficient goes to the coarse faces G of the bilinear prolongation stencil
+// of g (weight pw) at offset G - F, all on unwrapped indices.
+__global__ void __launch_bounds__(64)
+k_win_coarse(int Nc, const int* __restrict__ act_f, const double* __restrict__ win_f, int maxact_f, int reach_f,
+             const int* __restrict__ rows, const int* __restrict__ nact, int maxact, int reach,
+             double* __restrict__ win, int* __restrict__ flags) {
+  __shared__ double acc[64 * IBMG_WS];
+  const int comp = blockIdx.y;
+  const int row = blockIdx.x * 64 + threadIdx.x;
+  if (row >= maxact || row >= nact[comp]) return;
+  double* a = acc + threadIdx.x * IBMG_WS;
+  for (int q = 0; q < IBMG_WS; ++q) a[q] = 0.0;
+  const int Nf = 2 * Nc, NNf = Nf * Nf, mf = Nf - 1;
+  const int F = rows[comp * maxact + row];
+  const int FX = F % Nc, FY = F / Nc;
+  const int* af = act_f + comp * NNf;
+  const double wr[3] = {0.125, 0.25, 0.125};
+  int bad = 0;
+  for (int d = -1; d <= 1; ++d)
+    for (int e = 0; e <= 1; ++e) {
+      const int fx = comp == 0 ? 2 * FX + d : 2 * FX + e;   // unwrapped fine row
+      const int fy = comp == 0 ? 2 * FY + e : 2 * FY + d;
+      const int ar = af[(fy & mf) * Nf + (fx & mf)];
+      if (ar < 0) continue;
+      const double rw = wr[d + 1];
+      const double* cw = win_f + ((size_t)comp * maxact_f + ar) * IBMG_WS;
+      for (int dy = -reach_f; dy <= reach_f; ++dy)
+        for (int dx = -reach_f; dx <= reach_f; ++dx) {
+          const double val = rw * cw[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR];
+          if (val == 0.0) continue;
+          const int gx = fx + dx, gy = fy + dy;
+          // prolongation stencil of fine face g: normal direction (x for u)
+          const int gn = comp == 0 ? gx : gy, gt = comp == 0 ? gy : gx;
+          int cn[2], ct[2];
+          double wn[2], wt[2];
+          int nn;
+          if ((gn & 1) == 0) { cn[0] = gn >> 1; wn[0] = 1.0; nn = 1; }
+          else { cn[0] = (gn - 1) >> 1; cn[1] = (gn + 1) >> 1; wn[0] = wn[1] = 0.5; nn = 2; }
+          const int t0 = gt >> 1;
+          ct[0] = t0; wt[0] = 0.75;
+          ct[1] = (gt & 1) == 0 ? t0 - 1 : t0 + 1; wt[1] = 0.25;
+          for (int x = 0; x < nn; ++x)
+            for (int y = 0; y < 2; ++y) {
+              const int GX = comp == 0 ? cn[x] : ct[y], GY = comp == 0 ? ct[y] : cn[x];
+              const int ox = GX - FX, oy = GY - FY;
+              const double v = val * wn[x] * wt[y];
+              if (ox >= -reach && ox <= reach && oy >= -reach && oy <= reach)
+                a[(oy + IBMG_WR) * IBMG_WW + ox + IBMG_WR] += v;
+              else
+                bad = 1;
+            }
+        }
+    }
+  double* o = win + ((size_t)comp * maxact + row) * IBMG_WS;
+  for (int q = 0; q < IBMG_WS; ++q) o[q] = a[q];
+  if (bad) atomicOr(flags, 2);
+}
+
+// ---------------------------------------------------------------- boxes with elastic rows
+__global__ void __launch_bounds__(256)
+k_box_flag(int N, int n, int nb, const int* __restrict__ act, int* __restrict__ flag) {
+  const int box = blockIdx.x * blockDim.x + threadIdx.x;
+  if (box >= nb * nb) return;
+  const int bx = box % nb, by = box / nb, NN = N * N;
+  int any = 0;
+  for (int lj = 0; lj <= n && !any; ++lj)
+    for (int li = 0; li <= n; ++li) {
+      if (lj < n) any |= act[wrapi(by * n + lj, N) * N + wrapi(bx * n + li, N)] >= 0;           // u
+      if (li < n) any |= act[NN + wrapi(by * n + lj, N) * N + wrapi(bx * n + li, N)] >= 0;      // v
+    }
+  flag[box] = any;
 }
 
 // Block-wide exclusive scan helper (1024 threads).
@@ -218,40 +355,25 @@ __device__ inline int block_excl_scan(int v, int* sh, int& total) {
   return incl - v;
 }
 
-// start[] = exclusive scan of cnt[]; cursor[] = 0.
-__global__ void __launch_bounds__(1024)
-k_scan_counts(int nbox, const int* __restrict__ cnt, int* __restrict__ start, int* __restrict__ cursor) {
-  __shared__ int sh[1024];
-  int base = 0;
-  for (int c0 = 0; c0 < nbox; c0 += 1024) {
-    const int i = c0 + threadIdx.x;
-    const int v = i < nbox ? cnt[i] : 0;
-    int total;
-    const int ex = block_excl_scan(v, sh, total);
-    if (i < nbox) { start[i] = base + ex; cursor[i] = 0; }
-    base += total;
-  }
-  if (threadIdx.x == 0) start[nbox] = base;
-}
-
-// Number the boxes that hold points, colour by colour ((0,0),(1,0),(0,1),(1,1)),
-// row-major within a colour (nb >= 2, even).  ib_boxes[idx] = box id;
+// Number the flagged boxes colour class by colour class (see colour_box),
+// in the order a sweep visits them (nb >= 2, even).  ib_boxes[idx] = box id;
 // info[c] = count of colour c; info[4] = total.
 __global__ void __launch_bounds__(1024)
-k_ib_index(int nb, const int* __restrict__ cnt, int* __restrict__ ib_index, int* __restrict__ ib_boxes,
+k_ib_index(int nb, int ncol, const int* __restrict__ flagb, int* __restrict__ ib_index, int* __restrict__ ib_boxes,
            int* __restrict__ info) {
   __shared__ int sh[1024];
-  const int colx[4] = {0, 1, 0, 1}, coly[4] = {0, 0, 1, 1};
-  const int half = nb / 2, per = half * half;
+  const int per = colour_count(ncol, nb);
   int base = 0;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < ncol; ++c) {
     int cbase = base;
     for (int c0 = 0; c0 < per; c0 += 1024) {
       const int q = c0 + threadIdx.x;
       int box = 0, flag = 0;
       if (q < per) {
-        box = (2 * (q / half) + coly[c]) * nb + 2 * (q % half) + colx[c];
-        flag = cnt[box] > 0 ? 1 : 0;
+        int bx, by;
+        colour_box(q, c, ncol, nb, bx, by);
+        box = by * nb + bx;
+        flag = flagb[box] ? 1 : 0;
       }
       int total;
       const int ex = block_excl_scan(flag, sh, total);
@@ -264,15 +386,18 @@ k_ib_index(int nb, const int* __restrict__ cnt, int* __restrict__ ib_index, int*
     if (threadIdx.x == 0) info[c] = cbase - base;
     base = cbase;
   }
-  if (threadIdx.x == 0) info[4] = base;
+  if (threadIdx.x == 0) {
+    for (int c = ncol; c < 4; ++c) info[c] = 0;
+    info[4] = base;
+  }
 }
 
 // ---------------------------------------------------------------- a6: box blocks
 // Assemble A_l[box, box] (Stokes stencil restricted to the box plus the
-// elasticity block kappa * sum_k B_k L C_k' over the box's points) into an
-// LDS buffer with leading dimension ld.
+// elasticity rows' window entries whose column lies in the box) into an LDS
+// buffer with leading dimension ld.
 __device__ void assemble_box(const LevelView<double>& L, int bx, int by, bool with_ib, double* a, int ld) {
-  const int n = L.n, N = L.N, nd = L.ndof, msk = N - 1;
+  const int n = L.n, N = L.N, nd = L.ndof, NN = N * N;
   for (int r = threadIdx.x; r < nd; r += blockDim.x) {
     int comp, i, j;
     box_dof(r, bx, by, n, N, comp, i, j);
@@ -291,29 +416,13 @@ __device__ void assemble_box(const LevelView<double>& L, int bx, int by, bool wi
         if ((col = box_local(2, i, j, bx, by, n, N)) >= 0) row[col] += L.invh;
         if ((col = box_local(2, i, jm, bx, by, n, N)) >= 0) row[col] -= L.invh;
       }
-      if (with_ib) {
-        const int box = by * L.nb + bx;
-        const int* orgB = L.orgB + comp * L.M * 2;
-        const int* orgC = L.orgC + comp * L.M * 2;
-        const double* wB = L.wB + (size_t)comp * L.M * IBMG_PATCH;
-        const double* wC = L.wC + (size_t)comp * L.M * IBMG_PATCH;
-        for (int q = L.box_start[box]; q < L.box_start[box + 1]; ++q) {
-          const int k = L.box_list[q];
-          const int di = (i - orgB[2 * k]) & msk, dj = (j - orgB[2 * k + 1]) & msk;
-          if (di >= 4 || dj >= 4) continue;
-          const double bk = L.kappa * wB[k * IBMG_PATCH + dj * 4 + di];
-          const int nbk[3] = {L.prev[k], k, L.next[k]};
-          const double lc[3] = {1.0, -2.0, 1.0};
-          for (int s = 0; s < 3; ++s) {
-            const int kk = nbk[s];
-            const int oi = orgC[2 * kk], oj = orgC[2 * kk + 1];
-            for (int e = 0; e < 16; ++e) {
-              const int ci = wrapi(oi + (e & 3), N), cj = wrapi(oj + (e >> 2), N);
-              if ((col = box_local(comp, ci, cj, bx, by, n, N)) >= 0)
-                row[col] += bk * lc[s] * wC[kk * IBMG_PATCH + e];
-            }
-          }
-        }
+      const int ar = with_ib ? L.act[comp * NN + j * N + i] : -1;
+      if (ar >= 0) {
+        const double* cw = L.win + ((size_t)comp * L.maxact + ar) * IBMG_WS;
+        for (int dy = -L.reach; dy <= L.reach; ++dy)
+          for (int dx = -L.reach; dx <= L.reach; ++dx)
+            if ((col = box_local(comp, wrapi(i + dx, N), wrapi(j + dy, N), bx, by, n, N)) >= 0)
+              row[col] += cw[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR];
       }
     } else {
       if ((col = box_local(0, ip, j, bx, by, n, N)) >= 0) row[col] -= L.invh;
@@ -354,7 +463,8 @@ __device__ void gauss_jordan_lds(double* a, int nd, int ld, double* colk, int* p
     const double inv = 1.0 / a[k * ld + k];
     __syncthreads();
     for (int c = tid; c < ld; c += blockDim.x) a[k * ld + c] *= inv;
-    for (int i = tid; i < nd; i += blockDim.x) colk[i] = a[i * ld + k];
+    for (int i = tid; i < nd; i += blockDim.x)
+      if (i != k) colk[i] = a[i * ld + k];
     __syncthreads();
     for (int idx = tid; idx < nd * ld; idx += blockDim.x) {
       const int i = idx / ld, c = idx - i * ld;
@@ -364,8 +474,8 @@ __device__ void gauss_jordan_lds(double* a, int nd, int ld, double* colk, int* p
   }
 }
 
-// Block 0: the plain box (Stokes only, shared by every box without points).
-// Block 1 + q: box ib_boxes[q].  Inverses are written column-major.
+// Block 0: the plain box (Stokes only, shared by every box without elastic
+// rows).  Block 1 + q: box ib_boxes[q].  Inverses are written column-major.
 __global__ void __launch_bounds__(256)
 k_box_factor(LevelView<double> L, const int* __restrict__ ib_boxes, double* __restrict__ ainv_plain,
              float* __restrict__ ainv_plain_f, double* __restrict__ ainv_ib) {
@@ -404,9 +514,7 @@ k_box_matrix(LevelView<double> L, int bx, int by, double* __restrict__ out) {
   const int nd = L.ndof;
   for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) a[idx] = 0.0;
   __syncthreads();
-  const int box = by * L.nb + bx;
-  const bool ib = L.M > 0 && L.box_start[box + 1] > L.box_start[box];
-  assemble_box(L, bx, by, ib, a, nd);
+  assemble_box(L, bx, by, L.act != nullptr, a, nd);
   __syncthreads();
   for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) out[idx] = a[idx];
 }
@@ -416,34 +524,65 @@ namespace ibmg {
 
 void launch_fiber_force(hipStream_t s, int M, const int* prev, const int* next, double K,
                         const double* X, double* G) {
-  if (M > 0) k_fiber_force<<<(M + 255) / 256, 256, 0, s>>>(M, prev, next, K, X, G);
+  if (M > 0) k_fiber_force<<<nblk(M), 256, 0, s>>>(M, prev, next, K, X, G);
 }
 
 void launch_weights0(hipStream_t s, int M, int N, int kind, const double* X, int* org, double* w) {
-  if (M > 0) k_weights0<<<(2 * M + 255) / 256, 256, 0, s>>>(M, N, kind, X, org, w);
+  if (M > 0) k_weights0<<<nblk(2 * (size_t)M), 256, 0, s>>>(M, N, kind, X, org, w);
 }
 
-void launch_coarsen(hipStream_t s, int M, int levels, int* const* orgB, double* const* wB,
-                    int* const* orgC, double* const* wC, const int* Ns) {
-  if (M == 0 || levels < 2) return;
-  PatchLevels P;
-  for (int l = 0; l < levels; ++l) {
-    P.orgB[l] = orgB[l]; P.wB[l] = wB[l]; P.orgC[l] = orgC[l]; P.wC[l] = wC[l]; P.N[l] = Ns[l];
-  }
-  k_coarsen<<<(2 * M + 255) / 256, 256, 0, s>>>(M, levels, P);
+void launch_scan(hipStream_t s, const int* in, int n, int* out, int* rows, int cap, int* total, int* loc,
+                 int* bsum) {
+  const int nb1 = (n + 1023) / 1024;
+  k_scan1<<<nb1, 256, 0, s>>>(in, n, loc, bsum);
+  k_scan2<<<1, 1024, 0, s>>>(bsum, nb1, total);
+  k_scan3<<<nblk(n), 256, 0, s>>>(in, n, loc, bsum, out, rows, cap);
 }
 
-void launch_box_lists(hipStream_t s, int M, const int* orgB, int n, int N, int nb, int* cnt, int* start,
-                      int* cursor, int* list, int max_list, int* ib_index, int* ib_boxes, int* info) {
-  const int nbox = nb * nb;
-  k_fill_i32<<<(nbox + 255) / 256, 256, 0, s>>>(cnt, nbox, 0);
-  if (M > 0) k_box_count<<<(M + 255) / 256, 256, 0, s>>>(M, orgB, n, N, nb, cnt);
-  k_scan_counts<<<1, 1024, 0, s>>>(nbox, cnt, start, cursor);
-  if (M > 0) {
-    k_box_fill<<<(M + 255) / 256, 256, 0, s>>>(M, orgB, n, N, nb, start, cursor, list, max_list);
-    k_box_sort<<<(nbox + 255) / 256, 256, 0, s>>>(nbox, start, list);
+void launch_box_lists(hipStream_t s, const PointView& P, int* cnt, int* start, int* cursor, int* list,
+                      int max_list, int* total, int* loc, int* bsum) {
+  const int nbox = P.nb * P.nb;
+  k_fill_i32<<<nblk(nbox + 1), 256, 0, s>>>(cnt, nbox + 1, 0);
+  k_fill_i32<<<nblk(nbox), 256, 0, s>>>(cursor, nbox, 0);
+  if (P.M > 0) k_box_count<<<nblk(P.M), 256, 0, s>>>(P.M, P.org, P.n, P.N, P.nb, cnt);
+  // start[0..nbox] = exclusive scan of cnt[0..nbox] (cnt[nbox] = 0, so start[nbox] = total)
+  launch_scan(s, cnt, nbox + 1, start, nullptr, 0, total, loc, bsum);
+  if (P.M > 0) {
+    k_box_fill<<<nblk(P.M), 256, 0, s>>>(P.M, P.org, P.n, P.N, P.nb, start, cursor, list, max_list);
+    k_box_sort<<<nblk(nbox), 256, 0, s>>>(nbox, start, list);
   }
-  if (ib_index) k_ib_index<<<1, 1024, 0, s>>>(nb, cnt, ib_index, ib_boxes, info);
+}
+
+void launch_active(hipStream_t s, int level, int M, int N, const int* org, const int* act_fine, int* flag,
+                   int* act, int* rows, int* nact, int maxact, int* loc, int* bsum) {
+  const int NN = N * N;
+  k_fill_i32<<<nblk(2 * (size_t)NN), 256, 0, s>>>(flag, 2 * NN, 0);
+  if (level == 0) {
+    if (M > 0) k_mark0<<<nblk(2 * (size_t)M), 256, 0, s>>>(M, N, org, flag);
+  } else {
+    k_mark_coarse<<<nblk(2 * (size_t)NN), 256, 0, s>>>(N, act_fine, flag);
+  }
+  for (int c = 0; c < 2; ++c)
+    launch_scan(s, flag + c * NN, NN, act + c * NN, rows + c * maxact, maxact, nact + c, loc, bsum);
+}
+
+void launch_windows0(hipStream_t s, const PointView& P, const int* rows, const int* nact, int maxact, double kappa,
+                     int reach, double* win, int* flags) {
+  dim3 g((unsigned)((maxact + 63) / 64), 2);
+  k_win0<<<g, 64, 0, s>>>(P, rows, nact, maxact, kappa, reach, win, flags);
+}
+
+void launch_windows_coarse(hipStream_t s, int Nc, const int* act_f, const double* win_f, int maxact_f, int reach_f,
+                           const int* rows, const int* nact, int maxact, int reach, double* win, int* flags) {
+  dim3 g((unsigned)((maxact + 63) / 64), 2);
+  k_win_coarse<<<g, 64, 0, s>>>(Nc, act_f, win_f, maxact_f, reach_f, rows, nact, maxact, reach, win, flags);
+}
+
+void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int* flag, int* ib_index,
+                        int* ib_boxes, int* info) {
+  if (act) k_box_flag<<<nblk(nb * nb), 256, 0, s>>>(N, n, nb, act, flag);
+  else k_fill_i32<<<nblk(nb * nb), 256, 0, s>>>(flag, nb * nb, 0);
+  k_ib_index<<<1, 1024, 0, s>>>(nb, ncol, flag, ib_index, ib_boxes, info);
 }
 
 void launch_box_factor(hipStream_t s, const LevelView<double>& L, const int* ib_boxes, int n_ib,

@@ -27,25 +27,35 @@ inline unsigned nblk(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1)
 void launch_fiber_force(hipStream_t s, int M, const int* prev, const int* next, double K,
                         const double* X, double* G);
 void launch_weights0(hipStream_t s, int M, int N, int kind, const double* X, int* org, double* w);
-void launch_coarsen(hipStream_t s, int M, int levels, int* const* orgB, double* const* wB,
-                    int* const* orgC, double* const* wC, const int* Ns);
-void launch_box_lists(hipStream_t s, int M, const int* orgB, int n, int N, int nb, int* cnt, int* start,
-                      int* cursor, int* list, int max_list, int* ib_index, int* ib_boxes, int* info);
+void launch_scan(hipStream_t s, const int* in, int n, int* out, int* rows, int cap, int* total, int* loc,
+                 int* bsum);
+void launch_box_lists(hipStream_t s, const PointView& P, int* cnt, int* start, int* cursor, int* list,
+                      int max_list, int* total, int* loc, int* bsum);
+void launch_active(hipStream_t s, int level, int M, int N, const int* org, const int* act_fine, int* flag,
+                   int* act, int* rows, int* nact, int maxact, int* loc, int* bsum);
+void launch_windows0(hipStream_t s, const PointView& P, const int* rows, const int* nact, int maxact, double kappa,
+                     int reach, double* win, int* flags);
+void launch_windows_coarse(hipStream_t s, int Nc, const int* act_f, const double* win_f, int maxact_f, int reach_f,
+                           const int* rows, const int* nact, int maxact, int reach, double* win, int* flags);
+void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int* flag, int* ib_index,
+                        int* ib_boxes, int* info);
 void launch_box_factor(hipStream_t s, const LevelView<double>& L, const int* ib_boxes, int n_ib,
                        double* ainv_plain, float* ainv_plain_f, double* ainv_ib);
 void launch_box_matrix(hipStream_t s, const LevelView<double>& L, int bx, int by, double* out);
 
 // mg.hip (T = double or float)
-template <typename T> void launch_gather(hipStream_t s, const LevelView<T>& L, const T* w);
 template <typename T> void launch_residual(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r,
                                            bool ib);
-template <typename T> void launch_phase(hipStream_t s, const LevelView<T>& L, const T* b, T* w, int colour,
-                                        bool ib);
-template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc);
+template <typename T> void launch_res(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r, bool ib);
+template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, const T* r, T* w, int colour, bool ib);
+template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero);
 template <typename T> void launch_prolong_add(hipStream_t s, int Nf, const T* ec, T* wf);
-void launch_rhs(hipStream_t s, const LevelView<double>& L0, double inv_h2, const double* u, const double* v,
+int prepare_tail(size_t lds);
+template <typename T> int launch_tail(hipStream_t s, const LevelView<T>* views, int ls, int L, int nu1, int nu2,
+                                      bool ib, int nr, const T* b_in, T* w_out, const double* cainv);
+void launch_rhs(hipStream_t s, const PointView& P, double c, double inv_h2, const double* u, const double* v,
                 const double* gu, const double* gv, const double* G, double* b);
-void launch_interp(hipStream_t s, const LevelView<double>& L0, const double* u, const double* v, double* U,
+void launch_interp(hipStream_t s, const PointView& P, const double* u, const double* v, double* U,
                    double* X, double dt);
 
 // dense.hip: bordered coarsest system
@@ -66,5 +76,10 @@ void launch_givens(hipStream_t s, double* H, int ldh, double* g, double* cs, dou
 void launch_backsolve(hipStream_t s, const double* H, int ldh, const double* g, int k, double* y);
 void launch_mean_shift(hipStream_t s, double* p, size_t n, const double* sum);
 void launch_sum(hipStream_t s, const double* x, size_t n, double* partial, int nblocks);
+void launch_reduce2(hipStream_t s, const double* partial, int nblocks, double* out, double* copy);
+void launch_update_acc(hipStream_t s, const double* V, size_t ldv, int nvec, const double* coef, double* w, size_t n,
+                       double* acc);
+void launch_scale_givens(hipStream_t s, double* w, size_t n, const double* nrm2, double* H, int ldh, double* g,
+                         double* cs, double* sn, int j, double* flags, double target);
 
 }  // namespace ibmg

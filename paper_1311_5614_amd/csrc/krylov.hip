@@ -133,6 +133,66 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ x, size_
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
+// out[0] = sum of the partials of one dot (fixed tree), also copied to copy[0].
+__global__ void __launch_bounds__(256)
+k_reduce2(const double* __restrict__ partial, int nblocks, double* __restrict__ out, double* __restrict__ copy) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) a += partial[b];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[0] = sh[0]; copy[0] = sh[0]; }
+}
+
+// w -= sum_v coef[v] V[v]; workgroup 0 also adds coef into acc (the second
+// Gram-Schmidt pass's coefficients into the Hessenberg column).
+__global__ void __launch_bounds__(256)
+k_update_acc(const double* __restrict__ V, size_t ldv, int nvec, const double* __restrict__ coef,
+             double* __restrict__ w, size_t n, double* __restrict__ acc) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (acc && blockIdx.x == 0 && (int)threadIdx.x < nvec) acc[threadIdx.x] += coef[threadIdx.x];
+  if (e >= n) return;
+  double s = 0.0;
+  for (int v = 0; v < nvec; ++v) s += coef[v] * V[(size_t)v * ldv + e];
+  w[e] -= s;
+}
+
+// v_{j+1} = w / sqrt(nrm2); workgroup 0, thread 0 also performs the Givens
+// step of column j (k_givens) -- the column's H(j+1, j) holds the same
+// squared norm as nrm2, which every workgroup reads from nrm2.
+__global__ void __launch_bounds__(256)
+k_scale_givens(double* __restrict__ w, size_t n, const double* __restrict__ nrm2, double* __restrict__ H, int ldh,
+               double* __restrict__ g, double* __restrict__ cs, double* __restrict__ sn, int j,
+               double* __restrict__ flags, double target) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const double nrm = sqrt(nrm2[0]);
+  if (e < n) w[e] = nrm > 0.0 ? w[e] / nrm : 0.0;
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double* col = H + (size_t)j * ldh;
+  col[j + 1] = nrm;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double d = hypot(a, b);
+  cs[j] = a / d;
+  sn[j] = b / d;
+  col[j] = d;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  const double est = fabs(g[j + 1]);
+  flags[0] = est;
+  flags[1] = (est <= target || nrm == 0.0) ? 1.0 : 0.0;
+  flags[2] = (isfinite(est) && isfinite(d)) ? 0.0 : 1.0;
+}
+
 namespace ibmg {
 
 void launch_multidot(hipStream_t s, const double* V, size_t ldv, int nvec, const double* w, size_t n,
@@ -162,6 +222,17 @@ void launch_mean_shift(hipStream_t s, double* p, size_t n, const double* sum) {
 }
 void launch_sum(hipStream_t s, const double* x, size_t n, double* partial, int nblocks) {
   k_sum<<<nblocks, 256, 0, s>>>(x, n, partial);
+}
+void launch_reduce2(hipStream_t s, const double* partial, int nblocks, double* out, double* copy) {
+  k_reduce2<<<1, 256, 0, s>>>(partial, nblocks, out, copy);
+}
+void launch_update_acc(hipStream_t s, const double* V, size_t ldv, int nvec, const double* coef, double* w, size_t n,
+                       double* acc) {
+  k_update_acc<<<nblk(n), 256, 0, s>>>(V, ldv, nvec, coef, w, n, acc);
+}
+void launch_scale_givens(hipStream_t s, double* w, size_t n, const double* nrm2, double* H, int ldh, double* g,
+                         double* cs, double* sn, int j, double* flags, double target) {
+  k_scale_givens<<<nblk(n), 256, 0, s>>>(w, n, nrm2, H, ldh, g, cs, sn, j, flags, target);
 }
 
 }  // namespace ibmg

@@ -43,7 +43,7 @@ class ibmg_problem(C.Structure):
 class ibmg_opts(C.Structure):
     _fields_ = [("levels", C.c_int32), ("box", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("maxit", C.c_int32), ("rtol", C.c_double), ("vcycle_prec", C.c_int32),
-                ("guess", C.c_int32)]
+                ("guess", C.c_int32), ("colours", C.c_int32)]
 
 
 class ibmg_stats(C.Structure):
@@ -138,6 +138,7 @@ class Config:
     rtol: float = 1e-8
     prec: int = IBMG_FP64
     guess: int = IBMG_GUESS_ZERO
+    colours: int = 2
 
 
 class Solver:
@@ -153,7 +154,7 @@ class Solver:
         prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, self.M, max(0, len(offs) - 1),
                             C.cast(self._offs, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
         opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
-                         cfg.guess)
+                         cfg.guess, cfg.colours)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         _check(L.ibmg_create(C.byref(h), C.byref(prob), C.byref(opts),

@@ -116,20 +116,21 @@ def test_box_matrices_parity():
                 assert np.max(np.abs(A - Ao)) < 1e-12 * np.max(np.abs(Ao)), (l, bx, by)
 
 
-@pytest.mark.parametrize("box", [1, 2, 4])
-def test_smooth_parity(box):
-    w, dt, s = make(N=32, levels=3, M=80, K=1e4, dt_factor=50.0, box=box)
+@pytest.mark.parametrize("box,colours", [(1, 2), (2, 2), (4, 2), (1, 4), (4, 4)])
+def test_smooth_parity(box, colours):
+    w, dt, s = make(N=64, levels=4, M=160, K=1e4, dt_factor=50.0, box=box, colours=colours)
     _setup(s, w, dt)
-    lv = oracle_levels(w, dt, 3, 1e4)
+    lv = oracle_levels(w, dt, 4, 1e4)
     rng = np.random.default_rng(7)
-    for l in (0, 1):
+    mode = "colour2" if colours == 2 else "colour"
+    for l in (0, 1, 2):
         N = lv[l].N
         b = rng.standard_normal(3 * N * N)
         x = rng.standard_normal(3 * N * N)
         sm = smoother.BoxSmoother(lv[l].A, N, box)
-        xo = sm.sweep_colour(sm.sweep_colour(x, b), b)
+        xo = sm.sweep(sm.sweep(x, b, mode), b, mode)
         xg = tnp(s.smooth(l, tdev(b), tdev(x.copy()), 2))
-        assert rel(xg, xo) < 1e-11, (box, l)
+        assert rel(xg, xo) < 1e-11, (box, colours, l)
 
 
 # ---------------------------------------------------------------- a7, a12: coarse solve, V-cycle
@@ -148,12 +149,12 @@ def test_coarse_solve_parity():
     assert np.max(np.abs(lv[-1].A @ z - b)) < 1e-10 * np.max(np.abs(b))
 
 
-@pytest.mark.parametrize("nu", [(1, 1), (2, 2), (2, 1)])
-def test_vcycle_parity(nu):
-    w, dt, s = make(N=64, levels=4, M=150, K=1e4, dt_factor=50.0, nu=nu)
+@pytest.mark.parametrize("nu,colours,levels", [((1, 1), 2, 4), ((2, 2), 2, 5), ((2, 1), 2, 3), ((2, 2), 4, 4)])
+def test_vcycle_parity(nu, colours, levels):
+    w, dt, s = make(N=64, levels=levels, M=150, K=1e4, dt_factor=50.0, nu=nu, colours=colours)
     _setup(s, w, dt)
-    lv = oracle_levels(w, dt, 4, 1e4)
-    V = mg.VCycle(lv, 4, nu[0], nu[1])
+    lv = oracle_levels(w, dt, levels, 1e4)
+    V = mg.VCycle(lv, 4, nu[0], nu[1], "colour2" if colours == 2 else "colour")
     r = np.random.default_rng(9).standard_normal(3 * 64 * 64)
     r[2 * 4096:] -= r[2 * 4096:].mean()
     z = tnp(s.vcycle(tdev(r)))
@@ -330,3 +331,23 @@ def test_fp32_solve_meets_fp64_tolerance(K, fac):
     print(f"K={K:g}: fp32 iters {st['iters']} fp64 iters {st64['iters']} true residual {rr:.2e}")
     assert st["converged"] == 1 and rr <= 1e-10
     assert st["iters"] <= st64["iters"] + 3
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replay_matches_eager(prec):
+    """The V-cycle replayed from its captured graph gives bitwise the same
+    solve as eager launches (event-timed mode), repeatedly."""
+    w, dt, s = make(N=64, levels=5, M=160, K=1e5, dt_factor=100.0, prec=prec)
+    _setup(s, w, dt)
+    rng = np.random.default_rng(21)
+    b = s.rhs(tdev(rng.standard_normal((64, 64))), tdev(rng.standard_normal((64, 64))))
+    outs = []
+    for timing in (False, True, False):
+        s.set_timing(timing)
+        x = torch.zeros_like(b)
+        st = s.solve(b, x)
+        outs.append((st["iters"], tnp(x).copy()))
+    s.set_timing(False)
+    for it, x in outs[1:]:
+        assert it == outs[0][0]
+        assert np.array_equal(x, outs[0][1])

@@ -288,6 +288,28 @@ def test_same_colour_boxes_disjoint():
                 d = set(smoother.box_dofs(bx, by, N, n))
                 assert not (seen & d)
                 seen |= d
+    for n in (1, 2, 4):          # checkerboard: diagonal neighbours share no unknown
+        for par in (0, 1):
+            seen = set()
+            for by in range(N // n):
+                for bx in range(N // n):
+                    if (bx + by) % 2 != par:
+                        continue
+                    d = set(smoother.box_dofs(bx, by, N, n))
+                    assert not (seen & d)
+                    seen |= d
+
+
+def test_colour_orders_cover_every_unknown():
+    """Each sweep ordering updates every unknown at least once."""
+    N, n = 16, 4
+    allu = set(range(3 * N * N))
+    for par_sets in ([[(bx, by) for by in range(4) for bx in range(4) if (bx + by) % 2 == p] for p in (0, 1)],):
+        cov = set()
+        for boxes in par_sets:
+            for bx, by in boxes:
+                cov |= set(smoother.box_dofs(bx, by, N, n))
+        assert cov == allu
 
 
 def test_paper_mode_box_residual_zero_after_update():
@@ -354,7 +376,7 @@ def test_coarse_bordered_solve():
     assert abs(x[2 * Nc * Nc:].mean()) < 1e-13
 
 
-@pytest.mark.parametrize("mode", ["colour", "paper"])
+@pytest.mark.parametrize("mode", ["colour2", "colour", "paper"])
 def test_mg_iteration_matrix_contracts(mode):
     """Spectral radius of the V-cycle iteration matrix on the mean-zero
     pressure space is < 1; at K = 0 it is of the size the paper reports for
