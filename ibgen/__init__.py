@@ -173,7 +173,8 @@ def config_c3() -> Workload:
 
 def config_c4(n_problems: int = 64):
     """Batch of independent problems, N ~ U{64,128,256,512}, one ellipse of
-    round(0.8 pi N) points, K = 10**U(3,7), dt 100x, 10 steps."""
+    round(0.8 pi N) points, K = 10**U(3,7), dt 100x, 10 steps; levels down
+    to a 4 x 4 coarsest grid (the paper's max(4, box) rule)."""
     out = []
     for inst in range(n_problems):
         rng = np.random.default_rng(seed_for(4, inst))
@@ -181,7 +182,7 @@ def config_c4(n_problems: int = 64):
         M = int(round(0.8 * np.pi * N))
         X, meta = ellipse(rng, M)
         K = float(10.0 ** rng.uniform(3.0, 7.0))
-        levels = int(np.log2(N // 16)) + 1
+        levels = int(np.log2(N // 4)) + 1
         out.append(Workload(f"batch{inst}-{N}x{N}-M{M}", N, levels, X,
                             np.array([0, M], np.int32), K, 100.0, rtol=1e-8,
                             steps=10, seed=seed_for(4, inst), meta=meta))

@@ -125,8 +125,9 @@ int ibmg_phase_timing(ibmg_handle* h, double* total_ms, int64_t* launches, doubl
 /* Operator setup at positions X (Sec. 2.3.2 lags S at X^n; Sec. 3.2 builds the
  * coarse elasticity operators by Galerkin products; Sec. 8 notes the box
  * factors are re-formed near the structure each step): fibre forces, delta
- * weights, restricted/prolonged per-point patches on every level, point-to-box
- * binning, box factors and the bordered coarsest inverse, for time step dt.
+ * weights, point-to-box binning, the elastic rows of M_0 as coefficient
+ * windows and M_{l+1} = R M_l P as windows on every coarser level, box
+ * inverses and the bordered coarsest inverse, for time step dt.
  * X: M x 2.  Synchronises.  Errors: EINVAL, ENOMEM, EHIP, ENONFINITE. */
 int ibmg_setup(ibmg_handle* h, double dt, const double* X);
 
@@ -180,6 +181,39 @@ int ibmg_fiber_force(ibmg_handle* h, const double* X, double* G);
 int ibmg_spread(ibmg_handle* h, const double* X, const double* G, double* f_u, double* f_v);
 /* U = S^* (u, v) = h^2 S_0^T (u, v).  U: M x 2. */
 int ibmg_interp(ibmg_handle* h, const double* X, const double* u, const double* v, double* U);
+
+/* --- Batched form: many independent problems, each with its own grid,
+ *     structure, stiffness, dt and options, advanced together.  Every
+ *     problem runs the same method as ibmg_step (Sec. 2.3.2 step, FGMRES of
+ *     Sec. 3.3, V-cycle of Algorithm 1), and its outputs are bitwise equal to
+ *     ibmg_step on a handle created with the same problem and options.  The
+ *     FGMRES iterations of all problems run in lockstep rounds: one launch
+ *     per V-cycle step and per Krylov step covers every problem taking part,
+ *     and the V-cycle over all problems is one captured graph. --- */
+typedef struct ibmg_batch ibmg_batch;
+/* nprob problems (1..4096); probs and opts are HOST arrays of nprob entries
+ * (copied).  All opts must share vcycle_prec.  Errors as ibmg_create. */
+int ibmg_batch_create(ibmg_batch** out, int32_t nprob, const ibmg_problem* probs,
+                      const ibmg_opts* opts, void* hip_stream);
+/* One device workspace for every problem plus the batch's tables. */
+int ibmg_batch_workspace_bytes(const ibmg_batch* b, size_t* bytes);
+/* Bind it (>= ibmg_batch_workspace_bytes).  Also allocates two small pinned
+ * host buffers for the per-round tables.  Errors: ENOMEM, EHIP. */
+int ibmg_batch_bind_workspace(ibmg_batch* b, void* dev_ptr, size_t bytes);
+/* One implicit step of every problem.  dt: HOST [nprob].  u, v, p, X: HOST
+ * arrays of nprob DEVICE pointers, in/out as for ibmg_step (X may be NULL
+ * for a problem without points).  g_u, g_v: NULL, or HOST arrays of nprob
+ * nullable DEVICE pointers.  out: HOST [nprob] stats, nullable.  Returns the
+ * first error met, else IBMG_NOT_CONVERGED if any problem missed rtol, else
+ * IBMG_OK.  Synchronises. */
+int ibmg_batch_step(ibmg_batch* b, const double* dt, double* const* u, double* const* v,
+                    double* const* p, double* const* X, const double* const* g_u,
+                    const double* const* g_v, ibmg_stats* out);
+/* 1 (default) = replay the captured V-cycle graph, 0 = launch it eagerly. */
+int ibmg_batch_set_graph(ibmg_batch* b, int on);
+/* Lockstep FGMRES rounds run so far (one host synchronisation each). */
+int ibmg_batch_rounds(const ibmg_batch* b, int64_t* rounds);
+int ibmg_batch_destroy(ibmg_batch* b);
 
 #ifdef __cplusplus
 }

@@ -12,76 +12,10 @@
 
 #include "../../include/ibmg.h"
 #include "common.h"
+#include "handle.h"
 #include "kernels.h"
 
-namespace {
-
-constexpr int kPW = 16;          // panel width of the coarse Gauss-Jordan (dense.hip)
-constexpr int kDotBlocks = 256;  // workgroups of the deterministic dot products
-constexpr int kMaxTimed = 8192;  // timed phase launches per solve
-constexpr int kSmallLevel = 32;  // levels up to this size run in one workgroup per V-cycle leg
-
-struct Buf {
-  size_t off = 0, bytes = 0;
-};
-
-struct LevelBufs {
-  int N = 0, nb = 0, maxact = 0, reach = 0;
-  Buf w, b, r;               // V-cycle vectors in the V-cycle precision
-  Buf act, rows, nact;       // active elastic rows of this level
-  Buf win, winf;             // FP64 windows and their FP32 copy
-  Buf yib;                   // elastic rows evaluated before a colour phase (V-cycle precision)
-  Buf ib_index, ib_boxes, boxflag, info;
-  Buf ainv_plain, ainv_plain_f, ainv_ib;
-  int max_ib = 0;
-};
-
-}  // namespace
-
-struct ibmg_handle {
-  // problem and options
-  int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 2, nu2 = 2, maxit = 100, prec = 0, guess = 0;
-  int ncol = 2;
-  double rho = 1, mu = 1, K = 0, rtol = 1e-8;
-  std::vector<int> prev, next;
-  hipStream_t stream = nullptr;
-  // workspace
-  char* ws = nullptr;
-  size_t ws_bytes = 0, need = 0;
-  LevelBufs L[IBMG_MAX_LEVELS];
-  Buf X0, G, prev_d, next_d, U;
-  Buf org, wts, cnt, start, cursor, list, ltotal;   // finest-level point data and bins
-  Buf flag, loc, bsum, meta;                        // scan scratch and setup flags
-  int max_list = 0;
-  Buf V, Z, H, g, cs, sn, y, flags, partial, scal, hc;
-  Buf bvec, xvec, rvec, w0f, b0f;
-  Buf aug, cm, cpiv, crowpos, cused, cY, cainv;
-  int nr = 0, ndof = 0;
-  // state
-  bool setup_ok = false, has_ib = false, launch_error = false;
-  // the V-cycle as a captured graph (fixed buffers b0g -> w0g), rebuilt when dt changes
-  hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  double graph_dt = -1.0;
-  Buf b0g, w0g;
-  double dt = 0;
-  int n_ib[IBMG_MAX_LEVELS][5] = {};
-  // timing of the box-relaxation phase kernel
-  bool timing = false;
-  std::vector<hipEvent_t> ev;
-  int ev_used = 0;
-  std::vector<double> ev_bytes;
-  double t_total_ms = 0, t_bytes = 0;
-  int64_t t_launches = 0;
-
-  template <typename T> T* p(const Buf& b) const { return reinterpret_cast<T*>(ws + b.off); }
-  size_t n0() const { return 3 * (size_t)N * N; }
-};
-
-namespace {
-
-using namespace ibmg;
+namespace ibmg {
 
 void take(size_t& cur, Buf& b, size_t bytes) {
   cur = (cur + 255) & ~(size_t)255;
@@ -193,52 +127,11 @@ void layout(ibmg_handle* h) {
   h->need = cur + 256;
 }
 
-template <typename T>
-LevelView<T> view(const ibmg_handle* h, int l) {
-  const LevelBufs& B = h->L[l];
-  LevelView<T> v{};
-  v.N = B.N;
-  v.nb = B.nb;
-  v.n = h->n;
-  v.ndof = h->ndof;
-  v.ncol = h->ncol;
-  const double hl = 1.0 / B.N;
-  v.c = (T)(h->rho / h->dt);
-  v.muh2 = (T)(h->mu / (hl * hl));
-  v.invh = (T)(1.0 / hl);
-  v.reach = B.reach;
-  v.maxact = B.maxact;
-  if (h->has_ib) {
-    v.act = h->p<int>(B.act);
-    v.rows = h->p<int>(B.rows);
-    v.nact = h->p<int>(B.nact);
-    v.yib = h->p<T>(B.yib);
-    v.win = sizeof(T) == sizeof(float) ? reinterpret_cast<const T*>(h->p<float>(B.winf))
-                                       : reinterpret_cast<const T*>(h->p<double>(B.win));
-  }
-  if (l < h->levels - 1) {
-    v.ib_index = h->p<int>(B.ib_index);
-    v.ainv_plain = sizeof(T) == sizeof(float) ? reinterpret_cast<const T*>(h->p<float>(B.ainv_plain_f))
-                                              : reinterpret_cast<const T*>(h->p<double>(B.ainv_plain));
-    v.ainv_ib = h->p<double>(B.ainv_ib);
-  }
-  return v;
-}
+}  // namespace ibmg
 
-PointView points(const ibmg_handle* h) {
-  PointView P{};
-  P.M = h->M;
-  P.N = h->N;
-  P.n = h->n;
-  P.nb = h->L[0].nb;
-  P.prev = h->p<int>(h->prev_d);
-  P.next = h->p<int>(h->next_d);
-  P.org = h->p<int>(h->org);
-  P.wts = h->p<double>(h->wts);
-  P.box_start = h->p<int>(h->start);
-  P.box_list = h->p<int>(h->list);
-  return P;
-}
+namespace {
+
+using namespace ibmg;
 
 int sync(ibmg_handle* h) {
   IBMG_HIP(hipStreamSynchronize(h->stream));
@@ -374,7 +267,14 @@ void dot(ibmg_handle* h, const double* a, const double* b, double* dev) {
 
 // ---------------------------------------------------------------- setup
 
-int do_setup(ibmg_handle* h, double dt, const double* X) {
+}  // namespace
+
+namespace ibmg {
+
+// First half of the per-step setup: points, bins, elastic windows on every
+// level and box classes, then the asynchronous read-back of the counts that
+// setup_finish checks.  Nothing here waits for the device.
+int setup_launch(ibmg_handle* h, double dt, const double* X) {
   if (!h->ws) return IBMG_ENOMEM;
   if (!(dt > 0.0) || !std::isfinite(dt)) return IBMG_EINVAL;
   hipStream_t s = h->stream;
@@ -421,15 +321,27 @@ int do_setup(ibmg_handle* h, double dt, const double* X) {
                        h->p<int>(B.ib_index), h->p<int>(B.ib_boxes), h->p<int>(B.info));
   }
   // read back counts: boxes with elastic rows per colour, active rows, flags
-  std::vector<int> info(8 * Lv, 0), nact(2 * Lv, 0), mt(8, 0), lt(4, 0);
+  h->rb_info.assign(8 * Lv, 0);
+  h->rb_nact.assign(2 * Lv, 0);
+  h->rb_mt.assign(8, 0);
+  h->rb_lt.assign(4, 0);
   for (int l = 0; l + 1 < Lv; ++l)
-    IBMG_HIP(hipMemcpyAsync(&info[8 * l], h->p<int>(h->L[l].info), 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+    IBMG_HIP(hipMemcpyAsync(&h->rb_info[8 * l], h->p<int>(h->L[l].info), 8 * sizeof(int), hipMemcpyDeviceToHost, s));
   if (h->has_ib)
     for (int l = 0; l < Lv; ++l)
-      IBMG_HIP(hipMemcpyAsync(&nact[2 * l], h->p<int>(h->L[l].nact), 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  IBMG_HIP(hipMemcpyAsync(mt.data(), meta, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-  if (M > 0) IBMG_HIP(hipMemcpyAsync(lt.data(), h->p<int>(h->ltotal), sizeof(int), hipMemcpyDeviceToHost, s));
-  IBMG_HIP(hipStreamSynchronize(s));
+      IBMG_HIP(hipMemcpyAsync(&h->rb_nact[2 * l], h->p<int>(h->L[l].nact), 2 * sizeof(int), hipMemcpyDeviceToHost,
+                              s));
+  IBMG_HIP(hipMemcpyAsync(h->rb_mt.data(), meta, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+  if (M > 0) IBMG_HIP(hipMemcpyAsync(h->rb_lt.data(), h->p<int>(h->ltotal), sizeof(int), hipMemcpyDeviceToHost, s));
+  return IBMG_OK;
+}
+
+// Second half, after the stream has reached the read-back: capacity and
+// window checks, box inverses, coarsest system.  Launches only.
+int setup_finish(ibmg_handle* h) {
+  hipStream_t s = h->stream;
+  const int M = h->M, Lv = h->levels;
+  const std::vector<int>&info = h->rb_info, &nact = h->rb_nact, &mt = h->rb_mt, &lt = h->rb_lt;
   if (M > 0 && lt[0] > h->max_list) return IBMG_ENOMEM;
   for (int l = 0; l < Lv && h->has_ib; ++l)
     if (nact[2 * l] > h->L[l].maxact || nact[2 * l + 1] > h->L[l].maxact) return IBMG_ENOMEM;
@@ -449,7 +361,20 @@ int do_setup(ibmg_handle* h, double dt, const double* X) {
       return IBMG_EHIP;
   }
   IBMG_HIP(hipGetLastError());
-  IBMG_HIP(hipStreamSynchronize(s));
+  return IBMG_OK;
+}
+
+}  // namespace ibmg
+
+namespace {
+
+int do_setup(ibmg_handle* h, double dt, const double* X) {
+  int rc = setup_launch(h, dt, X);
+  if (rc) return rc;
+  IBMG_HIP(hipStreamSynchronize(h->stream));
+  rc = setup_finish(h);
+  if (rc) return rc;
+  IBMG_HIP(hipStreamSynchronize(h->stream));
   h->setup_ok = true;
   return IBMG_OK;
 }
@@ -554,6 +479,72 @@ bool ready(const ibmg_handle* h) { return h && h->ws; }
 
 }  // namespace
 
+namespace ibmg {
+
+int bind(ibmg_handle* h, void* dev, size_t bytes, bool own_capture_stream) {
+  if (!h || !dev) return IBMG_EINVAL;
+  char* base = (char*)(((uintptr_t)dev + 255) & ~(uintptr_t)255);
+  if (bytes < h->need || (size_t)(base - (char*)dev) + h->need - 256 > bytes) return IBMG_ENOMEM;
+  h->ws = base;
+  h->ws_bytes = bytes;
+  h->setup_ok = false;
+  h->graph_dt = -1.0;
+  if (own_capture_stream && !h->cap) IBMG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  // dynamic LDS of the V-cycle tail (levels of at most kSmallLevel cells per side)
+  if (prepare_tail(tail_lds(h, sizeof(double))) != 0) return IBMG_EHIP;
+  if (h->M > 0) {
+    IBMG_HIP(hipMemcpyAsync(h->p<int>(h->prev_d), h->prev.data(), h->M * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+    IBMG_HIP(hipMemcpyAsync(h->p<int>(h->next_d), h->next.data(), h->M * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+    IBMG_HIP(hipStreamSynchronize(h->stream));
+  }
+  return IBMG_OK;
+}
+
+// Right-hand side (a4) into bvec and the initial iterate into xvec.
+int step_begin(ibmg_handle* h, double dt, const double* u, const double* v, const double* p, const double* gu,
+               const double* gv) {
+  hipStream_t s = h->stream;
+  const size_t NN = (size_t)h->N * h->N, n0 = h->n0();
+  double* b = h->p<double>(h->bvec);
+  double* x = h->p<double>(h->xvec);
+  launch_rhs(s, points(h), h->rho / dt, (double)h->N * h->N, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr,
+             b);
+  if (h->guess == IBMG_GUESS_PREV) {
+    IBMG_HIP(hipMemcpyAsync(x, u, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(x + NN, v, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(x + 2 * NN, p, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    k_fill<double><<<nblk(n0), 256, 0, s>>>(x, n0, 0.0);
+  }
+  IBMG_HIP(hipGetLastError());
+  return IBMG_OK;
+}
+
+// Zero-mean pressure, then move the structure with the lagged S^n (a14) and
+// copy the new state out.  Launches only.
+int step_end(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X) {
+  hipStream_t s = h->stream;
+  const size_t NN = (size_t)h->N * h->N;
+  double* x = h->p<double>(h->xvec);
+  double* part = h->p<double>(h->partial);
+  double* scal = h->p<double>(h->scal);
+  launch_sum(s, x + 2 * NN, NN, part, kDotBlocks);
+  launch_reduce(s, part, kDotBlocks, 1, scal, 0);
+  launch_mean_shift(s, x + 2 * NN, NN, scal);
+  if (h->M > 0) launch_interp(s, points(h), x, x + NN, h->p<double>(h->U), h->p<double>(h->X0), dt);
+  IBMG_HIP(hipMemcpyAsync(u, x, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  IBMG_HIP(hipMemcpyAsync(v, x + NN, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  IBMG_HIP(hipMemcpyAsync(p, x + 2 * NN, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (h->M > 0)
+    IBMG_HIP(hipMemcpyAsync(X, h->p<double>(h->X0), 2 * (size_t)h->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  IBMG_HIP(hipGetLastError());
+  return IBMG_OK;
+}
+
+}  // namespace ibmg
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -627,31 +618,7 @@ int ibmg_workspace_bytes(const ibmg_handle* h, size_t* bytes) {
 }
 
 int ibmg_bind_workspace(ibmg_handle* h, void* dev, size_t bytes) {
-  if (!h || !dev) return IBMG_EINVAL;
-  char* base = (char*)(((uintptr_t)dev + 255) & ~(uintptr_t)255);
-  if (bytes < h->need || (size_t)(base - (char*)dev) + h->need - 256 > bytes) return IBMG_ENOMEM;
-  h->ws = base;
-  h->ws_bytes = bytes;
-  h->setup_ok = false;
-  h->graph_dt = -1.0;
-  if (!h->cap) IBMG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-  {
-    // dynamic LDS of the V-cycle tail: the levels of at most kSmallLevel cells
-    // per side and the coarsest, three vectors each
-    int ls = h->levels - 1;
-    while (ls > 0 && h->L[ls - 1].N <= kSmallLevel) --ls;
-    size_t lds = 0;
-    for (int l = ls; l < h->levels; ++l) lds += 9 * (size_t)h->L[l].N * h->L[l].N * sizeof(double);
-    if (prepare_tail(lds) != 0) return IBMG_EHIP;
-  }
-  if (h->M > 0) {
-    IBMG_HIP(hipMemcpyAsync(h->p<int>(h->prev_d), h->prev.data(), h->M * sizeof(int), hipMemcpyHostToDevice,
-                            h->stream));
-    IBMG_HIP(hipMemcpyAsync(h->p<int>(h->next_d), h->next.data(), h->M * sizeof(int), hipMemcpyHostToDevice,
-                            h->stream));
-    IBMG_HIP(hipStreamSynchronize(h->stream));
-  }
-  return IBMG_OK;
+  return bind(h, dev, bytes, true);
 }
 
 int ibmg_destroy(ibmg_handle* h) {
@@ -729,36 +696,13 @@ int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double
   int rc = do_setup(h, dt, X);
   if (rc) return rc;
   const double t1 = now_ms();
-  hipStream_t s = h->stream;
-  const size_t NN = (size_t)h->N * h->N, n0 = h->n0();
-  double* b = h->p<double>(h->bvec);
-  double* x = h->p<double>(h->xvec);
-  launch_rhs(s, points(h), h->rho / dt, (double)h->N * h->N, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr,
-             b);
-  if (h->guess == IBMG_GUESS_PREV) {
-    IBMG_HIP(hipMemcpyAsync(x, u, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
-    IBMG_HIP(hipMemcpyAsync(x + NN, v, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
-    IBMG_HIP(hipMemcpyAsync(x + 2 * NN, p, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
-  } else {
-    k_fill<double><<<nblk(n0), 256, 0, s>>>(x, n0, 0.0);
-  }
-  rc = do_solve(h, b, x, &st);
+  if ((rc = step_begin(h, dt, u, v, p, gu, gv))) return rc;
+  rc = do_solve(h, h->p<double>(h->bvec), h->p<double>(h->xvec), &st);
   const double t2 = now_ms();
   if (rc < 0) return rc;
-  // zero-mean pressure, then move the structure with the lagged S^n
-  double* part = h->p<double>(h->partial);
-  double* scal = h->p<double>(h->scal);
-  launch_sum(s, x + 2 * NN, NN, part, kDotBlocks);
-  launch_reduce(s, part, kDotBlocks, 1, scal, 0);
-  launch_mean_shift(s, x + 2 * NN, NN, scal);
-  if (h->M > 0) launch_interp(s, points(h), x, x + NN, h->p<double>(h->U), h->p<double>(h->X0), dt);
-  IBMG_HIP(hipMemcpyAsync(u, x, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
-  IBMG_HIP(hipMemcpyAsync(v, x + NN, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
-  IBMG_HIP(hipMemcpyAsync(p, x + 2 * NN, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
-  if (h->M > 0)
-    IBMG_HIP(hipMemcpyAsync(X, h->p<double>(h->X0), 2 * (size_t)h->M * sizeof(double), hipMemcpyDeviceToDevice, s));
-  IBMG_HIP(hipGetLastError());
-  IBMG_HIP(hipStreamSynchronize(s));
+  const int rc_end = step_end(h, dt, u, v, p, X);
+  if (rc_end) return rc_end;
+  IBMG_HIP(hipStreamSynchronize(h->stream));
   h->setup_ok = false;   // the operator belongs to X^n
   st.t_setup_ms = t1 - t0;
   st.t_solve_ms = t2 - t1;

@@ -1,0 +1,152 @@
+// Internal host-side state shared by the single-problem ABI (api.hip) and
+// the batched ABI (batch.hip): the handle, its workspace layout and the
+// level views handed to the kernels.
+#pragma once
+#include <vector>
+
+#include "../../include/ibmg.h"
+#include "common.h"
+
+namespace ibmg {
+
+constexpr int kPW = 16;          // panel width of the coarse Gauss-Jordan (dense.hip)
+constexpr int kDotBlocks = 256;  // workgroups of the deterministic dot products
+constexpr int kMaxTimed = 8192;  // timed phase launches per solve
+constexpr int kSmallLevel = 32;  // levels up to this size run in one workgroup per V-cycle leg
+
+struct Buf {
+  size_t off = 0, bytes = 0;
+};
+
+struct LevelBufs {
+  int N = 0, nb = 0, maxact = 0, reach = 0;
+  Buf w, b, r;               // V-cycle vectors in the V-cycle precision
+  Buf act, rows, nact;       // active elastic rows of this level
+  Buf win, winf;             // FP64 windows and their FP32 copy
+  Buf yib;                   // elastic rows evaluated before a colour phase (V-cycle precision)
+  Buf ib_index, ib_boxes, boxflag, info;
+  Buf ainv_plain, ainv_plain_f, ainv_ib;
+  int max_ib = 0;
+};
+
+}  // namespace ibmg
+
+using ibmg::Buf;
+using ibmg::LevelBufs;
+
+struct ibmg_handle {
+  // problem and options
+  int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 2, nu2 = 2, maxit = 100, prec = 0, guess = 0;
+  int ncol = 2;
+  double rho = 1, mu = 1, K = 0, rtol = 1e-8;
+  std::vector<int> prev, next;
+  hipStream_t stream = nullptr;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0, need = 0;
+  LevelBufs L[IBMG_MAX_LEVELS];
+  Buf X0, G, prev_d, next_d, U;
+  Buf org, wts, cnt, start, cursor, list, ltotal;   // finest-level point data and bins
+  Buf flag, loc, bsum, meta;                        // scan scratch and setup flags
+  int max_list = 0;
+  Buf V, Z, H, g, cs, sn, y, flags, partial, scal, hc;
+  Buf bvec, xvec, rvec, w0f, b0f;
+  Buf aug, cm, cpiv, crowpos, cused, cY, cainv;
+  int nr = 0, ndof = 0;
+  // state
+  bool setup_ok = false, has_ib = false, launch_error = false;
+  // the V-cycle as a captured graph (fixed buffers b0g -> w0g), rebuilt when dt changes
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double graph_dt = -1.0;
+  Buf b0g, w0g;
+  double dt = 0;
+  int n_ib[IBMG_MAX_LEVELS][5] = {};
+  // setup counts read back between setup_launch and setup_finish
+  std::vector<int> rb_info, rb_nact, rb_mt, rb_lt;
+  // timing of the box-relaxation phase kernel
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  std::vector<double> ev_bytes;
+  double t_total_ms = 0, t_bytes = 0;
+  int64_t t_launches = 0;
+
+  template <typename T> T* p(const Buf& b) const { return reinterpret_cast<T*>(ws + b.off); }
+  size_t n0() const { return 3 * (size_t)N * N; }
+};
+
+namespace ibmg {
+
+template <typename T>
+inline LevelView<T> view(const ibmg_handle* h, int l) {
+  const LevelBufs& B = h->L[l];
+  LevelView<T> v{};
+  v.N = B.N;
+  v.nb = B.nb;
+  v.n = h->n;
+  v.ndof = h->ndof;
+  v.ncol = h->ncol;
+  const double hl = 1.0 / B.N;
+  v.c = (T)(h->rho / h->dt);
+  v.muh2 = (T)(h->mu / (hl * hl));
+  v.invh = (T)(1.0 / hl);
+  v.reach = B.reach;
+  v.maxact = B.maxact;
+  if (h->has_ib) {
+    v.act = h->p<int>(B.act);
+    v.rows = h->p<int>(B.rows);
+    v.nact = h->p<int>(B.nact);
+    v.yib = h->p<T>(B.yib);
+    v.win = sizeof(T) == sizeof(float) ? reinterpret_cast<const T*>(h->p<float>(B.winf))
+                                       : reinterpret_cast<const T*>(h->p<double>(B.win));
+  }
+  if (l < h->levels - 1) {
+    v.ib_index = h->p<int>(B.ib_index);
+    v.ainv_plain = sizeof(T) == sizeof(float) ? reinterpret_cast<const T*>(h->p<float>(B.ainv_plain_f))
+                                              : reinterpret_cast<const T*>(h->p<double>(B.ainv_plain));
+    v.ainv_ib = h->p<double>(B.ainv_ib);
+  }
+  return v;
+}
+
+inline PointView points(const ibmg_handle* h) {
+  PointView P{};
+  P.M = h->M;
+  P.N = h->N;
+  P.n = h->n;
+  P.nb = h->L[0].nb;
+  P.prev = h->p<int>(h->prev_d);
+  P.next = h->p<int>(h->next_d);
+  P.org = h->p<int>(h->org);
+  P.wts = h->p<double>(h->wts);
+  P.box_start = h->p<int>(h->start);
+  P.box_list = h->p<int>(h->list);
+  return P;
+}
+
+// First level handled by the LDS-resident tail of the V-cycle: every level
+// from there down has at most kSmallLevel cells per side.
+inline int tail_start(const ibmg_handle* h) {
+  int ls = h->levels - 1;
+  while (ls > 0 && h->L[ls - 1].N <= kSmallLevel) --ls;
+  return ls;
+}
+
+// Dynamic LDS of the tail: three vectors (nine arrays) per level from ls on.
+inline size_t tail_lds(const ibmg_handle* h, size_t elem) {
+  size_t lds = 0;
+  for (int l = tail_start(h); l < h->levels; ++l) lds += 9 * (size_t)h->L[l].N * h->L[l].N * elem;
+  return lds;
+}
+
+void layout(ibmg_handle* h);
+int bind(ibmg_handle* h, void* dev, size_t bytes, bool own_capture_stream);
+int setup_launch(ibmg_handle* h, double dt, const double* X);
+int setup_finish(ibmg_handle* h);
+int step_begin(ibmg_handle* h, double dt, const double* u, const double* v, const double* p, const double* gu,
+               const double* gv);
+int step_end(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X);
+
+}  // namespace ibmg

@@ -8,418 +8,38 @@
 #include "common.h"
 #include "kernels.h"
 
-// ---------------------------------------------------------------- a8: y = A w or r = b - A w
-// Stokes part here; the elastic rows are added by k_ib_rows afterwards.
+#include "level_ops.h"
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_residual(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* __restrict__ r) {
-  const int NN = L.N * L.N;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 3 * NN) return;
-  const int comp = idx / NN, rem = idx - comp * NN;
-  const int j = rem / L.N, i = rem - j * L.N;
-  const T y = stokes_row(L, w, comp, i, j);
-  r[idx] = b ? b[idx] - y : y;
+  residual_body<T>(L, b, w, r, blockIdx.x);
 }
-
-// ---------------------------------------------------------------- (M_l w) on the active rows
-// Sixteen lanes per active row split its window entries in a fixed pattern
-// and reduce with a fixed shuffle tree; lane 0 stores.  mode 0: yib[row] =
-// (M w)_f (formed before each colour phase from the iterate at the start of
-// the phase -- a window reaches past the next box of the same colour, so the
-// phase kernel must not evaluate it while those boxes are being updated);
-// mode 1: out[f] += (M w)_f; mode 2: out[f] -= (M w)_f.
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_ib_rows(LevelView<T> L, const T* __restrict__ w, T* __restrict__ out, int mode) {
-  const int comp = blockIdx.y;
-  const int row = (blockIdx.x * 256 + threadIdx.x) >> 4;
-  const int lane = threadIdx.x & 15;
-  if (row >= L.maxact || row >= L.nact[comp]) return;   // uniform over the 16 lanes of a row
-  const int N = L.N, msk = N - 1, NN = N * N;
-  const int f = L.rows[comp * L.maxact + row];
-  const int j = f / N, i = f - j * N;
-  const int r = L.reach, W = 2 * r + 1;
-  const T* c = L.win + ((size_t)comp * L.maxact + row) * IBMG_WS;
-  const T* x = w + (size_t)comp * NN;
-  T acc = T(0);
-  for (int q = lane; q < W * W; q += 16) {
-    const int dy = q / W - r, dx = q - (q / W) * W - r;
-    acc += c[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR] * x[((j + dy) & msk) * N + ((i + dx) & msk)];
-  }
-  acc += __shfl_xor(acc, 8, 16);
-  acc += __shfl_xor(acc, 4, 16);
-  acc += __shfl_xor(acc, 2, 16);
-  acc += __shfl_xor(acc, 1, 16);
-  if (lane != 0) return;
-  if (mode == 0) L.yib[comp * L.maxact + row] = acc;
-  else if (mode == 1) out[(size_t)comp * NN + f] += acc;
-  else out[(size_t)comp * NN + f] -= acc;
+__global__ void __launch_bounds__(256) k_ib_rows(LevelView<T> L, const T* __restrict__ w, T* __restrict__ out, int mode) {
+  ib_rows_body<T>(L, w, out, mode, blockIdx.x, blockIdx.y);
 }
-
-// ---------------------------------------------------------------- a9: one colour phase
-// A phase is two launches so that every box of the colour solves from the
-// iterate at the start of the phase (the 5-point stencil of a box's edge
-// unknowns, and every elastic window, reaches unknowns of other boxes of the
-// same colour).  k_res_ib: r = b - (Stokes part of A) w on every unknown, and
-// yib = (M_l w) on every active elastic row (16 lanes per row, fixed-order
-// shuffle tree).  k_box: one 64-lane workgroup per box of the colour; lane r
-// takes res = r - yib at local unknown r, z = A_box^{-1} res, w[box] += z.
-// Boxes of one colour share no unknowns, so the update is race-free.  Boxes
-// that touch the structure use their own FP64 inverse with the residual
-// promoted to FP64.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_res_ib(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* __restrict__ r, int nres_blocks) {
-  const int N = L.N, NN = N * N;
-  if ((int)blockIdx.x < nres_blocks) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= 3 * NN) return;
-    const int comp = idx / NN, rem = idx - comp * NN;
-    const int j = rem / N, i = rem - j * N;
-    r[idx] = b[idx] - stokes_row(L, w, comp, i, j);
-    return;
-  }
-  const int q = (((int)blockIdx.x - nres_blocks) * 256 + (int)threadIdx.x) >> 4;
-  const int comp = q >= L.maxact ? 1 : 0, row = q - comp * L.maxact;
-  const int lane = threadIdx.x & 15;
-  if (row >= L.maxact || row >= L.nact[comp]) return;    // uniform over the 16 lanes of a row
-  const int msk = N - 1;
-  const int f = L.rows[comp * L.maxact + row];
-  const int j = f / N, i = f - j * N;
-  const int rr = L.reach, W = 2 * rr + 1;
-  const T* c = L.win + ((size_t)comp * L.maxact + row) * IBMG_WS;
-  const T* x = w + (size_t)comp * NN;
-  T acc = T(0);
-  for (int e = lane; e < W * W; e += 16) {
-    const int dy = e / W - rr, dx = e - (e / W) * W - rr;
-    acc += c[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR] * x[((j + dy) & msk) * N + ((i + dx) & msk)];
-  }
-  acc += __shfl_xor(acc, 8, 16);
-  acc += __shfl_xor(acc, 4, 16);
-  acc += __shfl_xor(acc, 2, 16);
-  acc += __shfl_xor(acc, 1, 16);
-  if (lane == 0) L.yib[comp * L.maxact + row] = acc;
+  res_ib_body<T>(L, b, w, r, nres_blocks, blockIdx.x);
 }
-
 template <typename T>
-__global__ void __launch_bounds__(64)
-k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour) {
-  __shared__ double res[64];
-  int bx, by;
-  colour_box(blockIdx.x, colour, L.ncol, L.nb, bx, by);
-  const int box = by * L.nb + bx;
-  const int lane = threadIdx.x, nd = L.ndof, N = L.N, NN = N * N;
-  const int ibx = L.ib_index ? L.ib_index[box] : -1;
-  int comp = 0, i = 0, j = 0;
-  size_t g = 0;
-  if (lane < nd) {
-    box_dof(lane, bx, by, L.n, N, comp, i, j);
-    g = (size_t)comp * NN + (size_t)j * N + i;
-    T y = r[g];
-    if (ibx >= 0 && comp < 2) {
-      const int a = L.act[comp * NN + j * N + i];
-      if (a >= 0) y -= L.yib[comp * L.maxact + a];
-    }
-    res[lane] = (double)y;
-  }
-  __syncthreads();
-  if (lane >= nd) return;
-  if (ibx >= 0) {
-    const double* A = L.ainv_ib + (size_t)ibx * nd * nd;
-    double z = 0.0;
-#pragma unroll 8
-    for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * res[c];
-    w[g] += (T)z;
-  } else {
-    const T* A = L.ainv_plain;
-    T z = T(0);
-#pragma unroll 8
-    for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * (T)res[c];
-    w[g] += z;
-  }
+__global__ void __launch_bounds__(64) k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour) {
+  box_body<T>(L, r, w, colour, blockIdx.x);
 }
-
-// ---------------------------------------------------------------- a10: restriction (Sec. 3.1)
-// The coarse correction of Algorithm 1 starts from zero, so the same launch
-// clears the coarse iterate (wz, nullable).
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int Nf, const T* __restrict__ rf, T* __restrict__ rc,
                                                   T* __restrict__ wz) {
-  const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf, mf = Nf - 1;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 3 * NNc) return;
-  const int comp = idx / NNc, rem = idx - comp * NNc;
-  const int J = rem / Nc, I = rem - J * Nc;
-  const T* f = rf + (size_t)comp * NNf;
-  T s = T(0);
-  if (comp == 0) {
-    for (int e = 0; e < 2; ++e) {
-      const int jj = 2 * J + e;
-      s += T(0.125) * f[jj * Nf + ((2 * I - 1) & mf)] + T(0.25) * f[jj * Nf + 2 * I] +
-           T(0.125) * f[jj * Nf + ((2 * I + 1) & mf)];
-    }
-  } else if (comp == 1) {
-    for (int e = 0; e < 2; ++e) {
-      const int ii = 2 * I + e;
-      s += T(0.125) * f[((2 * J - 1) & mf) * Nf + ii] + T(0.25) * f[(2 * J) * Nf + ii] +
-           T(0.125) * f[((2 * J + 1) & mf) * Nf + ii];
-    }
-  } else {
-    s = T(0.25) * (f[2 * J * Nf + 2 * I] + f[2 * J * Nf + 2 * I + 1] + f[(2 * J + 1) * Nf + 2 * I] +
-                   f[(2 * J + 1) * Nf + 2 * I + 1]);
-  }
-  rc[idx] = s;
-  if (wz) wz[idx] = T(0);
+  restrict_body<T>(Nf, rf, rc, wz, blockIdx.x);
 }
-
-// ---------------------------------------------------------------- a11: prolong and correct (Sec. 3.1)
-template <typename T>
-__device__ inline T bilinear(const T* c, int Nc, int in, int it, bool normal_is_x) {
-  // in: fine index along the face normal, it: along the tangent
-  const int mc = Nc - 1;
-  int n0, n1;
-  T wn0, wn1;
-  if ((in & 1) == 0) { n0 = in >> 1; n1 = n0; wn0 = T(1); wn1 = T(0); }
-  else { n0 = (in - 1) >> 1; n1 = ((in + 1) >> 1) & mc; wn0 = T(0.5); wn1 = T(0.5); }
-  const int t0 = it >> 1;
-  const int t1 = ((it & 1) == 0 ? t0 - 1 : t0 + 1) & mc;
-  auto at = [&](int a, int b) -> T { return normal_is_x ? c[b * Nc + a] : c[a * Nc + b]; };
-  T s = T(0.75) * (wn0 * at(n0, t0)) + T(0.25) * (wn0 * at(n0, t1));
-  if ((in & 1) != 0) s += T(0.75) * (wn1 * at(n1, t0)) + T(0.25) * (wn1 * at(n1, t1));
-  return s;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(int Nf, const T* __restrict__ ec, T* __restrict__ wf) {
-  const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 3 * NNf) return;
-  const int comp = idx / NNf, rem = idx - comp * NNf;
-  const int j = rem / Nf, i = rem - j * Nf;
-  const T* c = ec + (size_t)comp * NNc;
-  T add;
-  if (comp == 0) add = bilinear(c, Nc, i, j, true);
-  else if (comp == 1) add = bilinear(c, Nc, j, i, false);
-  else add = c[(j >> 1) * Nc + (i >> 1)];
-  wf[idx] += add;
+  prolong_body<T>(Nf, ec, wf, blockIdx.x);
 }
-
-// ---------------------------------------------------------------- small levels in one workgroup
-// Levels of at most 32 x 32 cells carry too little work to fill the chip; one
-// 1024-thread workgroup runs all of their colour phases (k_tail) with
-// workgroup barriers in place of kernel launches.  Same arithmetic as k_res_ib and
-// k_box: the residual and the elastic rows are formed before each colour
-// from the iterate at its start, then each wave solves one box of the colour
-// per round, in the same fixed order as k_box.
-// One thread per elastic row, window loops unrolled so that all loads of a
-// window row are in flight together (fixed summation order: dy, then dx).
-template <typename T, int R>
-__device__ inline T win_row(const T* __restrict__ c, const T* __restrict__ x, int N, int i, int j) {
-  const int msk = N - 1;
-  T acc = T(0);
-#pragma unroll
-  for (int dy = -R; dy <= R; ++dy) {
-    const T* row = x + ((j + dy) & msk) * N;
-    const T* cw = c + (dy + IBMG_WR) * IBMG_WW + IBMG_WR;
-#pragma unroll
-    for (int dx = -R; dx <= R; ++dx) acc += cw[dx] * row[(i + dx) & msk];
-  }
-  return acc;
-}
-
-template <typename T>
-__device__ void small_ib_rows(const LevelView<T>& L, const T* __restrict__ w, T* __restrict__ out, int mode) {
-  const int N = L.N, NN = N * N;
-  const int n0 = min(L.nact[0], L.maxact), n1 = min(L.nact[1], L.maxact);
-  for (int q = threadIdx.x; q < n0 + n1; q += blockDim.x) {
-    const int comp = q < n0 ? 0 : 1, row = q - comp * n0;
-    const int f = L.rows[comp * L.maxact + row];
-    const int j = f / N, i = f - j * N;
-    const T* c = L.win + ((size_t)comp * L.maxact + row) * IBMG_WS;
-    const T* x = w + (size_t)comp * NN;
-    T acc;
-    if (L.reach <= 3) acc = win_row<T, 3>(c, x, N, i, j);
-    else if (L.reach == 4) acc = win_row<T, 4>(c, x, N, i, j);
-    else acc = win_row<T, 5>(c, x, N, i, j);
-    if (mode == 0) L.yib[comp * L.maxact + row] = acc;
-    else if (mode == 1) out[(size_t)comp * NN + f] += acc;
-    else out[(size_t)comp * NN + f] -= acc;
-  }
-}
-
-template <typename T>
-__device__ void small_sweep(const LevelView<T>& L, const T* __restrict__ b, T* __restrict__ w, T* __restrict__ r,
-                            bool ib) {
-  __shared__ double res[16][64];
-  const int N = L.N, NN = N * N, nd = L.ndof;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
-  for (int colour = 0; colour < L.ncol; ++colour) {
-    // residual and elastic rows from the iterate at the start of the colour
-    for (int idx = threadIdx.x; idx < 3 * NN; idx += blockDim.x) {
-      const int comp = idx / NN, rem = idx - comp * NN;
-      const int j = rem / N, i = rem - j * N;
-      r[idx] = b[idx] - stokes_row(L, w, comp, i, j);
-    }
-    if (ib) small_ib_rows<T>(L, w, nullptr, 0);
-    __syncthreads();
-    const int cnt = colour_count(L.ncol, L.nb);
-    const int rounds = (cnt + nwaves - 1) / nwaves;
-    for (int round = 0; round < rounds; ++round) {
-      const int q = round * nwaves + wave;
-      const bool active = q < cnt;
-      int bx = 0, by = 0, comp = 0, i = 0, j = 0, ibx = -1;
-      size_t g = 0;
-      if (active) {
-        colour_box(q, colour, L.ncol, L.nb, bx, by);
-        ibx = ib ? L.ib_index[by * L.nb + bx] : -1;
-        if (lane < nd) {
-          box_dof(lane, bx, by, L.n, N, comp, i, j);
-          g = (size_t)comp * NN + (size_t)j * N + i;
-          T y = r[g];
-          if (ibx >= 0 && comp < 2) {
-            const int a = L.act[comp * NN + j * N + i];
-            if (a >= 0) y -= L.yib[comp * L.maxact + a];
-          }
-          res[wave][lane] = (double)y;
-        }
-      }
-      __syncthreads();
-      if (active && lane < nd) {
-        if (ibx >= 0) {
-          const double* A = L.ainv_ib + (size_t)ibx * nd * nd;
-          double z = 0.0;
-#pragma unroll 8
-          for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * res[wave][c];
-          w[g] += (T)z;
-        } else {
-          const T* A = L.ainv_plain;
-          T z = T(0);
-#pragma unroll 8
-          for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * (T)res[wave][c];
-          w[g] += z;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// The tail of the V-cycle: every level from ls down to the coarsest, and the
-// coarsest exact solve, in one workgroup with the fields of those levels
-// resident in LDS.  Entry: b_ls in global memory (the restricted residual of
-// the level above, or the preconditioner input when ls = 0).  Exit: w_ls in
-// global memory.  Same steps as the per-level kernels (Algorithm 1).
-template <typename T>
-struct TailArgs {
-  LevelView<T> v[IBMG_MAX_LEVELS];
-  int ls, L, nu1, nu2, ib, nr;
-  const T* b_in;
-  T* w_out;
-  const double* cainv;
-};
-
-template <typename T>
-__device__ void tail_restrict(int N, const T* __restrict__ r, T* __restrict__ bc, T* __restrict__ wc) {
-  const int NN = N * N, Nc = N / 2, NNc = Nc * Nc, mf = N - 1;
-  for (int idx = threadIdx.x; idx < 3 * NNc; idx += blockDim.x) {
-    const int comp = idx / NNc, rem = idx - comp * NNc;
-    const int J = rem / Nc, I = rem - J * Nc;
-    const T* f = r + (size_t)comp * NN;
-    T sacc = T(0);
-    if (comp == 0) {
-      for (int e = 0; e < 2; ++e) {
-        const int jj = 2 * J + e;
-        sacc += T(0.125) * f[jj * N + ((2 * I - 1) & mf)] + T(0.25) * f[jj * N + 2 * I] +
-                T(0.125) * f[jj * N + ((2 * I + 1) & mf)];
-      }
-    } else if (comp == 1) {
-      for (int e = 0; e < 2; ++e) {
-        const int ii = 2 * I + e;
-        sacc += T(0.125) * f[((2 * J - 1) & mf) * N + ii] + T(0.25) * f[(2 * J) * N + ii] +
-                T(0.125) * f[((2 * J + 1) & mf) * N + ii];
-      }
-    } else {
-      sacc = T(0.25) * (f[2 * J * N + 2 * I] + f[2 * J * N + 2 * I + 1] + f[(2 * J + 1) * N + 2 * I] +
-                        f[(2 * J + 1) * N + 2 * I + 1]);
-    }
-    bc[idx] = sacc;
-    wc[idx] = T(0);
-  }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(1024) k_tail(TailArgs<T> A) {
-  extern __shared__ double smem[];
-  T* w[IBMG_MAX_LEVELS];
-  T* b[IBMG_MAX_LEVELS];
-  T* r[IBMG_MAX_LEVELS];
-  {
-    T* p = reinterpret_cast<T*>(smem);
-    for (int l = A.ls; l < A.L; ++l) {
-      const int n3 = 3 * A.v[l].N * A.v[l].N;
-      w[l] = p; p += n3;
-      b[l] = p; p += n3;
-      r[l] = p; p += n3;
-    }
-  }
-  const int ib = A.ib;
-  {
-    const int n3 = 3 * A.v[A.ls].N * A.v[A.ls].N;
-    for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) {
-      b[A.ls][idx] = A.b_in[idx];
-      w[A.ls][idx] = T(0);
-    }
-  }
-  __syncthreads();
-  for (int l = A.ls; l + 1 < A.L; ++l) {
-    const LevelView<T>& L = A.v[l];
-    const int N = L.N, NN = N * N;
-    for (int s = 0; s < A.nu1; ++s) small_sweep<T>(L, b[l], w[l], r[l], ib != 0);
-    for (int idx = threadIdx.x; idx < 3 * NN; idx += blockDim.x) {
-      const int comp = idx / NN, rem = idx - comp * NN;
-      const int j = rem / N, i = rem - j * N;
-      r[l][idx] = b[l][idx] - stokes_row(L, w[l], comp, i, j);
-    }
-    __syncthreads();
-    if (ib) small_ib_rows<T>(L, w[l], r[l], 2);
-    __syncthreads();
-    tail_restrict<T>(N, r[l], b[l + 1], w[l + 1]);
-    __syncthreads();
-  }
-  {
-    // coarsest: w = first nr-1 entries of A^{-1} [b; 0]; one wave per row
-    const int lc = A.L - 1, nr = A.nr;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
-    for (int row = wave; row < nr - 1; row += nwaves) {
-      const double* a = A.cainv + (size_t)row * nr;
-      double acc = 0.0;
-      for (int c = lane; c < nr - 1; c += 64) acc += a[c] * (double)b[lc][c];
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
-      if (lane == 0) w[lc][row] = (T)acc;
-    }
-    __syncthreads();
-  }
-  for (int l = A.L - 2; l >= A.ls; --l) {
-    const LevelView<T>& L = A.v[l];
-    const int N = L.N, NN = N * N, Nc = N / 2, NNc = Nc * Nc;
-    for (int idx = threadIdx.x; idx < 3 * NN; idx += blockDim.x) {
-      const int comp = idx / NN, rem = idx - comp * NN;
-      const int j = rem / N, i = rem - j * N;
-      const T* c = w[l + 1] + (size_t)comp * NNc;
-      T add;
-      if (comp == 0) add = bilinear(c, Nc, i, j, true);
-      else if (comp == 1) add = bilinear(c, Nc, j, i, false);
-      else add = c[(j >> 1) * Nc + (i >> 1)];
-      w[l][idx] += add;
-    }
-    __syncthreads();
-    for (int s = 0; s < A.nu2; ++s) small_sweep<T>(L, b[l], w[l], r[l], ib != 0);
-  }
-  {
-    const int n3 = 3 * A.v[A.ls].N * A.v[A.ls].N;
-    for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) A.w_out[idx] = w[A.ls][idx];
-  }
+  tail_body<T>(A);
 }
 
 // ---------------------------------------------------------------- a4: right-hand side

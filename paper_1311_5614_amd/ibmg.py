@@ -31,6 +31,8 @@ EXPORTS = [
     "ibmg_rhs", "ibmg_solve", "ibmg_apply", "ibmg_residual", "ibmg_smooth", "ibmg_restrict",
     "ibmg_prolong_add", "ibmg_coarse_solve", "ibmg_vcycle", "ibmg_box_matrix",
     "ibmg_fiber_force", "ibmg_spread", "ibmg_interp",
+    "ibmg_batch_create", "ibmg_batch_workspace_bytes", "ibmg_batch_bind_workspace", "ibmg_batch_step",
+    "ibmg_batch_set_graph", "ibmg_batch_rounds", "ibmg_batch_destroy",
 ]
 
 
@@ -83,6 +85,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ibmg_fiber_force": [vp, vp, vp],
         "ibmg_spread": [vp, vp, vp, vp, vp],
         "ibmg_interp": [vp, vp, vp, vp, vp],
+        "ibmg_batch_create": [C.POINTER(vp), i32, C.POINTER(ibmg_problem), C.POINTER(ibmg_opts), vp],
+        "ibmg_batch_workspace_bytes": [vp, C.POINTER(sz)],
+        "ibmg_batch_bind_workspace": [vp, vp, sz],
+        "ibmg_batch_step": [vp, C.POINTER(dbl), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                            C.POINTER(vp), C.POINTER(vp), C.POINTER(ibmg_stats)],
+        "ibmg_batch_set_graph": [vp, i32],
+        "ibmg_batch_rounds": [vp, C.POINTER(C.c_int64)],
+        "ibmg_batch_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -141,6 +151,18 @@ class Config:
     colours: int = 2
 
 
+def _problem(cfg: Config, fiber_offsets):
+    """(ibmg_problem, ibmg_opts, keep-alive offsets array, M) of a config."""
+    offs = [int(x) for x in (fiber_offsets if fiber_offsets is not None else [0])]
+    M = offs[-1] if len(offs) > 1 else 0
+    arr = (C.c_int32 * len(offs))(*offs)
+    prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, M, max(0, len(offs) - 1),
+                        C.cast(arr, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
+    opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
+                     cfg.guess, cfg.colours)
+    return prob, opts, arr, M
+
+
 class Solver:
     """One handle plus its torch-owned workspace on `device`."""
 
@@ -148,13 +170,7 @@ class Solver:
         L = lib()
         self.cfg = cfg
         self.device = torch.device(device)
-        offs = [int(x) for x in (fiber_offsets if fiber_offsets is not None else [0])]
-        self.M = offs[-1] if len(offs) > 1 else 0
-        self._offs = (C.c_int32 * len(offs))(*offs)
-        prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, self.M, max(0, len(offs) - 1),
-                            C.cast(self._offs, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
-        opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
-                         cfg.guess, cfg.colours)
+        prob, opts, self._offs, self.M = _problem(cfg, fiber_offsets)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         _check(L.ibmg_create(C.byref(h), C.byref(prob), C.byref(opts),
@@ -270,3 +286,74 @@ class Solver:
         ms, n, by = C.c_double(), C.c_int64(), C.c_double()
         _check(lib().ibmg_phase_timing(self.h, C.byref(ms), C.byref(n), C.byref(by)), "ibmg_phase_timing")
         return dict(total_ms=ms.value, launches=n.value, bytes=by.value)
+
+
+class Batch:
+    """A batch handle (ibmg_batch_*) over several problems plus its workspace."""
+
+    def __init__(self, cfgs, fiber_offsets, device="cuda:0", stream=None):
+        L = lib()
+        self.cfgs = list(cfgs)
+        self.device = torch.device(device)
+        P = len(self.cfgs)
+        parts = [_problem(c, o) for c, o in zip(self.cfgs, fiber_offsets)]
+        self._keep = [pt[2] for pt in parts]
+        self.M = [pt[3] for pt in parts]
+        probs = (ibmg_problem * P)(*[pt[0] for pt in parts])
+        opts = (ibmg_opts * P)(*[pt[1] for pt in parts])
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.ibmg_batch_create(C.byref(h), P, probs, opts, C.c_void_p(self.stream.cuda_stream)),
+               "ibmg_batch_create")
+        self.h = h
+        nbytes = C.c_size_t()
+        _check(L.ibmg_batch_workspace_bytes(h, C.byref(nbytes)), "ibmg_batch_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        _check(L.ibmg_batch_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value),
+               "ibmg_batch_bind_workspace")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ibmg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ptrs(ts, allow_none=False):
+        arr = (C.c_void_p * len(ts))()
+        for i, t in enumerate(ts):
+            if t is None:
+                if not allow_none:
+                    raise ValueError("device tensor expected")
+                arr[i] = None
+            else:
+                arr[i] = _ptr(t).value
+        return arr
+
+    def step(self, dts, us, vs, ps, Xs, g_us=None, g_vs=None):
+        P = len(self.cfgs)
+        dt = (C.c_double * P)(*[float(x) for x in dts])
+        st = (ibmg_stats * P)()
+        gu = self._ptrs(g_us, True) if g_us is not None else None
+        gv = self._ptrs(g_vs, True) if g_vs is not None else None
+        code = _check(lib().ibmg_batch_step(self.h, dt, self._ptrs(us), self._ptrs(vs), self._ptrs(ps),
+                                            self._ptrs(Xs, True), gu, gv, st), "ibmg_batch_step")
+        out = []
+        for i in range(P):
+            d = st[i].as_dict()
+            d["status"] = code
+            out.append(d)
+        return out
+
+    def set_graph(self, on=True):
+        _check(lib().ibmg_batch_set_graph(self.h, 1 if on else 0), "ibmg_batch_set_graph")
+
+    def rounds(self):
+        n = C.c_int64()
+        _check(lib().ibmg_batch_rounds(self.h, C.byref(n)), "ibmg_batch_rounds")
+        return n.value

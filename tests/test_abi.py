@@ -99,3 +99,40 @@ def test_status_strings():
     _, L = _lib()
     for code in (0, 1, -1, -2, -3, -4, -5, -6, 99):
         assert L.ibmg_status_string(code).decode()
+
+
+def test_batch_create_validates_without_gpu():
+    ibmg, L = _lib()
+    offs = [(C.c_int32 * 2)(0, 40), (C.c_int32 * 2)(0, 80)]
+
+    def make(Ns, precs, levels):
+        probs = (ibmg.ibmg_problem * len(Ns))(*[
+            ibmg.ibmg_problem(N, 1.0, 1.0, o[1], 1, C.cast(o, C.POINTER(C.c_int32)), 1e3, 0)
+            for N, o in zip(Ns, offs)])
+        opts = (ibmg.ibmg_opts * len(Ns))(*[ibmg.ibmg_opts(lv, 4, 2, 2, 100, 1e-8, pr, 0, 2)
+                                            for pr, lv in zip(precs, levels)])
+        h = C.c_void_p()
+        return L.ibmg_batch_create(C.byref(h), len(Ns), probs, opts, None), h
+
+    rc, h = make([32, 64], [0, 0], [4, 5])
+    assert rc == 0
+    n = C.c_size_t()
+    assert L.ibmg_batch_workspace_bytes(h, C.byref(n)) == 0
+    # the batch holds at least the two problems' own workspaces
+    need = 0
+    for N, lv in ((32, 4), (64, 5)):
+        rc1, h1, _ = _create(N=N, levels=lv, offs=(0, 40 if N == 32 else 80))
+        n1 = C.c_size_t()
+        L.ibmg_workspace_bytes(h1, C.byref(n1))
+        need += n1.value
+        L.ibmg_destroy(h1)
+    assert n.value >= need
+    # unbound -> ENOMEM before any device work
+    one = (C.c_double * 2)(1e-3, 1e-3)
+    ptrs = (C.c_void_p * 2)()
+    assert L.ibmg_batch_step(h, one, ptrs, ptrs, ptrs, ptrs, None, None, None) == -4
+    assert L.ibmg_batch_destroy(h) == 0
+    assert make([32, 64], [0, 1], [4, 5])[0] == -1   # mixed V-cycle precision
+    assert make([32, 48], [0, 0], [4, 5])[0] == -2   # one bad grid
+    h = C.c_void_p()
+    assert L.ibmg_batch_create(C.byref(h), 0, None, None, None) == -1
