@@ -46,6 +46,8 @@ def workloads(name):
         return [ibgen.config_c5()], [load_dt("c5")[0]["dt"]]
     if name == "c3":
         return [ibgen.config_c3()], [load_dt("c3")[0]["dt"]]
+    if name == "c4":
+        return ibgen.config_c4(), [d["dt"] for d in load_dt("c4")]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -75,6 +77,62 @@ class Run:
 
     def step(self):
         return self.s.step(self.dt, self.u, self.v, self.p, self.X, self.gu, self.gv)
+
+
+class BatchRun:
+    """Every trajectory of the workload in one batch handle."""
+
+    def __init__(self, ws, dts, prec, dev):
+        import torch
+        from paper_1311_5614_amd import ibmg
+        self.ws, self.dts = ws, dts
+        cfgs = [ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
+                            nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2))
+                for w in ws]
+        self.b = ibmg.Batch(cfgs, [w.fiber_offsets for w in ws], dev)
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+        self.X0 = [t(w.X) for w in ws]
+        self.g = [(t(w.g_u), t(w.g_v)) if w.g_u is not None else (None, None) for w in ws]
+        z = lambda w: torch.zeros(w.N, w.N, dtype=torch.float64, device=dev)
+        self.u = [z(w) for w in ws]
+        self.v = [z(w) for w in ws]
+        self.p = [z(w) for w in ws]
+        self.X = [x.clone() for x in self.X0]
+
+    def reset(self):
+        for a in self.u + self.v + self.p:
+            a.zero_()
+        for x, x0 in zip(self.X, self.X0):
+            x.copy_(x0)
+
+    def step(self):
+        return self.b.step(self.dts, self.u, self.v, self.p, self.X, [g[0] for g in self.g],
+                           [g[1] for g in self.g])
+
+
+def timed_batch(br, steps, warmup):
+    import torch
+    br.reset()
+    for _ in range(warmup):
+        br.step()
+    br.reset()
+    torch.cuda.synchronize()
+    its, conv = [], []
+    r0 = br.b.rounds()
+    phases = [0.0, 0.0, 0.0]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = br.step()
+        for st in out:
+            its.append(st["iters"])
+            conv.append(st["converged"])
+        phases[0] += out[0]["t_setup_ms"]
+        phases[1] += out[0]["t_solve_ms"]
+        phases[2] += out[0]["t_step_ms"]
+    torch.cuda.synchronize()
+    print(f"[bench] batch host phases per step: setup {phases[0] / steps:.1f} ms, solve {phases[1] / steps:.1f} ms, "
+          f"step {phases[2] / steps:.1f} ms", file=sys.stderr, flush=True)
+    return time.perf_counter() - t0, its, conv, br.b.rounds() - r0
 
 
 def timed(runs, steps, warmup, timing=False):
@@ -158,6 +216,20 @@ def main():
     forms = args.forms.split(",")
     res = {}
     for form in forms:
+        if form.startswith("batch"):
+            # all trajectories in one batch handle: "batch" = FP32 V-cycle, "batch64" = FP64
+            prec = ibmg.IBMG_FP64 if form == "batch64" else ibmg.IBMG_FP32
+            br = BatchRun(cases, dts, prec, dev)
+            t, its, conv, rounds = timed_batch(br, args.steps, args.warmup)
+            n = args.steps * len(cases)
+            res[form] = dict(time_s=t, timesteps=n, rate=n / t, iters_mean=sum(its) / len(its), iters_max=max(its),
+                             converged=sum(conv), rounds=rounds, phase=None)
+            print(f"[bench] {form}: {n} steps in {t:.3f} s -> {n / t:.2f} steps/s, iters mean "
+                  f"{res[form]['iters_mean']:.2f} max {max(its)}, converged {sum(conv)}/{n}, {rounds} lockstep "
+                  f"rounds", file=sys.stderr, flush=True)
+            del br
+            torch.cuda.empty_cache()
+            continue
         prec = ibmg.IBMG_FP32 if form == "fp32" else ibmg.IBMG_FP64
         runs = [Run(w, dt, prec, dev) for w, dt in zip(cases, dts)]
         t, its, conv, _ = timed(runs, args.steps, args.warmup, timing=False)
@@ -173,9 +245,9 @@ def main():
               flush=True)
         del runs
         torch.cuda.empty_cache()
-    chosen = "fp32" if "fp32" in res else forms[0]
+    chosen = next((f for f in ("batch", "fp32") if f in res), forms[0])
     rc = res[chosen]
-    ph = rc["phase"]
+    ph = next((res[f]["phase"] for f in (chosen, "fp32", "plain") if f in res and res[f]["phase"]), None)
     achieved = ph["bytes"] / (ph["total_ms"] * 1e-3) / 1e9 if ph and ph["total_ms"] > 0 else None
     w0 = cases[0]
     out = {

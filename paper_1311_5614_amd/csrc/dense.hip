@@ -10,6 +10,7 @@
 // to every other column.  Each V-cycle applies the inverse as a matrix-vector
 // product.
 #include "common.h"
+#include "gj.h"
 #include "kernels.h"
 
 #define PW 16   // panel width
@@ -198,6 +199,24 @@ k_coarse_apply(const double* __restrict__ ainv, int nr, const T* __restrict__ b,
   if (lane == 0) w[row] = (T)acc;
 }
 
+// Small bordered systems (nr <= IBMG_MAX_NDOF, e.g. the 4 x 4 coarsest grid):
+// the whole augmented matrix in LDS, inverted by one workgroup.
+__global__ void __launch_bounds__(128)
+k_coarse_small(const double* __restrict__ aug, int nr, double* __restrict__ ainv) {
+  __shared__ double a[IBMG_MAX_NDOF * 2 * IBMG_MAX_NDOF];
+  __shared__ double colk[IBMG_MAX_NDOF];
+  __shared__ int piv;
+  __shared__ double pval;
+  const int ld = 2 * nr;
+  for (int idx = threadIdx.x; idx < nr * ld; idx += blockDim.x) a[idx] = aug[idx];
+  __syncthreads();
+  gauss_jordan_cols(a, nr, ld, colk, &piv, &pval);
+  for (int idx = threadIdx.x; idx < nr * nr; idx += blockDim.x) {
+    const int r = idx / nr, c = idx - r * nr;
+    ainv[idx] = a[r * ld + nr + c];
+  }
+}
+
 namespace ibmg {
 
 void launch_coarse_assemble(hipStream_t s, const LevelView<double>& L, double* aug, int nr) {
@@ -207,6 +226,10 @@ void launch_coarse_assemble(hipStream_t s, const LevelView<double>& L, double* a
 int coarse_factor(hipStream_t s, double* aug, int nr, double* m, int* piv, double* dpiv, int* rowpos,
                   int* used, double* Y, double* ainv) {
   (void)dpiv;
+  if (nr <= IBMG_MAX_NDOF) {
+    k_coarse_small<<<1, 128, 0, s>>>(aug, nr, ainv);
+    return 0;
+  }
   const size_t lds = (size_t)nr * PW * sizeof(double) + (size_t)nr * sizeof(int);
   if (lds > 65536 && hipFuncSetAttribute((const void*)k_coarse_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)lds) != hipSuccess)

@@ -8,6 +8,7 @@
 // (Sec. 3.2); box relaxation blocks (Sec. 5-6); plain boxes share one factor
 // while boxes near the structure get their own, re-formed every step (Sec. 8).
 #include "common.h"
+#include "gj.h"
 #include "kernels.h"
 
 // ---------------------------------------------------------------- a1: G = K L X
@@ -219,24 +220,31 @@ __device__ inline int wrap_half(int d, int N) {   // periodic offset into (-N/2,
 
 // Finest level: row f of M_0 = -dt K S_0 L S^* (S_0 = W / h^2, S^* = W^T):
 // kappa * sum over points k covering f of W_k(f) * sum_{k'} L_{k k'} W_{k'}.
-// One thread per active row, window accumulated in LDS, points in ascending
-// id order from the face's box list.  flags[0] |= 1 if a nonzero falls
-// outside the window.
-__global__ void __launch_bounds__(64)
+// One wavefront per active row; lane t owns window entries t and t + 64 and
+// gathers, for each point of the face's box list (ascending id) and each of
+// its three fibre neighbours, the one patch entry that lands on it.  Every
+// entry therefore sums its terms in (point, neighbour) order.  flags[0] |= 1
+// if a nonzero falls outside the window.
+__global__ void __launch_bounds__(256)
 k_win0(PointView P, const int* __restrict__ rows, const int* __restrict__ nact, int maxact, double kappa,
        int reach, double* __restrict__ win, int* __restrict__ flags) {
-  __shared__ double acc[64 * IBMG_WS];
   const int comp = blockIdx.y;
-  const int row = blockIdx.x * 64 + threadIdx.x;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (row >= maxact || row >= nact[comp]) return;
-  double* a = acc + threadIdx.x * IBMG_WS;
-  for (int q = 0; q < IBMG_WS; ++q) a[q] = 0.0;
   const int N = P.N, msk = N - 1;
   const int f = rows[comp * maxact + row];
   const int i = f % N, j = f / N;
   const int box = (j / P.n) * P.nb + (i / P.n);
   const int* org = P.org + comp * P.M * 2;
   const double* wts = P.wts + (size_t)comp * P.M * IBMG_PATCH;
+  const int q1 = lane + 64;
+  const bool has1 = q1 < IBMG_WS;
+  const int dx0 = lane % IBMG_WW - IBMG_WR, dy0 = lane / IBMG_WW - IBMG_WR;
+  const int dx1 = q1 % IBMG_WW - IBMG_WR, dy1 = q1 / IBMG_WW - IBMG_WR;
+  const bool in0 = dx0 >= -reach && dx0 <= reach && dy0 >= -reach && dy0 <= reach;
+  const bool in1 = has1 && dx1 >= -reach && dx1 <= reach && dy1 >= -reach && dy1 <= reach;
+  double acc0 = 0.0, acc1 = 0.0;
   int bad = 0;
   for (int q = P.box_start[box]; q < P.box_start[box + 1]; ++q) {
     const int k = P.box_list[q];
@@ -248,78 +256,119 @@ k_win0(PointView P, const int* __restrict__ rows, const int* __restrict__ nact, 
     for (int s = 0; s < 3; ++s) {
       const int kk = nbk[s];
       const int oi = org[2 * kk], oj = org[2 * kk + 1];
-      for (int e = 0; e < 16; ++e) {
-        const double val = bk * lc[s] * wts[kk * IBMG_PATCH + e];
-        const int dx = wrap_half(oi + (e & 3) - i, N), dy = wrap_half(oj + (e >> 2) - j, N);
-        if (dx >= -reach && dx <= reach && dy >= -reach && dy <= reach)
-          a[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR] += val;
-        else if (val != 0.0)
-          bad = 1;
+      const double* wk = wts + kk * IBMG_PATCH;
+      const double bl = bk * lc[s];
+      if (in0) {
+        const int ex = (i + dx0 - oi) & msk, ey = (j + dy0 - oj) & msk;
+        if (ex < 4 && ey < 4 && wrap_half(oi + ex - i, N) == dx0 && wrap_half(oj + ey - j, N) == dy0)
+          acc0 += bl * wk[ey * 4 + ex];
+      }
+      if (in1) {
+        const int ex = (i + dx1 - oi) & msk, ey = (j + dy1 - oj) & msk;
+        if (ex < 4 && ey < 4 && wrap_half(oi + ex - i, N) == dx1 && wrap_half(oj + ey - j, N) == dy1)
+          acc1 += bl * wk[ey * 4 + ex];
+      }
+      if (lane < 16) {   // does patch entry `lane` fall outside the window?
+        const double val = bl * wk[lane];
+        const int dx = wrap_half(oi + (lane & 3) - i, N), dy = wrap_half(oj + (lane >> 2) - j, N);
+        if ((dx < -reach || dx > reach || dy < -reach || dy > reach) && val != 0.0) bad = 1;
       }
     }
   }
   double* o = win + ((size_t)comp * maxact + row) * IBMG_WS;
-  for (int q = 0; q < IBMG_WS; ++q) o[q] = a[q];
+  o[lane] = acc0;
+  if (has1) o[q1] = acc1;
   if (bad) atomicOr(flags, 1);
 }
 
 // Level l -> l+1: row F of R M_l P.  For each fine row f of the restriction
 // stencil of F (weight rw) and each window entry g = f + d of that row, the
 // coefficient goes to the coarse faces G of the bilinear prolongation stencil
-// of g (weight pw) at offset G - F, all on unwrapped indices.
-__global__ void __launch_bounds__(64)
-k_win_coarse(int Nc, const int* __restrict__ act_f, const double* __restrict__ win_f, int maxact_f, int reach_f,
-             const int* __restrict__ rows, const int* __restrict__ nact, int maxact, int reach,
-             double* __restrict__ win, int* __restrict__ flags) {
-  __shared__ double acc[64 * IBMG_WS];
-  const int comp = blockIdx.y;
-  const int row = blockIdx.x * 64 + threadIdx.x;
-  if (row >= maxact || row >= nact[comp]) return;
-  double* a = acc + threadIdx.x * IBMG_WS;
-  for (int q = 0; q < IBMG_WS; ++q) a[q] = 0.0;
-  const int Nf = 2 * Nc, NNf = Nf * Nf, mf = Nf - 1;
-  const int F = rows[comp * maxact + row];
-  const int FX = F % Nc, FY = F / Nc;
-  const int* af = act_f + comp * NNf;
+// of g (weight pw) at offset G - F, all on unwrapped indices.  One wavefront
+// per coarse row; lane t owns coarse entries t and t + 64 and gathers the
+// fine entries g whose prolongation reaches it (normal index 2G-1..2G+1,
+// tangential 2G-1..2G+2), fine rows in stencil order and g in row-major
+// order within each.  flags[0] |= 2 if a contribution falls outside the
+// coarse window.
+__device__ inline double win_coarse_entry(int comp, int FX, int FY, int ox, int oy, const int* __restrict__ af,
+                                          const double* __restrict__ win_f, int maxact_f, int reach_f, int Nf) {
+  const int mf = Nf - 1;
   const double wr[3] = {0.125, 0.25, 0.125};
-  int bad = 0;
+  const int GX = FX + ox, GY = FY + oy;
+  const int gn0 = 2 * (comp == 0 ? GX : GY), gt0 = 2 * (comp == 0 ? GY : GX);
+  double acc = 0.0;
   for (int d = -1; d <= 1; ++d)
     for (int e = 0; e <= 1; ++e) {
-      const int fx = comp == 0 ? 2 * FX + d : 2 * FX + e;   // unwrapped fine row
+      const int fx = comp == 0 ? 2 * FX + d : 2 * FX + e;
       const int fy = comp == 0 ? 2 * FY + e : 2 * FY + d;
       const int ar = af[(fy & mf) * Nf + (fx & mf)];
       if (ar < 0) continue;
       const double rw = wr[d + 1];
       const double* cw = win_f + ((size_t)comp * maxact_f + ar) * IBMG_WS;
-      for (int dy = -reach_f; dy <= reach_f; ++dy)
-        for (int dx = -reach_f; dx <= reach_f; ++dx) {
+      // g in row-major (gy outer) order
+      const int ylo = comp == 0 ? gt0 - 1 : gn0 - 1, yhi = comp == 0 ? gt0 + 2 : gn0 + 1;
+      const int xlo = comp == 0 ? gn0 - 1 : gt0 - 1, xhi = comp == 0 ? gn0 + 1 : gt0 + 2;
+      for (int gy = ylo; gy <= yhi; ++gy) {
+        const int dy = gy - fy;
+        if (dy < -reach_f || dy > reach_f) continue;
+        for (int gx = xlo; gx <= xhi; ++gx) {
+          const int dx = gx - fx;
+          if (dx < -reach_f || dx > reach_f) continue;
           const double val = rw * cw[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR];
           if (val == 0.0) continue;
-          const int gx = fx + dx, gy = fy + dy;
-          // prolongation stencil of fine face g: normal direction (x for u)
           const int gn = comp == 0 ? gx : gy, gt = comp == 0 ? gy : gx;
-          int cn[2], ct[2];
-          double wn[2], wt[2];
-          int nn;
-          if ((gn & 1) == 0) { cn[0] = gn >> 1; wn[0] = 1.0; nn = 1; }
-          else { cn[0] = (gn - 1) >> 1; cn[1] = (gn + 1) >> 1; wn[0] = wn[1] = 0.5; nn = 2; }
-          const int t0 = gt >> 1;
-          ct[0] = t0; wt[0] = 0.75;
-          ct[1] = (gt & 1) == 0 ? t0 - 1 : t0 + 1; wt[1] = 0.25;
-          for (int x = 0; x < nn; ++x)
-            for (int y = 0; y < 2; ++y) {
-              const int GX = comp == 0 ? cn[x] : ct[y], GY = comp == 0 ? ct[y] : cn[x];
-              const int ox = GX - FX, oy = GY - FY;
-              const double v = val * wn[x] * wt[y];
-              if (ox >= -reach && ox <= reach && oy >= -reach && oy <= reach)
-                a[(oy + IBMG_WR) * IBMG_WW + ox + IBMG_WR] += v;
-              else
-                bad = 1;
-            }
+          const double wn = gn == gn0 ? 1.0 : 0.5;
+          const double wt = (gt == gt0 || gt == gt0 + 1) ? 0.75 : 0.25;
+          acc += val * wn * wt;
         }
+      }
     }
+  return acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_win_coarse(int Nc, const int* __restrict__ act_f, const double* __restrict__ win_f, int maxact_f, int reach_f,
+             const int* __restrict__ rows, const int* __restrict__ nact, int maxact, int reach,
+             double* __restrict__ win, int* __restrict__ flags) {
+  const int comp = blockIdx.y;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= maxact || row >= nact[comp]) return;
+  const int Nf = 2 * Nc, NNf = Nf * Nf, mf = Nf - 1;
+  const int F = rows[comp * maxact + row];
+  const int FX = F % Nc, FY = F / Nc;
+  const int* af = act_f + comp * NNf;
+  const int q1 = lane + 64;
+  const bool has1 = q1 < IBMG_WS;
+  const int dx0 = lane % IBMG_WW - IBMG_WR, dy0 = lane / IBMG_WW - IBMG_WR;
+  const int dx1 = q1 % IBMG_WW - IBMG_WR, dy1 = q1 / IBMG_WW - IBMG_WR;
+  double acc0 = 0.0, acc1 = 0.0;
+  if (dx0 >= -reach && dx0 <= reach && dy0 >= -reach && dy0 <= reach)
+    acc0 = win_coarse_entry(comp, FX, FY, dx0, dy0, af, win_f, maxact_f, reach_f, Nf);
+  if (has1 && dx1 >= -reach && dx1 <= reach && dy1 >= -reach && dy1 <= reach)
+    acc1 = win_coarse_entry(comp, FX, FY, dx1, dy1, af, win_f, maxact_f, reach_f, Nf);
   double* o = win + ((size_t)comp * maxact + row) * IBMG_WS;
-  for (int q = 0; q < IBMG_WS; ++q) o[q] = a[q];
+  o[lane] = acc0;
+  if (has1) o[q1] = acc1;
+  // window check: every nonzero fine entry's prolongation targets
+  int bad = 0;
+  for (int d = -1; d <= 1; ++d)
+    for (int e = 0; e <= 1; ++e) {
+      const int fx = comp == 0 ? 2 * FX + d : 2 * FX + e;
+      const int fy = comp == 0 ? 2 * FY + e : 2 * FY + d;
+      const int ar = af[(fy & mf) * Nf + (fx & mf)];
+      if (ar < 0) continue;
+      const double* cw = win_f + ((size_t)comp * maxact_f + ar) * IBMG_WS;
+      for (int q = lane; q < IBMG_WS; q += 64) {
+        const int dx = q % IBMG_WW - IBMG_WR, dy = q / IBMG_WW - IBMG_WR;
+        if (dx < -reach_f || dx > reach_f || dy < -reach_f || dy > reach_f || cw[q] == 0.0) continue;
+        const int gn = comp == 0 ? fx + dx : fy + dy, gt = comp == 0 ? fy + dy : fx + dx;
+        const int n0 = gn >> 1, n1 = (gn + 1) >> 1;               // coarse normal indices reached
+        const int t0 = (gt >> 1) - ((gt & 1) == 0 ? 1 : 0), t1 = (gt >> 1) + ((gt & 1) == 0 ? 0 : 1);
+        const int Fn = comp == 0 ? FX : FY, Ft = comp == 0 ? FY : FX;
+        if (n0 - Fn < -reach || n1 - Fn > reach || t0 - Ft < -reach || t1 - Ft > reach) bad = 1;
+      }
+    }
   if (bad) atomicOr(flags, 2);
 }
 
@@ -433,55 +482,15 @@ __device__ void assemble_box(const LevelView<double>& L, int bx, int by, bool wi
   }
 }
 
-// Gauss-Jordan with partial pivoting on [A | I] in LDS (ties -> lowest row).
-__device__ void gauss_jordan_lds(double* a, int nd, int ld, double* colk, int* piv) {
-  const int tid = threadIdx.x;
-  for (int k = 0; k < nd; ++k) {
-    if (tid < 64) {
-      double bv = -1.0;
-      int bi = nd;
-      for (int i = k + tid; i < nd; i += 64) {
-        const double v = fabs(a[i * ld + k]);
-        if (v > bv) { bv = v; bi = i; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
-      if (tid == 0) *piv = bi;
-    }
-    __syncthreads();
-    const int p = *piv;
-    if (p != k)
-      for (int c = tid; c < ld; c += blockDim.x) {
-        const double t = a[k * ld + c];
-        a[k * ld + c] = a[p * ld + c];
-        a[p * ld + c] = t;
-      }
-    __syncthreads();
-    const double inv = 1.0 / a[k * ld + k];
-    __syncthreads();
-    for (int c = tid; c < ld; c += blockDim.x) a[k * ld + c] *= inv;
-    for (int i = tid; i < nd; i += blockDim.x)
-      if (i != k) colk[i] = a[i * ld + k];
-    __syncthreads();
-    for (int idx = tid; idx < nd * ld; idx += blockDim.x) {
-      const int i = idx / ld, c = idx - i * ld;
-      if (i != k && c >= k) a[idx] -= colk[i] * a[k * ld + c];
-    }
-    __syncthreads();
-  }
-}
-
 // Block 0: the plain box (Stokes only, shared by every box without elastic
 // rows).  Block 1 + q: box ib_boxes[q].  Inverses are written column-major.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(128)
 k_box_factor(LevelView<double> L, const int* __restrict__ ib_boxes, double* __restrict__ ainv_plain,
              float* __restrict__ ainv_plain_f, double* __restrict__ ainv_ib) {
   __shared__ double a[IBMG_MAX_NDOF * 2 * IBMG_MAX_NDOF];
   __shared__ double colk[IBMG_MAX_NDOF];
   __shared__ int piv;
+  __shared__ double pval;
   const int nd = L.ndof, ld = 2 * nd;
   const bool plain = blockIdx.x == 0;
   int bx = 0, by = 0;
@@ -497,7 +506,7 @@ k_box_factor(LevelView<double> L, const int* __restrict__ ib_boxes, double* __re
   __syncthreads();
   assemble_box(L, bx, by, !plain, a, ld);
   __syncthreads();
-  gauss_jordan_lds(a, nd, ld, colk, &piv);
+  gauss_jordan_cols(a, nd, ld, colk, &piv, &pval);
   double* out = plain ? ainv_plain : ainv_ib + (size_t)(blockIdx.x - 1) * nd * nd;
   for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) {
     const int r = idx / nd, c = idx - r * nd;
@@ -568,14 +577,14 @@ void launch_active(hipStream_t s, int level, int M, int N, const int* org, const
 
 void launch_windows0(hipStream_t s, const PointView& P, const int* rows, const int* nact, int maxact, double kappa,
                      int reach, double* win, int* flags) {
-  dim3 g((unsigned)((maxact + 63) / 64), 2);
-  k_win0<<<g, 64, 0, s>>>(P, rows, nact, maxact, kappa, reach, win, flags);
+  dim3 g((unsigned)((maxact + 3) / 4), 2);
+  k_win0<<<g, 256, 0, s>>>(P, rows, nact, maxact, kappa, reach, win, flags);
 }
 
 void launch_windows_coarse(hipStream_t s, int Nc, const int* act_f, const double* win_f, int maxact_f, int reach_f,
                            const int* rows, const int* nact, int maxact, int reach, double* win, int* flags) {
-  dim3 g((unsigned)((maxact + 63) / 64), 2);
-  k_win_coarse<<<g, 64, 0, s>>>(Nc, act_f, win_f, maxact_f, reach_f, rows, nact, maxact, reach, win, flags);
+  dim3 g((unsigned)((maxact + 3) / 4), 2);
+  k_win_coarse<<<g, 256, 0, s>>>(Nc, act_f, win_f, maxact_f, reach_f, rows, nact, maxact, reach, win, flags);
 }
 
 void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int* flag, int* ib_index,
@@ -587,7 +596,7 @@ void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int
 
 void launch_box_factor(hipStream_t s, const LevelView<double>& L, const int* ib_boxes, int n_ib,
                        double* ainv_plain, float* ainv_plain_f, double* ainv_ib) {
-  k_box_factor<<<1 + n_ib, 256, 0, s>>>(L, ib_boxes, ainv_plain, ainv_plain_f, ainv_ib);
+  k_box_factor<<<1 + n_ib, 128, 0, s>>>(L, ib_boxes, ainv_plain, ainv_plain_f, ainv_ib);
 }
 
 void launch_box_matrix(hipStream_t s, const LevelView<double>& L, int bx, int by, double* out) {

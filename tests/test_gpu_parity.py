@@ -135,10 +135,13 @@ def test_smooth_parity(box, colours):
 
 # ---------------------------------------------------------------- a7, a12: coarse solve, V-cycle
 
-def test_coarse_solve_parity():
-    w, dt, s = make(N=64, levels=3, M=120, K=1e5, dt_factor=100.0)
+@pytest.mark.parametrize("N,levels", [(64, 3), (32, 3), (32, 4)])
+def test_coarse_solve_parity(N, levels):
+    # coarsest 16^2 and 8^2 take the blocked panel inverse, 4^2 the
+    # single-workgroup inverse
+    w, dt, s = make(N=N, levels=levels, M=120 if N == 64 else 60, K=1e5, dt_factor=100.0)
     _setup(s, w, dt)
-    lv = oracle_levels(w, dt, 3, 1e5)
+    lv = oracle_levels(w, dt, levels, 1e5)
     V = mg.VCycle(lv, 4, 2, 2)
     Nc = lv[-1].N
     b = np.random.default_rng(8).standard_normal(3 * Nc * Nc)
