@@ -59,7 +59,8 @@ class Run:
         from paper_1311_5614_amd import ibmg
         self.w, self.dt = w, dt
         cfg = ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
-                          nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2))
+                          nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
+                          tail_max=getattr(w, "tail_max", 0))
         self.s = ibmg.Solver(cfg, w.fiber_offsets, dev)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
         self.X0 = t(w.X)
@@ -87,7 +88,8 @@ class BatchRun:
         from paper_1311_5614_amd import ibmg
         self.ws, self.dts = ws, dts
         cfgs = [ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
-                            nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2))
+                            nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
+                            tail_max=getattr(w, "tail_max", 0))
                 for w in ws]
         self.b = ibmg.Batch(cfgs, [w.fiber_offsets for w in ws], dev)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
@@ -198,7 +200,19 @@ def main():
     ap.add_argument("--levels", type=int, default=0, help="override the workload's level count")
     ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
     ap.add_argument("--colours", type=int, default=2)
+    ap.add_argument("--tail-max", type=int, default=0, help="override the V-cycle tail size")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy a device buffer of this many MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 5}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
                                    "described in DESIGN.md, not implemented)"}))
@@ -213,6 +227,8 @@ def main():
         if args.nu:
             c.nu1, c.nu2 = (int(x) for x in args.nu.split(","))
         c.colours = args.colours
+        if args.tail_max:
+            c.tail_max = args.tail_max
     forms = args.forms.split(",")
     res = {}
     for form in forms:
@@ -273,7 +289,7 @@ def main():
         },
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "phase"} for k, v in res.items()},
         "roofline": {
-            "kernel": "k_phase (box relaxation, one colour)",
+            "kernel": "k_box (box relaxation, one colour phase)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -94,6 +94,13 @@ typedef struct {
                           4 = (bx mod 2, by mod 2) in the order (0,0),(1,0),(0,1),(1,1);
                           within a colour every box solves from the residual at
                           the start of that colour                                  */
+  int32_t tail_max;    /* V-cycle schedule: levels of at most tail_max cells per
+                          side (and the coarsest) run in one LDS-resident
+                          workgroup, larger ones as grid-wide launches; 0 = 32,
+                          else a power of two 1..32 (1: only the coarsest solve,
+                          then as a grid-wide matrix-vector product).  Changes
+                          the launch schedule and the summation order of the
+                          elastic rows, not the method.                         */
 } ibmg_opts;
 
 typedef struct {

@@ -187,10 +187,10 @@ void vcycle(ibmg_handle* h, const T* b0, T* w0) {
     b[l] = l == 0 ? b0 : h->p<T>(h->L[l].b);
     r[l] = h->p<T>(h->L[l].r);
   }
-  // levels ls.. (at most kSmallLevel cells per side, plus the coarsest) run in
-  // one LDS-resident workgroup
-  int ls = Lv - 1;
-  while (ls > 0 && v[ls - 1].N <= kSmallLevel) --ls;
+  // levels ls.. (at most tail_max cells per side, plus the coarsest) run in
+  // one LDS-resident workgroup; a tail of the coarsest level alone is its
+  // matrix-vector product, spread over the grid
+  const int ls = tail_start(h);
   if (ls > 0) {
     const size_t n3 = 3 * (size_t)v[0].N * v[0].N;
     k_fill<T><<<nblk(n3), 256, 0, s>>>(w[0], n3, T(0));
@@ -200,7 +200,9 @@ void vcycle(ibmg_handle* h, const T* b0, T* w0) {
     launch_residual<T>(s, v[l], b[l], w[l], r[l], h->has_ib);
     launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b), w[l + 1]);   // also zeroes w[l+1]
   }
-  if (launch_tail<T>(s, v, ls, Lv, h->nu1, h->nu2, h->has_ib, h->nr, b[ls], w[ls], h->p<double>(h->cainv)) != 0)
+  if (ls == Lv - 1)
+    launch_coarse_apply<T>(s, h->p<double>(h->cainv), h->nr, b[ls], w[ls]);
+  else if (launch_tail<T>(s, v, ls, Lv, h->nu1, h->nu2, h->has_ib, h->nr, b[ls], w[ls], h->p<double>(h->cainv)) != 0)
     h->launch_error = true;
   for (int l = ls - 1; l >= 0; --l) {
     launch_prolong_add<T>(s, v[l].N, w[l + 1], w[l]);
@@ -581,6 +583,8 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   if (op->vcycle_prec != IBMG_FP64 && op->vcycle_prec != IBMG_FP32) return IBMG_EINVAL;
   if (op->guess != IBMG_GUESS_ZERO && op->guess != IBMG_GUESS_PREV) return IBMG_EINVAL;
   if (op->colours != 2 && op->colours != 4) return IBMG_EINVAL;
+  if (op->tail_max != 0 && (op->tail_max < 1 || op->tail_max > kSmallLevel || (op->tail_max & (op->tail_max - 1))))
+    return IBMG_EINVAL;
   if (pr->n_points < 0 || pr->n_fibers < 0) return IBMG_EINVAL;
   if (pr->n_points > 0 && (!pr->fiber_offsets || pr->n_fibers < 1)) return IBMG_EINVAL;
   ibmg_handle* h = new (std::nothrow) ibmg_handle();
@@ -589,6 +593,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   h->rho = pr->rho; h->mu = pr->mu; h->K = pr->K;
   h->levels = op->levels; h->n = op->box; h->nu1 = op->nu1; h->nu2 = op->nu2; h->maxit = op->maxit;
   h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess; h->ncol = op->colours;
+  h->tail_max = op->tail_max ? op->tail_max : kSmallLevel;
   h->stream = (hipStream_t)stream;
   h->prev.assign(h->M, 0);
   h->next.assign(h->M, 0);

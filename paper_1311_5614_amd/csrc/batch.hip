@@ -139,7 +139,7 @@ kb_box(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __res
 template <typename T>
 __global__ void __launch_bounds__(1024) kb_tail(const TailArgs<T>* __restrict__ A, const int* __restrict__ active) {
   if (!active[blockIdx.x]) return;
-  tail_body<T>(A[blockIdx.x]);
+  tail_body_n<T>(A[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------- Krylov kernels (FP64)

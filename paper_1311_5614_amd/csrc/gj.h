@@ -10,7 +10,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-__device__ inline void gauss_jordan_cols(double* a, int nd, int ld, double* colk, int* piv, double* pval) {
+__device__ inline void gauss_jordan_cols(double* __restrict__ a, int nd, int ld, double* __restrict__ colk,
+                                         int* __restrict__ piv, double* __restrict__ pval) {
   const int tid = threadIdx.x;
   for (int k = 0; k < nd; ++k) {
     if (tid < 64) {
@@ -32,17 +33,34 @@ __device__ inline void gauss_jordan_cols(double* a, int nd, int ld, double* colk
       }
     }
     __syncthreads();
-    // columns left of k are already unit columns: row k holds 0 there
+    // columns left of k are already unit columns: row k holds 0 there.  Each
+    // thread updates its own column; rows go eight at a time so that the LDS
+    // accesses of a group are independent.
+    const int p = *piv;
+    const double inv = 1.0 / *pval, ck = colk[k];
     for (int c = k + tid; c < ld; c += blockDim.x) {
-      const int p = *piv;
-      const double inv = 1.0 / *pval;
       const double ak = a[k * ld + c], ap = a[p * ld + c];
       const double nk = ap * inv;
       a[p * ld + c] = ak;
       a[k * ld + c] = nk;
-      for (int i = 0; i < nd; ++i) {
+      int i = 0;
+      for (; i + 8 <= nd; i += 8) {
+        double v[8], f[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          v[u] = a[(i + u) * ld + c];
+          f[u] = colk[i + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int ii = i + u;
+          if (ii == k) continue;
+          a[ii * ld + c] = v[u] - (ii == p ? ck : f[u]) * nk;
+        }
+      }
+      for (; i < nd; ++i) {
         if (i == k) continue;
-        const double f = i == p ? colk[k] : colk[i];
+        const double f = i == p ? ck : colk[i];
         a[i * ld + c] -= f * nk;
       }
     }

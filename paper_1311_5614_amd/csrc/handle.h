@@ -12,7 +12,7 @@ namespace ibmg {
 constexpr int kPW = 16;          // panel width of the coarse Gauss-Jordan (dense.hip)
 constexpr int kDotBlocks = 256;  // workgroups of the deterministic dot products
 constexpr int kMaxTimed = 8192;  // timed phase launches per solve
-constexpr int kSmallLevel = 32;  // levels up to this size run in one workgroup per V-cycle leg
+constexpr int kSmallLevel = 32;  // default (and largest) level size run in one workgroup per V-cycle leg
 
 struct Buf {
   size_t off = 0, bytes = 0;
@@ -38,6 +38,7 @@ struct ibmg_handle {
   // problem and options
   int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 2, nu2 = 2, maxit = 100, prec = 0, guess = 0;
   int ncol = 2;
+  int tail_max = ibmg::kSmallLevel;   // largest level size run by the LDS-resident tail
   double rho = 1, mu = 1, K = 0, rtol = 1e-8;
   std::vector<int> prev, next;
   hipStream_t stream = nullptr;
@@ -127,16 +128,17 @@ inline PointView points(const ibmg_handle* h) {
 }
 
 // First level handled by the LDS-resident tail of the V-cycle: every level
-// from there down has at most kSmallLevel cells per side.
+// from there down has at most tail_max cells per side.
 inline int tail_start(const ibmg_handle* h) {
   int ls = h->levels - 1;
-  while (ls > 0 && h->L[ls - 1].N <= kSmallLevel) --ls;
+  while (ls > 0 && h->L[ls - 1].N <= h->tail_max) --ls;
   return ls;
 }
 
-// Dynamic LDS of the tail: three vectors (nine arrays) per level from ls on.
+// Dynamic LDS of the tail: three vectors (nine arrays) per level from ls on,
+// and one plain-box inverse.
 inline size_t tail_lds(const ibmg_handle* h, size_t elem) {
-  size_t lds = 0;
+  size_t lds = (size_t)h->ndof * h->ndof * elem;
   for (int l = tail_start(h); l < h->levels; ++l) lds += 9 * (size_t)h->L[l].N * h->L[l].N * elem;
   return lds;
 }

@@ -14,11 +14,11 @@
 template <typename T>
 __device__ inline void residual_body(const LevelView<T>& L, const T* __restrict__ b, const T* __restrict__ w,
                                      T* __restrict__ r, int blk) {
-  const int NN = L.N * L.N;
+  const int NN = L.N * L.N, lg = __builtin_ctz(L.N);
   const int idx = blk * 256 + threadIdx.x;
   if (idx >= 3 * NN) return;
-  const int comp = idx / NN, rem = idx - comp * NN;
-  const int j = rem / L.N, i = rem - j * L.N;
+  const int comp = idx >> (2 * lg), rem = idx & (NN - 1);
+  const int j = rem >> lg, i = rem & (L.N - 1);
   const T y = stokes_row(L, w, comp, i, j);
   r[idx] = b ? b[idx] - y : y;
 }
@@ -43,9 +43,13 @@ __device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__
   const T* c = L.win + ((size_t)comp * L.maxact + row) * IBMG_WS;
   const T* x = w + (size_t)comp * NN;
   T acc = T(0);
+  // entries lane, lane + 16, ... of the W x W window, row-major
+  int qy = lane / W, qx = lane - qy * W;
   for (int q = lane; q < W * W; q += 16) {
-    const int dy = q / W - r, dx = q - (q / W) * W - r;
+    const int dy = qy - r, dx = qx - r;
     acc += c[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR] * x[((j + dy) & msk) * N + ((i + dx) & msk)];
+    qx += 16;
+    while (qx >= W) { qx -= W; ++qy; }
   }
   acc += __shfl_xor(acc, 8, 16);
   acc += __shfl_xor(acc, 4, 16);
@@ -71,12 +75,12 @@ __device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__
 template <typename T>
 __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ b, const T* __restrict__ w,
                                    T* __restrict__ r, int nres_blocks, int blk) {
-  const int N = L.N, NN = N * N;
+  const int N = L.N, NN = N * N, lg = __builtin_ctz(N);
   if (blk < nres_blocks) {
     const int idx = blk * 256 + threadIdx.x;
     if (idx >= 3 * NN) return;
-    const int comp = idx / NN, rem = idx - comp * NN;
-    const int j = rem / N, i = rem - j * N;
+    const int comp = idx >> (2 * lg), rem = idx & (NN - 1);
+    const int j = rem >> lg, i = rem & (N - 1);
     r[idx] = b[idx] - stokes_row(L, w, comp, i, j);
     return;
   }
@@ -91,9 +95,12 @@ __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ 
   const T* c = L.win + ((size_t)comp * L.maxact + row) * IBMG_WS;
   const T* x = w + (size_t)comp * NN;
   T acc = T(0);
+  int qy = lane / W, qx = lane - qy * W;
   for (int e = lane; e < W * W; e += 16) {
-    const int dy = e / W - rr, dx = e - (e / W) * W - rr;
+    const int dy = qy - rr, dx = qx - rr;
     acc += c[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR] * x[((j + dy) & msk) * N + ((i + dx) & msk)];
+    qx += 16;
+    while (qx >= W) { qx -= W; ++qy; }
   }
   acc += __shfl_xor(acc, 8, 16);
   acc += __shfl_xor(acc, 4, 16);
@@ -146,11 +153,11 @@ __device__ inline void box_body(const LevelView<T>& L, const T* __restrict__ r, 
 template <typename T>
 __device__ inline void restrict_body(int Nf, const T* __restrict__ rf, T* __restrict__ rc, T* __restrict__ wz,
                                      int blk) {
-  const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf, mf = Nf - 1;
+  const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf, mf = Nf - 1, lgc = __builtin_ctz(Nc);
   const int idx = blk * 256 + threadIdx.x;
   if (idx >= 3 * NNc) return;
-  const int comp = idx / NNc, rem = idx - comp * NNc;
-  const int J = rem / Nc, I = rem - J * Nc;
+  const int comp = idx >> (2 * lgc), rem = idx & (NNc - 1);
+  const int J = rem >> lgc, I = rem & (Nc - 1);
   const T* f = rf + (size_t)comp * NNf;
   T s = T(0);
   if (comp == 0) {
@@ -192,11 +199,11 @@ __device__ inline T bilinear(const T* c, int Nc, int in, int it, bool normal_is_
 
 template <typename T>
 __device__ inline void prolong_body(int Nf, const T* __restrict__ ec, T* __restrict__ wf, int blk) {
-  const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf;
+  const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf, lgf = __builtin_ctz(Nf);
   const int idx = blk * 256 + threadIdx.x;
   if (idx >= 3 * NNf) return;
-  const int comp = idx / NNf, rem = idx - comp * NNf;
-  const int j = rem / Nf, i = rem - j * Nf;
+  const int comp = idx >> (2 * lgf), rem = idx & (NNf - 1);
+  const int j = rem >> lgf, i = rem & (Nf - 1);
   const T* c = ec + (size_t)comp * NNc;
   T add;
   if (comp == 0) add = bilinear(c, Nc, i, j, true);
@@ -248,11 +255,15 @@ __device__ void small_ib_rows(const LevelView<T>& L, const T* __restrict__ w, T*
   }
 }
 
-template <typename T>
+// Ap: the level's plain-box inverse staged in LDS.  The box edge NB is a
+// compile-time constant so that every inverse load of a box solve is issued
+// before the first product needs it.
+template <typename T, int NB>
 __device__ void small_sweep(const LevelView<T>& L, const T* __restrict__ b, T* __restrict__ w, T* __restrict__ r,
-                            bool ib) {
+                            bool ib, const T* __restrict__ Ap) {
   __shared__ double res[16][64];
-  const int N = L.N, NN = N * N, nd = L.ndof;
+  constexpr int nd = 2 * NB * (NB + 1) + NB * NB;
+  const int N = L.N, NN = N * N;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
   for (int colour = 0; colour < L.ncol; ++colour) {
     // residual and elastic rows from the iterate at the start of the colour
@@ -274,7 +285,7 @@ __device__ void small_sweep(const LevelView<T>& L, const T* __restrict__ b, T* _
         colour_box(q, colour, L.ncol, L.nb, bx, by);
         ibx = ib ? L.ib_index[by * L.nb + bx] : -1;
         if (lane < nd) {
-          box_dof(lane, bx, by, L.n, N, comp, i, j);
+          box_dof(lane, bx, by, NB, N, comp, i, j);
           g = (size_t)comp * NN + (size_t)j * N + i;
           T y = r[g];
           if (ibx >= 0 && comp < 2) {
@@ -289,14 +300,13 @@ __device__ void small_sweep(const LevelView<T>& L, const T* __restrict__ b, T* _
         if (ibx >= 0) {
           const double* A = L.ainv_ib + (size_t)ibx * nd * nd;
           double z = 0.0;
-#pragma unroll 8
+#pragma unroll
           for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * res[wave][c];
           w[g] += (T)z;
         } else {
-          const T* A = L.ainv_plain;
           T z = T(0);
 #pragma unroll 8
-          for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * (T)res[wave][c];
+          for (int c = 0; c < nd; ++c) z += Ap[c * nd + lane] * (T)res[wave][c];
           w[g] += z;
         }
       }
@@ -310,6 +320,8 @@ __device__ void small_sweep(const LevelView<T>& L, const T* __restrict__ b, T* _
 // resident in LDS.  Entry: b_ls in global memory (the restricted residual of
 // the level above, or the preconditioner input when ls = 0).  Exit: w_ls in
 // global memory.  Same steps as the per-level kernels (Algorithm 1).
+// Dynamic LDS of the tail: w, b, r of every level from ls down (9 N_l^2
+// values), then one plain-box inverse (nd^2 values).
 template <typename T>
 struct TailArgs {
   LevelView<T> v[IBMG_MAX_LEVELS];
@@ -348,12 +360,21 @@ __device__ void tail_restrict(int N, const T* __restrict__ r, T* __restrict__ bc
   }
 }
 
-template <typename T>
+// Copy level l's plain-box inverse into the LDS slot Ap.
+template <typename T, int NB>
+__device__ inline void stage_plain(const LevelView<T>& L, T* __restrict__ Ap) {
+  constexpr int nd = 2 * NB * (NB + 1) + NB * NB;
+  for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) Ap[idx] = L.ainv_plain[idx];
+  __syncthreads();
+}
+
+template <typename T, int NB>
 __device__ inline void tail_body(const TailArgs<T>& A) {
   extern __shared__ double smem[];
   T* w[IBMG_MAX_LEVELS];
   T* b[IBMG_MAX_LEVELS];
   T* r[IBMG_MAX_LEVELS];
+  T* Ap;
   {
     T* p = reinterpret_cast<T*>(smem);
     for (int l = A.ls; l < A.L; ++l) {
@@ -362,6 +383,7 @@ __device__ inline void tail_body(const TailArgs<T>& A) {
       b[l] = p; p += n3;
       r[l] = p; p += n3;
     }
+    Ap = p;
   }
   const int ib = A.ib;
   {
@@ -375,7 +397,8 @@ __device__ inline void tail_body(const TailArgs<T>& A) {
   for (int l = A.ls; l + 1 < A.L; ++l) {
     const LevelView<T>& L = A.v[l];
     const int N = L.N, NN = N * N;
-    for (int s = 0; s < A.nu1; ++s) small_sweep<T>(L, b[l], w[l], r[l], ib != 0);
+    if (A.nu1 > 0) stage_plain<T, NB>(L, Ap);
+    for (int s = 0; s < A.nu1; ++s) small_sweep<T, NB>(L, b[l], w[l], r[l], ib != 0, Ap);
     for (int idx = threadIdx.x; idx < 3 * NN; idx += blockDim.x) {
       const int comp = idx / NN, rem = idx - comp * NN;
       const int j = rem / N, i = rem - j * N;
@@ -414,7 +437,8 @@ __device__ inline void tail_body(const TailArgs<T>& A) {
       w[l][idx] += add;
     }
     __syncthreads();
-    for (int s = 0; s < A.nu2; ++s) small_sweep<T>(L, b[l], w[l], r[l], ib != 0);
+    if (A.nu2 > 0) stage_plain<T, NB>(L, Ap);
+    for (int s = 0; s < A.nu2; ++s) small_sweep<T, NB>(L, b[l], w[l], r[l], ib != 0, Ap);
   }
   {
     const int n3 = 3 * A.v[A.ls].N * A.v[A.ls].N;
@@ -422,3 +446,11 @@ __device__ inline void tail_body(const TailArgs<T>& A) {
   }
 }
 
+
+template <typename T>
+__device__ inline void tail_body_n(const TailArgs<T>& A) {
+  const int n = A.v[A.ls].n;
+  if (n == 4) tail_body<T, 4>(A);
+  else if (n == 2) tail_body<T, 2>(A);
+  else tail_body<T, 1>(A);
+}

@@ -37,9 +37,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(int Nf, const T* __restrict__ ec, T* __restrict__ wf) {
   prolong_body<T>(Nf, ec, wf, blockIdx.x);
 }
-template <typename T>
+template <typename T, int NB>
 __global__ void __launch_bounds__(1024) k_tail(TailArgs<T> A) {
-  tail_body<T>(A);
+  tail_body<T, NB>(A);
 }
 
 // ---------------------------------------------------------------- a4: right-hand side
@@ -126,19 +126,21 @@ template <typename T> int launch_tail(hipStream_t s, const LevelView<T>* views, 
     if (!ib) A.v[l].ib_index = nullptr;
     if (l >= ls) lds += 9 * (size_t)views[l].N * views[l].N * sizeof(T);
   }
+  lds += (size_t)views[0].ndof * views[0].ndof * sizeof(T);
   A.ls = ls; A.L = L; A.nu1 = nu1; A.nu2 = nu2; A.ib = ib ? 1 : 0; A.nr = nr;
   A.b_in = b_in; A.w_out = w_out; A.cainv = cainv;
-  k_tail<T><<<1, 1024, lds, s>>>(A);
+  if (views[0].n == 4) k_tail<T, 4><<<1, 1024, lds, s>>>(A);
+  else if (views[0].n == 2) k_tail<T, 2><<<1, 1024, lds, s>>>(A);
+  else k_tail<T, 1><<<1, 1024, lds, s>>>(A);
   return 0;
 }
 // Enable the tail kernels' dynamic LDS (up to lds bytes); outside any capture.
 int prepare_tail(size_t lds) {
   if (lds <= 65536) return 0;
-  if (hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-          hipSuccess ||
-      hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-          hipSuccess)
-    return -1;
+  const void* f[6] = {(const void*)k_tail<double, 1>, (const void*)k_tail<double, 2>, (const void*)k_tail<double, 4>,
+                      (const void*)k_tail<float, 1>,  (const void*)k_tail<float, 2>,  (const void*)k_tail<float, 4>};
+  for (const void* k : f)
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -1;
   return 0;
 }
 

@@ -19,13 +19,13 @@ def tnp(t):
 
 
 def make(N=32, levels=3, M=64, K=1e4, dt_factor=20.0, seed=5, box=4, nu=(2, 2), prec=0, n_fibers=1,
-         delta=0, maxit=100, rtol=1e-10, with_force=False, guess=0, colours=2):
+         delta=0, maxit=100, rtol=1e-10, with_force=False, guess=0, colours=2, tail_max=0):
     from paper_1311_5614_amd import ibmg
     w = ibgen.small_case(N=N, M=M, K=K, seed=seed, n_fibers=n_fibers, levels=levels, box=box,
                          with_force=with_force)
     dt = dt_factor * dtexp.dt_explicit(w.X, w.fiber_offsets, N, K, kind=delta) if K > 0 else 0.05
     cfg = ibmg.Config(N=N, levels=levels, K=K, box=box, nu1=nu[0], nu2=nu[1], maxit=maxit, rtol=rtol,
-                      prec=prec, delta=delta, guess=guess, colours=colours)
+                      prec=prec, delta=delta, guess=guess, colours=colours, tail_max=tail_max)
     s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
     return w, dt, s
 

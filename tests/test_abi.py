@@ -42,9 +42,9 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "ibmg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
          offsetof(ibmg_problem, fiber_offsets), offsetof(ibmg_problem, K), offsetof(ibmg_opts, rtol),
-         offsetof(ibmg_stats, t_step_ms), offsetof(ibmg_opts, colours));
+         offsetof(ibmg_stats, t_step_ms), offsetof(ibmg_opts, colours), offsetof(ibmg_opts, tail_max));
   return 0;
 }
 """
@@ -56,7 +56,8 @@ int main(void) {
         got = list(map(int, subprocess.run([exe], capture_output=True, text=True).stdout.split()))
     want = [C.sizeof(ibmg.ibmg_problem), C.sizeof(ibmg.ibmg_opts), C.sizeof(ibmg.ibmg_stats),
             ibmg.ibmg_problem.fiber_offsets.offset, ibmg.ibmg_problem.K.offset, ibmg.ibmg_opts.rtol.offset,
-            ibmg.ibmg_stats.t_step_ms.offset, ibmg.ibmg_opts.colours.offset]
+            ibmg.ibmg_stats.t_step_ms.offset, ibmg.ibmg_opts.colours.offset,
+            ibmg.ibmg_opts.tail_max.offset]
     assert got == want
 
 
@@ -66,7 +67,8 @@ def _create(N=32, levels=3, box=4, offs=(0, 40), **kw):
     prob = ibmg.ibmg_problem(N, kw.get("rho", 1.0), kw.get("mu", 1.0), offs[-1], len(offs) - 1,
                              C.cast(o, C.POINTER(C.c_int32)), kw.get("K", 1e3), kw.get("delta", 0))
     opts = ibmg.ibmg_opts(levels, box, kw.get("nu1", 2), kw.get("nu2", 2), kw.get("maxit", 100),
-                          kw.get("rtol", 1e-8), kw.get("prec", 0), kw.get("guess", 0), kw.get("colours", 2))
+                          kw.get("rtol", 1e-8), kw.get("prec", 0), kw.get("guess", 0), kw.get("colours", 2),
+                          kw.get("tail_max", 0))
     h = C.c_void_p()
     rc = L.ibmg_create(C.byref(h), C.byref(prob), C.byref(opts), None)
     return rc, h, L
@@ -93,6 +95,8 @@ def test_create_validates_shapes_without_gpu():
     assert _create(prec=3)[0] == -1
     assert _create(colours=3)[0] == -1
     assert _create(colours=4)[0] == 0
+    assert _create(tail_max=16)[0] == 0 and _create(tail_max=1)[0] == 0
+    assert _create(tail_max=12)[0] == -1 and _create(tail_max=64)[0] == -1
 
 
 def test_status_strings():
@@ -109,7 +113,7 @@ def test_batch_create_validates_without_gpu():
         probs = (ibmg.ibmg_problem * len(Ns))(*[
             ibmg.ibmg_problem(N, 1.0, 1.0, o[1], 1, C.cast(o, C.POINTER(C.c_int32)), 1e3, 0)
             for N, o in zip(Ns, offs)])
-        opts = (ibmg.ibmg_opts * len(Ns))(*[ibmg.ibmg_opts(lv, 4, 2, 2, 100, 1e-8, pr, 0, 2)
+        opts = (ibmg.ibmg_opts * len(Ns))(*[ibmg.ibmg_opts(lv, 4, 2, 2, 100, 1e-8, pr, 0, 2, 0)
                                             for pr, lv in zip(precs, levels)])
         h = C.c_void_p()
         return L.ibmg_batch_create(C.byref(h), len(Ns), probs, opts, None), h

@@ -22,7 +22,7 @@ def _gpu():
     from paper_1311_5614_amd import ibmg  # noqa: F401  (raises if the library is missing)
 
 
-# (N, levels, M, K, dt factor, box, (nu1, nu2), colours, seed, body force)
+# (N, levels, M, K, dt factor, box, (nu1, nu2), colours, seed, body force[, tail_max])
 SPECS = [
     (32, 4, 64, 1e4, 50.0, 4, (2, 2), 2, 11, False),    # whole V-cycle in the LDS tail
     (64, 5, 120, 1e5, 100.0, 4, (2, 2), 2, 12, True),   # one big level
@@ -30,13 +30,16 @@ SPECS = [
     (64, 4, 90, 1e6, 20.0, 2, (1, 1), 4, 14, False),    # 2x2 boxes, 4 colours, V(1,1), 8x8 coarsest
     (128, 6, 250, 0.0, 1.0, 4, (2, 1), 2, 15, True),    # no elastic coupling (K = 0)
     (64, 5, 160, 1e2, 10.0, 1, (2, 2), 2, 16, False),   # single-cell boxes (mild: weak smoother)
+    (128, 6, 280, 1e4, 50.0, 4, (2, 2), 2, 17, False, 8),  # tail from 8^2 down: four big levels
+    (64, 3, 140, 1e4, 50.0, 4, (2, 2), 2, 18, False, 1),   # 16^2 coarsest solved alone in the tail
 ]
 
 
 def _inputs():
     out = []
-    for (N, levels, M, K, fac, box, nu, col, seed, force) in SPECS:
+    for (N, levels, M, K, fac, box, nu, col, seed, force, *tm) in SPECS:
         w = ibgen.small_case(N=N, M=M, K=max(K, 1.0), seed=seed, levels=levels, box=box, with_force=force)
+        w.tail_max = tm[0] if tm else 0
         dt = fac * dtexp.dt_explicit(w.X, w.fiber_offsets, N, K) if K > 0 else 0.02
         out.append((w, K, dt, box, nu, col))
     return out
@@ -45,7 +48,7 @@ def _inputs():
 def _cfg(w, K, box, nu, col, prec):
     from paper_1311_5614_amd import ibmg
     return ibmg.Config(N=w.N, levels=w.levels, K=K, box=box, nu1=nu[0], nu2=nu[1], maxit=100, rtol=1e-9,
-                       prec=prec, colours=col)
+                       prec=prec, colours=col, tail_max=w.tail_max)
 
 
 def _state(w):

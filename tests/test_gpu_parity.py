@@ -165,6 +165,19 @@ def test_vcycle_parity(nu, colours, levels):
     assert rel(z, zo) < 1e-11
 
 
+@pytest.mark.parametrize("tail_max,levels", [(1, 5), (1, 3), (8, 5), (16, 5), (32, 4)])
+def test_vcycle_schedules(tail_max, levels):
+    # the LDS-resident tail, grid-wide level launches and the grid-wide
+    # coarsest product are schedules of the same V-cycle
+    w, dt, s = make(N=64, levels=levels, M=150, K=1e4, dt_factor=50.0, tail_max=tail_max)
+    _setup(s, w, dt)
+    lv = oracle_levels(w, dt, levels, 1e4)
+    V = mg.VCycle(lv, 4, 2, 2, "colour2")
+    r = np.random.default_rng(10).standard_normal(3 * 64 * 64)
+    r[2 * 4096:] -= r[2 * 4096:].mean()
+    assert rel(tnp(s.vcycle(tdev(r))), V(r)) < 1e-11
+
+
 # ---------------------------------------------------------------- a13, a15: solve and step
 
 def test_c1_step_parity():
