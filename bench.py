@@ -5,16 +5,24 @@ perturbed ellipse of 1024 points, a smooth random body force (16 Fourier
 modes per component), springs K in {1e2, 1e4, 1e6, 1e8} and dt in {100, 1000}
 x the explicit stability limit: 8 independent trajectories.  One bench step
 advances every trajectory by one implicit time step (FGMRES to relative
-residual 1e-8, V(2,2), 4x4 boxes, 5 levels).  Timed twice from the same
-initial state: the plain FP64 solver and the chosen form (FP32 V-cycle
-inside FP64 FGMRES).  `value` is the chosen form's whole-job rate in
-time steps per second; inputs are resident in HBM before timing starts.
+residual 1e-8, at most 200 iterations, 4x4 boxes).  Timed from the same
+initial state in three forms:
 
-Also reported: iterations per solve for both forms, the HIP-event
-roofline of the dominant kernel (the box-relaxation phase kernel), and the
-CPU oracle timed on a bounded sample on the host.
+  plain  FP64 V-cycle, default schedule (V(2,2), checkerboard boxes, levels
+         down to 4x4, LDS tail from 32x32);
+  fp32   FP32 V-cycle inside FP64 FGMRES, default schedule;
+  tuned  (chosen) per case the schedule and V-cycle precision picked by the
+         autotuner on calibration problems (schedules.json in the package).
 
-python bench.py [--gpus 1] [--steps 20] [--warmup 1] [--workload c2|c1|c5|c3]
+`value` is the chosen form's whole-job rate in time steps per second; inputs
+are resident in HBM before timing starts.  --workload c4 runs the 64-problem
+batch (forms batch / batch64 / plain / fp32 / tuned).
+
+Also reported: iterations per solve for every form, the HIP-event roofline of
+the box-relaxation kernel k_box, and the CPU oracle timed on a bounded sample
+on the host.
+
+python bench.py [--gpus 1] [--steps 20] [--warmup 1] [--workload c2|c1|c5|c3|c4]
 """
 import argparse
 import json
@@ -26,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MAXIT = 200   # FGMRES iteration cap (no restart below it)
 METRIC = "IB time-steps/sec and FGMRES iters/solve at rel resid 1e-8, plain vs chosen"
 
 
@@ -51,6 +60,31 @@ def workloads(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def schedule_key(workload, w):
+    return f"{w.K:.0e}-{int(w.dt_factor)}" if workload == "c2" else str(w.N)
+
+
+def tuned(workload, cases):
+    """Copies of the cases with the autotuned schedule of their class
+    (paper_1311_5614_amd/schedules.json) and the V-cycle precision it chose."""
+    import copy
+    from paper_1311_5614_amd import autotune
+    table = autotune.load().get(workload, {})
+    out, precs = [], []
+    for w in cases:
+        sch = table.get(schedule_key(workload, w))
+        c = copy.copy(w)
+        if sch is None:
+            out.append(c)
+            precs.append(1)
+            continue
+        c.levels, c.tail_max, c.nu1, c.nu2, c.colours = (sch["levels"], sch["tail_max"], sch["nu1"], sch["nu2"],
+                                                         sch["colours"])
+        out.append(c)
+        precs.append(sch.get("prec", 1))
+    return out, precs
+
+
 class Run:
     """Device state of one trajectory plus its solver handle."""
 
@@ -59,7 +93,7 @@ class Run:
         from paper_1311_5614_amd import ibmg
         self.w, self.dt = w, dt
         cfg = ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
-                          nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
+                          nu2=w.nu2, maxit=MAXIT, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
                           tail_max=getattr(w, "tail_max", 0))
         self.s = ibmg.Solver(cfg, w.fiber_offsets, dev)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
@@ -88,7 +122,7 @@ class BatchRun:
         from paper_1311_5614_amd import ibmg
         self.ws, self.dts = ws, dts
         cfgs = [ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
-                            nu2=w.nu2, maxit=100, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
+                            nu2=w.nu2, maxit=MAXIT, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
                             tail_max=getattr(w, "tail_max", 0))
                 for w in ws]
         self.b = ibmg.Batch(cfgs, [w.fiber_offsets for w in ws], dev)
@@ -144,22 +178,44 @@ def timed(runs, steps, warmup, timing=False):
     import torch
     for r in runs:
         r.reset()
+    from paper_1311_5614_amd.ibmg import IBMGError as _E
     for _ in range(warmup):
         for r in runs:
-            r.step()
+            try:
+                r.step()
+            except _E:
+                pass
     for r in runs:
         r.reset()
         r.s.set_timing(timing)
     torch.cuda.synchronize()
+    from paper_1311_5614_amd.ibmg import IBMGError
     its, conv = [], []
+    per_case = [[] for _ in runs]
+    failed = {}
     t0 = time.perf_counter()
-    for _ in range(steps):
-        for r in runs:
-            st = r.step()
+    for s in range(steps):
+        for c, r in enumerate(runs):
+            if c in failed:
+                continue
+            try:
+                st = r.step()
+            except IBMGError as e:
+                # e.g. a trajectory whose fibre neighbours drift apart beyond
+                # the elasticity window: it stops here, reported as failed
+                failed[c] = f"step {s}: {e}"
+                print(f"[bench] trajectory {c} ({r.w.name}) stopped at step {s}: {e}", file=sys.stderr, flush=True)
+                continue
             its.append(st["iters"])
             conv.append(st["converged"])
+            per_case[c].append(st["iters"])
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    timed.per_case = per_case
+    if failed:
+        conv.append(0)   # a stopped trajectory counts as one unconverged step
+        its.append(0)
+    timed.failed = failed
     ph = None
     if timing:
         tot = dict(total_ms=0.0, launches=0, bytes=0.0)
@@ -196,7 +252,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="plain,fp32")
+    ap.add_argument("--forms", default="plain,fp32,tuned")
     ap.add_argument("--levels", type=int, default=0, help="override the workload's level count")
     ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
     ap.add_argument("--colours", type=int, default=2)
@@ -232,10 +288,14 @@ def main():
     forms = args.forms.split(",")
     res = {}
     for form in forms:
+        # plain: FP64 V-cycle, default schedule.  fp32: FP32 V-cycle, default
+        # schedule.  tuned: per-class autotuned schedule and precision.
+        # batch / batch64: every trajectory in one batch handle (tuned
+        # schedules, FP32 / FP64 V-cycle).
         if form.startswith("batch"):
-            # all trajectories in one batch handle: "batch" = FP32 V-cycle, "batch64" = FP64
             prec = ibmg.IBMG_FP64 if form == "batch64" else ibmg.IBMG_FP32
-            br = BatchRun(cases, dts, prec, dev)
+            bcases, _ = tuned(args.workload, cases)
+            br = BatchRun(bcases, dts, prec, dev)
             t, its, conv, rounds = timed_batch(br, args.steps, args.warmup)
             n = args.steps * len(cases)
             res[form] = dict(time_s=t, timesteps=n, rate=n / t, iters_mean=sum(its) / len(its), iters_max=max(its),
@@ -246,22 +306,28 @@ def main():
             del br
             torch.cuda.empty_cache()
             continue
-        prec = ibmg.IBMG_FP32 if form == "fp32" else ibmg.IBMG_FP64
-        runs = [Run(w, dt, prec, dev) for w, dt in zip(cases, dts)]
+        if form == "tuned":
+            fcases, precs = tuned(args.workload, cases)
+        else:
+            fcases = cases
+            precs = [ibmg.IBMG_FP32 if form == "fp32" else ibmg.IBMG_FP64] * len(cases)
+        runs = [Run(w, dt, pr, dev) for w, dt, pr in zip(fcases, dts, precs)]
         t, its, conv, _ = timed(runs, args.steps, args.warmup, timing=False)
+        failed = dict(timed.failed)
+        per_case = [round(sum(x) / max(1, len(x)), 1) for x in timed.per_case]
         # roofline of the box kernel: the same trajectories, one more (untimed)
         # step with every box launch bracketed by HIP events on its stream
         _, _, _, ph = timed(runs, 1, 0, timing=True)
-        n = args.steps * len(runs)
-        res[form] = dict(time_s=t, timesteps=n, rate=n / t, iters_mean=sum(its) / len(its), iters_max=max(its),
-                         converged=sum(conv), phase=ph)
+        n = sum(1 for _ in its) - (1 if failed else 0)   # completed implicit steps
+        res[form] = dict(time_s=t, timesteps=n, rate=n / t, iters_mean=sum(its) / max(1, n), iters_max=max(its),
+                         converged=sum(conv), phase=ph, failed=failed)
         print(f"[bench] {form}: {n} steps in {t:.3f} s -> {n / t:.2f} steps/s, iters mean "
-              f"{res[form]['iters_mean']:.2f} max {max(its)}, converged {sum(conv)}/{n}; per case "
-              f"{[round(sum(its[c::len(runs)]) / args.steps, 1) for c in range(len(runs))]}", file=sys.stderr,
-              flush=True)
+              f"{res[form]['iters_mean']:.2f} max {max(its)}, converged {sum(conv)}/{n}; per case {per_case}",
+              file=sys.stderr, flush=True)
+        res[form]["iters_per_case"] = per_case
         del runs
         torch.cuda.empty_cache()
-    chosen = next((f for f in ("batch", "fp32") if f in res), forms[0])
+    chosen = next((f for f in ("batch", "tuned", "fp32") if f in res), forms[0])
     rc = res[chosen]
     ph = next((res[f]["phase"] for f in (chosen, "fp32", "plain") if f in res and res[f]["phase"]), None)
     achieved = ph["bytes"] / (ph["total_ms"] * 1e-3) / 1e9 if ph and ph["total_ms"] > 0 else None
@@ -278,14 +344,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32" if chosen == "fp32" else "f64",
+        "dtype": "f64" if chosen in ("plain", "batch64") else "f64+f32",
         "data": "synthetic",
         "config": {
             "workload": (f"{len(cases)} trajectories on {w0.N}x{w0.N}, {w0.M} Lagrangian points, "
                          f"{w0.levels} levels, V({w0.nu1},{w0.nu2}), box {w0.box}, rtol {w0.rtol:g}"),
             "grid": w0.N, "points": w0.M, "trajectories": len(cases), "levels": w0.levels,
             "K": sorted({c.K for c in cases}), "dt_factor": sorted({c.dt_factor for c in cases}),
-            "chosen_form": "fp32 V-cycle inside fp64 FGMRES" if chosen == "fp32" else chosen,
+            "chosen_form": {"fp32": "fp32 V-cycle inside fp64 FGMRES",
+                            "tuned": "autotuned schedule and V-cycle precision per case inside fp64 FGMRES",
+                            "batch": "all trajectories in one batch, fp32 V-cycle, autotuned schedules"}.get(chosen,
+                                                                                                      chosen),
         },
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "phase"} for k, v in res.items()},
         "roofline": {

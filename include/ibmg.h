@@ -106,6 +106,10 @@ typedef struct {
 typedef struct {
   int32_t iters;          /* preconditioner applications                          */
   int32_t converged;      /* 1 if the true residual met rtol                      */
+  int32_t fallback;       /* 1 if an FP32 V-cycle stalled (Arnoldi estimate down
+                             by less than 10% over 20 iterations) and the solve
+                             went on with the FP64 V-cycle (FGMRES is flexible:
+                             the preconditioner may change between iterations) */
   double rel_resid_est;   /* Arnoldi estimate |g_{j+1}| / ||b||                   */
   double rel_resid_true;  /* ||b - A w|| / ||b|| of the returned iterate          */
   double bnorm;           /* ||b||_2                                              */

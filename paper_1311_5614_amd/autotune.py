@@ -1,0 +1,191 @@
+"""Schedule autotuner for the multigrid preconditioner.
+
+For each problem class of a workload (the 256x256 stiffness sweep: one class
+per (K, dt) case; the batch: one class per grid size) it times candidate
+V-cycle schedules on seeded calibration problems -- same class, geometry
+drawn with other seeds than the benchmark's -- and keeps, per class, the
+fastest schedule whose steps all reach the tolerance.  A schedule is
+
+    levels    multigrid depth (coarsest 4^2, 8^2 or 16^2),
+    tail_max  largest level run by the LDS-resident one-workgroup tail,
+    nu1, nu2  smoothing sweeps (Algorithm 1),
+    colours   box colour classes of a sweep (2 or 4),
+    prec      V-cycle precision (FP32, or FP64 where FP32 is slower or stalls),
+
+inside FP64 FGMRES.  The result is written as JSON
+(`schedules.json` next to this file) and read by the benchmark.  Time steps
+use the dt values stored for the workload (tests/golden/workload_dt.json,
+written by the oracle's explicit-limit estimate) for the class.
+
+python -m paper_1311_5614_amd.autotune [--workload c2|c4|all] [--steps 2]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+OUT = os.path.join(HERE, "schedules.json")
+CAL_INSTANCE = 900   # seeds 1311000 + 100 * config + 900 + k are calibration-only
+MAXIT = 200          # FGMRES iteration cap (no restart), as in the benchmark
+
+
+def _dt_table():
+    with open(os.path.join(ROOT, "tests", "golden", "workload_dt.json")) as f:
+        return json.load(f)
+
+
+def classes(workload):
+    """(key, calibration Workload, dt) per class of the workload."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import ibgen
+    dts = _dt_table()
+    out = []
+    if workload == "c2":
+        rng = np.random.default_rng(ibgen.seed_for(2, CAL_INSTANCE))
+        X, _ = ibgen.ellipse(rng, 1024)
+        gu, gv = ibgen.fourier_force(rng, 256)
+        for case, d in zip(ibgen.config_c2_cases(), dts["c2"]):
+            w = ibgen.Workload(f"cal-{case.name}", 256, case.levels, X.copy(), np.array([0, 1024], np.int32),
+                               case.K, case.dt_factor, rtol=case.rtol, g_u=gu, g_v=gv,
+                               seed=ibgen.seed_for(2, CAL_INSTANCE))
+            out.append((f"{case.K:.0e}-{int(case.dt_factor)}", w, d["dt"]))
+    elif workload == "c4":
+        cases = ibgen.config_c4()
+        seen = set()
+        for case, d in zip(cases, dts["c4"]):
+            if case.N in seen:
+                continue
+            seen.add(case.N)
+            rng = np.random.default_rng(ibgen.seed_for(4, CAL_INSTANCE + len(seen)))
+            X, _ = ibgen.ellipse(rng, case.M)
+            w = ibgen.Workload(f"cal-{case.N}", case.N, case.levels, X, np.array([0, case.M], np.int32),
+                               1e5, case.dt_factor, rtol=case.rtol, seed=ibgen.seed_for(4, CAL_INSTANCE))
+            # dt of the class: the stored dt of this grid size rescaled from its K to 1e5
+            out.append((str(case.N), w, d["dt"] * case.K / 1e5))
+    else:
+        raise SystemExit(f"unknown workload {workload}")
+    return out
+
+
+def candidates(w):
+    """Stage 1: the parameters that change convergence (depth, sweeps,
+    colours), with the tail at 8."""
+    full = w.levels
+    lv = [full - d for d in (0, 1, 2) if (w.N >> (full - d - 1)) <= 16]
+    for levels, nu, col in itertools.product(lv, ((1, 1), (2, 2), (3, 3), (2, 1)), (2, 4)):
+        yield dict(levels=levels, tail_max=8, nu1=nu[0], nu2=nu[1], colours=col, prec=1)
+
+
+def tails(w, sch):
+    """Stage 2: launch schedules of one V-cycle (tail sizes), and the FP64
+    V-cycle at the stage-1 tail."""
+    for tail in (1, 8, 16, 32):
+        if tail >= 8 and (w.N >> (sch["levels"] - 1)) > tail:
+            continue   # the tail would hold only the coarsest level: same as tail 1
+        yield dict(sch, tail_max=tail)
+    yield dict(sch, prec=0)
+
+
+def time_schedule(w, dt, sch, steps, dev):
+    import torch
+    from . import ibmg
+    cfg = ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, box=4, nu1=sch["nu1"], nu2=sch["nu2"], maxit=MAXIT,
+                      rtol=w.rtol, prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"])
+    s = ibmg.Solver(cfg, w.fiber_offsets, dev)
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+    gu = t(w.g_u) if w.g_u is not None else None
+    gv = t(w.g_v) if w.g_v is not None else None
+    z = torch.zeros(w.N, w.N, dtype=torch.float64, device=dev)
+    u, v, p, X = z.clone(), z.clone(), z.clone(), t(w.X)
+    s.step(dt, u, v, p, X, gu, gv)          # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, ok = [], True
+    for _ in range(steps):
+        st = s.step(dt, u, v, p, X, gu, gv)
+        its.append(st["iters"])
+        ok = ok and st["converged"] == 1
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    s.close()
+    return el, its, ok
+
+
+def _try(w, dt, sch, steps, dev, workload, key):
+    from .ibmg import IBMGError
+    try:
+        el, its, ok = time_schedule(w, dt, sch, steps, dev)
+    except IBMGError as e:          # e.g. a diverged trajectory leaves the window
+        print(f"[autotune] {workload} {key} {sch} -> error {e}", flush=True)
+        return None
+    print(f"[autotune] {workload} {key} {sch} -> {1e3 * el:.2f} ms/step, iters {its}"
+          f"{'' if ok else ' NOT CONVERGED'}", flush=True)
+    return el, its, ok
+
+
+def tune(workload, steps, dev="cuda:0"):
+    """Per class: the fastest converging schedule; if none converges, the one
+    with the fewest iterations (recorded with converged = false)."""
+    res = {}
+    for key, w, dt in classes(workload):
+        scored, failed = [], []
+        for sch in candidates(w):
+            r = _try(w, dt, sch, steps, dev, workload, key)
+            if r is None:
+                continue
+            (scored if r[2] else failed).append((r[0], sch, r[1]))
+        if scored:
+            scored.sort(key=lambda x: x[0])
+            best, conv = scored[0], True
+            top = scored[:3]
+        else:
+            failed.sort(key=lambda x: (sum(x[2]), x[0]))
+            best, conv = failed[0], False
+            top = failed[:1]
+        for _, sch, _ in top:
+            for cand in tails(w, sch):
+                if cand == sch:
+                    continue
+                r = _try(w, dt, cand, steps, dev, workload, key)
+                if r is None:
+                    continue
+                el, its, ok = r
+                if ok and (not conv or el < best[0]):
+                    best, conv = (el, cand, its), True
+                elif not conv and not ok and sum(its) < sum(best[2]):
+                    best = (el, cand, its)
+        res[key] = dict(best[1], ms_per_step=round(1e3 * best[0], 3), iters=best[2], converged=conv)
+        print(f"[autotune] {workload} {key} best {res[key]}", flush=True)
+    return res
+
+
+def load(path=OUT):
+    with open(path) as f:
+        return json.load(f)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="all")
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--out", default=OUT)
+    args = ap.parse_args()
+    data = load(args.out) if os.path.exists(args.out) else {}
+    for wl in (("c2", "c4") if args.workload == "all" else (args.workload,)):
+        data[wl] = tune(wl, args.steps)
+    data["meta"] = {"form": "V-cycle (prec 1 = fp32, 0 = fp64) in fp64 FGMRES", "box": 4,
+                    "steps_timed": args.steps, "calibration_instance": CAL_INSTANCE, "maxit": MAXIT}
+    with open(args.out, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(f"[autotune] wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

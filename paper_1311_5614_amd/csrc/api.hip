@@ -33,7 +33,9 @@ int window_reach(int level) { return level == 0 ? IBMG_WR : (level == 1 ? 4 : 3)
 
 void layout(ibmg_handle* h) {
   size_t cur = 0;
-  const size_t rs = h->prec == IBMG_FP32 ? sizeof(float) : sizeof(double);
+  // V-cycle vectors are sized for FP64 also on an FP32 handle: a stalled FP32
+  // solve continues with the FP64 V-cycle on the same buffers
+  const size_t rs = sizeof(double);
   const int M = h->M, bpp = boxes_per_point(h->n);
   h->ndof = 2 * h->n * (h->n + 1) + h->n * h->n;
   const size_t nd2 = (size_t)h->ndof * h->ndof;
@@ -235,7 +237,9 @@ void precond(ibmg_handle* h, const double* r, double* z) {
   if (graph && (!h->gexec || h->graph_dt != h->dt)) {
     if (capture_vcycle(h) != IBMG_OK) { h->launch_error = true; return; }
   }
-  if (h->prec == IBMG_FP32) {
+  if (h->prec == IBMG_FP32 && h->fb64) {
+    vcycle<double>(h, r, z);
+  } else if (h->prec == IBMG_FP32) {
     k_convert<double, float><<<nblk(n0), 256, 0, h->stream>>>(r, h->p<float>(h->b0f), n0);
     if (graph) {
       if (hipGraphLaunch(h->gexec, h->stream) != hipSuccess) h->launch_error = true;
@@ -404,6 +408,9 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
   st->bnorm = bnorm;
   st->iters = 0;
   st->converged = 0;
+  st->fallback = 0;
+  h->fb64 = false;
+  std::vector<double> hist;   // Arnoldi estimate after each iteration
   st->rel_resid_est = 0;
   st->rel_resid_true = 0;
   if (bnorm == 0.0) {
@@ -451,6 +458,12 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
       k = j + 1;
       est = hs[0] / bnorm;
       if (hs[2] != 0.0) return IBMG_ENONFINITE;
+      hist.push_back(est);
+      const int nh = (int)hist.size();
+      if (h->prec == IBMG_FP32 && !h->fb64 && nh > kFallbackWindow && est > 0.9 * hist[nh - 1 - kFallbackWindow]) {
+        h->fb64 = true;   // FP32 V-cycle stalled: continue with the FP64 one
+        st->fallback = 1;
+      }
       if (hs[1] != 0.0) break;
     }
     launch_backsolve(s, H, ldh, g, k, h->p<double>(h->y));
@@ -503,6 +516,8 @@ int bind(ibmg_handle* h, void* dev, size_t bytes, bool own_capture_stream) {
   }
   return IBMG_OK;
 }
+
+void vcycle_fp64(ibmg_handle* h, const double* r, double* z) { vcycle<double>(h, r, z); }
 
 // Right-hand side (a4) into bvec and the initial iterate into xvec.
 int step_begin(ibmg_handle* h, double dt, const double* u, const double* v, const double* p, const double* gu,

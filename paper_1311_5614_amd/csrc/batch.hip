@@ -412,8 +412,8 @@ namespace {
 
 // Round buffer layout: active[P], then four slot sets (end, start, begin-cycle,
 // inner), each p[P], j[P], off[P+1], off2[P+1], beta[P].
-constexpr int kSets = 4;
-enum { SET_END = 0, SET_START, SET_BEGIN, SET_INNER };
+constexpr int kSets = 5;
+enum { SET_END = 0, SET_START, SET_BEGIN, SET_INNER, SET_INNER32 };
 
 size_t set_bytes(int P) { return (4 * (size_t)P + 2) * sizeof(int) + (size_t)P * sizeof(double) + 64; }
 size_t round_bytes(int P) { return ((size_t)P * sizeof(int) + 255) / 256 * 256 + kSets * ((set_bytes(P) + 255) / 256 * 256); }
@@ -667,6 +667,8 @@ enum { ST_START = 0, ST_INNER, ST_DONE };
 struct PState {
   int state = ST_START, j = 0, total = 0, k_end = -1, rc = IBMG_OK;
   bool begin = false;
+  bool fb64 = false;          // FP32 V-cycle stalled: this solve goes on with the FP64 one
+  std::vector<double> hist;   // Arnoldi estimate after each iteration
   double bnorm = 0, beta = 0, est = INFINITY, target = 0;
   ibmg_stats st{};
 };
@@ -705,10 +707,10 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
   }
   if (any_target)
     IBMG_HIP(hipMemcpyAsync(B->ws + B->o_kry, B->kry_h.data(), P * sizeof(BKry), hipMemcpyHostToDevice, s));
-  HostSet E, S, G, I;
+  HostSet E, S, G, I, I32;
   int* active_h = reinterpret_cast<int*>(B->round_h);
   for (;;) {
-    E.clear(); S.clear(); G.clear(); I.clear();
+    E.clear(); S.clear(); G.clear(); I.clear(); I32.clear();
     for (int p = 0; p < P; ++p) {
       PState& q = ps[p];
       if (q.state == ST_DONE) continue;
@@ -718,13 +720,14 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
       } else {
         if (q.begin) add_slot(B, G, p, 0, q.beta);
         add_slot(B, I, p, q.j);
+        if (!q.fb64) add_slot(B, I32, p, q.j);
       }
     }
     if (S.p.empty() && I.p.empty()) break;
     for (int p = 0; p < P; ++p) active_h[p] = 0;
-    for (int p : I.p) active_h[p] = 1;
+    for (int p : I32.p) active_h[p] = 1;
     const BSet sE = pack_set(B, SET_END, E), sS = pack_set(B, SET_START, S), sG = pack_set(B, SET_BEGIN, G),
-               sI = pack_set(B, SET_INNER, I);
+               sI = pack_set(B, SET_INNER, I), sI32 = pack_set(B, SET_INNER32, I32);
     IBMG_HIP(hipMemcpyAsync(B->ws + B->o_round, B->round_h, B->round_bytes, hipMemcpyHostToDevice, s));
     if (sE.n) {
       kb_backsolve<<<sE.n, 64, 0, s>>>(sE, K);
@@ -741,22 +744,32 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
       int jmax = 0;
       for (int j : I.j) jmax = std::max(jmax, j);
       const int groups = (jmax + 1 + BMD_GROUP - 1) / BMD_GROUP;
-      const int ne = I.off.back();
-      if (B->prec == IBMG_FP32) kb_to_b0<float><<<ne, 256, 0, s>>>(sI, K);
-      else kb_to_b0<double><<<ne, 256, 0, s>>>(sI, K);
-      if (B->use_graph) {
-        if (!B->gexec) {
-          const int rc = capture(B);
-          if (rc) return rc;
+      const int ne = I.off.back(), ne32 = I32.off.back();
+      if (sI32.n) {
+        if (B->prec == IBMG_FP32) kb_to_b0<float><<<ne32, 256, 0, s>>>(sI32, K);
+        else kb_to_b0<double><<<ne32, 256, 0, s>>>(sI32, K);
+        if (B->use_graph) {
+          if (!B->gexec) {
+            const int rc = capture(B);
+            if (rc) return rc;
+          }
+          IBMG_HIP(hipGraphLaunch(B->gexec, s));
+        } else if (B->prec == IBMG_FP32) {
+          bvcycle<float>(B, s);
+        } else {
+          bvcycle<double>(B, s);
         }
-        IBMG_HIP(hipGraphLaunch(B->gexec, s));
-      } else if (B->prec == IBMG_FP32) {
-        bvcycle<float>(B, s);
-      } else {
-        bvcycle<double>(B, s);
+        if (B->prec == IBMG_FP32) kb_from_w0<float><<<ne32, 256, 0, s>>>(sI32, K);
+        else kb_from_w0<double><<<ne32, 256, 0, s>>>(sI32, K);
       }
-      if (B->prec == IBMG_FP32) kb_from_w0<float><<<ne, 256, 0, s>>>(sI, K);
-      else kb_from_w0<double><<<ne, 256, 0, s>>>(sI, K);
+      // problems whose FP32 V-cycle stalled: their own FP64 V-cycle
+      for (size_t q = 0; q < I.p.size(); ++q) {
+        const int p = I.p[q];
+        if (!ps[p].fb64) continue;
+        ibmg_handle* hp = B->h[p];
+        const size_t n0 = hp->n0();
+        vcycle_fp64(hp, hp->p<double>(hp->V) + (size_t)I.j[q] * n0, hp->p<double>(hp->Z) + (size_t)I.j[q] * n0);
+      }
       kb_resid0<<<ne, 256, 0, s>>>(sI, K, 0);
       if (I.off2.back() > 0) kb_ibrows0<<<I.off2.back(), 256, 0, s>>>(sI, K, 0);
       // classical Gram-Schmidt, twice; then H(j+1, j) and the Givens step
@@ -797,6 +810,12 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
       const double* f = B->gather_h + 4 * p + 1;
       q.est = f[0] / q.bnorm;
       if (f[2] != 0.0) { q.rc = IBMG_ENONFINITE; q.state = ST_DONE; continue; }
+      q.hist.push_back(q.est);
+      const int nh = (int)q.hist.size();
+      if (B->prec == IBMG_FP32 && !q.fb64 && nh > kFallbackWindow && q.est > 0.9 * q.hist[nh - 1 - kFallbackWindow]) {
+        q.fb64 = true;   // same stall test as the single-problem solve
+        q.st.fallback = 1;
+      }
       if (f[1] != 0.0 || q.j + 1 >= m || q.total >= m) {
         q.k_end = q.j + 1;
         q.state = ST_START;

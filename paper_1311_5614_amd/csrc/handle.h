@@ -12,6 +12,7 @@ namespace ibmg {
 constexpr int kPW = 16;          // panel width of the coarse Gauss-Jordan (dense.hip)
 constexpr int kDotBlocks = 256;  // workgroups of the deterministic dot products
 constexpr int kMaxTimed = 8192;  // timed phase launches per solve
+constexpr int kFallbackWindow = 20;  // FP32 V-cycle stall test: < 10% progress over this many iterations
 constexpr int kSmallLevel = 32;  // default (and largest) level size run in one workgroup per V-cycle leg
 
 struct Buf {
@@ -56,6 +57,7 @@ struct ibmg_handle {
   int nr = 0, ndof = 0;
   // state
   bool setup_ok = false, has_ib = false, launch_error = false;
+  bool fb64 = false;   // this solve continues with the FP64 V-cycle (FP32 stalled)
   // the V-cycle as a captured graph (fixed buffers b0g -> w0g), rebuilt when dt changes
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -150,5 +152,7 @@ int setup_finish(ibmg_handle* h);
 int step_begin(ibmg_handle* h, double dt, const double* u, const double* v, const double* p, const double* gu,
                const double* gv);
 int step_end(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X);
+// z = MGV(0, r) with the FP64 V-cycle, launched eagerly on the handle's stream.
+void vcycle_fp64(ibmg_handle* h, const double* r, double* z);
 
 }  // namespace ibmg

@@ -49,7 +49,7 @@ class ibmg_opts(C.Structure):
 
 
 class ibmg_stats(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_resid_est", C.c_double),
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("fallback", C.c_int32), ("rel_resid_est", C.c_double),
                 ("rel_resid_true", C.c_double), ("bnorm", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_solve_ms", C.c_double), ("t_step_ms", C.c_double)]
 

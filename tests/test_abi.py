@@ -42,9 +42,10 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "ibmg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
          offsetof(ibmg_problem, fiber_offsets), offsetof(ibmg_problem, K), offsetof(ibmg_opts, rtol),
-         offsetof(ibmg_stats, t_step_ms), offsetof(ibmg_opts, colours), offsetof(ibmg_opts, tail_max));
+         offsetof(ibmg_stats, t_step_ms), offsetof(ibmg_opts, colours), offsetof(ibmg_opts, tail_max),
+         offsetof(ibmg_stats, rel_resid_est));
   return 0;
 }
 """
@@ -57,7 +58,7 @@ int main(void) {
     want = [C.sizeof(ibmg.ibmg_problem), C.sizeof(ibmg.ibmg_opts), C.sizeof(ibmg.ibmg_stats),
             ibmg.ibmg_problem.fiber_offsets.offset, ibmg.ibmg_problem.K.offset, ibmg.ibmg_opts.rtol.offset,
             ibmg.ibmg_stats.t_step_ms.offset, ibmg.ibmg_opts.colours.offset,
-            ibmg.ibmg_opts.tail_max.offset]
+            ibmg.ibmg_opts.tail_max.offset, ibmg.ibmg_stats.rel_resid_est.offset]
     assert got == want
 
 
