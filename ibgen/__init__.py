@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "Workload", "seed_for", "ellipse", "rings", "fourier_force",
     "config_c1", "config_c2_cases", "config_c3", "config_c4", "config_c5",
-    "small_case",
+    "small_case", "cnn_init",
 ]
 
 
@@ -217,3 +217,19 @@ def small_case(N: int = 16, M: int = 40, K: float = 1e3, seed: int = 7,
         gu, gv = fourier_force(rng, N, n_modes=4, kmax=2)
     return Workload(f"small-{N}-M{M}", N, levels, X, np.array(offs, np.int32), K,
                     1.0, box=box, rtol=1e-12, g_u=gu, g_v=gv, seed=seed)
+
+
+def cnn_init(seed: int, layers=((5, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))):
+    """Initial parameters of the warm-start network, flat FP32 in layer
+    order (per layer W [co, ci, 3, 3] row-major, then b [co]): W ~ N(0,
+    2 / (9 ci)) (He), b = 0, and the last layer all zero, so that the
+    untrained network proposes no change."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for li, (ci, co) in enumerate(layers):
+        if li == len(layers) - 1:
+            W = np.zeros(co * ci * 9)
+        else:
+            W = rng.standard_normal(co * ci * 9) * np.sqrt(2.0 / (9 * ci))
+        parts += [W, np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
