@@ -110,10 +110,13 @@ typedef struct {
                              by less than 10% over 20 iterations) and the solve
                              went on with the FP64 V-cycle (FGMRES is flexible:
                              the preconditioner may change between iterations) */
+  int32_t guess_rejected; /* ibmg_step_x0: 1 if the proposal was dropped
+                             (alpha = 0) and the solve started from w^n          */
   double rel_resid_est;   /* Arnoldi estimate |g_{j+1}| / ||b||                   */
   double rel_resid_true;  /* ||b - A w|| / ||b|| of the returned iterate          */
   double bnorm;           /* ||b||_2                                              */
   double t_setup_ms, t_solve_ms, t_step_ms;  /* host wall clock around the phases */
+  double guess_alpha;     /* ibmg_step_x0: the weight alpha of the proposal      */
 } ibmg_stats;
 
 /* Create a handle.  Validates shapes (box tiling, power-of-two N, levels) and
@@ -149,6 +152,16 @@ int ibmg_setup(ibmg_handle* h, double dt, const double* X);
  * u and v faces, nullable.  out: host stats, nullable. */
 int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X,
               const double* g_u, const double* g_v, ibmg_stats* out);
+
+/* ibmg_step with a proposed initial iterate x0 (3 N^2, device, e.g. w^n plus
+ * the learned correction below).  Guard: FGMRES starts from
+ * w^n + alpha (x0 - w^n) with alpha = <r, q> / <q, q>, r = b - A w^n,
+ * q = A (x0 - w^n), the weight that minimises ||b - A x|| on that line, so the
+ * start is never worse than w^n (alpha = 0, stats.guess_rejected = 1, when q
+ * vanishes or r and q are orthogonal); it then runs to the same rtol.  Errors
+ * as ibmg_step. */
+int ibmg_step_x0(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X,
+                 const double* g_u, const double* g_v, const double* x0, ibmg_stats* out);
 
 /* Right-hand side of the step system at the current setup (Sec. 2.3.2 with
  * the stiffness factor restored): b = [(rho/dt) u + S_0 G + g_u;
@@ -225,6 +238,45 @@ int ibmg_batch_set_graph(ibmg_batch* b, int on);
 /* Lockstep FGMRES rounds run so far (one host synchronisation each). */
 int ibmg_batch_rounds(const ibmg_batch* b, int64_t* rounds);
 int ibmg_batch_destroy(ibmg_batch* b);
+
+/* --- Learned initial iterate (Sec. 3.3 leaves the FGMRES initial iterate
+ *     free): a network Dw = F(u^n, v^n, p^n, f_u, f_v) with f = S_0 G^n the
+ *     spread elastic force, proposing x0 = w^n + Dw for ibmg_step_x0.  Six
+ *     3x3 periodic convolutions 5 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3 with
+ *     ReLU between layers (39331 parameters, flat FP32 in layer order: W
+ *     [co][ci][ky][kx] row-major, then b [co]); inputs divided by per-channel
+ *     scales s_in, outputs multiplied by s_out.  BF16 weights and
+ *     activations, FP32 accumulation (MFMA), FP32 masters and Adam
+ *     (beta1 0.9, beta2 0.999, eps 1e-8).  Loss: mean squared error of the
+ *     scaled output against (w^{n+1} - w^n) / s_out.  Planes (in5, dw3) are
+ *     DEVICE FP64, stacked channel after channel, N x N each. --- */
+typedef struct ibmg_cnn ibmg_cnn;
+/* N: power of two, 16..4096; max_pairs: capacity of the training store
+ * (a ring: the last max_pairs recorded pairs).  Errors: EINVAL, ESHAPE. */
+int ibmg_cnn_create(ibmg_cnn** out, int32_t N, int32_t max_pairs, void* hip_stream);
+int ibmg_cnn_workspace_bytes(const ibmg_cnn* c, size_t* bytes);
+/* Bind device memory; zeroes parameters and state. */
+int ibmg_cnn_bind_workspace(ibmg_cnn* c, void* dev_ptr, size_t bytes);
+/* Parameters (HOST FP32 [39331]); setting them resets the Adam state. */
+int ibmg_cnn_set_params(ibmg_cnn* c, const float* params);
+int ibmg_cnn_get_params(ibmg_cnn* c, float* params);
+/* Scales (HOST FP32: s_in[5], s_out[3], all > 0).  Unset, the first
+ * ibmg_cnn_train sets each to the RMS of its channel over the stored pairs
+ * (1 for an all-zero channel).  get: s8 = s_in then s_out.  */
+int ibmg_cnn_set_scales(ibmg_cnn* c, const float* s_in5, const float* s_out3);
+int ibmg_cnn_get_scales(ibmg_cnn* c, float* s8);
+/* Store one training pair (input planes in5 [5 N^2], target dw3 [3 N^2]). */
+int ibmg_cnn_record(ibmg_cnn* c, const double* in5, const double* dw3);
+int ibmg_cnn_pairs(const ibmg_cnn* c, int32_t* n);
+/* `epochs` passes over the stored pairs in recording order, one Adam step
+ * per pair at learning rate lr; mean loss of the first and last epoch
+ * (HOST, nullable).  Synchronises.  Errors: ESTATE (no pairs). */
+int ibmg_cnn_train(ibmg_cnn* c, int32_t epochs, float lr, float* loss_first, float* loss_last);
+/* dw3 = F(in5) (device).  Errors: ESTATE (scales unset). */
+int ibmg_cnn_infer(ibmg_cnn* c, const double* in5, double* dw3);
+/* Loss and gradient (HOST FP32 [39331]) of one pair, no update.  Synchronises. */
+int ibmg_cnn_loss_grad(ibmg_cnn* c, const double* in5, const double* dw3, float* loss, float* grad);
+int ibmg_cnn_destroy(ibmg_cnn* c);
 
 #ifdef __cplusplus
 }

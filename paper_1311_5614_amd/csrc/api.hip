@@ -707,8 +707,14 @@ int ibmg_solve(ibmg_handle* h, const double* b, double* w, ibmg_stats* out) {
   return rc;
 }
 
-int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X, const double* gu,
-              const double* gv, ibmg_stats* out) {
+}  // extern "C"
+
+namespace {
+
+// One implicit step; x0 (nullable) is a proposed initial iterate, used only
+// when its residual is below that of w^n.
+int step_impl(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X, const double* gu,
+              const double* gv, const double* x0, ibmg_stats* out) {
   if (!ready(h)) return IBMG_ENOMEM;
   if (!u || !v || !p || (h->M > 0 && !X)) return IBMG_EINVAL;
   ibmg_stats st{};
@@ -717,7 +723,41 @@ int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double
   if (rc) return rc;
   const double t1 = now_ms();
   if ((rc = step_begin(h, dt, u, v, p, gu, gv))) return rc;
+  if (x0) {
+    // x = w^n + alpha (x0 - w^n), alpha minimising ||b - A x||: with
+    // r = b - A w^n and q = A (x0 - w^n), alpha = <r, q> / <q, q>, so the
+    // start is never worse than w^n
+    hipStream_t s = h->stream;
+    const size_t NN = (size_t)h->N * h->N, n0 = h->n0();
+    double* x = h->p<double>(h->xvec);
+    double* b = h->p<double>(h->bvec);
+    double* V = h->p<double>(h->V);
+    double* scal = h->p<double>(h->scal);
+    double* d = h->p<double>(h->rvec);
+    IBMG_HIP(hipMemcpyAsync(x, u, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(x + NN, v, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(x + 2 * NN, p, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(d, x0, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    k_fill<double><<<1, 64, 0, s>>>(scal + 8, 1, 1.0);
+    launch_update(s, x, n0, 1, scal + 8, d, n0, -1.0);   // d = x0 - w^n
+    apply0(h, x, V, b);                                 // r
+    apply0(h, d, V + n0);                               // q
+    dot(h, V, V + n0, scal + 4);
+    dot(h, V + n0, V + n0, scal + 5);
+    double hs[2];
+    if ((rc = read_doubles(h, scal + 4, hs, 2))) return rc;
+    const double alpha = (hs[1] > 0.0 && std::isfinite(hs[0]) && std::isfinite(hs[1])) ? hs[0] / hs[1] : 0.0;
+    if (alpha != 0.0) {
+      IBMG_HIP(hipMemcpyAsync(scal + 9, &alpha, sizeof(double), hipMemcpyHostToDevice, s));
+      launch_update(s, d, n0, 1, scal + 9, x, n0, 1.0);
+      IBMG_HIP(hipStreamSynchronize(s));   // alpha lives on the host stack
+    } else {
+      st.guess_rejected = 1;
+    }
+    st.guess_alpha = alpha;
+  }  const int rejected = st.guess_rejected;
   rc = do_solve(h, h->p<double>(h->bvec), h->p<double>(h->xvec), &st);
+  st.guess_rejected = rejected;
   const double t2 = now_ms();
   if (rc < 0) return rc;
   const int rc_end = step_end(h, dt, u, v, p, X);
@@ -729,6 +769,21 @@ int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double
   st.t_step_ms = now_ms() - t0;
   if (out) *out = st;
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibmg_step(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X, const double* gu,
+              const double* gv, ibmg_stats* out) {
+  return step_impl(h, dt, u, v, p, X, gu, gv, nullptr, out);
+}
+
+int ibmg_step_x0(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X, const double* gu,
+                 const double* gv, const double* x0, ibmg_stats* out) {
+  if (!x0) return IBMG_EINVAL;
+  return step_impl(h, dt, u, v, p, X, gu, gv, x0, out);
 }
 
 }  // extern "C"

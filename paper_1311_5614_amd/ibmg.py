@@ -32,7 +32,10 @@ EXPORTS = [
     "ibmg_prolong_add", "ibmg_coarse_solve", "ibmg_vcycle", "ibmg_box_matrix",
     "ibmg_fiber_force", "ibmg_spread", "ibmg_interp",
     "ibmg_batch_create", "ibmg_batch_workspace_bytes", "ibmg_batch_bind_workspace", "ibmg_batch_step",
-    "ibmg_batch_set_graph", "ibmg_batch_rounds", "ibmg_batch_destroy",
+    "ibmg_batch_set_graph", "ibmg_batch_rounds", "ibmg_batch_destroy", "ibmg_step_x0",
+    "ibmg_cnn_create", "ibmg_cnn_workspace_bytes", "ibmg_cnn_bind_workspace", "ibmg_cnn_set_params",
+    "ibmg_cnn_get_params", "ibmg_cnn_set_scales", "ibmg_cnn_get_scales", "ibmg_cnn_record", "ibmg_cnn_pairs",
+    "ibmg_cnn_train", "ibmg_cnn_infer", "ibmg_cnn_loss_grad", "ibmg_cnn_destroy",
 ]
 
 
@@ -49,9 +52,10 @@ class ibmg_opts(C.Structure):
 
 
 class ibmg_stats(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("fallback", C.c_int32), ("rel_resid_est", C.c_double),
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("fallback", C.c_int32),
+                ("guess_rejected", C.c_int32), ("rel_resid_est", C.c_double),
                 ("rel_resid_true", C.c_double), ("bnorm", C.c_double), ("t_setup_ms", C.c_double),
-                ("t_solve_ms", C.c_double), ("t_step_ms", C.c_double)]
+                ("t_solve_ms", C.c_double), ("t_step_ms", C.c_double), ("guess_alpha", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,6 +97,20 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ibmg_batch_set_graph": [vp, i32],
         "ibmg_batch_rounds": [vp, C.POINTER(C.c_int64)],
         "ibmg_batch_destroy": [vp],
+        "ibmg_step_x0": [vp, dbl, vp, vp, vp, vp, vp, vp, vp, C.POINTER(ibmg_stats)],
+        "ibmg_cnn_create": [C.POINTER(vp), i32, i32, vp],
+        "ibmg_cnn_workspace_bytes": [vp, C.POINTER(sz)],
+        "ibmg_cnn_bind_workspace": [vp, vp, sz],
+        "ibmg_cnn_set_params": [vp, C.POINTER(C.c_float)],
+        "ibmg_cnn_get_params": [vp, C.POINTER(C.c_float)],
+        "ibmg_cnn_set_scales": [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+        "ibmg_cnn_get_scales": [vp, C.POINTER(C.c_float)],
+        "ibmg_cnn_record": [vp, vp, vp],
+        "ibmg_cnn_pairs": [vp, C.POINTER(C.c_int32)],
+        "ibmg_cnn_train": [vp, i32, C.c_float, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+        "ibmg_cnn_infer": [vp, vp, vp],
+        "ibmg_cnn_loss_grad": [vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+        "ibmg_cnn_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -202,6 +220,14 @@ class Solver:
         st = ibmg_stats()
         code = _check(lib().ibmg_step(self.h, float(dt), _ptr(u), _ptr(v), _ptr(p), _ptr(X),
                                       _ptr(g_u), _ptr(g_v), C.byref(st)), "ibmg_step")
+        d = st.as_dict()
+        d["status"] = code
+        return d
+
+    def step_x0(self, dt, u, v, p, X, x0, g_u=None, g_v=None):
+        st = ibmg_stats()
+        code = _check(lib().ibmg_step_x0(self.h, float(dt), _ptr(u), _ptr(v), _ptr(p), _ptr(X),
+                                         _ptr(g_u), _ptr(g_v), _ptr(x0), C.byref(st)), "ibmg_step_x0")
         d = st.as_dict()
         d["status"] = code
         return d
@@ -358,3 +384,90 @@ class Batch:
         n = C.c_int64()
         _check(lib().ibmg_batch_rounds(self.h, C.byref(n)), "ibmg_batch_rounds")
         return n.value
+
+
+CNN_PARAMS = 39331
+
+
+class Cnn:
+    """The warm-start network (ibmg_cnn_*) plus its workspace."""
+
+    def __init__(self, N, max_pairs, device="cuda:0", stream=None):
+        L = lib()
+        self.N = N
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.ibmg_cnn_create(C.byref(h), N, max_pairs, C.c_void_p(self.stream.cuda_stream)), "ibmg_cnn_create")
+        self.h = h
+        nbytes = C.c_size_t()
+        _check(L.ibmg_cnn_workspace_bytes(h, C.byref(nbytes)), "ibmg_cnn_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        _check(L.ibmg_cnn_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value),
+               "ibmg_cnn_bind_workspace")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ibmg_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _f32(a, n):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if a.size != n:
+            raise ValueError(f"{n} values expected")
+        return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+    def set_params(self, params):
+        a, ptr = self._f32(params, CNN_PARAMS)
+        _check(lib().ibmg_cnn_set_params(self.h, ptr), "ibmg_cnn_set_params")
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(CNN_PARAMS, dtype=np.float32)
+        _check(lib().ibmg_cnn_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float))), "ibmg_cnn_get_params")
+        return out
+
+    def set_scales(self, s_in, s_out):
+        a, pa = self._f32(s_in, 5)
+        b, pb = self._f32(s_out, 3)
+        _check(lib().ibmg_cnn_set_scales(self.h, pa, pb), "ibmg_cnn_set_scales")
+
+    def get_scales(self):
+        import numpy as np
+        out = np.empty(8, dtype=np.float32)
+        _check(lib().ibmg_cnn_get_scales(self.h, out.ctypes.data_as(C.POINTER(C.c_float))), "ibmg_cnn_get_scales")
+        return out
+
+    def record(self, in5, dw3):
+        _check(lib().ibmg_cnn_record(self.h, _ptr(in5), _ptr(dw3)), "ibmg_cnn_record")
+
+    def pairs(self):
+        n = C.c_int32()
+        _check(lib().ibmg_cnn_pairs(self.h, C.byref(n)), "ibmg_cnn_pairs")
+        return n.value
+
+    def train(self, epochs, lr):
+        lf, ll = C.c_float(), C.c_float()
+        _check(lib().ibmg_cnn_train(self.h, int(epochs), float(lr), C.byref(lf), C.byref(ll)), "ibmg_cnn_train")
+        return lf.value, ll.value
+
+    def infer(self, in5):
+        out = torch.empty(3, self.N, self.N, dtype=torch.float64, device=self.device)
+        _check(lib().ibmg_cnn_infer(self.h, _ptr(in5), _ptr(out)), "ibmg_cnn_infer")
+        return out
+
+    def loss_grad(self, in5, dw3):
+        import numpy as np
+        g = np.empty(CNN_PARAMS, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().ibmg_cnn_loss_grad(self.h, _ptr(in5), _ptr(dw3), C.byref(loss),
+                                        g.ctypes.data_as(C.POINTER(C.c_float))), "ibmg_cnn_loss_grad")
+        return loss.value, g

@@ -42,10 +42,10 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "ibmg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
          offsetof(ibmg_problem, fiber_offsets), offsetof(ibmg_problem, K), offsetof(ibmg_opts, rtol),
          offsetof(ibmg_stats, t_step_ms), offsetof(ibmg_opts, colours), offsetof(ibmg_opts, tail_max),
-         offsetof(ibmg_stats, rel_resid_est));
+         offsetof(ibmg_stats, rel_resid_est), offsetof(ibmg_stats, guess_rejected));
   return 0;
 }
 """
@@ -58,7 +58,8 @@ int main(void) {
     want = [C.sizeof(ibmg.ibmg_problem), C.sizeof(ibmg.ibmg_opts), C.sizeof(ibmg.ibmg_stats),
             ibmg.ibmg_problem.fiber_offsets.offset, ibmg.ibmg_problem.K.offset, ibmg.ibmg_opts.rtol.offset,
             ibmg.ibmg_stats.t_step_ms.offset, ibmg.ibmg_opts.colours.offset,
-            ibmg.ibmg_opts.tail_max.offset, ibmg.ibmg_stats.rel_resid_est.offset]
+            ibmg.ibmg_opts.tail_max.offset, ibmg.ibmg_stats.rel_resid_est.offset,
+            ibmg.ibmg_stats.guess_rejected.offset]
     assert got == want
 
 
@@ -141,3 +142,19 @@ def test_batch_create_validates_without_gpu():
     assert make([32, 48], [0, 0], [4, 5])[0] == -2   # one bad grid
     h = C.c_void_p()
     assert L.ibmg_batch_create(C.byref(h), 0, None, None, None) == -1
+
+
+
+def test_cnn_create_validates_without_gpu():
+    ibmg, L = _lib()
+    h = C.c_void_p()
+    assert L.ibmg_cnn_create(C.byref(h), 64, 4, None) == 0
+    n = C.c_size_t()
+    assert L.ibmg_cnn_workspace_bytes(h, C.byref(n)) == 0
+    # parameters, moments, gradient (4 x 39331 FP32) and the pair store (4 x 8 x 64^2 FP32) at least
+    assert n.value >= 4 * 39331 * 4 + 4 * 8 * 64 * 64 * 4
+    assert L.ibmg_cnn_infer(h, None, None) == -4          # unbound
+    assert L.ibmg_cnn_destroy(h) == 0
+    assert L.ibmg_cnn_create(C.byref(h), 48, 4, None) == -2
+    assert L.ibmg_cnn_create(C.byref(h), 8, 4, None) == -2
+    assert L.ibmg_cnn_create(C.byref(h), 64, 0, None) == -1

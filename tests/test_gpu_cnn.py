@@ -1,0 +1,188 @@
+"""GPU parity of the warm-start network (ibmg_cnn_*) against the oracle
+(oracle/cnn.py with its BF16 rounding points emulated), the guarded step
+with a proposed initial iterate, and the gain of the trained network on a
+short trajectory.
+
+Tolerances: the GPU accumulates in FP32 and the oracle in FP64 on the same
+BF16-rounded weights and activations, so a hidden activation can round to a
+neighbouring BF16 value (relative step 2^-8); outputs and gradients are
+compared in relative L2 norm at 2e-2, the loss at 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import DEV, make, tdev, tnp
+
+pytestmark = pytest.mark.gpu
+
+import ibgen  # noqa: E402
+from oracle import cnn as ocnn  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_5614_amd import ibmg  # noqa: F401  (raises if the library is missing)
+
+
+def _net(N, pairs=4, seed=3, last_scale=0.05):
+    from paper_1311_5614_amd import ibmg
+    th = ibgen.cnn_init(seed).astype(np.float64)
+    # give the (zero-initialised) last layer weights so every layer carries signal
+    rng = np.random.default_rng(seed + 1)
+    L = ocnn.unpack(th)
+    W6, b6 = L[-1]
+    L[-1] = (rng.standard_normal(W6.shape) * last_scale, rng.standard_normal(b6.shape) * 0.01)
+    th = ocnn.pack(L).astype(np.float32)
+    c = ibmg.Cnn(N, pairs, DEV)
+    c.set_params(th)
+    c.set_scales(np.ones(5), np.ones(3))
+    return c, th.astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+@pytest.mark.parametrize("N", [16, 64])
+def test_forward_matches_oracle(N):
+    c, th = _net(N)
+    x = np.random.default_rng(5).standard_normal((5, N, N))
+    y = tnp(c.infer(tdev(x)))
+    _, yo = ocnn.forward(th, x, emulate_bf16=True)
+    assert _rel(y, yo) < 2e-2
+
+
+def test_loss_and_gradient_match_oracle():
+    N = 32
+    c, th = _net(N)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((5, N, N))
+    t = rng.standard_normal((3, N, N)) * 0.1
+    loss, g = c.loss_grad(tdev(x), tdev(t))
+    Lo, go = ocnn.loss_grad(th, x, t, emulate_bf16=True)
+    assert abs(loss - Lo) <= 1e-3 * Lo
+    off = 0
+    for ci, co in ocnn.LAYERS:
+        n = co * ci * 9 + co
+        assert _rel(g[off:off + n], go[off:off + n]) < 2e-2, (ci, co)
+        off += n
+
+
+def test_adam_training_step_matches_oracle():
+    N = 16
+    c, th = _net(N, pairs=2)
+    rng = np.random.default_rng(7)
+    xs = [rng.standard_normal((5, N, N)) for _ in range(2)]
+    ts = [rng.standard_normal((3, N, N)) * 0.1 for _ in range(2)]
+    for x, t in zip(xs, ts):
+        c.record(tdev(x), tdev(t))
+    lr = 1e-3
+    c.train(1, lr)
+    got = c.get_params()
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    ref = th.copy()
+    for k, (x, t) in enumerate(zip(xs, ts)):
+        _, g = ocnn.loss_grad(ref, x, t, emulate_bf16=True)
+        ref, m, v = ocnn.adam(ref, m, v, g, k + 1, lr)
+    step_gpu, step_ref = got - th, ref - th
+    assert _rel(step_gpu, step_ref) < 5e-2
+
+
+def test_training_lowers_the_loss_and_scales_are_rms():
+    N = 32
+    from paper_1311_5614_amd import ibmg
+    c = ibmg.Cnn(N, 6, DEV)
+    c.set_params(ibgen.cnn_init(11))
+    rng = np.random.default_rng(8)
+    yy, xx = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    xs, ts = [], []
+    for k in range(6):
+        ph = rng.uniform(0, 2 * np.pi, size=5)
+        x = np.stack([np.sin(2 * np.pi * (xx + 3 * yy) / N + ph[i]) * (i + 1) for i in range(5)])
+        t = 0.1 * np.stack([x[0] - x[3], x[1] + x[4], 0.5 * x[2]])   # a local linear map
+        xs.append(x)
+        ts.append(t)
+        c.record(tdev(x), tdev(t))
+    lf, ll = c.train(40, 2e-3)
+    assert ll < 0.5 * lf, (lf, ll)
+    s = c.get_scales()
+    X = np.stack(xs)
+    T = np.stack(ts)
+    assert np.allclose(s[:5], np.sqrt((X ** 2).mean(axis=(0, 2, 3))), rtol=1e-4)
+    assert np.allclose(s[5:], np.sqrt((T ** 2).mean(axis=(0, 2, 3))), rtol=1e-4)
+
+
+def test_guarded_step():
+    from paper_1311_5614_amd import ibmg
+    w, dt, s = make(N=32, levels=4, M=64, K=1e4, dt_factor=20.0, rtol=1e-10)
+    z = torch.zeros(32, 32, dtype=torch.float64, device=DEV)
+    # reference: plain step from w^n = 0
+    u0, v0, p0, X0 = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    st0 = s.step(dt, u0, v0, p0, X0)
+    # a proposal equal to w^n carries no direction: dropped, identical to the plain step
+    u1, v1, p1, X1 = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    st1 = s.step_x0(dt, u1, v1, p1, X1, torch.zeros(3 * 32 * 32, dtype=torch.float64, device=DEV))
+    assert st1["guess_rejected"] == 1 and st1["iters"] == st0["iters"]
+    assert torch.equal(u0, u1) and torch.equal(v0, v1) and torch.equal(X0, X1)
+    # a scaled solution is rescaled by alpha to (nearly) the solution itself
+    u3, v3, p3, X3 = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    sol3 = 7.0 * torch.cat([u0.ravel(), v0.ravel(), p0.ravel()])
+    st3 = s.step_x0(dt, u3, v3, p3, X3, sol3)
+    assert abs(st3["guess_alpha"] - 1.0 / 7.0) < 1e-6 and st3["iters"] <= 2
+    # the converged solution as proposal: accepted, nothing left to do
+    u2, v2, p2, X2 = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    sol = torch.cat([u0.ravel(), v0.ravel(), p0.ravel()])
+    st2 = s.step_x0(dt, u2, v2, p2, X2, sol)
+    assert st2["guess_rejected"] == 0 and st2["iters"] <= 1 and st2["converged"] == 1
+    assert abs(st2["guess_alpha"] - 1.0) < 1e-6
+    assert float((u2 - u0).abs().max()) <= 1e-9 * float(u0.abs().max())
+
+
+def test_learned_guess_gain_on_a_trajectory():
+    """Train on the first steps of a 64x64 trajectory, then compare the
+    remaining steps started from w^n + alpha Dw against the same steps started
+    from w^n: the guard keeps every start at or below the residual of w^n, and
+    the solves need no more iterations in total."""
+    from paper_1311_5614_amd import ibmg
+    N, M = 64, 160
+    w = ibgen.small_case(N=N, M=M, K=1e5, seed=21, levels=5, with_force=True)
+    from oracle import dtexp
+    dt = 200.0 * dtexp.dt_explicit(w.X, w.fiber_offsets, N, 1e5)
+    cfg = ibmg.Config(N=N, levels=5, K=1e5, rtol=1e-8, maxit=200, guess=ibmg.IBMG_GUESS_PREV)
+    s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    net = ibmg.Cnn(N, 40, DEV)
+    net.set_params(ibgen.cnn_init(5))
+    z = torch.zeros(N, N, dtype=torch.float64, device=DEV)
+    u, v, p, X = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    gu, gv = tdev(w.g_u), tdev(w.g_v)
+
+    def features():
+        G = s.fiber_force(X)
+        fu, fv = s.spread(X, G)
+        return torch.stack([u, v, p, fu, fv]).contiguous()
+
+    for _ in range(30):
+        f = features()
+        old = torch.stack([u, v, p]).clone()
+        s.step(dt, u, v, p, X, gu, gv)
+        net.record(f, (torch.stack([u, v, p]) - old).contiguous())
+    lf, ll = net.train(30, 1e-3)
+    assert ll < lf
+    it_prev, it_cnn, rejected, alphas = 0, 0, 0, []
+    for _ in range(10):
+        f = features()
+        state = [t.clone() for t in (u, v, p, X)]
+        st = s.step(dt, *state, gu, gv)           # started from w^n
+        it_prev += st["iters"]
+        x0 = (torch.stack([u, v, p]) + net.infer(f)).reshape(-1).contiguous()
+        st2 = s.step_x0(dt, u, v, p, X, x0, gu, gv)
+        it_cnn += st2["iters"]
+        rejected += st2["guess_rejected"]
+        alphas.append(round(st2["guess_alpha"], 3))
+        assert st2["converged"] == 1
+    print(f"learned guess: iterations {it_cnn} vs {it_prev} from w^n, {rejected}/10 proposals dropped, "
+          f"alpha {alphas}, loss {lf:.3e} -> {ll:.3e}")
+    assert it_cnn <= it_prev
