@@ -35,7 +35,42 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MAXIT = 200   # FGMRES iteration cap (no restart below it)
+BOX_REPS = 200   # back-to-back box launches timed for the roofline
 METRIC = "IB time-steps/sec and FGMRES iters/solve at rel resid 1e-8, plain vs chosen"
+
+
+BOX_SOURCES = ("paper_1311_5614_amd/csrc/level_ops.h", "paper_1311_5614_amd/csrc/mg.hip",
+               "paper_1311_5614_amd/csrc/common.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_box_traffic.txt")
+
+
+def box_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in BOX_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch of the timed box launch from the committed
+    rocprofv3 counter summary (FETCH_SIZE, WRITE_SIZE scaled by the copy
+    calibration), or None if the summary is for another launch or the box
+    kernel's sources changed since the counters were taken."""
+    if not launch or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.strip().split("=", 1)
+                kv[k] = v
+    if kv.get("kernel_source_sha1") != box_source_hash():
+        return None
+    if kv.get("launch") != f"k_box<{'float' if launch['prec'] == 'fp32' else 'double'}> level 0 grid {launch['grid']}":
+        return None
+    return float(kv["traffic_bytes"])
 
 
 def load_dt(key):
@@ -51,8 +86,6 @@ def workloads(name):
         return cases, [d["dt"] for d in dts]
     if name == "c1":
         return [ibgen.config_c1()], [load_dt("c1")[0]["dt"]]
-    if name == "c5":
-        return [ibgen.config_c5()], [load_dt("c5")[0]["dt"]]
     if name == "c3":
         return [ibgen.config_c3()], [load_dt("c3")[0]["dt"]]
     if name == "c4":
@@ -228,27 +261,116 @@ def timed(runs, steps, warmup, timing=False):
     return t, its, conv, ph
 
 
-def cpu_baseline(w, dt, budget_note):
-    """Oracle (plain numpy/scipy, FP64) on one time step of one case."""
+def cpu_baseline(w, dt, budget_note, steps=3):
+    """Oracle (plain numpy/scipy, FP64): `steps` time steps of one case."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import step as ostep
     N = w.N
-    z = np.zeros((N, N))
+    u = v = p = np.zeros((N, N))
+    X = w.X
+    its = []
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        o = ostep.step(z, z, z, w.X, w.fiber_offsets, w.K, dt, w.levels, w.rho, w.mu, w.box, w.nu1,
-                       w.nu2, w.rtol, g_u=w.g_u, g_v=w.g_v)
+        for _ in range(steps):
+            o = ostep.step(u, v, p, X, w.fiber_offsets, w.K, dt, w.levels, w.rho, w.mu, w.box, w.nu1,
+                           w.nu2, w.rtol, g_u=w.g_u, g_v=w.g_v)
+            u, v, p, X = o.u, o.v, o.p, o.X
+            its.append(o.iters)
         t = time.perf_counter() - t0
-    return {"value": 1.0 / t, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 implicit step of {w.name} ({o.iters} FGMRES iterations, {t:.1f} s); "
+    return {"value": steps / t, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} implicit steps of {w.name} ({its} FGMRES iterations, {t:.1f} s); "
                       f"1 BLAS thread; {budget_note}"}
 
+
+def run_learned(args, dev):
+    """The 512x512 learned-warm-start trajectory: steps 1..H from w^n (guess
+    PREV) recording (features, w^{n+1} - w^n) pairs, training the network on
+    the GPU, then steps H+1..2H three ways from the same state at step H:
+    from w^n + alpha Dw (learned), from w^n, and from zero."""
+    import torch
+    from paper_1311_5614_amd import ibmg
+    import ibgen
+    w = ibgen.config_c5()
+    dt = load_dt("c5")[0]["dt"]
+    H = args.steps or 200        # half-trajectory length (default 200 of 400)
+    N = w.N
+    cfg = lambda guess: ibmg.Config(N=N, levels=7, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2, maxit=MAXIT,
+                                    rtol=w.rtol, prec=ibmg.IBMG_FP32, guess=guess, tail_max=1)
+    s = ibmg.Solver(cfg(ibmg.IBMG_GUESS_PREV), w.fiber_offsets, dev)
+    s0 = ibmg.Solver(cfg(ibmg.IBMG_GUESS_ZERO), w.fiber_offsets, dev)
+    net = ibmg.Cnn(N, H, dev)
+    net.set_params(ibgen.cnn_init(ibgen.seed_for(5, 1)))
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+    gu, gv = t(w.g_u), t(w.g_v)
+    z = torch.zeros(N, N, dtype=torch.float64, device=dev)
+    u, v, p, X = z.clone(), z.clone(), z.clone(), t(w.X)
+
+    def features(U, V, Pp, XX):
+        G = s.fiber_force(XX)
+        fu, fv = s.spread(XX, G)
+        return torch.stack([U, V, Pp, fu, fv]).contiguous()
+
+    t0 = time.perf_counter()
+    its_train = []
+    for n in range(H):
+        f = features(u, v, p, X)
+        old = torch.stack([u, v, p]).clone()
+        st = s.step(dt, u, v, p, X, gu, gv)
+        its_train.append(st["iters"])
+        net.record(f, (torch.stack([u, v, p]) - old).contiguous())
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss_first, loss_last = net.train(args.epochs, args.lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    start = [a.clone() for a in (u, v, p, X)]
+    res = {}
+    for form in ("learned", "prev", "zero"):
+        u, v, p, X = (a.clone() for a in start)
+        its, conv, alphas = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(H):
+            if form == "learned":
+                f = features(u, v, p, X)
+                x0 = (torch.stack([u, v, p]) + net.infer(f)).reshape(-1).contiguous()
+                st = s.step_x0(dt, u, v, p, X, x0, gu, gv)
+                alphas.append(st["guess_alpha"])
+            elif form == "prev":
+                st = s.step(dt, u, v, p, X, gu, gv)
+            else:
+                st = s0.step(dt, u, v, p, X, gu, gv)
+            its.append(st["iters"])
+            conv.append(st["converged"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[form] = dict(time_s=el, timesteps=H, rate=H / el, iters_mean=sum(its) / H, iters_max=max(its),
+                         converged=sum(conv))
+        if alphas:
+            res[form]["alpha_mean"] = sum(alphas) / len(alphas)
+        print(f"[bench] c5 {form}: {H} steps in {el:.3f} s -> {H / el:.2f} steps/s, iters mean "
+              f"{res[form]['iters_mean']:.2f}, converged {sum(conv)}/{H}", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC, "value": res["learned"]["rate"], "unit": "time-steps/s", "n_gpus": 1,
+        "steps": H, "warmup": 0, "ms_per_step": 1e3 * res["learned"]["time_s"] / H,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: steps 1-{H} record and train, steps {H + 1}-{2 * H} timed",
+                   "grid": N, "points": w.M, "K": w.K, "dt_factor": w.dt_factor,
+                   "chosen_form": "learned initial iterate (w^n + alpha Dw) in fp64 FGMRES, fp32 V-cycle"},
+        "forms": res,
+        "training": {"pairs": H, "epochs": args.epochs, "lr": args.lr, "loss_first": loss_first,
+                     "loss_last": loss_last, "train_s": t_train, "first_half_s": t_first,
+                     "first_half_iters_mean": sum(its_train) / H},
+    }
+    print(json.dumps(out))
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; c5: half-trajectory 200)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
@@ -257,6 +379,8 @@ def main():
     ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
     ap.add_argument("--colours", type=int, default=2)
     ap.add_argument("--tail-max", type=int, default=0, help="override the V-cycle tail size")
+    ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs of the warm-start network")
+    ap.add_argument("--lr", type=float, default=1e-3, help="c5: Adam learning rate")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy a device buffer of this many MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -276,6 +400,9 @@ def main():
     import torch
     from paper_1311_5614_amd import ibmg
     dev = "cuda:0"
+    if args.workload == "c5":
+        return run_learned(args, dev)
+    args.steps = args.steps or 20
     cases, dts = workloads(args.workload)
     for c in cases:
         if args.levels:
@@ -315,9 +442,18 @@ def main():
         t, its, conv, _ = timed(runs, args.steps, args.warmup, timing=False)
         failed = dict(timed.failed)
         per_case = [round(sum(x) / max(1, len(x)), 1) for x in timed.per_case]
-        # roofline of the box kernel: the same trajectories, one more (untimed)
-        # step with every box launch bracketed by HIP events on its stream
-        _, _, _, ph = timed(runs, 1, 0, timing=True)
+        # roofline of the box kernel: on the finest level of the first
+        # trajectory in the form's V-cycle precision, BOX_REPS back-to-back
+        # launches between two HIP events on the solver's stream
+        ph = None
+        main_prec = max(set(precs), key=precs.count)
+        rb = next((k for k, pr in enumerate(precs) if k not in failed and pr == main_prec), None)
+        if rb is not None:
+            r = runs[rb]
+            r.s.setup(r.dt, r.X)
+            us, by = r.s.box_bench(0, 0, BOX_REPS)
+            ph = dict(avg_us=us, bytes=by, level=0, grid=r.w.N, case=r.w.name,
+                      prec="fp32" if precs[rb] == ibmg.IBMG_FP32 else "fp64", reps=BOX_REPS)
         n = sum(1 for _ in its) - (1 if failed else 0)   # completed implicit steps
         res[form] = dict(time_s=t, timesteps=n, rate=n / t, iters_mean=sum(its) / max(1, n), iters_max=max(its),
                          converged=sum(conv), phase=ph, failed=failed)
@@ -329,8 +465,8 @@ def main():
         torch.cuda.empty_cache()
     chosen = next((f for f in ("batch", "tuned", "fp32") if f in res), forms[0])
     rc = res[chosen]
-    ph = next((res[f]["phase"] for f in (chosen, "fp32", "plain") if f in res and res[f]["phase"]), None)
-    achieved = ph["bytes"] / (ph["total_ms"] * 1e-3) / 1e9 if ph and ph["total_ms"] > 0 else None
+    ph = next((res[f]["phase"] for f in (chosen, "tuned", "fp32", "plain") if f in res and res[f]["phase"]), None)
+    achieved = ph["bytes"] / (ph["avg_us"] * 1e-6) / 1e9 if ph else None
     w0 = cases[0]
     out = {
         "metric": METRIC,
@@ -364,9 +500,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": None,
-            "launches": ph["launches"] if ph else 0,
-            "avg_launch_us": 1e3 * ph["total_ms"] / ph["launches"] if ph and ph["launches"] else None,
+            "traffic": measured_traffic(ph),
+            "launch": ph,
         },
     }
     if not args.no_cpu:

@@ -134,6 +134,15 @@ const char* ibmg_status_string(int status);
  * handle's stream (1 = on).  ibmg_phase_timing reads the accumulated total
  * (ms), the number of launches timed and their algorithmic bytes. */
 int ibmg_set_timing(ibmg_handle* h, int on);
+/* Kernel timing of the box-relaxation kernel alone: `reps` back-to-back
+ * launches of colour `colour` on level `level` (in place on the level's
+ * V-cycle iterate, in the handle's V-cycle precision), captured as a graph
+ * and replayed (after one warm-up replay) between two HIP events on the
+ * handle's stream.  avg_us: mean duration per launch; bytes: the
+ * launch's algorithmic bytes (read residual and iterate, write iterate, per
+ * unknown of the colour's boxes; the shared inverse once; each FP64 inverse
+ * of a box with elastic rows once).  Needs a setup.  Synchronises. */
+int ibmg_box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, double* bytes);
 int ibmg_phase_timing(ibmg_handle* h, double* total_ms, int64_t* launches, double* bytes);
 
 /* Operator setup at positions X (Sec. 2.3.2 lags S at X^n; Sec. 3.2 builds the

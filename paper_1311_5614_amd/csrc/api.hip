@@ -673,6 +673,64 @@ int ibmg_phase_timing(ibmg_handle* h, double* total_ms, int64_t* launches, doubl
   return IBMG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, double* bytes) {
+  LevelView<T> v = view<T>(h, level);
+  T* w = (level == 0 && h->prec == IBMG_FP64) ? h->p<T>(h->w0g) : h->p<T>(h->L[level].w);
+  T* r = h->p<T>(h->L[level].r);
+  // the launches are captured into a graph and replayed between the events,
+  // so that host launch overhead does not leave the GPU idle between them
+  if (!h->cap) return IBMG_ESTATE;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  IBMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  for (int q = 0; q < reps; ++q) launch_box<T>(h->cap, v, r, w, colour, h->has_ib);
+  IBMG_HIP(hipStreamEndCapture(h->cap, &g));
+  if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return IBMG_EHIP;
+  }
+  hipEvent_t e0, e1;
+  IBMG_HIP(hipEventCreate(&e0));
+  IBMG_HIP(hipEventCreate(&e1));
+  IBMG_HIP(hipGraphLaunch(ge, h->stream));   // warm-up replay
+  IBMG_HIP(hipEventRecord(e0, h->stream));
+  IBMG_HIP(hipGraphLaunch(ge, h->stream));
+  IBMG_HIP(hipEventRecord(e1, h->stream));
+  IBMG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  const hipError_t e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(ge);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return IBMG_EHIP;
+  if (avg_us) *avg_us = 1e3 * (double)ms / reps;
+  if (bytes) {
+    const double boxes = colour_count(v.ncol, v.nb);
+    double by = boxes * v.ndof * 3.0 * sizeof(T) + (double)v.ndof * v.ndof * sizeof(T);
+    if (h->has_ib) by += (double)h->n_ib[level][colour] * v.ndof * v.ndof * sizeof(double);
+    *bytes = by;
+  }
+  return IBMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibmg_box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, double* bytes) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!h->setup_ok) return IBMG_ESTATE;
+  if (level < 0 || level + 1 >= h->levels || colour < 0 || colour >= h->ncol || reps < 1) return IBMG_EINVAL;
+  return h->prec == IBMG_FP32 ? box_bench<float>(h, level, colour, reps, avg_us, bytes)
+                              : box_bench<double>(h, level, colour, reps, avg_us, bytes);
+}
+
 int ibmg_setup(ibmg_handle* h, double dt, const double* X) {
   if (!ready(h)) return IBMG_ENOMEM;
   return do_setup(h, dt, X);

@@ -27,7 +27,7 @@ IBMG_GUESS_ZERO, IBMG_GUESS_PREV = 0, 1
 
 EXPORTS = [
     "ibmg_create", "ibmg_workspace_bytes", "ibmg_bind_workspace", "ibmg_destroy",
-    "ibmg_status_string", "ibmg_set_timing", "ibmg_phase_timing", "ibmg_setup", "ibmg_step",
+    "ibmg_status_string", "ibmg_set_timing", "ibmg_phase_timing", "ibmg_box_bench", "ibmg_setup", "ibmg_step",
     "ibmg_rhs", "ibmg_solve", "ibmg_apply", "ibmg_residual", "ibmg_smooth", "ibmg_restrict",
     "ibmg_prolong_add", "ibmg_coarse_solve", "ibmg_vcycle", "ibmg_box_matrix",
     "ibmg_fiber_force", "ibmg_spread", "ibmg_interp",
@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ibmg_status_string": [i32],
         "ibmg_set_timing": [vp, i32],
         "ibmg_phase_timing": [vp, C.POINTER(dbl), C.POINTER(C.c_int64), C.POINTER(dbl)],
+        "ibmg_box_bench": [vp, i32, i32, i32, C.POINTER(dbl), C.POINTER(dbl)],
         "ibmg_setup": [vp, dbl, vp],
         "ibmg_step": [vp, dbl, vp, vp, vp, vp, vp, vp, C.POINTER(ibmg_stats)],
         "ibmg_rhs": [vp, vp, vp, vp, vp, vp],
@@ -305,6 +306,11 @@ class Solver:
         U = torch.empty_like(X)
         _check(lib().ibmg_interp(self.h, _ptr(X), _ptr(u), _ptr(v), _ptr(U)), "ibmg_interp")
         return U
+
+    def box_bench(self, level, colour, reps):
+        us, by = C.c_double(), C.c_double()
+        _check(lib().ibmg_box_bench(self.h, level, colour, reps, C.byref(us), C.byref(by)), "ibmg_box_bench")
+        return us.value, by.value
 
     def set_timing(self, on=True):
         _check(lib().ibmg_set_timing(self.h, 1 if on else 0), "ibmg_set_timing")
