@@ -73,6 +73,15 @@ struct BSet {
   const double* beta;     // initial residual norm of each slot
 };
 
+// XCD-aware order of a launch's work items: with workgroups dispatched to
+// the eight XCDs round-robin, item t is taken as item xcd_order(t, total) so
+// that each XCD walks a contiguous share of the (problem, block) list and
+// neighbouring blocks share an L2.  A bijection on [0, total).
+__device__ inline int xcd_order(int t, int total) {
+  const int m = total >> 3, r = total & 7, x = t & 7, k = t >> 3;
+  return x * m + (x < r ? x : r) + k;
+}
+
 __device__ inline int seg_find(const int* __restrict__ off, int n, int t) {
   int lo = 0, hi = n;   // off[lo] <= t < off[hi]
   while (hi - lo > 1) {
@@ -103,7 +112,8 @@ template <typename T, int KIND>
 __global__ void __launch_bounds__(256)
 kb_level(const BLv<T>* __restrict__ lv, const int* __restrict__ ls, int P, int k, const int* __restrict__ off) {
   const int total = off[P];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+  for (int tt = blockIdx.x; tt < total; tt += gridDim.x) {
+    const int t = xcd_order(tt, total);
     const int p = seg_find(off, P, t);
     const int blk = t - off[p];
     const BLv<T>& e = lv[(size_t)(KIND == OP_FILL0 ? ls[p] - 1 : k) * P + p];
@@ -128,7 +138,8 @@ template <typename T>
 __global__ void __launch_bounds__(64)
 kb_box(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __restrict__ off) {
   const int total = off[P];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+  for (int tt = blockIdx.x; tt < total; tt += gridDim.x) {
+    const int t = xcd_order(tt, total);
     const int p = seg_find(off, P, t);
     const BLv<T>& e = lv[(size_t)k * P + p];
     box_body<T>(e.L, e.r, e.w, colour, t - off[p]);

@@ -10,10 +10,20 @@
 
 #include "level_ops.h"
 
+// Workgroups are dispatched to the eight XCDs round-robin by id, and each XCD
+// has its own L2.  Block b of n runs work item xcd_remap(b, n): XCD x gets the
+// x-th contiguous share of the items (a band of rows or of box rows), so
+// neighbouring items that share cache lines share an L2.  A bijection on
+// [0, n).
+__device__ inline int xcd_remap(int b, int n) {
+  const int m = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+  return x * m + (x < r ? x : r) + k;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_residual(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* __restrict__ r) {
-  residual_body<T>(L, b, w, r, blockIdx.x);
+  residual_body<T>(L, b, w, r, xcd_remap(blockIdx.x, gridDim.x));
 }
 template <typename T>
 __global__ void __launch_bounds__(256) k_ib_rows(LevelView<T> L, const T* __restrict__ w, T* __restrict__ out, int mode) {
@@ -22,11 +32,12 @@ __global__ void __launch_bounds__(256) k_ib_rows(LevelView<T> L, const T* __rest
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_res_ib(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* __restrict__ r, int nres_blocks) {
-  res_ib_body<T>(L, b, w, r, nres_blocks, blockIdx.x);
+  const int blk = blockIdx.x;
+  res_ib_body<T>(L, b, w, r, nres_blocks, blk < nres_blocks ? xcd_remap(blk, nres_blocks) : blk);
 }
 template <typename T>
 __global__ void __launch_bounds__(64) k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour) {
-  box_body<T>(L, r, w, colour, blockIdx.x);
+  box_body<T>(L, r, w, colour, xcd_remap(blockIdx.x, gridDim.x));
 }
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int Nf, const T* __restrict__ rf, T* __restrict__ rc,
