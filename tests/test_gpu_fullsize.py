@@ -1,0 +1,152 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configurations
+bench.py times: the operator of every level at 256x256 and the finest one at
+1024x1024 against the oracle's assembled matrices (every element), one step
+of the 256x256 sweep with the autotuned schedule judged by the oracle's own
+operator and interpolation, a batch step over problems of every grid size of
+the 64-problem workload, and the warm-start network at 512x512 against the
+oracle's forward pass plus its translation property."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import DEV, tdev, tnp
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+import ibgen  # noqa: E402
+from oracle import cnn as ocnn, ib, system  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_5614_amd import ibmg  # noqa: F401  (raises if the library is missing)
+
+
+def _dts(key):
+    with open(os.path.join(ROOT, "tests", "golden", "workload_dt.json")) as f:
+        return [d["dt"] for d in json.load(f)[key]]
+
+
+def _schedule(workload, key):
+    from paper_1311_5614_amd import autotune
+    return autotune.load()[workload][key]
+
+
+def _rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _solver(w, levels, prec=0, **kw):
+    from paper_1311_5614_amd import ibmg
+    cfg = ibmg.Config(N=w.N, levels=levels, K=w.K, box=4, maxit=200, rtol=w.rtol, prec=prec, **kw)
+    return ibmg.Solver(cfg, w.fiber_offsets, DEV)
+
+
+def test_c2_operator_every_level():
+    cases, dts = ibgen.config_c2_cases(), _dts("c2")
+    w, dt = cases[5], dts[5]                      # K = 1e6, 1000 x dt_exp
+    s = _solver(w, w.levels)
+    s.setup(dt, tdev(w.X))
+    lv = system.hierarchy(w.N, w.levels, 1.0, 1.0, dt, w.X, w.fiber_offsets, w.K, 0)
+    rng = np.random.default_rng(20)
+    for l in range(w.levels):
+        x = rng.standard_normal(lv[l].A.shape[0])
+        y = tnp(s.apply(l, tdev(x)))
+        assert _rel(y, lv[l].A @ x) < 1e-12, l
+
+
+def test_c3_operator_finest_level():
+    w = ibgen.config_c3()
+    dt = _dts("c3")[0]
+    s = _solver(w, w.levels)
+    s.setup(dt, tdev(w.X))
+    lv = system.hierarchy(w.N, 1, 1.0, 1.0, dt, w.X, w.fiber_offsets, w.K, 0)
+    x = np.random.default_rng(21).standard_normal(lv[0].A.shape[0])
+    assert _rel(tnp(s.apply(0, tdev(x))), lv[0].A @ x) < 1e-12
+
+
+@pytest.mark.parametrize("case", [2, 5])
+def test_c2_tuned_step_meets_tolerance_in_oracle_norm(case):
+    from paper_1311_5614_amd import ibmg
+    cases, dts = ibgen.config_c2_cases(), _dts("c2")
+    w, dt = cases[case], dts[case]
+    sch = _schedule("c2", f"{w.K:.0e}-{int(w.dt_factor)}")
+    s = _solver(w, sch["levels"], prec=sch["prec"], nu1=sch["nu1"], nu2=sch["nu2"], colours=sch["colours"],
+                tail_max=sch["tail_max"])
+    z = torch.zeros(w.N, w.N, dtype=torch.float64, device=DEV)
+    u, v, p, X = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    st = s.step(dt, u, v, p, X, tdev(w.g_u), tdev(w.g_v))
+    assert st["converged"] == 1
+    lv = system.hierarchy(w.N, 1, 1.0, 1.0, dt, w.X, w.fiber_offsets, w.K, 0)
+    zz = np.zeros((w.N, w.N))
+    b = system.rhs(zz, zz, w.X, w.fiber_offsets, w.K, dt, 1.0, g_u=w.g_u, g_v=w.g_v)
+    sol = np.concatenate([tnp(u).ravel(), tnp(v).ravel(), tnp(p).ravel()])
+    rr = np.linalg.norm(b - lv[0].A @ sol) / np.linalg.norm(b)
+    assert rr <= 1.02 * w.rtol, rr
+    # positions: X^{n+1} = X^n + dt S^*(X^n) u^{n+1}, oracle interpolation of the GPU velocity
+    U = ib.interp(w.X, tnp(u), tnp(v), 0)
+    assert np.max(np.abs(tnp(X) - (w.X + dt * U))) <= 1e-12 * max(1.0, np.max(np.abs(w.X)))
+
+
+def test_c4_batch_step_every_grid_size():
+    from paper_1311_5614_amd import ibmg
+    cases, dts = ibgen.config_c4(), _dts("c4")
+    pick, seen = [], set()
+    for k, c in enumerate(cases):
+        if c.N not in seen:
+            seen.add(c.N)
+            pick.append(k)
+    assert sorted(seen) == [64, 128, 256, 512]
+    cfgs, ws = [], []
+    for k in pick:
+        c = cases[k]
+        sch = _schedule("c4", str(c.N))
+        cfgs.append(ibmg.Config(N=c.N, levels=sch["levels"], K=c.K, box=4, nu1=sch["nu1"], nu2=sch["nu2"],
+                                maxit=200, rtol=c.rtol, prec=ibmg.IBMG_FP32, colours=sch["colours"],
+                                tail_max=sch["tail_max"]))
+        ws.append(c)
+    B = ibmg.Batch(cfgs, [c.fiber_offsets for c in ws], DEV)
+    st = [[torch.zeros(c.N, c.N, dtype=torch.float64, device=DEV) for _ in range(3)] + [tdev(c.X)] for c in ws]
+    out = B.step([dts[k] for k in pick], [x[0] for x in st], [x[1] for x in st], [x[2] for x in st],
+                 [x[3] for x in st])
+    for c, k, (u, v, p, X), o in zip(ws, pick, st, out):
+        assert o["converged"] == 1
+        dt = dts[k]
+        lv = system.hierarchy(c.N, 1, 1.0, 1.0, dt, c.X, c.fiber_offsets, c.K, 0)
+        zz = np.zeros((c.N, c.N))
+        b = system.rhs(zz, zz, c.X, c.fiber_offsets, c.K, dt, 1.0)
+        sol = np.concatenate([tnp(u).ravel(), tnp(v).ravel(), tnp(p).ravel()])
+        rr = np.linalg.norm(b - lv[0].A @ sol) / np.linalg.norm(b)
+        assert rr <= 1.02 * c.rtol, (c.N, rr)
+    B.close()
+
+
+def test_c5_network_forward_full_size():
+    from paper_1311_5614_amd import ibmg
+    N = 512
+    th = ibgen.cnn_init(ibgen.seed_for(5, 1)).astype(np.float64)
+    rng = np.random.default_rng(22)
+    L = ocnn.unpack(th)
+    W6, b6 = L[-1]
+    L[-1] = (rng.standard_normal(W6.shape) * 0.05, rng.standard_normal(b6.shape) * 0.01)
+    th = ocnn.pack(L).astype(np.float32)
+    net = ibmg.Cnn(N, 1, DEV)
+    net.set_params(th)
+    net.set_scales(np.ones(5), np.ones(3))
+    yy, xx = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    x = np.stack([np.sin(2 * np.pi * (k + 1) * (xx + 2 * yy) / N) + 0.1 * rng.standard_normal((N, N))
+                  for k in range(5)])
+    y = tnp(net.infer(tdev(x)))
+    _, yo = ocnn.forward(th.astype(np.float64), x, emulate_bf16=True)
+    assert float(np.linalg.norm(y - yo) / np.linalg.norm(yo)) < 2e-2
+    # periodic translation: the output moves with the input, bit for bit
+    ys = tnp(net.infer(tdev(np.roll(x, (37, -5), axis=(1, 2)))))
+    assert np.array_equal(ys, np.roll(y, (37, -5), axis=(1, 2)))
