@@ -60,7 +60,7 @@ void layout(ibmg_handle* h) {
       take(cur, B.nact, 2 * sizeof(int));
       take(cur, B.win, 2 * (size_t)B.maxact * IBMG_WS * sizeof(double));
       if (h->prec == IBMG_FP32) take(cur, B.winf, 2 * (size_t)B.maxact * IBMG_WS * sizeof(float));
-      take(cur, B.yib, 2 * (size_t)B.maxact * sizeof(double));
+      take(cur, B.yib, 2 * NN * sizeof(double));
     }
     if (l < h->levels - 1) {
       const size_t nbox = (size_t)B.nb * B.nb;
@@ -238,7 +238,7 @@ void precond(ibmg_handle* h, const double* r, double* z) {
     if (capture_vcycle(h) != IBMG_OK) { h->launch_error = true; return; }
   }
   if (h->prec == IBMG_FP32 && h->fb64) {
-    vcycle<double>(h, r, z);
+    vcycle_fp64(h, r, z);
   } else if (h->prec == IBMG_FP32) {
     k_convert<double, float><<<nblk(n0), 256, 0, h->stream>>>(r, h->p<float>(h->b0f), n0);
     if (graph) {
@@ -319,6 +319,9 @@ int setup_launch(ibmg_handle* h, double dt, const double* X) {
         const size_t nw = 2 * (size_t)B.maxact * IBMG_WS;
         k_convert<double, float><<<nblk(nw), 256, 0, s>>>(h->p<double>(B.win), h->p<float>(B.winf), nw);
       }
+      // elastic rows by face: zero off this step's active rows
+      const size_t ny = 2 * (size_t)B.N * B.N;
+      k_fill<double><<<nblk(ny), 256, 0, s>>>(h->p<double>(B.yib), ny, 0.0);
     }
   }
   for (int l = 0; l + 1 < Lv; ++l) {
@@ -517,7 +520,16 @@ int bind(ibmg_handle* h, void* dev, size_t bytes, bool own_capture_stream) {
   return IBMG_OK;
 }
 
-void vcycle_fp64(ibmg_handle* h, const double* r, double* z) { vcycle<double>(h, r, z); }
+void vcycle_fp64(ibmg_handle* h, const double* r, double* z) {
+  // on an FP32 handle the elastic-row buffers hold FP32 values: read as FP64
+  // off the active rows they would not be zero, so clear them first
+  if (h->prec == IBMG_FP32 && h->has_ib)
+    for (int l = 0; l < h->levels; ++l) {
+      const size_t ny = 2 * (size_t)h->L[l].N * h->L[l].N;
+      k_fill<double><<<nblk(ny), 256, 0, h->stream>>>(h->p<double>(h->L[l].yib), ny, 0.0);
+    }
+  vcycle<double>(h, r, z);
+}
 
 // Right-hand side (a4) into bvec and the initial iterate into xvec.
 int step_begin(ibmg_handle* h, double dt, const double* u, const double* v, const double* p, const double* gu,

@@ -38,7 +38,7 @@ struct LevelView {
   const T* win;   // [2][maxact][WS] windows
   const int* rows;// [2][maxact] face of each active row
   const int* nact;// [2] active rows per component
-  T* yib;         // [2][maxact] (M_l w) on the active rows, formed before each colour phase
+  T* yib;         // [2][N^2] (M_l w) on the active rows, zero elsewhere; formed before each colour phase
   const int* ib_index;  // [nb^2] index of the box among boxes with elastic rows, or -1
   const T* ainv_plain;  // [ndof * ndof] inverse of the plain box block, column-major
   const double* ainv_ib;// [n_ib][ndof * ndof] inverses of boxes with elastic rows, column-major

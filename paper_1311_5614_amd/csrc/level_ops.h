@@ -56,7 +56,7 @@ __device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__
   acc += __shfl_xor(acc, 2, 16);
   acc += __shfl_xor(acc, 1, 16);
   if (lane != 0) return;
-  if (mode == 0) L.yib[comp * L.maxact + row] = acc;
+  if (mode == 0) L.yib[(size_t)comp * NN + f] = acc;
   else if (mode == 1) out[(size_t)comp * NN + f] += acc;
   else out[(size_t)comp * NN + f] -= acc;
 }
@@ -106,7 +106,7 @@ __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ 
   acc += __shfl_xor(acc, 4, 16);
   acc += __shfl_xor(acc, 2, 16);
   acc += __shfl_xor(acc, 1, 16);
-  if (lane == 0) L.yib[comp * L.maxact + row] = acc;
+  if (lane == 0) L.yib[(size_t)comp * NN + f] = acc;
 }
 
 template <typename T>
@@ -124,10 +124,7 @@ __device__ inline void box_body(const LevelView<T>& L, const T* __restrict__ r, 
     box_dof(lane, bx, by, L.n, N, comp, i, j);
     g = (size_t)comp * NN + (size_t)j * N + i;
     T y = r[g];
-    if (ibx >= 0 && comp < 2) {
-      const int a = L.act[comp * NN + j * N + i];
-      if (a >= 0) y -= L.yib[comp * L.maxact + a];
-    }
+    if (ibx >= 0 && comp < 2) y -= L.yib[g];   // zero off the active rows
     res[lane] = (double)y;
   }
   __syncthreads();
@@ -249,7 +246,7 @@ __device__ void small_ib_rows(const LevelView<T>& L, const T* __restrict__ w, T*
     if (L.reach <= 3) acc = win_row<T, 3>(c, x, N, i, j);
     else if (L.reach == 4) acc = win_row<T, 4>(c, x, N, i, j);
     else acc = win_row<T, 5>(c, x, N, i, j);
-    if (mode == 0) L.yib[comp * L.maxact + row] = acc;
+    if (mode == 0) L.yib[(size_t)comp * NN + f] = acc;
     else if (mode == 1) out[(size_t)comp * NN + f] += acc;
     else out[(size_t)comp * NN + f] -= acc;
   }
@@ -288,10 +285,7 @@ __device__ void small_sweep(const LevelView<T>& L, const T* __restrict__ b, T* _
           box_dof(lane, bx, by, NB, N, comp, i, j);
           g = (size_t)comp * NN + (size_t)j * N + i;
           T y = r[g];
-          if (ibx >= 0 && comp < 2) {
-            const int a = L.act[comp * NN + j * N + i];
-            if (a >= 0) y -= L.yib[comp * L.maxact + a];
-          }
+          if (ibx >= 0 && comp < 2) y -= L.yib[g];   // zero off the active rows
           res[wave][lane] = (double)y;
         }
       }

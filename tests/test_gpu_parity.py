@@ -367,3 +367,19 @@ def test_graph_replay_matches_eager(prec):
     for it, x in outs[1:]:
         assert it == outs[0][0]
         assert np.array_equal(x, outs[0][1])
+
+
+def test_fp32_stall_falls_back_to_fp64_and_converges():
+    # single-cell boxes at a moderate time step: the FP32 V-cycle stalls and
+    # the solve continues with the FP64 one; the result must meet rtol in the
+    # oracle's own operator
+    w, dt, s = make(N=64, levels=5, M=160, K=1e2, dt_factor=10.0, seed=16, box=1, prec=1, maxit=200, rtol=1e-9)
+    z = torch.zeros(64, 64, dtype=torch.float64, device=DEV)
+    u, v, p, X = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    st = s.step(dt, u, v, p, X)
+    assert st["fallback"] == 1 and st["converged"] == 1
+    lv = system.hierarchy(64, 1, 1.0, 1.0, dt, w.X, w.fiber_offsets, 1e2)
+    zz = np.zeros((64, 64))
+    b = system.rhs(zz, zz, w.X, w.fiber_offsets, 1e2, dt, 1.0)
+    sol = np.concatenate([tnp(u).ravel(), tnp(v).ravel(), tnp(p).ravel()])
+    assert np.linalg.norm(b - lv[0].A @ sol) / np.linalg.norm(b) <= 1.02e-9
