@@ -109,39 +109,58 @@ __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ 
   if (lane == 0) L.yib[(size_t)comp * NN + f] = acc;
 }
 
-template <typename T>
-__device__ inline void box_body(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
-                                int blk) {
+// One box of the colour per 64-lane workgroup, box edge NB fixed at compile
+// time.  Every global load a lane needs -- its residual, elastic row and
+// iterate entries, and its column entries of the shared plain inverse -- is
+// issued before the barrier, so the box costs one memory latency before its
+// product (the inverse of a box with elastic rows follows after it).
+template <typename T, int NB>
+__device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
+                                  int blk) {
+  constexpr int ND = 2 * NB * (NB + 1) + NB * NB;
   __shared__ double res[64];
   int bx, by;
   colour_box(blk, colour, L.ncol, L.nb, bx, by);
   const int box = by * L.nb + bx;
-  const int lane = threadIdx.x, nd = L.ndof, N = L.N, NN = N * N;
+  const int lane = threadIdx.x, N = L.N, NN = N * N;
   const int ibx = L.ib_index ? L.ib_index[box] : -1;
   int comp = 0, i = 0, j = 0;
   size_t g = 0;
-  if (lane < nd) {
-    box_dof(lane, bx, by, L.n, N, comp, i, j);
+  T y = T(0), wv = T(0), yb = T(0);
+  T a[ND];
+  if (lane < ND) {
+    box_dof(lane, bx, by, NB, N, comp, i, j);
     g = (size_t)comp * NN + (size_t)j * N + i;
-    T y = r[g];
-    if (ibx >= 0 && comp < 2) y -= L.yib[g];   // zero off the active rows
-    res[lane] = (double)y;
+    y = r[g];
+    wv = w[g];
+    if (L.yib && comp < 2) yb = L.yib[g];   // zero off the active rows
+#pragma unroll
+    for (int c = 0; c < ND; ++c) a[c] = L.ainv_plain[c * ND + lane];
   }
+  if (ibx >= 0 && comp < 2) y -= yb;
+  if (lane < ND) res[lane] = (double)y;
   __syncthreads();
-  if (lane >= nd) return;
+  if (lane >= ND) return;
   if (ibx >= 0) {
-    const double* A = L.ainv_ib + (size_t)ibx * nd * nd;
+    const double* A = L.ainv_ib + (size_t)ibx * ND * ND;
     double z = 0.0;
-#pragma unroll 8
-    for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * res[c];
-    w[g] += (T)z;
+#pragma unroll
+    for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[c];
+    w[g] = wv + (T)z;
   } else {
-    const T* A = L.ainv_plain;
     T z = T(0);
-#pragma unroll 8
-    for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * (T)res[c];
-    w[g] += z;
+#pragma unroll
+    for (int c = 0; c < ND; ++c) z += a[c] * (T)res[c];
+    w[g] = wv + z;
   }
+}
+
+template <typename T>
+__device__ inline void box_body(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
+                                int blk) {
+  if (L.n == 4) box_body_n<T, 4>(L, r, w, colour, blk);
+  else if (L.n == 2) box_body_n<T, 2>(L, r, w, colour, blk);
+  else box_body_n<T, 1>(L, r, w, colour, blk);
 }
 
 // ---------------------------------------------------------------- a10: restriction (Sec. 3.1)
