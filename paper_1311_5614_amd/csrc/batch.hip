@@ -31,6 +31,7 @@ namespace {
 
 using namespace ibmg;
 
+constexpr int kWorkStreams = 4;  // concurrent streams for the per-problem setup (hardware queues per process)
 constexpr int kCap256 = 2048;   // persistent grid of the 256-lane level kernels (8 per CU)
 constexpr int kCapBox = 8192;   // persistent grid of the 64-lane box kernel (32 per CU)
 
@@ -395,6 +396,7 @@ double now_ms() {
 struct ibmg_batch {
   int P = 0, prec = IBMG_FP64, Kmax = 0;
   hipStream_t stream = nullptr, cap = nullptr;
+  std::vector<hipStream_t> work;   // per-problem setup and step-end work, kWorkStreams-way concurrent
   std::vector<ibmg_handle*> h;
   std::vector<size_t> sub_off;
   size_t need = 0;
@@ -917,6 +919,11 @@ int ibmg_batch_bind_workspace(ibmg_batch* B, void* dev, size_t bytes) {
     IBMG_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)B->tail_lds));
   }
   if (!B->cap) IBMG_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+  while ((int)B->work.size() < kWorkStreams) {
+    hipStream_t w = nullptr;
+    IBMG_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+    B->work.push_back(w);
+  }
   if (!B->round_h) IBMG_HIP(hipHostMalloc((void**)&B->round_h, B->round_bytes, hipHostMallocDefault));
   if (!B->gather_h) IBMG_HIP(hipHostMalloc((void**)&B->gather_h, 4 * sizeof(double) * B->P, hipHostMallocDefault));
   std::memset(B->round_h, 0, B->round_bytes);
@@ -945,16 +952,31 @@ int ibmg_batch_step(ibmg_batch* B, const double* dt, double* const* u, double* c
   const double t0 = now_ms();
   hipStream_t s = B->stream;
   int rc;
-  for (int q = 0; q < P; ++q)
-    if ((rc = setup_launch(B->h[q], dt[q], X[q]))) return rc;
+  // the problems' setups and right-hand sides are independent: they run on
+  // the work streams, round-robin, after the caller's stream has produced the
+  // inputs; the solve runs on the handle's stream once they are all done
   IBMG_HIP(hipStreamSynchronize(s));
+  auto on_work = [&](bool w) {
+    for (int q = 0; q < P; ++q) B->h[q]->stream = w ? B->work[q % B->work.size()] : s;
+  };
+  auto sync_work = [&]() -> int {
+    for (hipStream_t w : B->work) IBMG_HIP(hipStreamSynchronize(w));
+    return IBMG_OK;
+  };
+  on_work(true);
   for (int q = 0; q < P; ++q)
-    if ((rc = setup_finish(B->h[q]))) return rc;
+    if ((rc = setup_launch(B->h[q], dt[q], X[q]))) { on_work(false); return rc; }
+  if ((rc = sync_work())) { on_work(false); return rc; }
+  for (int q = 0; q < P; ++q)
+    if ((rc = setup_finish(B->h[q]))) { on_work(false); return rc; }
   for (int q = 0; q < P; ++q) {
     const double* gu = g_u ? g_u[q] : nullptr;
     const double* gv = g_v ? g_v[q] : nullptr;
-    if ((rc = step_begin(B->h[q], dt[q], u[q], v[q], p[q], gu, gv))) return rc;
+    if ((rc = step_begin(B->h[q], dt[q], u[q], v[q], p[q], gu, gv))) { on_work(false); return rc; }
   }
+  rc = sync_work();
+  on_work(false);
+  if (rc) return rc;
   if (B->prec == IBMG_FP32) fill_tables<float>(B);
   else fill_tables<double>(B);
   if ((rc = upload_tables(B))) return rc;
@@ -969,9 +991,13 @@ int ibmg_batch_step(ibmg_batch* B, const double* dt, double* const* u, double* c
     if (ps[q].rc < 0) return ps[q].rc;
     if (!ps[q].st.converged) worst = IBMG_NOT_CONVERGED;
   }
-  for (int q = 0; q < P; ++q)
-    if ((rc = step_end(B->h[q], dt[q], u[q], v[q], p[q], X[q]))) return rc;
   IBMG_HIP(hipStreamSynchronize(s));
+  on_work(true);
+  for (int q = 0; q < P; ++q)
+    if ((rc = step_end(B->h[q], dt[q], u[q], v[q], p[q], X[q]))) { on_work(false); return rc; }
+  rc = sync_work();
+  on_work(false);
+  if (rc) return rc;
   const double t3 = now_ms();
   for (int q = 0; q < P; ++q) {
     B->h[q]->setup_ok = false;
@@ -996,6 +1022,7 @@ int ibmg_batch_destroy(ibmg_batch* B) {
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   if (B->cap) (void)hipStreamDestroy(B->cap);
+  for (hipStream_t w : B->work) (void)hipStreamDestroy(w);
   if (B->round_h) (void)hipHostFree(B->round_h);
   if (B->gather_h) (void)hipHostFree(B->gather_h);
   for (ibmg_handle* h : B->h) ibmg_destroy(h);
