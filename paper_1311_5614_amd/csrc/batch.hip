@@ -47,7 +47,7 @@ struct BLv {
   T* bc;      // next coarser level: right-hand side and iterate
   T* wc;
   int nres;   // residual workgroups (3 N_l^2 / 256)
-  int nibx;   // elastic-row workgroups per component (16 lanes per row)
+  int nibx;   // elastic-row workgroups per component (striding over the rows, 16 lanes each)
   int nibr;   // elastic-row workgroups of the fused residual (both components)
 };
 
@@ -122,11 +122,11 @@ kb_level(const BLv<T>* __restrict__ lv, const int* __restrict__ ls, int P, int k
       const int idx = blk * 256 + threadIdx.x;
       if (idx < 3 * e.L.N * e.L.N) e.w[idx] = T(0);
     } else if constexpr (KIND == OP_RES) {
-      res_ib_body<T>(e.L, e.b, e.w, e.r, e.nres, blk);
+      res_ib_body<T>(e.L, e.b, e.w, e.r, e.nres, blk, e.nibr);
     } else if constexpr (KIND == OP_RESID) {
       residual_body<T>(e.L, e.b, e.w, e.r, blk);
     } else if constexpr (KIND == OP_IBROWS) {
-      ib_rows_body<T>(e.L, e.w, e.r, e.b ? 2 : 1, blk % e.nibx, blk / e.nibx);
+      ib_rows_body<T>(e.L, e.w, e.r, e.b ? 2 : 1, blk % e.nibx, blk / e.nibx, e.nibx);
     } else if constexpr (KIND == OP_RESTRICT) {
       restrict_body<T>(e.L.N, e.r, e.bc, e.wc, blk);
     } else if constexpr (KIND == OP_PROLONG) {
@@ -172,8 +172,8 @@ __global__ void __launch_bounds__(256) kb_ibrows0(BSet S, const BKry* __restrict
   const int j = S.j[s];
   const size_t n0 = q.n0;
   const int blk = blockIdx.x - S.off2[s];
-  if (start) ib_rows_body<double>(q.v0, q.x, q.V, 2, blk % q.nibx, blk / q.nibx);
-  else ib_rows_body<double>(q.v0, q.Z + j * n0, q.V + (j + 1) * n0, 1, blk % q.nibx, blk / q.nibx);
+  if (start) ib_rows_body<double>(q.v0, q.x, q.V, 2, blk % q.nibx, blk / q.nibx, q.nibx);
+  else ib_rows_body<double>(q.v0, q.Z + j * n0, q.V + (j + 1) * n0, 1, blk % q.nibx, blk / q.nibx, q.nibx);
 }
 
 // Partial dot products, the per-problem partition of k_multidot (256
@@ -537,11 +537,11 @@ void build_schedule(ibmg_batch* B) {
         const bool in_sweep = sweep < (post ? hp->nu2 : hp->nu1) && colour < hp->ncol;
         switch (kind) {
           case OP_RES:
-            nb = in_sweep ? (int)nblk(3 * NN) + (ib ? (int)nblk(2 * (size_t)L.maxact * 16) : 0) : 0;
+            nb = in_sweep ? (int)nblk(3 * NN) + (ib ? 2 * ib_blocks(L.maxact) : 0) : 0;
             break;
           case OP_BOX: nb = in_sweep ? colour_count(hp->ncol, L.nb) : 0; break;
           case OP_RESID: nb = (int)nblk(3 * NN); break;
-          case OP_IBROWS: nb = ib ? 2 * (int)nblk((size_t)L.maxact * 16) : 0; break;
+          case OP_IBROWS: nb = ib ? 2 * ib_blocks(L.maxact) : 0; break;
           case OP_RESTRICT: nb = (int)nblk(3 * NN / 4); break;
           case OP_PROLONG: nb = (int)nblk(3 * NN); break;
         }
@@ -618,8 +618,8 @@ void fill_tables(ibmg_batch* B) {
       e.wc = h->p<T>(h->L[l + 1].w);
       const size_t NN = (size_t)v[l].N * v[l].N;
       e.nres = (int)nblk(3 * NN);
-      e.nibx = (int)nblk((size_t)v[l].maxact * 16);
-      e.nibr = (int)nblk(2 * (size_t)v[l].maxact * 16);
+      e.nibx = ib_blocks(v[l].maxact);
+      e.nibr = 2 * ib_blocks(v[l].maxact);
     }
     TailArgs<T>& A = ta[p];
     for (int l = 0; l < h->levels; ++l) A.v[l] = v[l];
@@ -638,7 +638,7 @@ void fill_tables(ibmg_batch* B) {
     q.b0 = b0; q.w0 = w0;
     q.n0 = (long long)h->n0();
     q.ldh = h->maxit + 1; q.m = h->maxit;
-    q.nibx = (int)nblk((size_t)h->L[0].maxact * 16);
+    q.nibx = ib_blocks(h->L[0].maxact);
     q.target = 0.0;   // set by the solve once ||b|| is known
   }
 }
@@ -670,7 +670,7 @@ void add_slot(ibmg_batch* B, HostSet& hs, int p, int j, double beta = 0.0) {
   hs.j.push_back(j);
   hs.beta.push_back(beta);
   hs.off.push_back(hs.off.back() + (int)nblk(h->n0()));
-  hs.off2.push_back(hs.off2.back() + (h->has_ib ? 2 * (int)nblk((size_t)h->L[0].maxact * 16) : 0));
+  hs.off2.push_back(hs.off2.back() + (h->has_ib ? 2 * ib_blocks(h->L[0].maxact) : 0));
 }
 
 // ---------------------------------------------------------------- lockstep FGMRES

@@ -70,6 +70,13 @@ __device__ inline double phi_kernel(double r, int kind) {
   return 0.0;
 }
 
+// Workgroups (256 lanes, 16 rows each) striding over the active elastic rows
+// of one component, and of both in the fused residual kernel.
+__host__ __device__ inline int ib_blocks(int maxact) {
+  const int b = (maxact * 16 + 255) / 256;
+  return b < 512 ? b : 512;
+}
+
 // q-th box of a colour class.  ncol = 2: checkerboard, colour = (bx + by) & 1,
 // nb * nb / 2 boxes per colour; ncol = 4: colour = (bx & 1) + 2 (by & 1),
 // (nb / 2)^2 boxes per colour.  Row-major within a colour.

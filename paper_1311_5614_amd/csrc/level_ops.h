@@ -31,13 +31,9 @@ __device__ inline void residual_body(const LevelView<T>& L, const T* __restrict_
 // phase kernel must not evaluate it while those boxes are being updated);
 // mode 1: out[f] += (M w)_f; mode 2: out[f] -= (M w)_f.
 template <typename T>
-__device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__ w, T* __restrict__ out, int mode,
-                                    int blk, int comp) {
-  const int row = (blk * 256 + threadIdx.x) >> 4;
-  const int lane = threadIdx.x & 15;
-  if (row >= L.maxact || row >= L.nact[comp]) return;   // uniform over the 16 lanes of a row
+__device__ inline T ib_row(const LevelView<T>& L, const T* __restrict__ w, int comp, int row, int lane, int& f) {
   const int N = L.N, msk = N - 1, NN = N * N;
-  const int f = L.rows[comp * L.maxact + row];
+  f = L.rows[comp * L.maxact + row];
   const int j = f / N, i = f - j * N;
   const int r = L.reach, W = 2 * r + 1;
   const T* c = L.win + ((size_t)comp * L.maxact + row) * IBMG_WS;
@@ -55,10 +51,25 @@ __device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__
   acc += __shfl_xor(acc, 4, 16);
   acc += __shfl_xor(acc, 2, 16);
   acc += __shfl_xor(acc, 1, 16);
-  if (lane != 0) return;
-  if (mode == 0) L.yib[(size_t)comp * NN + f] = acc;
-  else if (mode == 1) out[(size_t)comp * NN + f] += acc;
-  else out[(size_t)comp * NN + f] -= acc;
+  return acc;
+}
+
+// Rows of one component, nblk workgroups striding over the active rows (the
+// count is read on the device, so a captured launch stays valid when the
+// active set changes).
+template <typename T>
+__device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__ w, T* __restrict__ out, int mode,
+                                    int blk, int comp, int nblk) {
+  const int lane = threadIdx.x & 15, NN = L.N * L.N;
+  const int nrows = min(L.nact[comp], L.maxact);
+  for (int row = (blk * 256 + threadIdx.x) >> 4; row < nrows; row += nblk * 16) {   // uniform over 16 lanes
+    int f;
+    const T acc = ib_row(L, w, comp, row, lane, f);
+    if (lane != 0) continue;
+    if (mode == 0) L.yib[(size_t)comp * NN + f] = acc;
+    else if (mode == 1) out[(size_t)comp * NN + f] += acc;
+    else out[(size_t)comp * NN + f] -= acc;
+  }
 }
 
 // ---------------------------------------------------------------- a9: one colour phase
@@ -74,7 +85,7 @@ __device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__
 // promoted to FP64.
 template <typename T>
 __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ b, const T* __restrict__ w,
-                                   T* __restrict__ r, int nres_blocks, int blk) {
+                                   T* __restrict__ r, int nres_blocks, int blk, int nib) {
   const int N = L.N, NN = N * N, lg = __builtin_ctz(N);
   if (blk < nres_blocks) {
     const int idx = blk * 256 + threadIdx.x;
@@ -84,29 +95,15 @@ __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ 
     r[idx] = b[idx] - stokes_row(L, w, comp, i, j);
     return;
   }
-  const int q = ((blk - nres_blocks) * 256 + (int)threadIdx.x) >> 4;
-  const int comp = q >= L.maxact ? 1 : 0, row = q - comp * L.maxact;
+  // elastic rows of both components, nib workgroups striding over them
   const int lane = threadIdx.x & 15;
-  if (row >= L.maxact || row >= L.nact[comp]) return;    // uniform over the 16 lanes of a row
-  const int msk = N - 1;
-  const int f = L.rows[comp * L.maxact + row];
-  const int j = f / N, i = f - j * N;
-  const int rr = L.reach, W = 2 * rr + 1;
-  const T* c = L.win + ((size_t)comp * L.maxact + row) * IBMG_WS;
-  const T* x = w + (size_t)comp * NN;
-  T acc = T(0);
-  int qy = lane / W, qx = lane - qy * W;
-  for (int e = lane; e < W * W; e += 16) {
-    const int dy = qy - rr, dx = qx - rr;
-    acc += c[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR] * x[((j + dy) & msk) * N + ((i + dx) & msk)];
-    qx += 16;
-    while (qx >= W) { qx -= W; ++qy; }
+  const int n0 = min(L.nact[0], L.maxact), n1 = min(L.nact[1], L.maxact);
+  for (int q = ((blk - nres_blocks) * 256 + (int)threadIdx.x) >> 4; q < n0 + n1; q += nib * 16) {
+    const int comp = q < n0 ? 0 : 1, row = q - comp * n0;
+    int f;
+    const T acc = ib_row(L, w, comp, row, lane, f);
+    if (lane == 0) L.yib[(size_t)comp * NN + f] = acc;
   }
-  acc += __shfl_xor(acc, 8, 16);
-  acc += __shfl_xor(acc, 4, 16);
-  acc += __shfl_xor(acc, 2, 16);
-  acc += __shfl_xor(acc, 1, 16);
-  if (lane == 0) L.yib[(size_t)comp * NN + f] = acc;
 }
 
 // One box of the colour per 64-lane workgroup, box edge NB fixed at compile

@@ -27,13 +27,14 @@ k_residual(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* 
 }
 template <typename T>
 __global__ void __launch_bounds__(256) k_ib_rows(LevelView<T> L, const T* __restrict__ w, T* __restrict__ out, int mode) {
-  ib_rows_body<T>(L, w, out, mode, blockIdx.x, blockIdx.y);
+  ib_rows_body<T>(L, w, out, mode, blockIdx.x, blockIdx.y, gridDim.x);
 }
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_res_ib(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* __restrict__ r, int nres_blocks) {
   const int blk = blockIdx.x;
-  res_ib_body<T>(L, b, w, r, nres_blocks, blk < nres_blocks ? xcd_remap(blk, nres_blocks) : blk);
+  res_ib_body<T>(L, b, w, r, nres_blocks, blk < nres_blocks ? xcd_remap(blk, nres_blocks) : blk,
+                 (int)gridDim.x - nres_blocks);
 }
 template <typename T, int NB>
 __global__ void __launch_bounds__(64) k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour) {
@@ -110,11 +111,11 @@ namespace ibmg {
 template <typename T> void launch_residual(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r,
                                            bool ib) {
   k_residual<T><<<nblk(3 * (size_t)L.N * L.N), 256, 0, s>>>(L, b, w, r);
-  if (ib) k_ib_rows<T><<<dim3(nblk((size_t)L.maxact * 16), 2), 256, 0, s>>>(L, w, r, b ? 2 : 1);
+  if (ib) k_ib_rows<T><<<dim3(ib_blocks(L.maxact), 2), 256, 0, s>>>(L, w, r, b ? 2 : 1);
 }
 template <typename T> void launch_res(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r, bool ib) {
   const int nres = (int)nblk(3 * (size_t)L.N * L.N);
-  const int nib = ib ? (int)nblk(2 * (size_t)L.maxact * 16) : 0;
+  const int nib = ib ? 2 * ib_blocks(L.maxact) : 0;
   k_res_ib<T><<<nres + nib, 256, 0, s>>>(L, b, w, r, nres);
 }
 template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, const T* r, T* w, int colour, bool ib) {
