@@ -106,20 +106,32 @@ __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ 
   }
 }
 
-// One box of the colour per 64-lane workgroup, box edge NB fixed at compile
-// time.  Every global load a lane needs -- its residual, elastic row and
-// iterate entries, and its column entries of the shared plain inverse -- is
-// issued before the barrier, so the box costs one memory latency before its
-// product (the inverse of a box with elastic rows follows after it).
-template <typename T, int NB>
+// One box of the colour per 64-lane wave, box edge NB fixed at compile time;
+// W boxes (waves) per workgroup.  Every global load a lane needs -- its
+// residual, elastic row and iterate entries, and its column entries of the
+// shared plain inverse -- is issued before the residual exchange, so the box
+// costs one memory latency before its product (the inverse of a box with
+// elastic rows follows after it).  The residual is exchanged through a
+// 64-entry LDS slot per wave: with one wave per workgroup a workgroup barrier
+// orders it, with several each wave orders its own slot.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kBoxWavesMax = 4;   // boxes per workgroup on the large levels
+
+template <typename T, int NB, int W = 1>
 __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
                                   int blk) {
   constexpr int ND = 2 * NB * (NB + 1) + NB * NB;
-  __shared__ double res[64];
+  __shared__ double res_all[W][64];
+  double* res = res_all[W == 1 ? 0 : threadIdx.x >> 6];
   int bx, by;
   colour_box(blk, colour, L.ncol, L.nb, bx, by);
   const int box = by * L.nb + bx;
-  const int lane = threadIdx.x, N = L.N, NN = N * N;
+  const int lane = threadIdx.x & 63, N = L.N, NN = N * N;
   const int ibx = L.ib_index ? L.ib_index[box] : -1;
   int comp = 0, i = 0, j = 0;
   size_t g = 0;
@@ -136,7 +148,8 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
   }
   if (ibx >= 0 && comp < 2) y -= yb;
   if (lane < ND) res[lane] = (double)y;
-  __syncthreads();
+  if constexpr (W == 1) __syncthreads();
+  else wave_sync();
   if (lane >= ND) return;
   if (ibx >= 0) {
     const double* A = L.ainv_ib + (size_t)ibx * ND * ND;

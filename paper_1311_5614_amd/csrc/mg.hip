@@ -36,9 +36,13 @@ k_res_ib(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* __
   res_ib_body<T>(L, b, w, r, nres_blocks, blk < nres_blocks ? xcd_remap(blk, nres_blocks) : blk,
                  (int)gridDim.x - nres_blocks);
 }
-template <typename T, int NB>
-__global__ void __launch_bounds__(64) k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour) {
-  box_body_n<T, NB>(L, r, w, colour, xcd_remap(blockIdx.x, gridDim.x));
+// W boxes per workgroup: several on the large levels (fewer workgroups to
+// dispatch), one where the colour has too few boxes to fill the chip that way.
+template <typename T, int NB, int W>
+__global__ void __launch_bounds__(64 * W)
+k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour, int cnt) {
+  const int q = xcd_remap(blockIdx.x, gridDim.x) * W + (int)(threadIdx.x >> 6);
+  if (W == 1 || q < cnt) box_body_n<T, NB, W>(L, r, w, colour, q);
 }
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int Nf, const T* __restrict__ rf, T* __restrict__ rc,
@@ -121,10 +125,17 @@ template <typename T> void launch_res(hipStream_t s, const LevelView<T>& L, cons
 template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, const T* r, T* w, int colour, bool ib) {
   LevelView<T> V = L;
   if (!ib) V.ib_index = nullptr;
-  const int grid = colour_count(L.ncol, L.nb);
-  if (L.n == 4) k_box<T, 4><<<grid, 64, 0, s>>>(V, r, w, colour);
-  else if (L.n == 2) k_box<T, 2><<<grid, 64, 0, s>>>(V, r, w, colour);
-  else k_box<T, 1><<<grid, 64, 0, s>>>(V, r, w, colour);
+  const int cnt = colour_count(L.ncol, L.nb);
+  if (cnt >= kBoxWavesMax * 512) {
+    const int grid = (cnt + kBoxWavesMax - 1) / kBoxWavesMax;
+    if (L.n == 4) k_box<T, 4, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);
+    else if (L.n == 2) k_box<T, 2, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);
+    else k_box<T, 1, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);
+  } else {
+    if (L.n == 4) k_box<T, 4, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt);
+    else if (L.n == 2) k_box<T, 2, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt);
+    else k_box<T, 1, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt);
+  }
 }
 template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero) {
   k_restrict<T><<<nblk(3 * (size_t)(Nf / 2) * (Nf / 2)), 256, 0, s>>>(Nf, rf, rc, wc_zero);
