@@ -284,10 +284,14 @@ def cpu_baseline(w, dt, budget_note, steps=3):
 
 
 def run_learned(args, dev):
-    """The 512x512 learned-warm-start trajectory: steps 1..H from w^n (guess
-    PREV) recording (features, w^{n+1} - w^n) pairs, training the network on
-    the GPU, then steps H+1..2H three ways from the same state at step H:
-    from w^n + alpha Dw (learned), from w^n, and from zero."""
+    """The 512x512 learned-warm-start trajectory.  Steps 1..H run from w^n
+    (guess PREV) and record (features, target) pairs, the target being the
+    change of the step increment, Dw^n - Dw^{n-1}; the network is trained on
+    the GPU; then steps H+1..2H run four ways from the same state at step H:
+    learned (x0 = w^n + Dw^{n-1} + net(features), guarded by the minimal-
+    residual weight alpha), extrapolation alone (x0 = w^n + Dw^{n-1}, same
+    guard: what the network adds is the difference of the two), from w^n,
+    and from zero."""
     import torch
     from paper_1311_5614_amd import ibmg
     import ibgen
@@ -313,12 +317,15 @@ def run_learned(args, dev):
 
     t0 = time.perf_counter()
     its_train = []
+    dprev = torch.zeros(3, N, N, dtype=torch.float64, device=dev)
     for n in range(H):
         f = features(u, v, p, X)
         old = torch.stack([u, v, p]).clone()
         st = s.step(dt, u, v, p, X, gu, gv)
         its_train.append(st["iters"])
-        net.record(f, (torch.stack([u, v, p]) - old).contiguous())
+        d = torch.stack([u, v, p]) - old
+        net.record(f, (d - dprev).contiguous())
+        dprev = d
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -326,18 +333,21 @@ def run_learned(args, dev):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     start = [a.clone() for a in (u, v, p, X)]
+    dstart = dprev.clone()
     res = {}
-    for form in ("learned", "prev", "zero"):
+    for form in ("learned", "extrap", "prev", "zero"):
         u, v, p, X = (a.clone() for a in start)
+        dprev = dstart.clone()
         its, conv, alphas = [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for n in range(H):
-            if form == "learned":
-                f = features(u, v, p, X)
-                x0 = (torch.stack([u, v, p]) + net.infer(f)).reshape(-1).contiguous()
-                st = s.step_x0(dt, u, v, p, X, x0, gu, gv)
+            old = torch.stack([u, v, p])
+            if form in ("learned", "extrap"):
+                q = dprev + net.infer(features(u, v, p, X)) if form == "learned" else dprev
+                st = s.step_x0(dt, u, v, p, X, (old + q).reshape(-1).contiguous(), gu, gv)
                 alphas.append(st["guess_alpha"])
+                dprev = torch.stack([u, v, p]) - old
             elif form == "prev":
                 st = s.step(dt, u, v, p, X, gu, gv)
             else:
@@ -359,7 +369,8 @@ def run_learned(args, dev):
         "data": "synthetic",
         "config": {"workload": f"{w.name}: steps 1-{H} record and train, steps {H + 1}-{2 * H} timed",
                    "grid": N, "points": w.M, "K": w.K, "dt_factor": w.dt_factor,
-                   "chosen_form": "learned initial iterate (w^n + alpha Dw) in fp64 FGMRES, fp32 V-cycle"},
+                   "chosen_form": "learned initial iterate w^n + alpha (Dw^{n-1} + net) in fp64 FGMRES, "
+                                  "fp32 V-cycle"},
         "forms": res,
         "training": {"pairs": H, "epochs": args.epochs, "lr": args.lr, "loss_first": loss_first,
                      "loss_last": loss_last, "train_s": t_train, "first_half_s": t_first,

@@ -119,6 +119,7 @@ void layout(ibmg_handle* h) {
   take(cur, h->bvec, n0 * sizeof(double));
   take(cur, h->xvec, n0 * sizeof(double));
   take(cur, h->rvec, n0 * sizeof(double));
+  take(cur, h->xbest, n0 * sizeof(double));
   if (h->prec == IBMG_FP32) {
     take(cur, h->w0f, n0 * sizeof(float));
     take(cur, h->b0f, n0 * sizeof(float));
@@ -424,15 +425,33 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
   const double target = h->rtol * bnorm;
   int total = 0;
   double est = INFINITY;
+  // Each cycle starts from the true residual of the current iterate.  The
+  // iterate with the smallest true residual is kept: a cycle that ends worse
+  // than it started (a Krylov basis spoiled by a stalled FP32 V-cycle) is
+  // dropped, and the next cycle starts again from the best iterate.
+  double best = INFINITY;
+  double* xbest = h->p<double>(h->xbest);
   for (;;) {
     apply0(h, x, V, b);            // V[0] = b - A x
     dot(h, V, V, scal);
     if ((rc = read_doubles(h, scal, hs, 1))) return rc;
     const double beta = std::sqrt(hs[0]);
     if (!std::isfinite(beta)) return IBMG_ENONFINITE;
+    if (beta > best) {
+      IBMG_HIP(hipMemcpyAsync(x, xbest, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (h->prec == IBMG_FP32 && !h->fb64) {   // go on from the best iterate with the FP64 V-cycle
+        h->fb64 = true;
+        st->fallback = 1;
+        continue;
+      }
+      st->rel_resid_true = best / bnorm;        // nothing else to try: give back the best iterate
+      break;
+    }
     st->rel_resid_true = beta / bnorm;
     if (beta <= target) { st->converged = 1; break; }
     if (total >= m) break;
+    best = beta;
+    IBMG_HIP(hipMemcpyAsync(xbest, x, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_scale(s, V, V, n0, scal);
     k_fill<double><<<nblk(m + 2), 256, 0, s>>>(g, m + 2, 0.0);
     IBMG_HIP(hipMemcpyAsync(g, &beta, sizeof(double), hipMemcpyHostToDevice, s));
@@ -464,8 +483,9 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
       hist.push_back(est);
       const int nh = (int)hist.size();
       if (h->prec == IBMG_FP32 && !h->fb64 && nh > kFallbackWindow && est > 0.9 * hist[nh - 1 - kFallbackWindow]) {
-        h->fb64 = true;   // FP32 V-cycle stalled: continue with the FP64 one
+        h->fb64 = true;   // FP32 V-cycle stalled: restart from the current iterate with the FP64 one
         st->fallback = 1;
+        break;
       }
       if (hs[1] != 0.0) break;
     }

@@ -683,6 +683,7 @@ struct PState {
   bool fb64 = false;          // FP32 V-cycle stalled: this solve goes on with the FP64 one
   std::vector<double> hist;   // Arnoldi estimate after each iteration
   double bnorm = 0, beta = 0, est = INFINITY, target = 0;
+  double best = INFINITY;     // smallest true residual of the solve so far (iterate kept in xbest)
   ibmg_stats st{};
 };
 
@@ -801,15 +802,31 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
     IBMG_HIP(hipMemcpyAsync(B->gather_h, gat, 4 * (size_t)P * sizeof(double), hipMemcpyDeviceToHost, s));
     IBMG_HIP(hipStreamSynchronize(s));
     ++B->rounds;
+    // same restart and best-iterate rules as the single-problem solve
     for (int p : S.p) {
       PState& q = ps[p];
-      const int m = B->h[p]->maxit;
+      ibmg_handle* hp = B->h[p];
+      const int m = hp->maxit;
+      const size_t xb = hp->n0() * sizeof(double);
       q.k_end = -1;
       const double beta = std::sqrt(B->gather_h[4 * p]);
       if (!std::isfinite(beta)) { q.rc = IBMG_ENONFINITE; q.state = ST_DONE; continue; }
+      if (beta > q.best) {
+        IBMG_HIP(hipMemcpyAsync(hp->p<double>(hp->xvec), hp->p<double>(hp->xbest), xb, hipMemcpyDeviceToDevice, s));
+        if (B->prec == IBMG_FP32 && !q.fb64) {
+          q.fb64 = true;
+          q.st.fallback = 1;
+          continue;                 // state stays ST_START: residual of the best iterate next round
+        }
+        q.st.rel_resid_true = q.best / q.bnorm;
+        q.state = ST_DONE;
+        continue;
+      }
       q.st.rel_resid_true = beta / q.bnorm;
       if (beta <= q.target) { q.st.converged = 1; q.state = ST_DONE; continue; }
       if (q.total >= m) { q.state = ST_DONE; continue; }
+      q.best = beta;
+      IBMG_HIP(hipMemcpyAsync(hp->p<double>(hp->xbest), hp->p<double>(hp->xvec), xb, hipMemcpyDeviceToDevice, s));
       q.beta = beta;
       q.begin = true;
       q.j = 0;
@@ -826,8 +843,11 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
       q.hist.push_back(q.est);
       const int nh = (int)q.hist.size();
       if (B->prec == IBMG_FP32 && !q.fb64 && nh > kFallbackWindow && q.est > 0.9 * q.hist[nh - 1 - kFallbackWindow]) {
-        q.fb64 = true;   // same stall test as the single-problem solve
+        q.fb64 = true;   // same stall test as the single-problem solve: restart with the FP64 V-cycle
         q.st.fallback = 1;
+        q.k_end = q.j + 1;
+        q.state = ST_START;
+        continue;
       }
       if (f[1] != 0.0 || q.j + 1 >= m || q.total >= m) {
         q.k_end = q.j + 1;

@@ -53,6 +53,7 @@ struct ibmg_handle {
   int max_list = 0;
   Buf V, Z, H, g, cs, sn, y, flags, partial, scal, hc;
   Buf bvec, xvec, rvec, w0f, b0f;
+  Buf xbest;   // iterate with the smallest true residual of the solve so far
   Buf aug, cm, cpiv, crowpos, cused, cY, cainv;
   int nr = 0, ndof = 0;
   // state
