@@ -150,3 +150,31 @@ def test_c5_network_forward_full_size():
     # periodic translation: the output moves with the input, bit for bit
     ys = tnp(net.infer(tdev(np.roll(x, (37, -5), axis=(1, 2)))))
     assert np.array_equal(ys, np.roll(y, (37, -5), axis=(1, 2)))
+
+
+def test_c5_fp32_trajectory_through_a_stalled_step():
+    """The 512x512 warm-start trajectory with the FP32 V-cycle: at step 44 the
+    FP32-preconditioned solve stalls.  The solve restarts from its current
+    iterate with the FP64 V-cycle and keeps its best iterate, so every step
+    reaches the tolerance and, once the initial relaxation is over (points
+    then move about 0.13 cells per step), no step moves a point by a cell."""
+    from paper_1311_5614_amd import ibmg
+    w = ibgen.config_c5()
+    dt = _dts("c5")[0]
+    N = w.N
+    cfg = ibmg.Config(N=N, levels=7, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2, maxit=200, rtol=w.rtol,
+                      prec=ibmg.IBMG_FP32, guess=ibmg.IBMG_GUESS_PREV, tail_max=1)
+    s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    z = torch.zeros(N, N, dtype=torch.float64, device=DEV)
+    u, v, p, X = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    gu, gv = tdev(w.g_u), tdev(w.g_v)
+    fallbacks = 0
+    for n in range(46):
+        X_old = X.clone()
+        st = s.step(dt, u, v, p, X, gu, gv)
+        assert st["converged"] == 1 and st["rel_resid_true"] <= w.rtol, (n, st)
+        if n >= 10:
+            assert float((X - X_old).abs().max()) * N < 1.0, n
+        fallbacks += st["fallback"]
+    assert fallbacks >= 1      # the stalled step is on this stretch of the trajectory
+    s.close()
