@@ -618,7 +618,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   if (N < 4 || (N & (N - 1)) != 0) return IBMG_ESHAPE;
   if (!(pr->rho > 0) || !(pr->mu > 0) || !std::isfinite(pr->K) || pr->K < 0) return IBMG_EINVAL;
   if (pr->delta != IBMG_DELTA_IB4 && pr->delta != IBMG_DELTA_COS4) return IBMG_EINVAL;
-  if (op->box != 1 && op->box != 2 && op->box != 4) return IBMG_ESHAPE;
+  if (op->box != 1 && op->box != 2 && op->box != 4 && op->box != 8) return IBMG_ESHAPE;
   if (op->levels < 1 || op->levels > IBMG_MAX_LEVELS) return IBMG_ESHAPE;
   const int Nc = N >> (op->levels - 1);
   if (Nc < 4 || Nc > 16) return IBMG_ESHAPE;

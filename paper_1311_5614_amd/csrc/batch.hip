@@ -881,7 +881,9 @@ int ibmg_batch_create(ibmg_batch** out, int32_t nprob, const ibmg_problem* probs
   B->prec = opts[0].vcycle_prec;
   for (int p = 0; p < nprob; ++p) {
     ibmg_handle* h = nullptr;
-    int rc = opts[p].vcycle_prec != B->prec ? IBMG_EINVAL : ibmg_create(&h, &probs[p], &opts[p], stream);
+    int rc = opts[p].vcycle_prec != B->prec ? IBMG_EINVAL
+             : opts[p].box > 4              ? IBMG_ESHAPE   // the batched box kernel takes boxes of 1, 2 or 4 cells
+                                            : ibmg_create(&h, &probs[p], &opts[p], stream);
     if (rc) {
       for (ibmg_handle* q : B->h) ibmg_destroy(q);
       delete B;

@@ -11,6 +11,7 @@
 // product.
 #include "common.h"
 #include "gj.h"
+#include "gj_reg.h"
 #include "kernels.h"
 
 #define PW 16   // panel width
@@ -217,6 +218,18 @@ k_coarse_small(const double* __restrict__ aug, int nr, double* __restrict__ ainv
   }
 }
 
+// Bordered systems of IBMG_MAX_NDOF < nr <= 224 (the 8 x 8 coarsest grid):
+// the left half of the augmented matrix inverted in the registers of one
+// workgroup (gj_reg.h); inverse row-major.
+__global__ void __launch_bounds__(kGjLanes)
+k_coarse_regs(const double* __restrict__ aug, int nr, double* __restrict__ ainv) {
+  __shared__ GjScratch S;
+  const size_t ld = 2 * (size_t)nr;
+  gauss_jordan_regs(
+      nr, S, [&](int i, int j) { return aug[(size_t)i * ld + j]; },
+      [&](int r, int c, double v) { ainv[(size_t)r * nr + c] = v; });
+}
+
 namespace ibmg {
 
 void launch_coarse_assemble(hipStream_t s, const LevelView<double>& L, double* aug, int nr) {
@@ -228,6 +241,10 @@ int coarse_factor(hipStream_t s, double* aug, int nr, double* m, int* piv, doubl
   (void)dpiv;
   if (nr <= IBMG_MAX_NDOF) {
     k_coarse_small<<<1, 128, 0, s>>>(aug, nr, ainv);
+    return 0;
+  }
+  if (nr <= kGjMax) {
+    k_coarse_regs<<<1, kGjLanes, 0, s>>>(aug, nr, ainv);
     return 0;
   }
   const size_t lds = (size_t)nr * PW * sizeof(double) + (size_t)nr * sizeof(int);

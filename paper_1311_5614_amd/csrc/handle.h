@@ -134,6 +134,7 @@ inline PointView points(const ibmg_handle* h) {
 // from there down has at most tail_max cells per side.
 inline int tail_start(const ibmg_handle* h) {
   int ls = h->levels - 1;
+  if (h->n > 4) return ls;   // 8 x 8 boxes: the plain inverse does not fit the tail's LDS
   while (ls > 0 && h->L[ls - 1].N <= h->tail_max) --ls;
   return ls;
 }
@@ -141,6 +142,7 @@ inline int tail_start(const ibmg_handle* h) {
 // Dynamic LDS of the tail: three vectors (nine arrays) per level from ls on,
 // and one plain-box inverse.
 inline size_t tail_lds(const ibmg_handle* h, size_t elem) {
+  if (tail_start(h) == h->levels - 1) return 0;   // no tail kernel: the coarsest product only
   size_t lds = (size_t)h->ndof * h->ndof * elem;
   for (int l = tail_start(h); l < h->levels; ++l) lds += 9 * (size_t)h->L[l].N * h->L[l].N * elem;
   return lds;

@@ -9,6 +9,7 @@
 // while boxes near the structure get their own, re-formed every step (Sec. 8).
 #include "common.h"
 #include "gj.h"
+#include "gj_reg.h"
 #include "kernels.h"
 
 // ---------------------------------------------------------------- a1: G = K L X
@@ -516,16 +517,48 @@ k_box_factor(LevelView<double> L, const int* __restrict__ ib_boxes, double* __re
   }
 }
 
-// Assembled (not inverted) block of one box, row-major, for inspection.
+// Blocks of 8 x 8 boxes (208 unknowns): assembled row-major into their own
+// output slot, then inverted in registers (gj_reg.h) and written back
+// column-major over it.  Same block numbering as k_box_factor.
+__global__ void __launch_bounds__(kGjLanes)
+k_box_factor_big(LevelView<double> L, const int* __restrict__ ib_boxes, double* __restrict__ ainv_plain,
+                 float* __restrict__ ainv_plain_f, double* __restrict__ ainv_ib) {
+  __shared__ GjScratch S;
+  const int nd = L.ndof;
+  const bool plain = blockIdx.x == 0;
+  int bx = 0, by = 0;
+  if (!plain) {
+    const int box = ib_boxes[blockIdx.x - 1];
+    bx = box % L.nb;
+    by = box / L.nb;
+  }
+  double* slot = plain ? ainv_plain : ainv_ib + (size_t)(blockIdx.x - 1) * nd * nd;
+  for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) slot[idx] = 0.0;
+  __syncthreads();
+  assemble_box(L, bx, by, !plain, slot, nd);
+  __syncthreads();
+  float* f32 = plain ? ainv_plain_f : nullptr;
+  gauss_jordan_regs(
+      nd, S, [&](int i, int j) { return slot[(size_t)i * nd + j]; },
+      [&](int r, int c, double v) {
+        slot[(size_t)c * nd + r] = v;
+        if (f32) f32[(size_t)c * nd + r] = (float)v;
+      });
+}
+
+// Assembled (not inverted) block of one box, row-major, for inspection
+// (blocks larger than the LDS buffer are assembled in place in out).
 __global__ void __launch_bounds__(256)
 k_box_matrix(LevelView<double> L, int bx, int by, double* __restrict__ out) {
   __shared__ double a[IBMG_MAX_NDOF * IBMG_MAX_NDOF];
   const int nd = L.ndof;
-  for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) a[idx] = 0.0;
+  double* buf = nd <= IBMG_MAX_NDOF ? a : out;
+  for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) buf[idx] = 0.0;
   __syncthreads();
-  assemble_box(L, bx, by, L.act != nullptr, a, nd);
+  assemble_box(L, bx, by, L.act != nullptr, buf, nd);
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) out[idx] = a[idx];
+  if (buf == a)
+    for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) out[idx] = a[idx];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -596,7 +629,8 @@ void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int
 
 void launch_box_factor(hipStream_t s, const LevelView<double>& L, const int* ib_boxes, int n_ib,
                        double* ainv_plain, float* ainv_plain_f, double* ainv_ib) {
-  k_box_factor<<<1 + n_ib, 128, 0, s>>>(L, ib_boxes, ainv_plain, ainv_plain_f, ainv_ib);
+  if (L.ndof <= IBMG_MAX_NDOF) k_box_factor<<<1 + n_ib, 128, 0, s>>>(L, ib_boxes, ainv_plain, ainv_plain_f, ainv_ib);
+  else k_box_factor_big<<<1 + n_ib, kGjLanes, 0, s>>>(L, ib_boxes, ainv_plain, ainv_plain_f, ainv_ib);
 }
 
 void launch_box_matrix(hipStream_t s, const LevelView<double>& L, int bx, int by, double* out) {

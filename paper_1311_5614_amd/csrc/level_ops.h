@@ -165,6 +165,50 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
   }
 }
 
+// Boxes of 8 x 8 cells (208 unknowns): one 256-lane workgroup per box; the
+// inverse columns stream from L2 (the level's 173 KB FP32 plain inverse fits
+// neither a lane's registers nor a workgroup's LDS).  Same arithmetic and
+// summation order as box_body_n.
+constexpr int kBigBoxLanes = 256;
+
+template <typename T>
+__device__ inline void box_body_big(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
+                                    int blk) {
+  constexpr int NB = 8, ND = 2 * NB * (NB + 1) + NB * NB;
+  __shared__ double res[ND];
+  int bx, by;
+  colour_box(blk, colour, L.ncol, L.nb, bx, by);
+  const int lane = threadIdx.x, N = L.N, NN = N * N;
+  const int ibx = L.ib_index ? L.ib_index[by * L.nb + bx] : -1;
+  int comp = 0, i = 0, j = 0;
+  size_t g = 0;
+  T y = T(0), wv = T(0), yb = T(0);
+  if (lane < ND) {
+    box_dof(lane, bx, by, NB, N, comp, i, j);
+    g = (size_t)comp * NN + (size_t)j * N + i;
+    y = r[g];
+    wv = w[g];
+    if (L.yib && comp < 2) yb = L.yib[g];   // zero off the active rows
+  }
+  if (ibx >= 0 && comp < 2) y -= yb;
+  if (lane < ND) res[lane] = (double)y;
+  __syncthreads();
+  if (lane >= ND) return;
+  if (ibx >= 0) {
+    const double* A = L.ainv_ib + (size_t)ibx * ND * ND;
+    double z = 0.0;
+#pragma unroll 16
+    for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[c];
+    w[g] = wv + (T)z;
+  } else {
+    T z = T(0);
+#pragma unroll 16
+    for (int c = 0; c < ND; ++c) z += L.ainv_plain[c * ND + lane] * (T)res[c];
+    w[g] = wv + z;
+  }
+}
+
+// Boxes of 1, 2 or 4 cells (the batched kernels take no 8 x 8 boxes).
 template <typename T>
 __device__ inline void box_body(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
                                 int blk) {

@@ -45,6 +45,11 @@ k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour, in
   if (W == 1 || q < cnt) box_body_n<T, NB, W>(L, r, w, colour, q);
 }
 template <typename T>
+__global__ void __launch_bounds__(kBigBoxLanes)
+k_box_big(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour) {
+  box_body_big<T>(L, r, w, colour, xcd_remap(blockIdx.x, gridDim.x));
+}
+template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int Nf, const T* __restrict__ rf, T* __restrict__ rc,
                                                   T* __restrict__ wz) {
   restrict_body<T>(Nf, rf, rc, wz, blockIdx.x);
@@ -126,7 +131,9 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
   LevelView<T> V = L;
   if (!ib) V.ib_index = nullptr;
   const int cnt = colour_count(L.ncol, L.nb);
-  if (cnt >= kBoxWavesMax * 512) {
+  if (L.n == 8) {
+    k_box_big<T><<<cnt, kBigBoxLanes, 0, s>>>(V, r, w, colour);
+  } else if (cnt >= kBoxWavesMax * 512) {
     const int grid = (cnt + kBoxWavesMax - 1) / kBoxWavesMax;
     if (L.n == 4) k_box<T, 4, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);
     else if (L.n == 2) k_box<T, 2, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);

@@ -87,8 +87,11 @@ def test_create_validates_shapes_without_gpu():
     assert L.ibmg_destroy(h) == 0
     assert _create(N=48)[0] == -2                     # not a power of two
     assert _create(N=32, levels=5)[0] == -2           # coarsest 2x2
-    assert _create(N=16, levels=2, box=8)[0] == -2    # unsupported box
+    assert _create(N=16, levels=2, box=3)[0] == -2    # unsupported box
+    assert _create(N=16, levels=2, box=16)[0] == -2   # unsupported box
     assert _create(N=8, levels=2, box=4)[0] == 0      # 8x8 holds two 4x4 boxes per side
+    assert _create(N=16, levels=2, box=8)[0] == 0     # 16x16 holds two 8x8 boxes per side
+    assert _create(N=16, levels=3, box=8)[0] == -2    # an 8x8 smoothed level holds one 8x8 box
     assert _create(N=64, levels=2)[0] == -2           # coarsest 32 > 16
     assert _create(offs=(0, 30, 20))[0] == -1         # decreasing offsets
     assert _create(offs=(5, 40))[0] == -1             # offsets must start at 0
@@ -111,11 +114,11 @@ def test_batch_create_validates_without_gpu():
     ibmg, L = _lib()
     offs = [(C.c_int32 * 2)(0, 40), (C.c_int32 * 2)(0, 80)]
 
-    def make(Ns, precs, levels):
+    def make(Ns, precs, levels, box=4):
         probs = (ibmg.ibmg_problem * len(Ns))(*[
             ibmg.ibmg_problem(N, 1.0, 1.0, o[1], 1, C.cast(o, C.POINTER(C.c_int32)), 1e3, 0)
             for N, o in zip(Ns, offs)])
-        opts = (ibmg.ibmg_opts * len(Ns))(*[ibmg.ibmg_opts(lv, 4, 2, 2, 100, 1e-8, pr, 0, 2, 0)
+        opts = (ibmg.ibmg_opts * len(Ns))(*[ibmg.ibmg_opts(lv, box, 2, 2, 100, 1e-8, pr, 0, 2, 0)
                                             for pr, lv in zip(precs, levels)])
         h = C.c_void_p()
         return L.ibmg_batch_create(C.byref(h), len(Ns), probs, opts, None), h
@@ -140,6 +143,7 @@ def test_batch_create_validates_without_gpu():
     assert L.ibmg_batch_destroy(h) == 0
     assert make([32, 64], [0, 1], [4, 5])[0] == -1   # mixed V-cycle precision
     assert make([32, 48], [0, 0], [4, 5])[0] == -2   # one bad grid
+    assert make([32, 64], [0, 0], [2, 3], box=8)[0] == -2   # the batch takes boxes of 1, 2 or 4 cells
     h = C.c_void_p()
     assert L.ibmg_batch_create(C.byref(h), 0, None, None, None) == -1
 

@@ -102,13 +102,14 @@ def test_transfers_parity():
 
 # ---------------------------------------------------------------- a6, a9: boxes and smoothing
 
-def test_box_matrices_parity():
-    w, dt, s = make(N=32, levels=3, M=80, K=1e5, dt_factor=100.0)
+@pytest.mark.parametrize("box,N,levels", [(4, 32, 3), (8, 64, 3)])
+def test_box_matrices_parity(box, N, levels):
+    w, dt, s = make(N=N, levels=levels, M=80 if N == 32 else 160, K=1e5, dt_factor=100.0, box=box)
     _setup(s, w, dt)
-    lv = oracle_levels(w, dt, 3, 1e5)
+    lv = oracle_levels(w, dt, levels, 1e5)
     for l in (0, 1):
-        sm = smoother.BoxSmoother(lv[l].A, lv[l].N, 4)
-        nb = lv[l].N // 4
+        sm = smoother.BoxSmoother(lv[l].A, lv[l].N, box)
+        nb = lv[l].N // box
         for bx in range(nb):
             for by in range(nb):
                 A = tnp(s.box_matrix(l, bx, by))
@@ -116,7 +117,7 @@ def test_box_matrices_parity():
                 assert np.max(np.abs(A - Ao)) < 1e-12 * np.max(np.abs(Ao)), (l, bx, by)
 
 
-@pytest.mark.parametrize("box,colours", [(1, 2), (2, 2), (4, 2), (1, 4), (4, 4)])
+@pytest.mark.parametrize("box,colours", [(1, 2), (2, 2), (4, 2), (1, 4), (4, 4), (8, 2), (8, 4)])
 def test_smooth_parity(box, colours):
     w, dt, s = make(N=64, levels=4, M=160, K=1e4, dt_factor=50.0, box=box, colours=colours)
     _setup(s, w, dt)
@@ -137,8 +138,8 @@ def test_smooth_parity(box, colours):
 
 @pytest.mark.parametrize("N,levels", [(64, 3), (32, 3), (32, 4)])
 def test_coarse_solve_parity(N, levels):
-    # coarsest 16^2 and 8^2 take the blocked panel inverse, 4^2 the
-    # single-workgroup inverse
+    # coarsest 16^2 takes the blocked panel inverse, 8^2 the register-tile
+    # inverse of one workgroup, 4^2 the LDS inverse of one workgroup
     w, dt, s = make(N=N, levels=levels, M=120 if N == 64 else 60, K=1e5, dt_factor=100.0)
     _setup(s, w, dt)
     lv = oracle_levels(w, dt, levels, 1e5)
@@ -163,6 +164,19 @@ def test_vcycle_parity(nu, colours, levels):
     z = tnp(s.vcycle(tdev(r)))
     zo = V(r)
     assert rel(z, zo) < 1e-11
+
+
+@pytest.mark.parametrize("box,levels", [(8, 3), (8, 4)])
+def test_vcycle_parity_8x8_boxes(box, levels):
+    # 8 x 8 boxes: 208-unknown blocks inverted in registers, one 256-lane
+    # workgroup per box, no LDS-resident tail
+    w, dt, s = make(N=64, levels=levels, M=150, K=1e5, dt_factor=100.0, box=box)
+    _setup(s, w, dt)
+    lv = oracle_levels(w, dt, levels, 1e5)
+    V = mg.VCycle(lv, box, 2, 2, "colour2")
+    r = np.random.default_rng(11).standard_normal(3 * 64 * 64)
+    r[2 * 4096:] -= r[2 * 4096:].mean()
+    assert rel(tnp(s.vcycle(tdev(r))), V(r)) < 1e-11
 
 
 @pytest.mark.parametrize("tail_max,levels", [(1, 5), (1, 3), (8, 5), (16, 5), (32, 4)])
@@ -211,7 +225,7 @@ def test_c1_step_parity():
     assert abs(tnp(p).mean()) < 1e-12
 
 
-@pytest.mark.parametrize("K,fac,box", [(1e4, 20.0, 4), (1e6, 200.0, 4), (1e3, 10.0, 2)])
+@pytest.mark.parametrize("K,fac,box", [(1e4, 20.0, 4), (1e6, 200.0, 4), (1e3, 10.0, 2), (1e6, 200.0, 8)])
 def test_solve_parity_equal_iterations(K, fac, box):
     w, dt, s = make(N=64, levels=4, M=160, K=K, dt_factor=fac, n_fibers=2, box=box, rtol=1e-10)
     _setup(s, w, dt)
