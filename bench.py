@@ -389,6 +389,7 @@ def main():
     ap.add_argument("--levels", type=int, default=0, help="override the workload's level count")
     ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
     ap.add_argument("--colours", type=int, default=2)
+    ap.add_argument("--box", type=int, default=0, help="override the box edge (1, 2, 4 or 8 cells)")
     ap.add_argument("--tail-max", type=int, default=0, help="override the V-cycle tail size")
     ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs of the warm-start network")
     ap.add_argument("--lr", type=float, default=1e-3, help="c5: Adam learning rate")
@@ -421,6 +422,8 @@ def main():
         if args.nu:
             c.nu1, c.nu2 = (int(x) for x in args.nu.split(","))
         c.colours = args.colours
+        if args.box:
+            c.box = args.box
         if args.tail_max:
             c.tail_max = args.tail_max
     forms = args.forms.split(",")

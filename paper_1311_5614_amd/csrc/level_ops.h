@@ -165,46 +165,78 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
   }
 }
 
-// Boxes of 8 x 8 cells (208 unknowns): one 256-lane workgroup per box; the
-// inverse columns stream from L2 (the level's 173 KB FP32 plain inverse fits
-// neither a lane's registers nor a workgroup's LDS).  Same arithmetic and
-// summation order as box_body_n.
-constexpr int kBigBoxLanes = 256;
+// Boxes of 8 x 8 cells (208 unknowns): four 256-lane workgroups per box, each
+// computing 52 rows of z = A_box^{-1} res, so that the inverse (173 KB FP32
+// shared, 346 KB FP64 per box with elastic rows) is read by four CUs.  In a
+// workgroup, wave q takes columns 52 q .. 52 q + 51 of its rows (one row per
+// lane, loaded before the barrier like box_body_n's single column; the box's
+// class is known first, so only the inverse it uses is loaded) and the four
+// partial sums are added in a fixed order.  Boxes of one colour share no
+// unknowns, and every workgroup reads only r and the elastic term and writes
+// only its own rows of w, so the workgroups of a box need no ordering.
+constexpr int kBigBoxLanes = 256, kBigBoxRowBlocks = 4;
+
+template <typename T, typename A>
+__device__ inline void big_box_rows(const A* __restrict__ inv, T y, int row, int rr, int q, bool act, size_t gr,
+                                    T wv, T* __restrict__ w, double* res, double (*part)[52]) {
+  constexpr int ND = 208, CP = 52;
+  A a[CP];
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < CP; ++c) a[c] = inv[(q * CP + c) * ND + row];
+  }
+  if (threadIdx.x < ND) res[threadIdx.x] = (double)y;
+  __syncthreads();
+  if (act) {
+    A z = A(0);
+#pragma unroll
+    for (int c = 0; c < CP; ++c) z += a[c] * (A)res[q * CP + c];
+    part[q][rr] = (double)z;
+  }
+  __syncthreads();
+  if (act && q == 0) {
+    const A z = (((A)part[0][rr] + (A)part[1][rr]) + (A)part[2][rr]) + (A)part[3][rr];
+    w[gr] = wv + (T)z;
+  }
+}
 
 template <typename T>
 __device__ inline void box_body_big(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
-                                    int blk) {
-  constexpr int NB = 8, ND = 2 * NB * (NB + 1) + NB * NB;
+                                    int blk, int rb) {
+  constexpr int NB = 8, ND = 2 * NB * (NB + 1) + NB * NB, RR = ND / kBigBoxRowBlocks, PARTS = 4;
+  static_assert(RR == 52 && ND / PARTS == 52, "8 x 8 box split");
   __shared__ double res[ND];
+  __shared__ double part[PARTS][RR];
   int bx, by;
   colour_box(blk, colour, L.ncol, L.nb, bx, by);
   const int lane = threadIdx.x, N = L.N, NN = N * N;
   const int ibx = L.ib_index ? L.ib_index[by * L.nb + bx] : -1;
-  int comp = 0, i = 0, j = 0;
-  size_t g = 0;
-  T y = T(0), wv = T(0), yb = T(0);
+  // the residual of the whole box
+  T y = T(0), yb = T(0);
+  int comp = 0;
   if (lane < ND) {
+    int i, j;
     box_dof(lane, bx, by, NB, N, comp, i, j);
-    g = (size_t)comp * NN + (size_t)j * N + i;
+    const size_t g = (size_t)comp * NN + (size_t)j * N + i;
     y = r[g];
-    wv = w[g];
     if (L.yib && comp < 2) yb = L.yib[g];   // zero off the active rows
   }
-  if (ibx >= 0 && comp < 2) y -= yb;
-  if (lane < ND) res[lane] = (double)y;
-  __syncthreads();
-  if (lane >= ND) return;
+  // this workgroup's rows: lane = 64 q + rr, row = RR rb + rr
+  const int rr = lane & 63, q = lane >> 6, row = rb * RR + rr;
+  const bool act = rr < RR;
+  size_t gr = 0;
+  T wv = T(0);
+  if (act) {
+    int c2, i2, j2;
+    box_dof(row, bx, by, NB, N, c2, i2, j2);
+    gr = (size_t)c2 * NN + (size_t)j2 * N + i2;
+    if (q == 0) wv = w[gr];
+  }
   if (ibx >= 0) {
-    const double* A = L.ainv_ib + (size_t)ibx * ND * ND;
-    double z = 0.0;
-#pragma unroll 16
-    for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[c];
-    w[g] = wv + (T)z;
+    if (comp < 2) y -= yb;
+    big_box_rows<T, double>(L.ainv_ib + (size_t)ibx * ND * ND, y, row, rr, q, act, gr, wv, w, res, part);
   } else {
-    T z = T(0);
-#pragma unroll 16
-    for (int c = 0; c < ND; ++c) z += L.ainv_plain[c * ND + lane] * (T)res[c];
-    w[g] = wv + z;
+    big_box_rows<T, T>(L.ainv_plain, y, row, rr, q, act, gr, wv, w, res, part);
   }
 }
 

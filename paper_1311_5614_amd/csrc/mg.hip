@@ -47,7 +47,8 @@ k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour, in
 template <typename T>
 __global__ void __launch_bounds__(kBigBoxLanes)
 k_box_big(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour) {
-  box_body_big<T>(L, r, w, colour, xcd_remap(blockIdx.x, gridDim.x));
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);   // the row blocks of a box stay on one XCD
+  box_body_big<T>(L, r, w, colour, wg / kBigBoxRowBlocks, wg % kBigBoxRowBlocks);
 }
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int Nf, const T* __restrict__ rf, T* __restrict__ rc,
@@ -132,7 +133,7 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
   if (!ib) V.ib_index = nullptr;
   const int cnt = colour_count(L.ncol, L.nb);
   if (L.n == 8) {
-    k_box_big<T><<<cnt, kBigBoxLanes, 0, s>>>(V, r, w, colour);
+    k_box_big<T><<<cnt * kBigBoxRowBlocks, kBigBoxLanes, 0, s>>>(V, r, w, colour);
   } else if (cnt >= kBoxWavesMax * 512) {
     const int grid = (cnt + kBoxWavesMax - 1) / kBoxWavesMax;
     if (L.n == 4) k_box<T, 4, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);
