@@ -113,6 +113,7 @@ def tuned(workload, cases):
             continue
         c.levels, c.tail_max, c.nu1, c.nu2, c.colours = (sch["levels"], sch["tail_max"], sch["nu1"], sch["nu2"],
                                                          sch["colours"])
+        c.box = sch.get("box", 4)
         out.append(c)
         precs.append(sch.get("prec", 1))
     return out, precs

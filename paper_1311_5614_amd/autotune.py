@@ -6,6 +6,7 @@ V-cycle schedules on seeded calibration problems -- same class, geometry
 drawn with other seeds than the benchmark's -- and keeps, per class, the
 fastest schedule whose steps all reach the tolerance.  A schedule is
 
+    box       box edge n (4 x 4 or 8 x 8 cells; the batch takes 4 x 4 only),
     levels    multigrid depth (coarsest 4^2, 8^2 or 16^2),
     tail_max  largest level run by the LDS-resident one-workgroup tail,
     nu1, nu2  smoothing sweeps (Algorithm 1),
@@ -74,20 +75,23 @@ def classes(workload):
     return out
 
 
-def candidates(w):
-    """Stage 1: the parameters that change convergence (depth, sweeps,
-    colours), with the tail at 8."""
+def candidates(w, boxes=(4,)):
+    """Stage 1: the parameters that change convergence (box, depth, sweeps,
+    colours), with the tail at 8.  A smoothed level holds at least two boxes
+    per side, so 8 x 8 boxes stop at an 8^2 or 16^2 coarsest grid."""
     full = w.levels
-    lv = [full - d for d in (0, 1, 2) if (w.N >> (full - d - 1)) <= 16]
-    for levels, nu, col in itertools.product(lv, ((1, 1), (2, 2), (3, 3), (2, 1)), (2, 4)):
-        yield dict(levels=levels, tail_max=8, nu1=nu[0], nu2=nu[1], colours=col, prec=1)
+    for box in boxes:
+        lv = [full - d for d in (0, 1, 2)
+              if (w.N >> (full - d - 1)) <= 16 and (w.N >> (full - d - 2)) >= 2 * box]
+        for levels, nu, col in itertools.product(lv, ((1, 1), (2, 2), (3, 3), (2, 1)), (2, 4)):
+            yield dict(box=box, levels=levels, tail_max=8, nu1=nu[0], nu2=nu[1], colours=col, prec=1)
 
 
 def tails(w, sch):
     """Stage 2: launch schedules of one V-cycle (tail sizes), and the FP64
-    V-cycle at the stage-1 tail."""
+    V-cycle at the stage-1 tail.  (8 x 8 boxes run no LDS-resident tail.)"""
     for tail in (1, 8, 16, 32):
-        if tail >= 8 and (w.N >> (sch["levels"] - 1)) > tail:
+        if tail >= 8 and ((w.N >> (sch["levels"] - 1)) > tail or sch["box"] > 4):
             continue   # the tail would hold only the coarsest level: same as tail 1
         yield dict(sch, tail_max=tail)
     yield dict(sch, prec=0)
@@ -96,7 +100,7 @@ def tails(w, sch):
 def time_schedule(w, dt, sch, steps, dev):
     import torch
     from . import ibmg
-    cfg = ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, box=4, nu1=sch["nu1"], nu2=sch["nu2"], maxit=MAXIT,
+    cfg = ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, box=sch["box"], nu1=sch["nu1"], nu2=sch["nu2"], maxit=MAXIT,
                       rtol=w.rtol, prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"])
     s = ibmg.Solver(cfg, w.fiber_offsets, dev)
     t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
@@ -134,9 +138,10 @@ def tune(workload, steps, dev="cuda:0"):
     """Per class: the fastest converging schedule; if none converges, the one
     with the fewest iterations (recorded with converged = false)."""
     res = {}
+    boxes = (4, 8) if workload == "c2" else (4,)   # the batched kernels take 4 x 4 boxes
     for key, w, dt in classes(workload):
         scored, failed = [], []
-        for sch in candidates(w):
+        for sch in candidates(w, boxes):
             r = _try(w, dt, sch, steps, dev, workload, key)
             if r is None:
                 continue
@@ -180,7 +185,7 @@ def main():
     data = load(args.out) if os.path.exists(args.out) else {}
     for wl in (("c2", "c4") if args.workload == "all" else (args.workload,)):
         data[wl] = tune(wl, args.steps)
-    data["meta"] = {"form": "V-cycle (prec 1 = fp32, 0 = fp64) in fp64 FGMRES", "box": 4,
+    data["meta"] = {"form": "V-cycle (prec 1 = fp32, 0 = fp64) in fp64 FGMRES",
                     "steps_timed": args.steps, "calibration_instance": CAL_INSTANCE, "maxit": MAXIT}
     with open(args.out, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)

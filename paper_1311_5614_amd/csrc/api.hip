@@ -426,9 +426,9 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
   int total = 0;
   double est = INFINITY;
   // Each cycle starts from the true residual of the current iterate.  The
-  // iterate with the smallest true residual is kept: a cycle that ends worse
-  // than it started (a Krylov basis spoiled by a stalled FP32 V-cycle) is
-  // dropped, and the next cycle starts again from the best iterate.
+  // iterate with the smallest true residual so far is kept, and a solve that
+  // stops unconverged returns it (a cycle can end worse than it started when
+  // its basis was built with a stalled FP32 V-cycle).
   double best = INFINITY;
   double* xbest = h->p<double>(h->xbest);
   for (;;) {
@@ -437,21 +437,19 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
     if ((rc = read_doubles(h, scal, hs, 1))) return rc;
     const double beta = std::sqrt(hs[0]);
     if (!std::isfinite(beta)) return IBMG_ENONFINITE;
-    if (beta > best) {
-      IBMG_HIP(hipMemcpyAsync(x, xbest, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
-      if (h->prec == IBMG_FP32 && !h->fb64) {   // go on from the best iterate with the FP64 V-cycle
-        h->fb64 = true;
-        st->fallback = 1;
-        continue;
-      }
-      st->rel_resid_true = best / bnorm;        // nothing else to try: give back the best iterate
-      break;
-    }
     st->rel_resid_true = beta / bnorm;
     if (beta <= target) { st->converged = 1; break; }
-    if (total >= m) break;
-    best = beta;
-    IBMG_HIP(hipMemcpyAsync(xbest, x, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (beta < best) {
+      best = beta;
+      if (total < m) IBMG_HIP(hipMemcpyAsync(xbest, x, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if (total >= m) {
+      if (beta > best) {           // give back the best iterate
+        IBMG_HIP(hipMemcpyAsync(x, xbest, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        st->rel_resid_true = best / bnorm;
+      }
+      break;
+    }
     launch_scale(s, V, V, n0, scal);
     k_fill<double><<<nblk(m + 2), 256, 0, s>>>(g, m + 2, 0.0);
     IBMG_HIP(hipMemcpyAsync(g, &beta, sizeof(double), hipMemcpyHostToDevice, s));

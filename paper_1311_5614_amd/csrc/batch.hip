@@ -811,22 +811,22 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
       q.k_end = -1;
       const double beta = std::sqrt(B->gather_h[4 * p]);
       if (!std::isfinite(beta)) { q.rc = IBMG_ENONFINITE; q.state = ST_DONE; continue; }
-      if (beta > q.best) {
-        IBMG_HIP(hipMemcpyAsync(hp->p<double>(hp->xvec), hp->p<double>(hp->xbest), xb, hipMemcpyDeviceToDevice, s));
-        if (B->prec == IBMG_FP32 && !q.fb64) {
-          q.fb64 = true;
-          q.st.fallback = 1;
-          continue;                 // state stays ST_START: residual of the best iterate next round
+      q.st.rel_resid_true = beta / q.bnorm;
+      if (beta <= q.target) { q.st.converged = 1; q.state = ST_DONE; continue; }
+      if (beta < q.best) {
+        q.best = beta;
+        if (q.total < m)
+          IBMG_HIP(hipMemcpyAsync(hp->p<double>(hp->xbest), hp->p<double>(hp->xvec), xb, hipMemcpyDeviceToDevice, s));
+      }
+      if (q.total >= m) {
+        if (beta > q.best) {        // give back the best iterate
+          IBMG_HIP(hipMemcpyAsync(hp->p<double>(hp->xvec), hp->p<double>(hp->xbest), xb, hipMemcpyDeviceToDevice,
+                                  s));
+          q.st.rel_resid_true = q.best / q.bnorm;
         }
-        q.st.rel_resid_true = q.best / q.bnorm;
         q.state = ST_DONE;
         continue;
       }
-      q.st.rel_resid_true = beta / q.bnorm;
-      if (beta <= q.target) { q.st.converged = 1; q.state = ST_DONE; continue; }
-      if (q.total >= m) { q.state = ST_DONE; continue; }
-      q.best = beta;
-      IBMG_HIP(hipMemcpyAsync(hp->p<double>(hp->xbest), hp->p<double>(hp->xvec), xb, hipMemcpyDeviceToDevice, s));
       q.beta = beta;
       q.begin = true;
       q.j = 0;
