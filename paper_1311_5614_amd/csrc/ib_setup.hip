@@ -103,17 +103,41 @@ k_box_fill(int M, const int* __restrict__ org, int n, int N, int nb, const int* 
 }
 
 // Ascending point ids within each box (fixed summation order downstream).
-// Lists on the finest level hold only the points within a few cells.
+// One wavefront per box: the box's list is staged in LDS and every lane
+// places its entries at their rank (the number of smaller ids; ids in a box
+// are distinct).  A list longer than the staging area is sorted in place by
+// insertion, one lane.  Lists on the finest level hold only the points
+// within a few cells.
+constexpr int kSortCap = 512;
+
 __global__ void __launch_bounds__(256)
-k_box_sort(int nbox, const int* __restrict__ start, int* __restrict__ list) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+k_box_sort(int nbox, const int* __restrict__ start, int* __restrict__ list, int max_list) {
+  __shared__ int stage[4][kSortCap];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + wave;
   if (b >= nbox) return;
-  const int s = start[b], e = start[b + 1];
-  for (int i = s + 1; i < e; ++i) {
-    const int v = list[i];
-    int j = i - 1;
-    while (j >= s && list[j] > v) { list[j + 1] = list[j]; --j; }
-    list[j + 1] = v;
+  const int s = start[b], e = min(start[b + 1], max_list), m = e - s;
+  if (m <= 1) return;
+  if (m > kSortCap) {
+    if (lane == 0)
+      for (int i = s + 1; i < e; ++i) {
+        const int v = list[i];
+        int j = i - 1;
+        while (j >= s && list[j] > v) { list[j + 1] = list[j]; --j; }
+        list[j + 1] = v;
+      }
+    return;
+  }
+  int* st = stage[wave];
+  for (int i = lane; i < m; i += 64) st[i] = list[s + i];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int i = lane; i < m; i += 64) {
+    const int v = st[i];
+    int rank = 0;
+    for (int q = 0; q < m; ++q) rank += st[q] < v;
+    list[s + rank] = v;
   }
 }
 
@@ -591,7 +615,7 @@ void launch_box_lists(hipStream_t s, const PointView& P, int* cnt, int* start, i
   launch_scan(s, cnt, nbox + 1, start, nullptr, 0, total, loc, bsum);
   if (P.M > 0) {
     k_box_fill<<<nblk(P.M), 256, 0, s>>>(P.M, P.org, P.n, P.N, P.nb, start, cursor, list, max_list);
-    k_box_sort<<<nblk(nbox), 256, 0, s>>>(nbox, start, list);
+    k_box_sort<<<(nbox + 3) / 4, 256, 0, s>>>(nbox, start, list, max_list);
   }
 }
 
