@@ -16,8 +16,9 @@
 //   a[i][j] <- a[i][j] - a[i][k] a[p][j] / d   (d = a[p][k]).
 // After nd steps the tile holds the inverse with rows and columns permuted:
 // with piv[k] the pivot row of column k and pinv its inverse permutation,
-// A^{-1}[pinv[i]][piv[m]] = a[i][m].  Column k and pivot row p go through LDS
-// (double-buffered by step parity, so a step needs two barriers).
+// A^{-1}[pinv[i]][piv[m]] = a[i][m].  Column k goes through LDS (double-
+// buffered by step parity); the pivot row is shuffled inside each 16-lane
+// group, so a step needs one barrier.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -27,7 +28,6 @@ constexpr int kGjLanes = kGjGY * kGjGX;
 
 struct GjScratch {
   double col[2][kGjMax];
-  double row[2][kGjMax];
   int p[2];
   int piv[kGjMax];
   int pinv[kGjMax];
@@ -79,21 +79,23 @@ __device__ inline void gauss_jordan_regs(int nd, GjScratch& S, Load load, Store 
     }
     __syncthreads();
     const int p = __builtin_amdgcn_readfirstlane(S.p[b]), pt = p / kGjTR, pr = p - pt * kGjTR;
-    if (ty == pt) {
-#pragma unroll
-      for (int r = 0; r < kGjTR; ++r)
-        if (r == pr) {
-#pragma unroll
-          for (int c = 0; c < kGjTC; ++c) S.row[b][c0 + c] = a[r][c];
-        }
-      used |= 1u << pr;
-    }
+    if (ty == pt) used |= 1u << pr;
     if (tid == 0) S.piv[k] = p;
-    __syncthreads();
+    // the pivot row's entries in this lane's columns sit in lane pt of the
+    // same 16-lane group
+    double prow[kGjTC];
+#pragma unroll
+    for (int c = 0; c < kGjTC; ++c) prow[c] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kGjTR; ++r)
+      if (r == pr) {
+#pragma unroll
+        for (int c = 0; c < kGjTC; ++c) prow[c] = a[r][c];
+      }
     const double inv = 1.0 / S.col[b][p];
     double pj[kGjTC];
 #pragma unroll
-    for (int c = 0; c < kGjTC; ++c) pj[c] = S.row[b][c0 + c] * inv;
+    for (int c = 0; c < kGjTC; ++c) pj[c] = __shfl(prow[c], pt, kGjGY) * inv;
     // every element a[i][j] -= a[i][k] a[p][j] / d; then column k and row p
     // (whose values the uniform update does not produce) are overwritten
 #pragma unroll
