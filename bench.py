@@ -6,13 +6,15 @@ modes per component), springs K in {1e2, 1e4, 1e6, 1e8} and dt in {100, 1000}
 x the explicit stability limit: 8 independent trajectories.  One bench step
 advances every trajectory by one implicit time step (FGMRES to relative
 residual 1e-8, at most 200 iterations, 4x4 boxes).  Timed from the same
-initial state in three forms:
+initial state in four forms:
 
   plain  FP64 V-cycle, default schedule (V(2,2), checkerboard boxes, levels
          down to 4x4, LDS tail from 32x32);
   fp32   FP32 V-cycle inside FP64 FGMRES, default schedule;
-  tuned  (chosen) per case the schedule and V-cycle precision picked by the
-         autotuner on calibration problems (schedules.json in the package).
+  tuned  per case the schedule and V-cycle precision picked by the
+         autotuner on calibration problems (schedules.json in the package);
+  concurrent  (chosen) the tuned form with the eight trajectories advanced
+         at the same time, each on its own stream and host thread.
 
 `value` is the chosen form's whole-job rate in time steps per second; inputs
 are resident in HBM before timing starts.  --workload c4 runs the 64-problem
@@ -122,14 +124,14 @@ def tuned(workload, cases):
 class Run:
     """Device state of one trajectory plus its solver handle."""
 
-    def __init__(self, w, dt, prec, dev):
+    def __init__(self, w, dt, prec, dev, stream=None):
         import torch
         from paper_1311_5614_amd import ibmg
         self.w, self.dt = w, dt
         cfg = ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
                           nu2=w.nu2, maxit=MAXIT, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
                           tail_max=getattr(w, "tail_max", 0))
-        self.s = ibmg.Solver(cfg, w.fiber_offsets, dev)
+        self.s = ibmg.Solver(cfg, w.fiber_offsets, dev, stream=stream)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
         self.X0 = t(w.X)
         self.gu = t(w.g_u) if w.g_u is not None else None
@@ -203,6 +205,56 @@ def timed_batch(br, steps, warmup):
     print(f"[bench] batch host phases per step: setup {phases[0] / steps:.1f} ms, solve {phases[1] / steps:.1f} ms, "
           f"step {phases[2] / steps:.1f} ms", file=sys.stderr, flush=True)
     return time.perf_counter() - t0, its, conv, br.b.rounds() - r0
+
+
+def timed_concurrent(runs, steps, warmup):
+    """Like timed(), but every trajectory advances in a host thread of its own
+    on a stream of its own (the library's calls release the interpreter, and
+    each solve's small, latency-bound launches overlap with the others')."""
+    import threading
+    import torch
+    from paper_1311_5614_amd.ibmg import IBMGError
+    for r in runs:
+        r.reset()
+    for _ in range(warmup):          # graph capture, sequentially
+        for r in runs:
+            try:
+                r.step()
+            except IBMGError:
+                pass
+    for r in runs:
+        r.reset()
+    torch.cuda.synchronize()
+    per_case = [[] for _ in runs]
+    conv_case = [[] for _ in runs]
+    failed = {}
+
+    def work(c, r):
+        for s in range(steps):
+            try:
+                st = r.step()
+            except IBMGError as e:
+                failed[c] = f"step {s}: {e}"
+                return
+            per_case[c].append(st["iters"])
+            conv_case[c].append(st["converged"])
+
+    threads = [threading.Thread(target=work, args=(c, r)) for c, r in enumerate(runs)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    its = [i for pc in per_case for i in pc]
+    conv = [c for cc in conv_case for c in cc]
+    if failed:
+        conv.append(0)
+        its.append(0)
+    timed.per_case = per_case
+    timed.failed = failed
+    return t, its, conv, None
 
 
 def timed(runs, steps, warmup, timing=False):
@@ -386,7 +438,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="plain,fp32,tuned")
+    ap.add_argument("--forms", default="plain,fp32,tuned,concurrent")
     ap.add_argument("--levels", type=int, default=0, help="override the workload's level count")
     ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
     ap.add_argument("--colours", type=int, default=2)
@@ -448,13 +500,20 @@ def main():
             del br
             torch.cuda.empty_cache()
             continue
-        if form == "tuned":
+        if form in ("tuned", "concurrent"):
             fcases, precs = tuned(args.workload, cases)
         else:
             fcases = cases
             precs = [ibmg.IBMG_FP32 if form == "fp32" else ibmg.IBMG_FP64] * len(cases)
-        runs = [Run(w, dt, pr, dev) for w, dt, pr in zip(fcases, dts, precs)]
-        t, its, conv, _ = timed(runs, args.steps, args.warmup, timing=False)
+        if form == "concurrent":
+            # concurrent: the tuned form with every trajectory on its own
+            # stream and host thread
+            runs = [Run(w, dt, pr, dev, stream=torch.cuda.Stream(dev)) for w, dt, pr in zip(fcases, dts, precs)]
+            torch.cuda.synchronize()
+            t, its, conv, _ = timed_concurrent(runs, args.steps, args.warmup)
+        else:
+            runs = [Run(w, dt, pr, dev) for w, dt, pr in zip(fcases, dts, precs)]
+            t, its, conv, _ = timed(runs, args.steps, args.warmup, timing=False)
         failed = dict(timed.failed)
         per_case = [round(sum(x) / max(1, len(x)), 1) for x in timed.per_case]
         # roofline of the box kernel: on the finest level of the first
@@ -478,7 +537,7 @@ def main():
         res[form]["iters_per_case"] = per_case
         del runs
         torch.cuda.empty_cache()
-    chosen = next((f for f in ("batch", "tuned", "fp32") if f in res), forms[0])
+    chosen = next((f for f in ("batch", "concurrent", "tuned", "fp32") if f in res), forms[0])
     rc = res[chosen]
     ph = next((res[f]["phase"] for f in (chosen, "tuned", "fp32", "plain") if f in res and res[f]["phase"]), None)
     achieved = ph["bytes"] / (ph["avg_us"] * 1e-6) / 1e9 if ph else None
@@ -504,6 +563,8 @@ def main():
             "K": sorted({c.K for c in cases}), "dt_factor": sorted({c.dt_factor for c in cases}),
             "chosen_form": {"fp32": "fp32 V-cycle inside fp64 FGMRES",
                             "tuned": "autotuned schedule and V-cycle precision per case inside fp64 FGMRES",
+                            "concurrent": "autotuned schedule and V-cycle precision per case inside fp64 FGMRES, "
+                                          "trajectories advanced concurrently (one stream and host thread each)",
                             "batch": "all trajectories in one batch, fp32 V-cycle, autotuned schedules"}.get(chosen,
                                                                                                       chosen),
         },
