@@ -7,6 +7,7 @@
 // Galerkin coarsening M_{l+1} = R M_l P with the Sec. 3.1 transfers
 // (Sec. 3.2); box relaxation blocks (Sec. 5-6); plain boxes share one factor
 // while boxes near the structure get their own, re-formed every step (Sec. 8).
+#include <climits>
 #include "common.h"
 #include "gj.h"
 #include "gj_reg.h"
@@ -103,23 +104,23 @@ k_box_fill(int M, const int* __restrict__ org, int n, int N, int nb, const int* 
 }
 
 // Ascending point ids within each box (fixed summation order downstream).
-// One wavefront per box: the box's list is staged in LDS and every lane
-// places its entries at their rank (the number of smaller ids; ids in a box
-// are distinct).  A list longer than the staging area is sorted in place by
-// insertion, one lane.  Lists on the finest level hold only the points
-// within a few cells.
-constexpr int kSortCap = 512;
+// One workgroup per box: the box's list is staged in LDS and sorted there.
+// Short lists (at most one entry per lane) place every entry at its rank (the
+// number of smaller ids; ids in a box are distinct); longer ones, where points
+// crowd into a box, run a bitonic network over the list padded to a power of
+// two.  A list longer than the staging area is sorted in place by insertion,
+// one lane (not met on the benchmark workloads).
+constexpr int kSortCap = 4096, kSortLanes = 256;
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kSortLanes)
 k_box_sort(int nbox, const int* __restrict__ start, int* __restrict__ list, int max_list) {
-  __shared__ int stage[4][kSortCap];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int b = blockIdx.x * 4 + wave;
+  __shared__ int st[kSortCap];
+  const int b = blockIdx.x, tid = threadIdx.x;
   if (b >= nbox) return;
   const int s = start[b], e = min(start[b + 1], max_list), m = e - s;
   if (m <= 1) return;
   if (m > kSortCap) {
-    if (lane == 0)
+    if (tid == 0)
       for (int i = s + 1; i < e; ++i) {
         const int v = list[i];
         int j = i - 1;
@@ -128,17 +129,34 @@ k_box_sort(int nbox, const int* __restrict__ start, int* __restrict__ list, int 
       }
     return;
   }
-  int* st = stage[wave];
-  for (int i = lane; i < m; i += 64) st[i] = list[s + i];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int i = lane; i < m; i += 64) {
-    const int v = st[i];
-    int rank = 0;
-    for (int q = 0; q < m; ++q) rank += st[q] < v;
-    list[s + rank] = v;
+  if (m <= kSortLanes) {
+    const int v = tid < m ? list[s + tid] : 0;
+    if (tid < m) st[tid] = v;
+    __syncthreads();
+    if (tid < m) {
+      int rank = 0;
+      for (int q = 0; q < m; ++q) rank += st[q] < v;
+      list[s + rank] = v;
+    }
+    return;
   }
+  int P = 1;
+  while (P < m) P <<= 1;
+  for (int i = tid; i < P; i += kSortLanes) st[i] = i < m ? list[s + i] : INT_MAX;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < P; i += kSortLanes) {
+        const int l = i ^ j;
+        if (l > i) {
+          const int a = st[i], c = st[l];
+          const bool up = (i & k) == 0;
+          if ((a > c) == up) { st[i] = c; st[l] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = tid; i < m; i += kSortLanes) list[s + i] = st[i];
 }
 
 // ---------------------------------------------------------------- multi-block exclusive scan
@@ -615,7 +633,7 @@ void launch_box_lists(hipStream_t s, const PointView& P, int* cnt, int* start, i
   launch_scan(s, cnt, nbox + 1, start, nullptr, 0, total, loc, bsum);
   if (P.M > 0) {
     k_box_fill<<<nblk(P.M), 256, 0, s>>>(P.M, P.org, P.n, P.N, P.nb, start, cursor, list, max_list);
-    k_box_sort<<<(nbox + 3) / 4, 256, 0, s>>>(nbox, start, list, max_list);
+    k_box_sort<<<nbox, kSortLanes, 0, s>>>(nbox, start, list, max_list);
   }
 }
 

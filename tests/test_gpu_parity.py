@@ -397,3 +397,45 @@ def test_fp32_stall_falls_back_to_fp64_and_converges():
     b = system.rhs(zz, zz, w.X, w.fiber_offsets, 1e2, dt, 1.0)
     sol = np.concatenate([tnp(u).ravel(), tnp(v).ravel(), tnp(p).ravel()])
     assert np.linalg.norm(b - lv[0].A @ sol) / np.linalg.norm(b) <= 1.02e-9
+
+
+def test_concurrent_trajectories_match_sequential():
+    """Two trajectories advanced at once, each on its own stream and host
+    thread (the benchmark's concurrent form), give bit for bit the states of
+    the same trajectories advanced one after the other."""
+    import threading
+    from paper_1311_5614_amd import ibmg
+
+    def runs(streams):
+        out = []
+        for k, (K, box) in enumerate(((1e4, 4), (1e6, 8))):
+            w = ibgen.small_case(N=64, M=160, K=K, seed=30 + k, levels=4, with_force=True)
+            dt = 50.0 * dtexp.dt_explicit(w.X, w.fiber_offsets, 64, K)
+            cfg = ibmg.Config(N=64, levels=4, K=K, box=box, rtol=1e-9, prec=ibmg.IBMG_FP32)
+            s = ibmg.Solver(cfg, w.fiber_offsets, DEV, stream=streams[k] if streams else None)
+            z = torch.zeros(64, 64, dtype=torch.float64, device=DEV)
+            out.append((s, dt, [z.clone(), z.clone(), z.clone(), tdev(w.X)], tdev(w.g_u), tdev(w.g_v)))
+        torch.cuda.synchronize()
+        return out
+
+    def advance(r, its):
+        s, dt, st, gu, gv = r
+        for _ in range(3):
+            its.append(s.step(dt, *st, gu, gv)["iters"])
+
+    seq = runs(None)
+    its_seq = [[], []]
+    for k, r in enumerate(seq):
+        advance(r, its_seq[k])
+    con = runs([torch.cuda.Stream(DEV), torch.cuda.Stream(DEV)])
+    its_con = [[], []]
+    th = [threading.Thread(target=advance, args=(r, its_con[k])) for k, r in enumerate(con)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    assert its_seq == its_con
+    for a, b in zip(seq, con):
+        for x, y in zip(a[2], b[2]):
+            assert torch.equal(x, y)
