@@ -33,6 +33,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "schedules.json")
 CAL_INSTANCE = 900   # seeds 1311000 + 100 * config + 900 + k are calibration-only
+CAL_GEOMETRIES = 2   # calibration geometries per class of the 256x256 sweep
 MAXIT = 200          # FGMRES iteration cap (no restart), as in the benchmark
 
 
@@ -42,21 +43,24 @@ def _dt_table():
 
 
 def classes(workload):
-    """(key, calibration Workload, dt) per class of the workload."""
+    """(key, [calibration Workloads], dt) per class of the workload."""
     import numpy as np
     sys.path.insert(0, ROOT)
     import ibgen
     dts = _dt_table()
     out = []
     if workload == "c2":
-        rng = np.random.default_rng(ibgen.seed_for(2, CAL_INSTANCE))
-        X, _ = ibgen.ellipse(rng, 1024)
-        gu, gv = ibgen.fourier_force(rng, 256)
+        geos = []
+        for g in range(CAL_GEOMETRIES):
+            rng = np.random.default_rng(ibgen.seed_for(2, CAL_INSTANCE + g))
+            X, _ = ibgen.ellipse(rng, 1024)
+            gu, gv = ibgen.fourier_force(rng, 256)
+            geos.append((X, gu, gv, ibgen.seed_for(2, CAL_INSTANCE + g)))
         for case, d in zip(ibgen.config_c2_cases(), dts["c2"]):
-            w = ibgen.Workload(f"cal-{case.name}", 256, case.levels, X.copy(), np.array([0, 1024], np.int32),
-                               case.K, case.dt_factor, rtol=case.rtol, g_u=gu, g_v=gv,
-                               seed=ibgen.seed_for(2, CAL_INSTANCE))
-            out.append((f"{case.K:.0e}-{int(case.dt_factor)}", w, d["dt"]))
+            ws = [ibgen.Workload(f"cal-{case.name}", 256, case.levels, X.copy(), np.array([0, 1024], np.int32),
+                                 case.K, case.dt_factor, rtol=case.rtol, g_u=gu, g_v=gv, seed=seed)
+                  for X, gu, gv, seed in geos]
+            out.append((f"{case.K:.0e}-{int(case.dt_factor)}", ws, d["dt"]))
     elif workload == "c4":
         cases = ibgen.config_c4()
         seen = set()
@@ -69,7 +73,7 @@ def classes(workload):
             w = ibgen.Workload(f"cal-{case.N}", case.N, case.levels, X, np.array([0, case.M], np.int32),
                                1e5, case.dt_factor, rtol=case.rtol, seed=ibgen.seed_for(4, CAL_INSTANCE))
             # dt of the class: the stored dt of this grid size rescaled from its K to 1e5
-            out.append((str(case.N), w, d["dt"] * case.K / 1e5))
+            out.append((str(case.N), [w], d["dt"] * case.K / 1e5))
     else:
         raise SystemExit(f"unknown workload {workload}")
     return out
@@ -122,10 +126,17 @@ def time_schedule(w, dt, sch, steps, dev):
     return el, its, ok
 
 
-def _try(w, dt, sch, steps, dev, workload, key):
+def _try(ws, dt, sch, steps, dev, workload, key):
+    """Mean time per step and the iterations over the class's calibration
+    geometries."""
     from .ibmg import IBMGError
+    el, its, ok = 0.0, [], True
     try:
-        el, its, ok = time_schedule(w, dt, sch, steps, dev)
+        for w in ws:
+            e1, i1, o1 = time_schedule(w, dt, sch, steps, dev)
+            el += e1 / len(ws)
+            its += i1
+            ok = ok and o1
     except IBMGError as e:          # e.g. a diverged trajectory leaves the window
         print(f"[autotune] {workload} {key} {sch} -> error {e}", flush=True)
         return None
@@ -139,10 +150,11 @@ def tune(workload, steps, dev="cuda:0"):
     with the fewest iterations (recorded with converged = false)."""
     res = {}
     boxes = (4, 8) if workload == "c2" else (4,)   # the batched kernels take 4 x 4 boxes
-    for key, w, dt in classes(workload):
+    for key, ws, dt in classes(workload):
+        w = ws[0]
         scored, failed = [], []
         for sch in candidates(w, boxes):
-            r = _try(w, dt, sch, steps, dev, workload, key)
+            r = _try(ws, dt, sch, steps, dev, workload, key)
             if r is None:
                 continue
             (scored if r[2] else failed).append((r[0], sch, r[1]))
@@ -158,7 +170,7 @@ def tune(workload, steps, dev="cuda:0"):
             for cand in tails(w, sch):
                 if cand == sch:
                     continue
-                r = _try(w, dt, cand, steps, dev, workload, key)
+                r = _try(ws, dt, cand, steps, dev, workload, key)
                 if r is None:
                     continue
                 el, its, ok = r
@@ -185,7 +197,7 @@ def main():
     data = load(args.out) if os.path.exists(args.out) else {}
     for wl in (("c2", "c4") if args.workload == "all" else (args.workload,)):
         data[wl] = tune(wl, args.steps)
-    data["meta"] = {"form": "V-cycle (prec 1 = fp32, 0 = fp64) in fp64 FGMRES",
+    data["meta"] = {"form": "V-cycle (prec 1 = fp32, 0 = fp64) in fp64 FGMRES", "c2_geometries": CAL_GEOMETRIES,
                     "steps_timed": args.steps, "calibration_instance": CAL_INSTANCE, "maxit": MAXIT}
     with open(args.out, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)

@@ -34,8 +34,9 @@ using namespace ibmg;
 constexpr int kWorkStreams = 4;  // concurrent streams for the per-problem setup (hardware queues per process)
 constexpr int kCap256 = 2048;   // persistent grid of the 256-lane level kernels (8 per CU)
 constexpr int kCapBox = 8192;   // persistent grid of the 64-lane box kernel (32 per CU)
+constexpr int kCapBox8 = 2048;  // persistent grid of the 256-lane 8 x 8 box kernel (8 per CU)
 
-enum { OP_FILL0 = 0, OP_RES, OP_BOX, OP_RESID, OP_IBROWS, OP_RESTRICT, OP_PROLONG, OP_TAIL };
+enum { OP_FILL0 = 0, OP_RES, OP_BOX, OP_BOX8, OP_RESID, OP_IBROWS, OP_RESTRICT, OP_PROLONG, OP_TAIL };
 
 // One problem's level in a batched V-cycle step.
 template <typename T>
@@ -145,6 +146,22 @@ kb_box(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __res
     const BLv<T>& e = lv[(size_t)k * P + p];
     box_body<T>(e.L, e.r, e.w, colour, t - off[p]);
     __syncthreads();   // the box's LDS is reused by the next box of this workgroup
+  }
+}
+
+// 8 x 8 boxes: tiles are (problem, box, row block), the four row blocks of a
+// box adjacent (one XCD).
+template <typename T>
+__global__ void __launch_bounds__(kBigBoxLanes)
+kb_box_big(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __restrict__ off) {
+  const int total = off[P];
+  for (int tt = blockIdx.x; tt < total; tt += gridDim.x) {
+    const int t = xcd_order(tt, total);
+    const int p = seg_find(off, P, t);
+    const BLv<T>& e = lv[(size_t)k * P + p];
+    const int q = t - off[p];
+    box_body_big<T>(e.L, e.r, e.w, colour, q / kBigBoxRowBlocks, q % kBigBoxRowBlocks);
+    __syncthreads();   // the box's LDS is reused by the next tile of this workgroup
   }
 }
 
@@ -483,6 +500,7 @@ void launch_op(ibmg_batch* B, hipStream_t s, int o) {
     case OP_RESTRICT: kb_level<T, OP_RESTRICT><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
     case OP_PROLONG: kb_level<T, OP_PROLONG><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
     case OP_BOX: kb_box<T><<<op.cap, 64, 0, s>>>(lv, P, op.k, op.colour, off); break;
+    case OP_BOX8: kb_box_big<T><<<op.cap, kBigBoxLanes, 0, s>>>(lv, P, op.k, op.colour, off); break;
   }
 }
 
@@ -539,7 +557,8 @@ void build_schedule(ibmg_batch* B) {
           case OP_RES:
             nb = in_sweep ? (int)nblk(3 * NN) + (ib ? 2 * ib_blocks(L.maxact) : 0) : 0;
             break;
-          case OP_BOX: nb = in_sweep ? colour_count(hp->ncol, L.nb) : 0; break;
+          case OP_BOX: nb = in_sweep && hp->n <= 4 ? colour_count(hp->ncol, L.nb) : 0; break;
+          case OP_BOX8: nb = in_sweep && hp->n == 8 ? colour_count(hp->ncol, L.nb) * kBigBoxRowBlocks : 0; break;
           case OP_RESID: nb = (int)nblk(3 * NN); break;
           case OP_IBROWS: nb = ib ? 2 * ib_blocks(L.maxact) : 0; break;
           case OP_RESTRICT: nb = (int)nblk(3 * NN / 4); break;
@@ -549,7 +568,7 @@ void build_schedule(ibmg_batch* B) {
       B->blocks.push_back(nb);
       total += nb;
     }
-    op.cap = std::max(1, std::min(total, kind == OP_BOX ? kCapBox : kCap256));
+    op.cap = std::max(1, std::min(total, kind == OP_BOX ? kCapBox : kind == OP_BOX8 ? kCapBox8 : kCap256));
     B->ops.push_back(op);
   };
   B->blocks.clear();
@@ -559,6 +578,7 @@ void build_schedule(ibmg_batch* B) {
       for (int c = 0; c < ncol; ++c) {
         add(OP_RES, k, c, q, 0);
         add(OP_BOX, k, c, q, 0);
+        add(OP_BOX8, k, c, q, 0);
       }
     add(OP_RESID, k, 0, 0, 0);
     add(OP_IBROWS, k, 0, 0, 0);
@@ -571,6 +591,7 @@ void build_schedule(ibmg_batch* B) {
       for (int c = 0; c < ncol; ++c) {
         add(OP_RES, k, c, q, 1);
         add(OP_BOX, k, c, q, 1);
+        add(OP_BOX8, k, c, q, 1);
       }
   }
   // drop ops no problem takes part in (the tail marker stays)
@@ -881,9 +902,7 @@ int ibmg_batch_create(ibmg_batch** out, int32_t nprob, const ibmg_problem* probs
   B->prec = opts[0].vcycle_prec;
   for (int p = 0; p < nprob; ++p) {
     ibmg_handle* h = nullptr;
-    int rc = opts[p].vcycle_prec != B->prec ? IBMG_EINVAL
-             : opts[p].box > 4              ? IBMG_ESHAPE   // the batched box kernel takes boxes of 1, 2 or 4 cells
-                                            : ibmg_create(&h, &probs[p], &opts[p], stream);
+    int rc = opts[p].vcycle_prec != B->prec ? IBMG_EINVAL : ibmg_create(&h, &probs[p], &opts[p], stream);
     if (rc) {
       for (ibmg_handle* q : B->h) ibmg_destroy(q);
       delete B;

@@ -142,9 +142,11 @@ inline int tail_start(const ibmg_handle* h) {
 // Dynamic LDS of the tail: three vectors (nine arrays) per level from ls on,
 // and one plain-box inverse.
 inline size_t tail_lds(const ibmg_handle* h, size_t elem) {
-  if (tail_start(h) == h->levels - 1) return 0;   // no tail kernel: the coarsest product only
-  size_t lds = (size_t)h->ndof * h->ndof * elem;
-  for (int l = tail_start(h); l < h->levels; ++l) lds += 9 * (size_t)h->L[l].N * h->L[l].N * elem;
+  const int ls = tail_start(h);
+  // a tail of the coarsest level alone (the batched V-cycle runs it in the
+  // tail kernel) smooths nothing and stages no box inverse
+  size_t lds = ls < h->levels - 1 ? (size_t)h->ndof * h->ndof * elem : 0;
+  for (int l = ls; l < h->levels; ++l) lds += 9 * (size_t)h->L[l].N * h->L[l].N * elem;
   return lds;
 }
 

@@ -240,7 +240,7 @@ __device__ inline void box_body_big(const LevelView<T>& L, const T* __restrict__
   }
 }
 
-// Boxes of 1, 2 or 4 cells (the batched kernels take no 8 x 8 boxes).
+// Boxes of 1, 2 or 4 cells (8 x 8 boxes go through box_body_big).
 template <typename T>
 __device__ inline void box_body(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
                                 int blk) {
@@ -551,5 +551,5 @@ __device__ inline void tail_body_n(const TailArgs<T>& A) {
   const int n = A.v[A.ls].n;
   if (n == 4) tail_body<T, 4>(A);
   else if (n == 2) tail_body<T, 2>(A);
-  else tail_body<T, 1>(A);
+  else tail_body<T, 1>(A);   // n = 1; with 8 x 8 boxes the tail is the coarsest level alone (no box)
 }

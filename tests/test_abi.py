@@ -143,7 +143,10 @@ def test_batch_create_validates_without_gpu():
     assert L.ibmg_batch_destroy(h) == 0
     assert make([32, 64], [0, 1], [4, 5])[0] == -1   # mixed V-cycle precision
     assert make([32, 48], [0, 0], [4, 5])[0] == -2   # one bad grid
-    assert make([32, 64], [0, 0], [2, 3], box=8)[0] == -2   # the batch takes boxes of 1, 2 or 4 cells
+    rc8, h8 = make([32, 64], [0, 0], [2, 3], box=8)          # 8x8 boxes
+    assert rc8 == 0
+    assert L.ibmg_batch_destroy(h8) == 0
+    assert make([32, 64], [0, 0], [4, 3], box=8)[0] == -2    # an 8x8 level would hold one 8x8 box
     h = C.c_void_p()
     assert L.ibmg_batch_create(C.byref(h), 0, None, None, None) == -1
 

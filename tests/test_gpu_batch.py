@@ -32,6 +32,8 @@ SPECS = [
     (64, 5, 160, 1e2, 10.0, 1, (2, 2), 2, 16, False),   # single-cell boxes (mild: weak smoother)
     (128, 6, 280, 1e4, 50.0, 4, (2, 2), 2, 17, False, 8),  # tail from 8^2 down: four big levels
     (64, 3, 140, 1e4, 50.0, 4, (2, 2), 2, 18, False, 1),   # 16^2 coarsest solved alone in the tail
+    (64, 4, 150, 1e5, 100.0, 8, (2, 2), 2, 19, False),  # 8x8 boxes, 8^2 coarsest (register inverse)
+    (128, 5, 300, 1e4, 50.0, 8, (1, 1), 4, 20, True),   # 8x8 boxes, 4 colours, 16^2 coarsest
 ]
 
 
@@ -107,6 +109,19 @@ def test_batch_equals_single_bitwise(prec):
     # lockstep: the rounds of one step are bounded by the slowest problem's
     # iterations plus two rounds per Arnoldi cycle (start, end) and ||b||
     assert rounds <= sum(max(it[s][0] for _, it in single) + 4 for s in range(2))
+
+
+def test_batch_of_coarsest_only_tails_equals_single_bitwise():
+    """Every problem's LDS-resident tail is its coarsest level alone (tail
+    size 1, and 8x8 boxes): the tail kernel's LDS is sized for that level."""
+    inp = [i for i, spec in zip(_inputs(), SPECS) if spec[5] == 8 or spec[10:] == (1,)]
+    assert len(inp) == 3
+    single = _run_single(inp, 1, steps=1)
+    batch, _ = _run_batch(inp, 1, steps=1)
+    for (ts, its), (tb, itb) in zip(single, batch):
+        assert its == itb
+        for a, b in zip(ts, tb):
+            assert torch.equal(a, b)
 
 
 def test_batch_graph_equals_eager():
