@@ -229,7 +229,10 @@ def timed_concurrent(runs, steps, warmup):
     conv_case = [[] for _ in runs]
     failed = {}
 
+    case_s = [0.0] * len(runs)
+
     def work(c, r):
+        t_start = time.perf_counter()
         for s in range(steps):
             try:
                 st = r.step()
@@ -238,6 +241,7 @@ def timed_concurrent(runs, steps, warmup):
                 return
             per_case[c].append(st["iters"])
             conv_case[c].append(st["converged"])
+        case_s[c] = time.perf_counter() - t_start
 
     threads = [threading.Thread(target=work, args=(c, r)) for c, r in enumerate(runs)]
     t0 = time.perf_counter()
@@ -254,6 +258,7 @@ def timed_concurrent(runs, steps, warmup):
         its.append(0)
     timed.per_case = per_case
     timed.failed = failed
+    timed.case_s = case_s
     return t, its, conv, None
 
 
@@ -507,8 +512,18 @@ def main():
             precs = [ibmg.IBMG_FP32 if form == "fp32" else ibmg.IBMG_FP64] * len(cases)
         if form == "concurrent":
             # concurrent: the tuned form with every trajectory on its own
-            # stream and host thread
-            runs = [Run(w, dt, pr, dev, stream=torch.cuda.Stream(dev)) for w, dt, pr in zip(fcases, dts, precs)]
+            # stream and host thread.  Streams are spread over the device's
+            # hardware queues in creation order, so they are created from the
+            # most to the least expensive trajectory (the autotuner's time per
+            # step of its class): the costliest trajectories get queues of
+            # their own.
+            from paper_1311_5614_amd import autotune
+            table = autotune.load().get(args.workload, {})
+            cost = [table.get(schedule_key(args.workload, w), {}).get("ms_per_step", 0.0) for w in cases]
+            streams = [None] * len(cases)
+            for k in sorted(range(len(cases)), key=lambda k: -cost[k]):
+                streams[k] = torch.cuda.Stream(dev)
+            runs = [Run(w, dt, pr, dev, stream=st) for w, dt, pr, st in zip(fcases, dts, precs, streams)]
             torch.cuda.synchronize()
             t, its, conv, _ = timed_concurrent(runs, args.steps, args.warmup)
         else:
@@ -535,6 +550,10 @@ def main():
               f"{res[form]['iters_mean']:.2f} max {max(its)}, converged {sum(conv)}/{n}; per case {per_case}",
               file=sys.stderr, flush=True)
         res[form]["iters_per_case"] = per_case
+        if form == "concurrent":
+            res[form]["seconds_per_case"] = [round(x, 3) for x in timed.case_s]
+            print(f"[bench] concurrent: wall seconds per trajectory {res[form]['seconds_per_case']}",
+                  file=sys.stderr, flush=True)
         del runs
         torch.cuda.empty_cache()
     chosen = next((f for f in ("batch", "concurrent", "tuned", "fp32") if f in res), forms[0])
