@@ -443,7 +443,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="plain,fp32,tuned,concurrent")
+    ap.add_argument("--forms", default="concurrent,plain,fp32,tuned")
     ap.add_argument("--levels", type=int, default=0, help="override the workload's level count")
     ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
     ap.add_argument("--colours", type=int, default=2)
@@ -516,7 +516,8 @@ def main():
             # hardware queues in creation order, so they are created from the
             # most to the least expensive trajectory (the autotuner's time per
             # step of its class): the costliest trajectories get queues of
-            # their own.
+            # their own.  The form runs first in the default order, before
+            # other forms' streams come and go.
             from paper_1311_5614_amd import autotune
             table = autotune.load().get(args.workload, {})
             cost = [table.get(schedule_key(args.workload, w), {}).get("ms_per_step", 0.0) for w in cases]
