@@ -353,8 +353,17 @@ int setup_finish(ibmg_handle* h) {
   const int M = h->M, Lv = h->levels;
   const std::vector<int>&info = h->rb_info, &nact = h->rb_nact, &mt = h->rb_mt, &lt = h->rb_lt;
   if (M > 0 && lt[0] > h->max_list) return IBMG_ENOMEM;
-  for (int l = 0; l < Lv && h->has_ib; ++l)
+  for (int l = 0; l < Lv && h->has_ib; ++l) {
     if (nact[2 * l] > h->L[l].maxact || nact[2 * l + 1] > h->L[l].maxact) return IBMG_ENOMEM;
+    // launch size of the elastic-row passes: grows with the active set (a
+    // quarter of headroom), and a V-cycle graph captured with a smaller one
+    // is captured again
+    const int need = std::max(nact[2 * l], nact[2 * l + 1]);
+    if (need > h->L[l].rowhint) {
+      h->L[l].rowhint = std::min(h->L[l].maxact, need + need / 4 + 64);
+      h->graph_dt = -1.0;
+    }
+  }
   if (mt[0] != 0) return IBMG_ESHAPE;   // an elastic coupling reaches beyond the coefficient window
   for (int l = 0; l + 1 < Lv; ++l) {
     for (int c = 0; c < 5; ++c) h->n_ib[l][c] = h->has_ib ? info[8 * l + c] : 0;

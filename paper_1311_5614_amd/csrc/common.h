@@ -34,6 +34,8 @@ struct LevelView {
   T invh;         // 1 / h_l
   int reach;      // window reach on this level
   int maxact;     // row capacity of the window store per component
+  int rowhint;    // launch size of the elastic-row passes: expected active rows per component (<= maxact;
+                  // the passes stride over the device-side count, so any size is correct)
   const int* act; // [2][N^2] active-row index of each face, or -1
   const T* win;   // [2][maxact][WS] windows
   const int* rows;// [2][maxact] face of each active row

@@ -28,6 +28,7 @@ struct LevelBufs {
   Buf ib_index, ib_boxes, boxflag, info;
   Buf ainv_plain, ainv_plain_f, ainv_ib;
   int max_ib = 0;
+  int rowhint = 0;           // launch-size hint of the elastic-row passes (see LevelView)
 };
 
 }  // namespace ibmg
@@ -98,6 +99,7 @@ inline LevelView<T> view(const ibmg_handle* h, int l) {
   v.invh = (T)(1.0 / hl);
   v.reach = B.reach;
   v.maxact = B.maxact;
+  v.rowhint = B.rowhint > 0 ? B.rowhint : B.maxact;
   if (h->has_ib) {
     v.act = h->p<int>(B.act);
     v.rows = h->p<int>(B.rows);

@@ -121,11 +121,11 @@ namespace ibmg {
 template <typename T> void launch_residual(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r,
                                            bool ib) {
   k_residual<T><<<nblk(3 * (size_t)L.N * L.N), 256, 0, s>>>(L, b, w, r);
-  if (ib) k_ib_rows<T><<<dim3(ib_blocks(L.maxact), 2), 256, 0, s>>>(L, w, r, b ? 2 : 1);
+  if (ib) k_ib_rows<T><<<dim3(ib_blocks(L.rowhint), 2), 256, 0, s>>>(L, w, r, b ? 2 : 1);
 }
 template <typename T> void launch_res(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r, bool ib) {
   const int nres = (int)nblk(3 * (size_t)L.N * L.N);
-  const int nib = ib ? 2 * ib_blocks(L.maxact) : 0;
+  const int nib = ib ? 2 * ib_blocks(L.rowhint) : 0;
   k_res_ib<T><<<nres + nib, 256, 0, s>>>(L, b, w, r, nres);
 }
 template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, const T* r, T* w, int colour, bool ib) {
