@@ -150,13 +150,19 @@ int read_doubles(ibmg_handle* h, const double* dev, double* host, int n) {
 // ---------------------------------------------------------------- V-cycle schedule
 
 // One colour phase (residual + elastic rows, then box solves), with the box
-// kernel timed by events when timing is on.
+// kernel timed by events when timing is on.  from_zero: the iterate is zero
+// (the first phase of a level's pre-smoothing: Algorithm 1 starts the
+// correction at zero), so the residual is b itself and the elastic term is
+// zero; the boxes read b directly and no residual pass is launched.
 template <typename T>
-void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r, int colour) {
-  launch_res<T>(h->stream, v, b, w, r, h->has_ib);
+void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r, int colour,
+                 bool from_zero) {
+  LevelView<T> vb = v;
+  if (from_zero) vb.yib = nullptr;
+  else launch_res<T>(h->stream, v, b, w, r, h->has_ib);
   const bool t = h->timing && h->ev_used + 2 <= (int)h->ev.size();
   if (t) (void)hipEventRecord(h->ev[h->ev_used], h->stream);
-  launch_box<T>(h->stream, v, r, w, colour, h->has_ib);
+  launch_box<T>(h->stream, vb, from_zero ? b : r, w, colour, h->has_ib);
   if (t) {
     (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
     // algorithmic bytes of one box launch: per unknown of the colour's boxes
@@ -171,8 +177,8 @@ void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w,
 }
 
 template <typename T>
-void sweep(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r) {
-  for (int c = 0; c < h->ncol; ++c) phase_timed<T>(h, v, l, b, w, r, c);
+void sweep(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r, bool from_zero = false) {
+  for (int c = 0; c < h->ncol; ++c) phase_timed<T>(h, v, l, b, w, r, c, from_zero && c == 0);
 }
 
 // z = MGV(0, r) on level 0 (Algorithm 1), vectors in precision T.
@@ -199,7 +205,8 @@ void vcycle(ibmg_handle* h, const T* b0, T* w0) {
     k_fill<T><<<nblk(n3), 256, 0, s>>>(w[0], n3, T(0));
   }
   for (int l = 0; l < ls; ++l) {
-    for (int q = 0; q < h->nu1; ++q) sweep<T>(h, v[l], l, b[l], w[l], r[l]);
+    // w[l] is zero here (cleared above, or by the restriction into level l)
+    for (int q = 0; q < h->nu1; ++q) sweep<T>(h, v[l], l, b[l], w[l], r[l], q == 0);
     launch_residual<T>(s, v[l], b[l], w[l], r[l], h->has_ib);
     launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b), w[l + 1]);   // also zeroes w[l+1]
   }

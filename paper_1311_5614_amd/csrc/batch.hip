@@ -136,15 +136,19 @@ kb_level(const BLv<T>* __restrict__ lv, const int* __restrict__ ls, int P, int k
   }
 }
 
+// from_zero: the first phase of a level's pre-smoothing, where the iterate
+// is zero -- the boxes read b as the residual and no elastic term.
 template <typename T>
 __global__ void __launch_bounds__(64)
-kb_box(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __restrict__ off) {
+kb_box(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __restrict__ off, int from_zero) {
   const int total = off[P];
   for (int tt = blockIdx.x; tt < total; tt += gridDim.x) {
     const int t = xcd_order(tt, total);
     const int p = seg_find(off, P, t);
     const BLv<T>& e = lv[(size_t)k * P + p];
-    box_body<T>(e.L, e.r, e.w, colour, t - off[p]);
+    LevelView<T> L = e.L;
+    if (from_zero) L.yib = nullptr;
+    box_body<T>(L, from_zero ? e.b : e.r, e.w, colour, t - off[p]);
     __syncthreads();   // the box's LDS is reused by the next box of this workgroup
   }
 }
@@ -153,14 +157,16 @@ kb_box(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __res
 // box adjacent (one XCD).
 template <typename T>
 __global__ void __launch_bounds__(kBigBoxLanes)
-kb_box_big(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __restrict__ off) {
+kb_box_big(const BLv<T>* __restrict__ lv, int P, int k, int colour, const int* __restrict__ off, int from_zero) {
   const int total = off[P];
   for (int tt = blockIdx.x; tt < total; tt += gridDim.x) {
     const int t = xcd_order(tt, total);
     const int p = seg_find(off, P, t);
     const BLv<T>& e = lv[(size_t)k * P + p];
     const int q = t - off[p];
-    box_body_big<T>(e.L, e.r, e.w, colour, q / kBigBoxRowBlocks, q % kBigBoxRowBlocks);
+    LevelView<T> L = e.L;
+    if (from_zero) L.yib = nullptr;
+    box_body_big<T>(L, from_zero ? e.b : e.r, e.w, colour, q / kBigBoxRowBlocks, q % kBigBoxRowBlocks);
     __syncthreads();   // the box's LDS is reused by the next tile of this workgroup
   }
 }
@@ -395,6 +401,7 @@ __global__ void kb_gather(const BKry* __restrict__ K, int P, double* __restrict_
 struct BOp {
   int kind, k, colour;
   int cap;
+  int from_zero;   // box op of the first pre-smoothing phase (iterate zero, no residual op before it)
 };
 
 // Host-side slot set of a round, mirrored into the round buffer.
@@ -499,8 +506,8 @@ void launch_op(ibmg_batch* B, hipStream_t s, int o) {
     case OP_IBROWS: kb_level<T, OP_IBROWS><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
     case OP_RESTRICT: kb_level<T, OP_RESTRICT><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
     case OP_PROLONG: kb_level<T, OP_PROLONG><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
-    case OP_BOX: kb_box<T><<<op.cap, 64, 0, s>>>(lv, P, op.k, op.colour, off); break;
-    case OP_BOX8: kb_box_big<T><<<op.cap, kBigBoxLanes, 0, s>>>(lv, P, op.k, op.colour, off); break;
+    case OP_BOX: kb_box<T><<<op.cap, 64, 0, s>>>(lv, P, op.k, op.colour, off, op.from_zero); break;
+    case OP_BOX8: kb_box_big<T><<<op.cap, kBigBoxLanes, 0, s>>>(lv, P, op.k, op.colour, off, op.from_zero); break;
   }
 }
 
@@ -536,8 +543,8 @@ void build_schedule(ibmg_batch* B) {
     ncol = std::max(ncol, B->h[p]->ncol);
   }
   B->ops.clear();
-  auto add = [&](int kind, int k, int colour, int sweep, int post) {
-    BOp op{kind, k, colour, 0};
+  auto add = [&](int kind, int k, int colour, int sweep, int post, int from_zero = 0) {
+    BOp op{kind, k, colour, 0, from_zero};
     int total = 0;
     for (int p = 0; p < P; ++p) {
       const ibmg_handle* hp = B->h[p];
@@ -576,9 +583,12 @@ void build_schedule(ibmg_batch* B) {
   for (int k = B->Kmax - 1; k >= 0; --k) {
     for (int q = 0; q < nu1; ++q)
       for (int c = 0; c < ncol; ++c) {
-        add(OP_RES, k, c, q, 0);
-        add(OP_BOX, k, c, q, 0);
-        add(OP_BOX8, k, c, q, 0);
+        // the level's iterate is zero before its first phase (FILL0 or the
+        // restriction into it cleared it): no residual op, boxes read b
+        const int fz = q == 0 && c == 0;
+        if (!fz) add(OP_RES, k, c, q, 0);
+        add(OP_BOX, k, c, q, 0, fz);
+        add(OP_BOX8, k, c, q, 0, fz);
       }
     add(OP_RESID, k, 0, 0, 0);
     add(OP_IBROWS, k, 0, 0, 0);
