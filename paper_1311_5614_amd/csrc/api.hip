@@ -207,8 +207,10 @@ void vcycle(ibmg_handle* h, const T* b0, T* w0) {
   for (int l = 0; l < ls; ++l) {
     // w[l] is zero here (cleared above, or by the restriction into level l)
     for (int q = 0; q < h->nu1; ++q) sweep<T>(h, v[l], l, b[l], w[l], r[l], q == 0);
-    launch_residual<T>(s, v[l], b[l], w[l], r[l], h->has_ib);
-    launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b), w[l + 1]);   // also zeroes w[l+1]
+    // Stokes residual and the elastic term in one pass; the restriction
+    // subtracts the elastic term (also zeroes w[l+1])
+    launch_res<T>(s, v[l], b[l], w[l], r[l], h->has_ib);
+    launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b), w[l + 1], h->has_ib ? v[l].yib : nullptr);
   }
   if (ls == Lv - 1)
     launch_coarse_apply<T>(s, h->p<double>(h->cainv), h->nr, b[ls], w[ls]);

@@ -36,7 +36,7 @@ constexpr int kCap256 = 2048;   // persistent grid of the 256-lane level kernels
 constexpr int kCapBox = 8192;   // persistent grid of the 64-lane box kernel (32 per CU)
 constexpr int kCapBox8 = 2048;  // persistent grid of the 256-lane 8 x 8 box kernel (8 per CU)
 
-enum { OP_FILL0 = 0, OP_RES, OP_BOX, OP_BOX8, OP_RESID, OP_IBROWS, OP_RESTRICT, OP_PROLONG, OP_TAIL };
+enum { OP_FILL0 = 0, OP_RES, OP_BOX, OP_BOX8, OP_RESID, OP_RESTRICT, OP_PROLONG, OP_TAIL };
 
 // One problem's level in a batched V-cycle step.
 template <typename T>
@@ -48,7 +48,6 @@ struct BLv {
   T* bc;      // next coarser level: right-hand side and iterate
   T* wc;
   int nres;   // residual workgroups (3 N_l^2 / 256)
-  int nibx;   // elastic-row workgroups per component (striding over the rows, 16 lanes each)
   int nibr;   // elastic-row workgroups of the fused residual (both components)
 };
 
@@ -125,11 +124,11 @@ kb_level(const BLv<T>* __restrict__ lv, const int* __restrict__ ls, int P, int k
     } else if constexpr (KIND == OP_RES) {
       res_ib_body<T>(e.L, e.b, e.w, e.r, e.nres, blk, e.nibr);
     } else if constexpr (KIND == OP_RESID) {
-      residual_body<T>(e.L, e.b, e.w, e.r, blk);
-    } else if constexpr (KIND == OP_IBROWS) {
-      ib_rows_body<T>(e.L, e.w, e.r, e.b ? 2 : 1, blk % e.nibx, blk / e.nibx, e.nibx);
+      // residual before the restriction: Stokes part and elastic term in one
+      // pass; the restriction subtracts the elastic term
+      res_ib_body<T>(e.L, e.b, e.w, e.r, e.nres, blk, e.nibr);
     } else if constexpr (KIND == OP_RESTRICT) {
-      restrict_body<T>(e.L.N, e.r, e.bc, e.wc, blk);
+      restrict_body<T>(e.L.N, e.r, e.bc, e.wc, blk, e.L.yib);
     } else if constexpr (KIND == OP_PROLONG) {
       prolong_body<T>(e.L.N, e.wc, e.w, blk);
     }
@@ -503,7 +502,6 @@ void launch_op(ibmg_batch* B, hipStream_t s, int o) {
     case OP_FILL0: kb_level<T, OP_FILL0><<<op.cap, 256, 0, s>>>(lv, ls, P, 0, off); break;
     case OP_RES: kb_level<T, OP_RES><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
     case OP_RESID: kb_level<T, OP_RESID><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
-    case OP_IBROWS: kb_level<T, OP_IBROWS><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
     case OP_RESTRICT: kb_level<T, OP_RESTRICT><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
     case OP_PROLONG: kb_level<T, OP_PROLONG><<<op.cap, 256, 0, s>>>(lv, ls, P, op.k, off); break;
     case OP_BOX: kb_box<T><<<op.cap, 64, 0, s>>>(lv, P, op.k, op.colour, off, op.from_zero); break;
@@ -566,8 +564,7 @@ void build_schedule(ibmg_batch* B) {
             break;
           case OP_BOX: nb = in_sweep && hp->n <= 4 ? colour_count(hp->ncol, L.nb) : 0; break;
           case OP_BOX8: nb = in_sweep && hp->n == 8 ? colour_count(hp->ncol, L.nb) * kBigBoxRowBlocks : 0; break;
-          case OP_RESID: nb = (int)nblk(3 * NN); break;
-          case OP_IBROWS: nb = ib ? 2 * ib_blocks(L.maxact) : 0; break;
+          case OP_RESID: nb = (int)nblk(3 * NN) + (ib ? 2 * ib_blocks(L.maxact) : 0); break;
           case OP_RESTRICT: nb = (int)nblk(3 * NN / 4); break;
           case OP_PROLONG: nb = (int)nblk(3 * NN); break;
         }
@@ -591,7 +588,6 @@ void build_schedule(ibmg_batch* B) {
         add(OP_BOX8, k, c, q, 0, fz);
       }
     add(OP_RESID, k, 0, 0, 0);
-    add(OP_IBROWS, k, 0, 0, 0);
     add(OP_RESTRICT, k, 0, 0, 0);
   }
   add(OP_TAIL, 0, 0, 0, 0);   // the LDS-resident tail of every problem
@@ -649,7 +645,6 @@ void fill_tables(ibmg_batch* B) {
       e.wc = h->p<T>(h->L[l + 1].w);
       const size_t NN = (size_t)v[l].N * v[l].N;
       e.nres = (int)nblk(3 * NN);
-      e.nibx = ib_blocks(v[l].maxact);
       e.nibr = 2 * ib_blocks(v[l].maxact);
     }
     TailArgs<T>& A = ta[p];

@@ -48,7 +48,9 @@ template <typename T> void launch_residual(hipStream_t s, const LevelView<T>& L,
                                            bool ib);
 template <typename T> void launch_res(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r, bool ib);
 template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, const T* r, T* w, int colour, bool ib);
-template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero);
+// yf (nullable): elastic term of the fine residual (rf - yf is restricted)
+template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero,
+                                           const T* yf = nullptr);
 template <typename T> void launch_prolong_add(hipStream_t s, int Nf, const T* ec, T* wf);
 int prepare_tail(size_t lds);
 template <typename T> int launch_tail(hipStream_t s, const LevelView<T>* views, int ls, int L, int nu1, int nu2,

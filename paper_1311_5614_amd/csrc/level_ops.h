@@ -251,28 +251,36 @@ __device__ inline void box_body(const LevelView<T>& L, const T* __restrict__ r, 
 
 // ---------------------------------------------------------------- a10: restriction (Sec. 3.1)
 // The coarse correction of Algorithm 1 starts from zero, so the same launch
-// clears the coarse iterate (wz, nullable).
+// clears the coarse iterate (wz, nullable).  yf (nullable): the elastic term
+// of the fine residual, zero off the active rows -- the fine residual is
+// rf - yf, formed here (one subtraction, as the elastic-row pass would).
+template <typename T>
+__device__ inline T res_at(const T* __restrict__ rf, const T* __restrict__ yf, size_t i) {
+  return yf ? rf[i] - yf[i] : rf[i];
+}
+
 template <typename T>
 __device__ inline void restrict_body(int Nf, const T* __restrict__ rf, T* __restrict__ rc, T* __restrict__ wz,
-                                     int blk) {
+                                     int blk, const T* __restrict__ yf = nullptr) {
   const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf, mf = Nf - 1, lgc = __builtin_ctz(Nc);
   const int idx = blk * 256 + threadIdx.x;
   if (idx >= 3 * NNc) return;
   const int comp = idx >> (2 * lgc), rem = idx & (NNc - 1);
   const int J = rem >> lgc, I = rem & (Nc - 1);
   const T* f = rf + (size_t)comp * NNf;
+  const T* y = yf && comp < 2 ? yf + (size_t)comp * NNf : nullptr;
   T s = T(0);
   if (comp == 0) {
     for (int e = 0; e < 2; ++e) {
       const int jj = 2 * J + e;
-      s += T(0.125) * f[jj * Nf + ((2 * I - 1) & mf)] + T(0.25) * f[jj * Nf + 2 * I] +
-           T(0.125) * f[jj * Nf + ((2 * I + 1) & mf)];
+      s += T(0.125) * res_at(f, y, jj * Nf + ((2 * I - 1) & mf)) + T(0.25) * res_at(f, y, jj * Nf + 2 * I) +
+           T(0.125) * res_at(f, y, jj * Nf + ((2 * I + 1) & mf));
     }
   } else if (comp == 1) {
     for (int e = 0; e < 2; ++e) {
       const int ii = 2 * I + e;
-      s += T(0.125) * f[((2 * J - 1) & mf) * Nf + ii] + T(0.25) * f[(2 * J) * Nf + ii] +
-           T(0.125) * f[((2 * J + 1) & mf) * Nf + ii];
+      s += T(0.125) * res_at(f, y, ((2 * J - 1) & mf) * Nf + ii) + T(0.25) * res_at(f, y, (2 * J) * Nf + ii) +
+           T(0.125) * res_at(f, y, ((2 * J + 1) & mf) * Nf + ii);
     }
   } else {
     s = T(0.25) * (f[2 * J * Nf + 2 * I] + f[2 * J * Nf + 2 * I + 1] + f[(2 * J + 1) * Nf + 2 * I] +

@@ -52,8 +52,8 @@ k_box_big(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour
 }
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int Nf, const T* __restrict__ rf, T* __restrict__ rc,
-                                                  T* __restrict__ wz) {
-  restrict_body<T>(Nf, rf, rc, wz, blockIdx.x);
+                                                  T* __restrict__ wz, const T* __restrict__ yf) {
+  restrict_body<T>(Nf, rf, rc, wz, blockIdx.x, yf);
 }
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(int Nf, const T* __restrict__ ec, T* __restrict__ wf) {
@@ -145,8 +145,8 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
     else k_box<T, 1, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt);
   }
 }
-template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero) {
-  k_restrict<T><<<nblk(3 * (size_t)(Nf / 2) * (Nf / 2)), 256, 0, s>>>(Nf, rf, rc, wc_zero);
+template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero, const T* yf) {
+  k_restrict<T><<<nblk(3 * (size_t)(Nf / 2) * (Nf / 2)), 256, 0, s>>>(Nf, rf, rc, wc_zero, yf);
 }
 template <typename T> void launch_prolong_add(hipStream_t s, int Nf, const T* ec, T* wf) {
   k_prolong_add<T><<<nblk(3 * (size_t)Nf * Nf), 256, 0, s>>>(Nf, ec, wf);
@@ -191,7 +191,7 @@ void launch_interp(hipStream_t s, const PointView& P, const double* u, const dou
   template void launch_residual<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, bool);     \
   template void launch_res<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, bool);         \
   template void launch_box<T>(hipStream_t, const LevelView<T>&, const T*, T*, int, bool);             \
-  template void launch_restrict<T>(hipStream_t, int, const T*, T*, T*);                                 \
+  template void launch_restrict<T>(hipStream_t, int, const T*, T*, T*, const T*);                                 \
   template void launch_prolong_add<T>(hipStream_t, int, const T*, T*);                                  \
   template int launch_tail<T>(hipStream_t, const LevelView<T>*, int, int, int, int, bool, int, const T*, T*,   \
                               const double*);
