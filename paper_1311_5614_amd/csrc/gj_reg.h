@@ -34,8 +34,6 @@ struct GjScratch {
 };
 
 // load(i, j) -> A[i][j] for i, j < nd; store(r, c, v) receives A^{-1}[r][c].
-// Every lane of the kGjLanes-lane workgroup must call this.
-// load(i, j) -> A[i][j] for i, j < nd; store(r, c, v) receives A^{-1}[r][c].
 // Every lane of the kGjLanes-lane workgroup must call this.  The pivot row is
 // made wave-uniform (readfirstlane) so that its tile row is picked by scalar
 // branches; the tile column of k is picked by selects in the one wave that

@@ -10,7 +10,8 @@
 #include "common.h"
 
 // ---------------------------------------------------------------- a8: y = A w or r = b - A w
-// Stokes part here; the elastic rows are added by k_ib_rows afterwards.
+// Stokes part here; the elastic rows are added by an elastic-row pass
+// afterwards (ib_rows_body), or formed beside it (res_ib_body).
 template <typename T>
 __device__ inline void residual_body(const LevelView<T>& L, const T* __restrict__ b, const T* __restrict__ w,
                                      T* __restrict__ r, int blk) {
@@ -78,11 +79,12 @@ __device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__
 // unknowns, and every elastic window, reaches unknowns of other boxes of the
 // same colour).  k_res_ib: r = b - (Stokes part of A) w on every unknown, and
 // yib = (M_l w) on every active elastic row (16 lanes per row, fixed-order
-// shuffle tree).  k_box: one 64-lane workgroup per box of the colour; lane r
-// takes res = r - yib at local unknown r, z = A_box^{-1} res, w[box] += z.
-// Boxes of one colour share no unknowns, so the update is race-free.  Boxes
-// that touch the structure use their own FP64 inverse with the residual
-// promoted to FP64.
+// shuffle tree).  k_box: one 64-lane wave per box of the colour; lane r takes
+// res = r - yib at local unknown r, z = A_box^{-1} res, w[box] += z.  Boxes
+// of one colour share no unknowns, so the update is race-free.  Boxes that
+// touch the structure use their own FP64 inverse with the residual promoted
+// to FP64.  The same fused pass forms the residual before each restriction,
+// which subtracts yib (restrict_body).
 template <typename T>
 __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ b, const T* __restrict__ w,
                                    T* __restrict__ r, int nres_blocks, int blk, int nib) {
