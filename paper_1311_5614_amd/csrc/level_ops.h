@@ -31,23 +31,39 @@ __device__ inline void residual_body(const LevelView<T>& L, const T* __restrict_
 // the phase -- a window reaches past the next box of the same colour, so the
 // phase kernel must not evaluate it while those boxes are being updated);
 // mode 1: out[f] += (M w)_f; mode 2: out[f] -= (M w)_f.
+// Lane dx + R of the 16 takes window column dx (lanes past 2R idle) and sums
+// its 2R + 1 entries top to bottom; every load is issued before the first
+// product, so a row costs one memory latency.
+template <typename T, int R>
+__device__ inline T ib_col(const T* __restrict__ c, const T* __restrict__ x, int N, int i, int j, int lane) {
+  constexpr int W = 2 * R + 1;
+  const int msk = N - 1;
+  T acc = T(0);
+  if (lane < W) {
+    const int dx = lane - R, ic = (i + dx) & msk;
+    T cv[W], xv[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      cv[t] = c[(t - R + IBMG_WR) * IBMG_WW + dx + IBMG_WR];
+      xv[t] = x[((j + t - R) & msk) * N + ic];
+    }
+#pragma unroll
+    for (int t = 0; t < W; ++t) acc += cv[t] * xv[t];
+  }
+  return acc;
+}
+
 template <typename T>
 __device__ inline T ib_row(const LevelView<T>& L, const T* __restrict__ w, int comp, int row, int lane, int& f) {
-  const int N = L.N, msk = N - 1, NN = N * N;
+  const int N = L.N, NN = N * N, lg = __builtin_ctz(N);
   f = L.rows[comp * L.maxact + row];
-  const int j = f / N, i = f - j * N;
-  const int r = L.reach, W = 2 * r + 1;
+  const int j = f >> lg, i = f & (N - 1);
   const T* c = L.win + ((size_t)comp * L.maxact + row) * IBMG_WS;
   const T* x = w + (size_t)comp * NN;
-  T acc = T(0);
-  // entries lane, lane + 16, ... of the W x W window, row-major
-  int qy = lane / W, qx = lane - qy * W;
-  for (int q = lane; q < W * W; q += 16) {
-    const int dy = qy - r, dx = qx - r;
-    acc += c[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR] * x[((j + dy) & msk) * N + ((i + dx) & msk)];
-    qx += 16;
-    while (qx >= W) { qx -= W; ++qy; }
-  }
+  T acc;
+  if (L.reach <= 3) acc = ib_col<T, 3>(c, x, N, i, j, lane);
+  else if (L.reach == 4) acc = ib_col<T, 4>(c, x, N, i, j, lane);
+  else acc = ib_col<T, 5>(c, x, N, i, j, lane);
   acc += __shfl_xor(acc, 8, 16);
   acc += __shfl_xor(acc, 4, 16);
   acc += __shfl_xor(acc, 2, 16);
