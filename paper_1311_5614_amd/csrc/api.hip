@@ -374,13 +374,23 @@ int setup_finish(ibmg_handle* h) {
     }
   }
   if (mt[0] != 0) return IBMG_ESHAPE;   // an elastic coupling reaches beyond the coefficient window
+  // box inverses of all levels in one launch (the levels are independent)
+  BoxFactorLevels F{};
+  F.nl = Lv - 1;
+  int nfb = 0;
   for (int l = 0; l + 1 < Lv; ++l) {
     for (int c = 0; c < 5; ++c) h->n_ib[l][c] = h->has_ib ? info[8 * l + c] : 0;
     if (h->n_ib[l][4] > h->L[l].max_ib) return IBMG_ENOMEM;
-    LevelView<double> v = view<double>(h, l);
-    launch_box_factor(s, v, h->p<int>(h->L[l].ib_boxes), h->n_ib[l][4], h->p<double>(h->L[l].ainv_plain),
-                      h->p<float>(h->L[l].ainv_plain_f), h->p<double>(h->L[l].ainv_ib));
+    F.v[l] = view<double>(h, l);
+    F.ib_boxes[l] = h->p<int>(h->L[l].ib_boxes);
+    F.ainv_plain[l] = h->p<double>(h->L[l].ainv_plain);
+    F.ainv_plain_f[l] = h->p<float>(h->L[l].ainv_plain_f);
+    F.ainv_ib[l] = h->p<double>(h->L[l].ainv_ib);
+    F.first[l] = nfb;
+    nfb += 1 + h->n_ib[l][4];
   }
+  F.first[F.nl] = nfb;
+  launch_box_factor(s, F);
   {
     LevelView<double> v = view<double>(h, Lv - 1);
     launch_coarse_assemble(s, v, h->p<double>(h->aug), h->nr);

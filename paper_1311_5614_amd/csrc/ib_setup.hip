@@ -527,18 +527,27 @@ __device__ void assemble_box(const LevelView<double>& L, int bx, int by, bool wi
 
 // Block 0: the plain box (Stokes only, shared by every box without elastic
 // rows).  Block 1 + q: box ib_boxes[q].  Inverses are written column-major.
-__global__ void __launch_bounds__(128)
-k_box_factor(LevelView<double> L, const int* __restrict__ ib_boxes, double* __restrict__ ainv_plain,
-             float* __restrict__ ainv_plain_f, double* __restrict__ ainv_ib) {
+// Level of block blk of a multi-level factor launch (uniform per block).
+__device__ inline int factor_level(const ibmg::BoxFactorLevels& F, int blk) {
+  int l = 0;
+  while (l + 1 < F.nl && blk >= F.first[l + 1]) ++l;
+  return l;
+}
+
+__global__ void __launch_bounds__(128) k_box_factor(ibmg::BoxFactorLevels F) {
   __shared__ double a[IBMG_MAX_NDOF * 2 * IBMG_MAX_NDOF];
   __shared__ double colk[IBMG_MAX_NDOF];
   __shared__ int piv;
   __shared__ double pval;
+  const int lv = factor_level(F, blockIdx.x), blk = blockIdx.x - F.first[lv];
+  const LevelView<double>& L = F.v[lv];
+  double* ainv_plain = F.ainv_plain[lv];
+  float* ainv_plain_f = F.ainv_plain_f[lv];
   const int nd = L.ndof, ld = 2 * nd;
-  const bool plain = blockIdx.x == 0;
+  const bool plain = blk == 0;
   int bx = 0, by = 0;
   if (!plain) {
-    const int box = ib_boxes[blockIdx.x - 1];
+    const int box = F.ib_boxes[lv][blk - 1];
     bx = box % L.nb;
     by = box / L.nb;
   }
@@ -550,7 +559,7 @@ k_box_factor(LevelView<double> L, const int* __restrict__ ib_boxes, double* __re
   assemble_box(L, bx, by, !plain, a, ld);
   __syncthreads();
   gauss_jordan_cols(a, nd, ld, colk, &piv, &pval);
-  double* out = plain ? ainv_plain : ainv_ib + (size_t)(blockIdx.x - 1) * nd * nd;
+  double* out = plain ? ainv_plain : F.ainv_ib[lv] + (size_t)(blk - 1) * nd * nd;
   for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) {
     const int r = idx / nd, c = idx - r * nd;
     const double v = a[r * ld + nd + c];
@@ -562,24 +571,24 @@ k_box_factor(LevelView<double> L, const int* __restrict__ ib_boxes, double* __re
 // Blocks of 8 x 8 boxes (208 unknowns): assembled row-major into their own
 // output slot, then inverted in registers (gj_reg.h) and written back
 // column-major over it.  Same block numbering as k_box_factor.
-__global__ void __launch_bounds__(kGjLanes)
-k_box_factor_big(LevelView<double> L, const int* __restrict__ ib_boxes, double* __restrict__ ainv_plain,
-                 float* __restrict__ ainv_plain_f, double* __restrict__ ainv_ib) {
+__global__ void __launch_bounds__(kGjLanes) k_box_factor_big(ibmg::BoxFactorLevels F) {
   __shared__ GjScratch S;
+  const int lv = factor_level(F, blockIdx.x), blk = blockIdx.x - F.first[lv];
+  const LevelView<double>& L = F.v[lv];
   const int nd = L.ndof;
-  const bool plain = blockIdx.x == 0;
+  const bool plain = blk == 0;
   int bx = 0, by = 0;
   if (!plain) {
-    const int box = ib_boxes[blockIdx.x - 1];
+    const int box = F.ib_boxes[lv][blk - 1];
     bx = box % L.nb;
     by = box / L.nb;
   }
-  double* slot = plain ? ainv_plain : ainv_ib + (size_t)(blockIdx.x - 1) * nd * nd;
+  double* slot = plain ? F.ainv_plain[lv] : F.ainv_ib[lv] + (size_t)(blk - 1) * nd * nd;
   for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) slot[idx] = 0.0;
   __syncthreads();
   assemble_box(L, bx, by, !plain, slot, nd);
   __syncthreads();
-  float* f32 = plain ? ainv_plain_f : nullptr;
+  float* f32 = plain ? F.ainv_plain_f[lv] : nullptr;
   gauss_jordan_regs(
       nd, S, [&](int i, int j) { return slot[(size_t)i * nd + j]; },
       [&](int r, int c, double v) {
@@ -669,10 +678,11 @@ void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int
   k_ib_index<<<1, 1024, 0, s>>>(nb, ncol, flag, ib_index, ib_boxes, info);
 }
 
-void launch_box_factor(hipStream_t s, const LevelView<double>& L, const int* ib_boxes, int n_ib,
-                       double* ainv_plain, float* ainv_plain_f, double* ainv_ib) {
-  if (L.ndof <= IBMG_MAX_NDOF) k_box_factor<<<1 + n_ib, 128, 0, s>>>(L, ib_boxes, ainv_plain, ainv_plain_f, ainv_ib);
-  else k_box_factor_big<<<1 + n_ib, kGjLanes, 0, s>>>(L, ib_boxes, ainv_plain, ainv_plain_f, ainv_ib);
+void launch_box_factor(hipStream_t s, const BoxFactorLevels& F) {
+  const int nblocks = F.first[F.nl];
+  if (F.nl <= 0 || nblocks <= 0) return;
+  if (F.v[0].ndof <= IBMG_MAX_NDOF) k_box_factor<<<nblocks, 128, 0, s>>>(F);
+  else k_box_factor_big<<<nblocks, kGjLanes, 0, s>>>(F);
 }
 
 void launch_box_matrix(hipStream_t s, const LevelView<double>& L, int bx, int by, double* out) {

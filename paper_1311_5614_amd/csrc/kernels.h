@@ -39,8 +39,20 @@ void launch_windows_coarse(hipStream_t s, int Nc, const int* act_f, const double
                            const int* rows, const int* nact, int maxact, int reach, double* win, int* flags);
 void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int* flag, int* ib_index,
                         int* ib_boxes, int* info);
-void launch_box_factor(hipStream_t s, const LevelView<double>& L, const int* ib_boxes, int n_ib,
-                       double* ainv_plain, float* ainv_plain_f, double* ainv_ib);
+// Box inverses of every non-coarsest level in one launch: level l owns blocks
+// first[l] .. first[l + 1] - 1, the first of them its plain block and the
+// others its boxes with elastic rows (ib_boxes[l]).
+struct BoxFactorLevels {
+  LevelView<double> v[IBMG_MAX_LEVELS - 1];
+  const int* ib_boxes[IBMG_MAX_LEVELS - 1];
+  double* ainv_plain[IBMG_MAX_LEVELS - 1];
+  float* ainv_plain_f[IBMG_MAX_LEVELS - 1];
+  double* ainv_ib[IBMG_MAX_LEVELS - 1];
+  int first[IBMG_MAX_LEVELS];
+  int nl;
+};
+static_assert(sizeof(BoxFactorLevels) <= 4096, "kernel argument size");
+void launch_box_factor(hipStream_t s, const BoxFactorLevels& F);
 void launch_box_matrix(hipStream_t s, const LevelView<double>& L, int bx, int by, double* out);
 
 // mg.hip (T = double or float)
