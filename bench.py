@@ -436,6 +436,54 @@ def run_learned(args, dev):
     }
     print(json.dumps(out))
 
+PROBE_N = 4096   # bandwidth probe: plain V(2,2) with no structure on this grid
+
+
+def vcycle_probe(dev, N=PROBE_N, reps=10):
+    """Plain FP64 V(2,2) with 4x4 boxes and no structure on an N x N grid
+    (coarsest 16 x 16), large enough to be bandwidth-bound rather than
+    latency-bound.  Times `reps` V-cycles (one captured graph each) between
+    HIP events on the solver's stream, and the finest-level box launch.
+    Algorithmic bytes of a V(nu1, nu2): (9 (nu1 + nu2) + 13.5) words per
+    finest cell times 4/3 for the level hierarchy (one read of b and w and
+    one write of w per sweep and level, plus residual, restriction and
+    prolongation), 528 B per cell in FP64 at V(2,2)."""
+    import math
+    import torch
+    from paper_1311_5614_amd import ibmg
+    levels = int(math.log2(N // 16)) + 1
+    cfg = ibmg.Config(N=N, levels=levels, K=0.0, box=4, nu1=2, nu2=2, maxit=4, prec=ibmg.IBMG_FP64)
+    s = ibmg.Solver(cfg, None, dev)
+    try:
+        s.setup(1.0 / N, None)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(1311_4096)
+        r = torch.randn(3 * N * N, dtype=torch.float64, device=dev, generator=gen)
+        for _ in range(2):
+            s.vcycle(r)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        for _ in range(reps):
+            s.vcycle(r)
+        e1.record(s.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        alg = (9 * (cfg.nu1 + cfg.nu2) + 13.5) * 8 * 4 / 3 * N * N
+        us, by = s.box_bench(0, 0, BOX_REPS)
+        gbs = alg / (ms * 1e-3) / 1e9
+        kb = by / (us * 1e-6) / 1e9
+        out = {"workload": f"{N}x{N}, {levels} levels, plain FP64 V(2,2), 4x4 boxes, 2 colours, no structure",
+               "vcycle_ms": ms, "vcycle_bytes": alg, "vcycle_GBs": gbs, "vcycle_frac": gbs / HBM_PEAK_GBS,
+               "k_box_us": us, "k_box_bytes": by, "k_box_GBs": kb, "k_box_frac": kb / HBM_PEAK_GBS}
+        print(f"[bench] probe {N}x{N}: V-cycle {ms:.3f} ms -> {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f} %), "
+              f"k_box {us:.1f} us -> {kb:.0f} GB/s ({100 * kb / HBM_PEAK_GBS:.1f} %)", file=sys.stderr, flush=True)
+        return out
+    finally:
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,6 +499,9 @@ def main():
     ap.add_argument("--tail-max", type=int, default=0, help="override the V-cycle tail size")
     ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs of the warm-start network")
     ap.add_argument("--lr", type=float, default=1e-3, help="c5: Adam learning rate")
+    ap.add_argument("--no-probe", action="store_true", help="skip the 4096x4096 bandwidth probe")
+    ap.add_argument("--probe-only", action="store_true", help="run only the 4096x4096 bandwidth probe")
+    ap.add_argument("--probe-n", type=int, default=PROBE_N, help="grid of the bandwidth probe")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy a device buffer of this many MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -470,6 +521,9 @@ def main():
     import torch
     from paper_1311_5614_amd import ibmg
     dev = "cuda:0"
+    if args.probe_only:
+        print(json.dumps({"probe": vcycle_probe(dev, args.probe_n)}))
+        return
     if args.workload == "c5":
         return run_learned(args, dev)
     args.steps = args.steps or 20
@@ -600,6 +654,11 @@ def main():
             "launch": ph,
         },
     }
+    if not args.no_probe:
+        try:
+            out["probe"] = vcycle_probe(dev)
+        except Exception as e:   # the probe is an extra figure; the workload's line stands without it
+            out["probe"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu:
         k = 2 if len(cases) > 2 else 0
         out["cpu_baseline"] = cpu_baseline(cases[k], dts[k], "bounded sample of the same workload")

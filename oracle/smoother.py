@@ -45,6 +45,48 @@ def box_dofs(bx, by, N, n):
     return np.array(u + v + p, dtype=np.int64)
 
 
+def box_dof_table(N, n):
+    """box_dofs of every box as one (nb^2, ndof) array, row by * nb + bx."""
+    nb = N // n
+    NN = N * N
+    by, bx = np.divmod(np.arange(nb * nb), nb)
+    bx, by = bx[:, None], by[:, None]
+    lu_j, lu_i = np.divmod(np.arange(n * (n + 1)), n + 1)   # u faces: n rows of n + 1
+    lv_j, lv_i = np.divmod(np.arange(n * (n + 1)), n)       # v faces: n + 1 rows of n
+    lp_j, lp_i = np.divmod(np.arange(n * n), n)
+    u = ((by * n + lu_j) % N) * N + (bx * n + lu_i) % N
+    v = NN + ((by * n + lv_j) % N) * N + (bx * n + lv_i) % N
+    p = 2 * NN + ((by * n + lp_j) % N) * N + (bx * n + lp_i) % N
+    return np.concatenate([u, v, p], axis=1).astype(np.int64)
+
+
+def sweep_shared(A, N, n, w, b, mode="colour2"):
+    """One coloured sweep (Jacobi within a colour, colour order as
+    BoxSmoother.sweep_colour2 / sweep_colour) on a level without elastic
+    rows.  The periodic Stokes operator is invariant under translation, so
+    every box block is the same matrix: the block of box (0, 0) is factored
+    once and all boxes of a colour are solved together from the residual at
+    the start of that colour.  Boxes of one colour share no unknowns, so the
+    scatter of their updates has no repeated index."""
+    A = A.tocsr()
+    D = box_dof_table(N, n)
+    lu = sla.lu_factor(A[D[0]][:, D[0]].toarray())
+    nb = N // n
+    by, bx = np.divmod(np.arange(nb * nb), nb)
+    if mode == "colour2":
+        classes = [(bx + by) % 2 == par for par in (0, 1)]
+    elif mode == "colour":
+        classes = [(bx % 2 == cx) & (by % 2 == cy) for cx, cy in COLOURS]
+    else:
+        raise ValueError(mode)
+    w = w.copy()
+    for sel in classes:
+        r = b - A @ w
+        Dc = D[sel]
+        w[Dc] += sla.lu_solve(lu, r[Dc].T).T
+    return w
+
+
 class BoxSmoother:
     """Box relaxation on one level: extracts and factors every box block."""
 

@@ -124,62 +124,120 @@ __device__ inline void res_ib_body(const LevelView<T>& L, const T* __restrict__ 
   }
 }
 
-// One box of the colour per 64-lane wave, box edge NB fixed at compile time;
-// W boxes (waves) per workgroup.  Every global load a lane needs -- its
-// residual, elastic row and iterate entries, and its column entries of the
-// shared plain inverse -- is issued before the residual exchange, so the box
-// costs one memory latency before its product (the inverse of a box with
-// elastic rows follows after it).  The residual is exchanged through a
-// 64-entry LDS slot per wave: with one wave per workgroup a workgroup barrier
-// orders it, with several each wave orders its own slot.
+// Boxes of the colour q0 .. q0 + B nper - 1 (below cnt) on one 64-lane wave,
+// B at a time, box edge NB fixed at compile time; W waves per workgroup.
+// Lane r owns local unknown r of each box.  The lane's column of the shared
+// plain inverse is loaded once and serves every box the wave takes: one
+// column per box would read 56 x 56 inverse entries from L2 per box, far more
+// than the box's own data.  For each group of B boxes every global load the
+// lane needs (residual, elastic term, iterate) is issued before the residual
+// exchange, so the group costs one memory latency before its products (the
+// inverse of a box with elastic rows follows after it).  The residuals are
+// exchanged through B 64-entry LDS slots per wave: with one wave per
+// workgroup a workgroup barrier orders them, with several each wave orders
+// its own.  Each box's arithmetic does not depend on B or nper.
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kBoxWavesMax = 4;   // boxes per workgroup on the large levels
+constexpr int kBoxWavesMax = 4;          // waves per workgroup on the large levels
+constexpr int kBoxWaveTarget = 16384;    // waves per launch beyond which a wave takes several groups of boxes
+constexpr int kBoxGroupMin = 16384;      // boxes per colour from which a wave takes 4x4 boxes four at a time
 
-template <typename T, int NB, int W = 1>
+template <typename T, int NB, int W = 1, int B = 1>
 __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
-                                  int blk) {
+                                  int q0, int nper = 1, int cnt = 0x7fffffff) {
   constexpr int ND = 2 * NB * (NB + 1) + NB * NB;
-  __shared__ double res_all[W][64];
-  double* res = res_all[W == 1 ? 0 : threadIdx.x >> 6];
-  int bx, by;
-  colour_box(blk, colour, L.ncol, L.nb, bx, by);
-  const int box = by * L.nb + bx;
+  __shared__ double res_all[W][B][64];
+  double (*res)[64] = res_all[W == 1 ? 0 : threadIdx.x >> 6];
   const int lane = threadIdx.x & 63, N = L.N, NN = N * N;
-  const int ibx = L.ib_index ? L.ib_index[box] : -1;
-  int comp = 0, i = 0, j = 0;
-  size_t g = 0;
-  T y = T(0), wv = T(0), yb = T(0);
+  // the lane's column of the shared plain inverse, kept in registers for
+  // every box the wave takes.  One box per wave: loaded after the box's own
+  // loads, so that the residual exchange does not wait for it; several:
+  // loaded first (fewer registers live across the loop)
   T a[ND];
-  if (lane < ND) {
-    box_dof(lane, bx, by, NB, N, comp, i, j);
-    g = (size_t)comp * NN + (size_t)j * N + i;
-    y = r[g];
-    wv = w[g];
-    if (L.yib && comp < 2) yb = L.yib[g];   // zero off the active rows
+  if constexpr (B > 1) {
+    if (lane < ND) {
 #pragma unroll
-    for (int c = 0; c < ND; ++c) a[c] = L.ainv_plain[c * ND + lane];
+      for (int c = 0; c < ND; ++c) a[c] = L.ainv_plain[c * ND + lane];
+    }
   }
-  if (ibx >= 0 && comp < 2) y -= yb;
-  if (lane < ND) res[lane] = (double)y;
-  if constexpr (W == 1) __syncthreads();
-  else wave_sync();
-  if (lane >= ND) return;
-  if (ibx >= 0) {
-    const double* A = L.ainv_ib + (size_t)ibx * ND * ND;
-    double z = 0.0;
+  // one box per wave always comes with one group per wave: a compile-time
+  // single pass leaves the column dead on the path of boxes with elastic
+  // rows, whose inverse loads then all issue together
+  const int np = B == 1 ? 1 : nper;
+  for (int k = 0; k < np; ++k) {
+    const int qb = q0 + k * B;
+    if (qb >= cnt) break;   // uniform over the wave
+    int ibx[B];
+    size_t g[B];
+    T y[B], wv[B], yb[B];
+    int comp = 0;
 #pragma unroll
-    for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[c];
-    w[g] = wv + (T)z;
-  } else {
-    T z = T(0);
+    for (int b = 0; b < B; ++b) {
+      ibx[b] = -2;   // past the colour's last box
+      g[b] = 0;
+      y[b] = T(0);
+      wv[b] = T(0);
+      yb[b] = T(0);
+      if (qb + b >= cnt) continue;
+      int bx, by;
+      colour_box(qb + b, colour, L.ncol, L.nb, bx, by);
+      ibx[b] = L.ib_index ? L.ib_index[by * L.nb + bx] : -1;
+      if (lane < ND) {
+        int i, j;
+        box_dof(lane, bx, by, NB, N, comp, i, j);
+        g[b] = (size_t)comp * NN + (size_t)j * N + i;
+        y[b] = r[g[b]];
+        wv[b] = w[g[b]];
+        // zero off the active rows.  One box per wave: loaded whatever the
+        // box's class, so that no load waits for another (the launch is
+        // latency-bound); several: only for boxes with elastic rows (fewer
+        // registers; the launch is bandwidth-bound)
+        if constexpr (B == 1) {
+          if (L.yib && comp < 2) yb[b] = L.yib[g[b]];
+        } else {
+          if (ibx[b] >= 0 && L.yib && comp < 2) yb[b] = L.yib[g[b]];
+        }
+      }
+    }
+    if (B == 1 && k == 0 && lane < ND) {
 #pragma unroll
-    for (int c = 0; c < ND; ++c) z += a[c] * (T)res[c];
-    w[g] = wv + z;
+      for (int c = 0; c < ND; ++c) a[c] = L.ainv_plain[c * ND + lane];
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      if (ibx[b] >= 0 && comp < 2) y[b] -= yb[b];
+    if (k > 0) {   // the previous boxes' products have read the slots
+      if constexpr (W == 1) __syncthreads();
+      else wave_sync();
+    }
+    if (lane < ND) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) res[b][lane] = (double)y[b];
+    }
+    if constexpr (W == 1) __syncthreads();
+    else wave_sync();
+    if (lane < ND) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (ibx[b] == -2) continue;
+        if (ibx[b] >= 0) {
+          const double* A = L.ainv_ib + (size_t)ibx[b] * ND * ND;
+          double z = 0.0;
+#pragma unroll
+          for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[b][c];
+          w[g[b]] = wv[b] + (T)z;
+        } else {
+          T z = T(0);
+#pragma unroll
+          for (int c = 0; c < ND; ++c) z += a[c] * (T)res[b][c];
+          w[g[b]] = wv[b] + z;
+        }
+      }
+    }
   }
 }
 

@@ -36,13 +36,14 @@ k_res_ib(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* __
   res_ib_body<T>(L, b, w, r, nres_blocks, blk < nres_blocks ? xcd_remap(blk, nres_blocks) : blk,
                  (int)gridDim.x - nres_blocks);
 }
-// W boxes per workgroup: several on the large levels (fewer workgroups to
+// W waves per workgroup: several on the large levels (fewer workgroups to
 // dispatch), one where the colour has too few boxes to fill the chip that way.
-template <typename T, int NB, int W>
+// Each wave takes B nper consecutive boxes of the colour, B at a time.
+template <typename T, int NB, int W, int B = 1>
 __global__ void __launch_bounds__(64 * W)
-k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour, int cnt) {
-  const int q = xcd_remap(blockIdx.x, gridDim.x) * W + (int)(threadIdx.x >> 6);
-  if (W == 1 || q < cnt) box_body_n<T, NB, W>(L, r, w, colour, q);
+k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour, int cnt, int nper) {
+  const int q = (xcd_remap(blockIdx.x, gridDim.x) * W + (int)(threadIdx.x >> 6)) * nper * B;
+  if (q < cnt) box_body_n<T, NB, W, B>(L, r, w, colour, q, nper, cnt);
 }
 template <typename T>
 __global__ void __launch_bounds__(kBigBoxLanes)
@@ -135,14 +136,25 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
   if (L.n == 8) {
     k_box_big<T><<<cnt * kBigBoxRowBlocks, kBigBoxLanes, 0, s>>>(V, r, w, colour);
   } else if (cnt >= kBoxWavesMax * 512) {
-    const int grid = (cnt + kBoxWavesMax - 1) / kBoxWavesMax;
-    if (L.n == 4) k_box<T, 4, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);
-    else if (L.n == 2) k_box<T, 2, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);
-    else k_box<T, 1, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt);
+    // B boxes at a time per wave once the colour has enough boxes for cnt / B
+    // waves to fill the chip (4x4 boxes at 256^2, 2048 per colour: 4.9 us
+    // with B = 1, 11 us with B = 2; at 1024^2, 32768 per colour: 33 us with
+    // B = 1, 24 us with B = 4); groups per wave: one up to kBoxWaveTarget
+    // groups, then as many as keep about kBoxWaveTarget waves in the launch
+    const int B = (L.n == 4 && cnt >= kBoxGroupMin) ? 4 : 1;
+    const int groups = (cnt + B - 1) / B;
+    const int nper = (B > 1 && groups > kBoxWaveTarget) ? groups / kBoxWaveTarget : 1;
+    const int waves = (groups + nper - 1) / nper;
+    const int grid = (waves + kBoxWavesMax - 1) / kBoxWavesMax;
+    if (L.n == 4) {
+      if (B == 4) k_box<T, 4, kBoxWavesMax, 4><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt, nper);
+      else k_box<T, 4, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt, nper);
+    } else if (L.n == 2) k_box<T, 2, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt, nper);
+    else k_box<T, 1, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt, nper);
   } else {
-    if (L.n == 4) k_box<T, 4, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt);
-    else if (L.n == 2) k_box<T, 2, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt);
-    else k_box<T, 1, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt);
+    if (L.n == 4) k_box<T, 4, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt, 1);
+    else if (L.n == 2) k_box<T, 2, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt, 1);
+    else k_box<T, 1, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt, 1);
   }
 }
 template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero, const T* yf) {

@@ -134,6 +134,29 @@ def test_smooth_parity(box, colours):
         assert rel(xg, xo) < 1e-11, (box, colours, l)
 
 
+@pytest.mark.parametrize("N,levels,colours", [(1024, 7, 4), (2048, 8, 2)])
+def test_smooth_parity_large_levels(N, levels, colours):
+    """Levels with at least 16384 boxes per colour take the box kernel's
+    wide form (each wave keeps its inverse column and solves 4x4 boxes four at
+    a time; at 2048^2 each wave also takes two such groups).  One sweep
+    without elastic rows against the oracle's shared-block sweep."""
+    from paper_1311_5614_amd import ibmg
+    dt = 0.05
+    cfg = ibmg.Config(N=N, levels=levels, K=0.0, box=4, nu1=1, nu2=1, colours=colours, prec=ibmg.IBMG_FP64)
+    s = ibmg.Solver(cfg, None, DEV)
+    try:
+        s.setup(dt, None)
+        A = system.hierarchy(N, 1, 1.0, 1.0, dt)[0].A
+        rng = np.random.default_rng(11)
+        b = rng.standard_normal(3 * N * N)
+        x = rng.standard_normal(3 * N * N)
+        xo = smoother.sweep_shared(A, N, 4, x, b, "colour2" if colours == 2 else "colour")
+        xg = tnp(s.smooth(0, tdev(b), tdev(x.copy()), 1))
+        assert rel(xg, xo) < 1e-11, (N, colours)
+    finally:
+        s.close()
+
+
 # ---------------------------------------------------------------- a7, a12: coarse solve, V-cycle
 
 @pytest.mark.parametrize("N,levels", [(64, 3), (32, 3), (32, 4)])

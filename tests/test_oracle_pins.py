@@ -349,6 +349,26 @@ def test_colour_phase_exact_without_elasticity(n):
             assert np.max(np.abs(r2[sm.dofs[(bx, by)]])) < 1e-10 * np.max(np.abs(b))
 
 
+@pytest.mark.parametrize("n,mode", [(1, "colour2"), (2, "colour"), (4, "colour2"), (4, "colour")])
+def test_shared_block_sweep_equals_per_box_sweep(n, mode):
+    """Without elastic rows the one-factorisation sweep reproduces the
+    per-box sweep (each box's own block and LU) on random data, and the box
+    table lists each box's unknowns in box_dofs order."""
+    N = 16
+    lv = system.hierarchy(N, 2, 1.0, 1.0, 0.05)
+    A = lv[0].A
+    sm = smoother.BoxSmoother(A, N, n)
+    D = smoother.box_dof_table(N, n)
+    for by in range(N // n):
+        for bx in range(N // n):
+            assert np.array_equal(D[by * (N // n) + bx], sm.dofs[(bx, by)])
+    b = rng.standard_normal(3 * N * N)
+    x = rng.standard_normal(3 * N * N)
+    ref = sm.sweep(x, b, mode)
+    got = smoother.sweep_shared(A, N, n, x, b, mode)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
 def test_box_matrix_is_restriction_of_operator():
     """A_box entries equal the level operator's entries (spot check against
     the stencil: diagonal c + 4 mu / h^2 plus the elastic diagonal)."""
