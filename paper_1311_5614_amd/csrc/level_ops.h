@@ -144,7 +144,7 @@ __device__ inline void wave_sync() {
 
 constexpr int kBoxWavesMax = 4;          // waves per workgroup on the large levels
 constexpr int kBoxWaveTarget = 16384;    // waves per launch beyond which a wave takes several groups of boxes
-constexpr int kBoxGroupMin = 16384;      // boxes per colour from which a wave takes 4x4 boxes four at a time
+constexpr int kBoxGroupMin = 16384;      // boxes per colour from which a wave takes 4x4 boxes four at a time (levels without elastic rows)
 
 template <typename T, int NB, int W = 1, int B = 1>
 __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,

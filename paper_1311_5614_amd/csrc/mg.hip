@@ -136,12 +136,16 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
   if (L.n == 8) {
     k_box_big<T><<<cnt * kBigBoxRowBlocks, kBigBoxLanes, 0, s>>>(V, r, w, colour);
   } else if (cnt >= kBoxWavesMax * 512) {
-    // B boxes at a time per wave once the colour has enough boxes for cnt / B
-    // waves to fill the chip (4x4 boxes at 256^2, 2048 per colour: 4.9 us
-    // with B = 1, 11 us with B = 2; at 1024^2, 32768 per colour: 33 us with
-    // B = 1, 24 us with B = 4); groups per wave: one up to kBoxWaveTarget
-    // groups, then as many as keep about kBoxWaveTarget waves in the launch
-    const int B = (L.n == 4 && cnt >= kBoxGroupMin) ? 4 : 1;
+    // B boxes at a time per wave on levels without elastic rows once the
+    // colour has enough boxes for cnt / B waves to fill the chip (4x4 boxes at
+    // 256^2, 2048 per colour: 4.9 us with B = 1, 11 us with B = 2; at 1024^2,
+    // 32768 per colour: 33 us with B = 1, 24 us with B = 4).  Boxes with
+    // elastic rows cluster along the structure, and a wave taking several of
+    // them issues their inverse loads one box after another (the 1024^2
+    // eight-ring workload ran 9 % slower with B = 4), so such levels keep one
+    // box per wave.  Groups per wave: one up to kBoxWaveTarget groups, then as
+    // many as keep about kBoxWaveTarget waves in the launch.
+    const int B = (L.n == 4 && !ib && cnt >= kBoxGroupMin) ? 4 : 1;
     const int groups = (cnt + B - 1) / B;
     const int nper = (B > 1 && groups > kBoxWaveTarget) ? groups / kBoxWaveTarget : 1;
     const int waves = (groups + nper - 1) / nper;

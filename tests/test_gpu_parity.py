@@ -136,10 +136,10 @@ def test_smooth_parity(box, colours):
 
 @pytest.mark.parametrize("N,levels,colours", [(1024, 7, 4), (2048, 8, 2)])
 def test_smooth_parity_large_levels(N, levels, colours):
-    """Levels with at least 16384 boxes per colour take the box kernel's
-    wide form (each wave keeps its inverse column and solves 4x4 boxes four at
-    a time; at 2048^2 each wave also takes two such groups).  One sweep
-    without elastic rows against the oracle's shared-block sweep."""
+    """Levels without elastic rows and with at least 16384 boxes per colour
+    take the box kernel's wide form (each wave keeps its inverse column and
+    solves 4x4 boxes four at a time; at 2048^2 each wave also takes two such
+    groups).  One sweep against the oracle's shared-block sweep."""
     from paper_1311_5614_amd import ibmg
     dt = 0.05
     cfg = ibmg.Config(N=N, levels=levels, K=0.0, box=4, nu1=1, nu2=1, colours=colours, prec=ibmg.IBMG_FP64)
