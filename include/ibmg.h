@@ -31,7 +31,8 @@
  *     kernels wrap them internally.
  *   - The library never allocates device memory: the caller queries
  *     ibmg_workspace_bytes() and binds one device buffer it owns with
- *     ibmg_bind_workspace().  The handle keeps only host-side bookkeeping.
+ *     ibmg_bind_workspace().  The handle keeps host-side bookkeeping and a
+ *     few bytes of pinned host memory.
  *   - All work is enqueued on the stream given at creation (a hipStream_t
  *     passed as void*; NULL = default stream).  Calls that return stats, or
  *     that read device scalars for control flow (solve, step, setup),
@@ -126,7 +127,10 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* prob, const ibmg_opts* op
                 void* hip_stream);
 /* Bytes of device workspace the handle needs (256-byte aligned pointer). */
 int ibmg_workspace_bytes(const ibmg_handle* h, size_t* bytes);
-/* Bind caller-owned device memory (>= ibmg_workspace_bytes).  Errors: ENOMEM. */
+/* Bind caller-owned device memory (>= ibmg_workspace_bytes).  The first bind
+ * also allocates 64 bytes of pinned host memory (freed by ibmg_destroy) that
+ * the solver's per-iteration convergence flags are written into.
+ * Errors: ENOMEM, EHIP. */
 int ibmg_bind_workspace(ibmg_handle* h, void* dev_ptr, size_t bytes);
 int ibmg_destroy(ibmg_handle* h);
 const char* ibmg_status_string(int status);

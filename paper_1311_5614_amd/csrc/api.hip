@@ -501,8 +501,9 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
       launch_multidot(s, vn, 0, 1, vn, n0, partial, kDotBlocks);
       launch_reduce2(s, partial, kDotBlocks, colj + j + 1, scal + 1);
       launch_scale_givens(s, vn, n0, scal + 1, H, ldh, g, h->p<double>(h->cs), h->p<double>(h->sn), j,
-                          h->p<double>(h->flags), target);
-      if ((rc = read_doubles(h, h->p<double>(h->flags), hs, 3))) return rc;
+                          h->flags_d, target);
+      IBMG_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < 3; ++q) hs[q] = reinterpret_cast<volatile double*>(h->flags_h)[q];
       k = j + 1;
       est = hs[0] / bnorm;
       if (hs[2] != 0.0) return IBMG_ENONFINITE;
@@ -554,6 +555,12 @@ int bind(ibmg_handle* h, void* dev, size_t bytes, bool own_capture_stream) {
   h->setup_ok = false;
   h->graph_dt = -1.0;
   if (own_capture_stream && !h->cap) IBMG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  if (!h->flags_h) {
+    // the per-iteration flags of FGMRES go straight to host memory: no copy
+    // is enqueued between the Givens step and the host's decision
+    IBMG_HIP(hipHostMalloc((void**)&h->flags_h, 8 * sizeof(double), hipHostMallocDefault));
+    IBMG_HIP(hipHostGetDevicePointer((void**)&h->flags_d, h->flags_h, 0));
+  }
   // dynamic LDS of the V-cycle tail (levels of at most kSmallLevel cells per side)
   if (prepare_tail(tail_lds(h, sizeof(double))) != 0) return IBMG_EHIP;
   if (h->M > 0) {
@@ -705,6 +712,7 @@ int ibmg_destroy(ibmg_handle* h) {
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->flags_h) (void)hipHostFree(h->flags_h);
   delete h;
   return IBMG_OK;
 }

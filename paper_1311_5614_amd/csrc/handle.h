@@ -62,6 +62,8 @@ struct ibmg_handle {
   bool fb64 = false;   // this solve continues with the FP64 V-cycle (FP32 stalled)
   // the V-cycle as a captured graph (fixed buffers b0g -> w0g), rebuilt when dt changes
   hipStream_t cap = nullptr;
+  double* flags_h = nullptr;   // pinned host memory the Givens kernel writes its flags into
+  double* flags_d = nullptr;   // the same memory as the device addresses it
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   double graph_dt = -1.0;
