@@ -297,6 +297,8 @@ __global__ void __launch_bounds__(256) kb_update_acc(BSet S, const BKry* __restr
   if (acc && blk == 0 && (int)threadIdx.x < nvec) acc[threadIdx.x] += coef[threadIdx.x];
   if (e >= n) return;
   double sum = 0.0;
+  // unrolled so that eight basis loads are in flight; the sum keeps its order
+#pragma unroll 8
   for (int v = 0; v < nvec; ++v) sum += coef[v] * q.V[(size_t)v * n + e];
   q.V[(j + 1) * n + e] -= sum;
 }
@@ -367,6 +369,8 @@ __global__ void __launch_bounds__(256) kb_update_x(BSet S, const BKry* __restric
   const size_t e = (size_t)(blockIdx.x - S.off[s]) * 256 + threadIdx.x;
   if (e >= n) return;
   double sum = 0.0;
+  // unrolled so that eight basis loads are in flight; the sum keeps its order
+#pragma unroll 8
   for (int v = 0; v < k; ++v) sum += q.y[v] * q.Z[(size_t)v * n + e];
   q.x[e] += 1.0 * sum;
 }

@@ -58,6 +58,8 @@ k_update(const double* __restrict__ V, size_t ldv, int nvec, const double* __res
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
   double s = 0.0;
+  // unrolled so that eight basis loads are in flight; the sum keeps its order
+#pragma unroll 8
   for (int v = 0; v < nvec; ++v) s += coef[v] * V[(size_t)v * ldv + e];
   w[e] += sign * s;
 }
@@ -157,6 +159,8 @@ k_update_acc(const double* __restrict__ V, size_t ldv, int nvec, const double* _
   if (acc && blockIdx.x == 0 && (int)threadIdx.x < nvec) acc[threadIdx.x] += coef[threadIdx.x];
   if (e >= n) return;
   double s = 0.0;
+  // unrolled so that eight basis loads are in flight; the sum keeps its order
+#pragma unroll 8
   for (int v = 0; v < nvec; ++v) s += coef[v] * V[(size_t)v * ldv + e];
   w[e] -= s;
 }
