@@ -220,13 +220,18 @@ __global__ void __launch_bounds__(256) kb_multidot(BSet S, const BKry* __restric
   else if (kind == 2) { V = q.V + (j + 1) * n; w = V; }
   else { V = q.b; w = q.b; }
   double acc[BMD_GROUP];
+  // rows past the group's last vector repeat it (unconditional loads, as in
+  // k_multidot; their sums are never stored)
+  const double* Vc[BMD_GROUP];
 #pragma unroll
-  for (int c = 0; c < BMD_GROUP; ++c) acc[c] = 0.0;
+  for (int c = 0; c < BMD_GROUP; ++c) {
+    acc[c] = 0.0;
+    Vc[c] = V + (size_t)(g0 + min(c, ng - 1)) * ldv;
+  }
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)256 * 256) {
     const double we = w[e];
 #pragma unroll
-    for (int c = 0; c < BMD_GROUP; ++c)
-      if (c < ng) acc[c] += V[(size_t)(g0 + c) * ldv + e] * we;
+    for (int c = 0; c < BMD_GROUP; ++c) acc[c] += Vc[c][e] * we;
   }
 #pragma unroll
   for (int c = 0; c < BMD_GROUP; ++c) sh[c][threadIdx.x] = acc[c];

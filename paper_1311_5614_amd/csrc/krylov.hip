@@ -15,13 +15,19 @@ k_multidot(const double* __restrict__ V, size_t ldv, int nvec, const double* __r
   const int g0 = blockIdx.y * MD_GROUP;
   const int ng = min(MD_GROUP, nvec - g0);
   double acc[MD_GROUP];
+  // rows past the group's last vector repeat that vector: every load is
+  // unconditional, so all of them are in flight together (their sums are
+  // never stored)
+  const double* Vq[MD_GROUP];
 #pragma unroll
-  for (int q = 0; q < MD_GROUP; ++q) acc[q] = 0.0;
+  for (int q = 0; q < MD_GROUP; ++q) {
+    acc[q] = 0.0;
+    Vq[q] = V + (size_t)(g0 + min(q, ng - 1)) * ldv;
+  }
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
     const double we = w[e];
 #pragma unroll
-    for (int q = 0; q < MD_GROUP; ++q)
-      if (q < ng) acc[q] += V[(size_t)(g0 + q) * ldv + e] * we;
+    for (int q = 0; q < MD_GROUP; ++q) acc[q] += Vq[q][e] * we;
   }
 #pragma unroll
   for (int q = 0; q < MD_GROUP; ++q) sh[q][threadIdx.x] = acc[q];
@@ -165,36 +171,51 @@ k_update_acc(const double* __restrict__ V, size_t ldv, int nvec, const double* _
   w[e] -= s;
 }
 
-// v_{j+1} = w / sqrt(nrm2); workgroup 0, thread 0 also performs the Givens
-// step of column j (k_givens) -- the column's H(j+1, j) holds the same
-// squared norm as nrm2, which every workgroup reads from nrm2.
+// v_{j+1} = w / sqrt(nrm2); workgroup 0 also performs the Givens step of
+// column j (k_givens) -- the column's H(j+1, j) holds the same squared norm as
+// nrm2, which every workgroup reads from nrm2.  The column and the previous
+// rotations are first staged in LDS by the whole workgroup, so the serial
+// chain of rotations (thread 0, same operations in the same order as
+// k_givens) reads LDS instead of waiting on a global load per rotation.
+constexpr int kGivensMax = 256;   // >= the largest Krylov dimension + 2
 __global__ void __launch_bounds__(256)
 k_scale_givens(double* __restrict__ w, size_t n, const double* __restrict__ nrm2, double* __restrict__ H, int ldh,
                double* __restrict__ g, double* __restrict__ cs, double* __restrict__ sn, int j,
                double* __restrict__ flags, double target) {
+  __shared__ double scol[kGivensMax], scs[kGivensMax], ssn[kGivensMax];
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   const double nrm = sqrt(nrm2[0]);
   if (e < n) w[e] = nrm > 0.0 ? w[e] / nrm : 0.0;
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (blockIdx.x != 0) return;
   double* col = H + (size_t)j * ldh;
-  col[j + 1] = nrm;
-  for (int i = 0; i < j; ++i) {
-    const double a = col[i], b = col[i + 1];
-    col[i] = cs[i] * a + sn[i] * b;
-    col[i + 1] = -sn[i] * a + cs[i] * b;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) scol[i] = col[i];
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    scs[i] = cs[i];
+    ssn[i] = sn[i];
   }
-  const double a = col[j], b = col[j + 1];
-  const double d = hypot(a, b);
-  cs[j] = a / d;
-  sn[j] = b / d;
-  col[j] = d;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  const double est = fabs(g[j + 1]);
-  flags[0] = est;
-  flags[1] = (est <= target || nrm == 0.0) ? 1.0 : 0.0;
-  flags[2] = (isfinite(est) && isfinite(d)) ? 0.0 : 1.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    scol[j + 1] = nrm;
+    for (int i = 0; i < j; ++i) {
+      const double a = scol[i], b = scol[i + 1];
+      scol[i] = scs[i] * a + ssn[i] * b;
+      scol[i + 1] = -ssn[i] * a + scs[i] * b;
+    }
+    const double a = scol[j], b = scol[j + 1];
+    const double d = hypot(a, b);
+    cs[j] = a / d;
+    sn[j] = b / d;
+    scol[j] = d;
+    scol[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    const double est = fabs(g[j + 1]);
+    flags[0] = est;
+    flags[1] = (est <= target || nrm == 0.0) ? 1.0 : 0.0;
+    flags[2] = (isfinite(est) && isfinite(d)) ? 0.0 : 1.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) col[i] = scol[i];
 }
 
 namespace ibmg {
