@@ -482,7 +482,10 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
     k_fill<double><<<nblk(m + 2), 256, 0, s>>>(g, m + 2, 0.0);
     IBMG_HIP(hipMemcpyAsync(g, &beta, sizeof(double), hipMemcpyHostToDevice, s));
     int k = 0;
-    for (int j = 0; j < m && total < m; ++j) {
+    // Iteration j: preconditioner, operator, classical Gram-Schmidt twice,
+    // H(j+1, j) and the Givens step; its flags land in pinned slot j & 1 and
+    // an event marks them.
+    auto enqueue = [&](int j) -> int {
       double* vj = V + (size_t)j * n0;
       double* vn = V + (size_t)(j + 1) * n0;
       double* zj = Z + (size_t)j * n0;
@@ -490,8 +493,6 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
       precond(h, vj, zj);
       if (h->launch_error) return IBMG_EHIP;
       apply0(h, zj, vn);
-      ++total;
-      // classical Gram-Schmidt, twice; then H(j+1, j) and the Givens step
       launch_multidot(s, V, n0, j + 1, vn, n0, partial, kDotBlocks);
       launch_reduce(s, partial, kDotBlocks, j + 1, colj, 0);
       launch_update_acc(s, V, n0, j + 1, colj, vn, n0, nullptr);
@@ -501,9 +502,29 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
       launch_multidot(s, vn, 0, 1, vn, n0, partial, kDotBlocks);
       launch_reduce2(s, partial, kDotBlocks, colj + j + 1, scal + 1);
       launch_scale_givens(s, vn, n0, scal + 1, H, ldh, g, h->p<double>(h->cs), h->p<double>(h->sn), j,
-                          h->flags_d, target);
-      IBMG_HIP(hipStreamSynchronize(s));
-      for (int q = 0; q < 3; ++q) hs[q] = reinterpret_cast<volatile double*>(h->flags_h)[q];
+                          h->flags_d + 4 * (j & 1), target);
+      IBMG_HIP(hipEventRecord(h->flag_ev[j & 1], s));
+      return IBMG_OK;
+    };
+    // Iteration j + 1 is enqueued before iteration j's flags are read, so the
+    // device does not wait for the host's decision.  If the cycle stops at j,
+    // iteration j + 1 has written only state that the update below does not
+    // read (basis vector j + 2, preconditioned vector j + 1, column j + 1 of
+    // H, g[j + 1] and g[j + 2], rotation j + 1); the iterates are the same as
+    // without the lookahead.  Off while phases are timed.
+    const bool lookahead = !h->timing;
+    int j = 0;
+    bool queued = false;   // iteration j is enqueued
+    if (j < m && total < m) {
+      if ((rc = enqueue(0))) return rc;
+      queued = true;
+    }
+    while (queued) {
+      const bool ahead = lookahead && j + 1 < m && total + 1 < m;
+      if (ahead && (rc = enqueue(j + 1))) return rc;
+      IBMG_HIP(hipEventSynchronize(h->flag_ev[j & 1]));
+      for (int q = 0; q < 3; ++q) hs[q] = reinterpret_cast<volatile double*>(h->flags_h)[4 * (j & 1) + q];
+      ++total;
       k = j + 1;
       est = hs[0] / bnorm;
       if (hs[2] != 0.0) return IBMG_ENONFINITE;
@@ -515,6 +536,11 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
         break;
       }
       if (hs[1] != 0.0) break;
+      ++j;
+      if (!ahead) {
+        queued = j < m && total < m;
+        if (queued && (rc = enqueue(j))) return rc;
+      }
     }
     launch_backsolve(s, H, ldh, g, k, h->p<double>(h->y));
     launch_update(s, Z, n0, k, h->p<double>(h->y), x, n0, 1.0);
@@ -556,10 +582,12 @@ int bind(ibmg_handle* h, void* dev, size_t bytes, bool own_capture_stream) {
   h->graph_dt = -1.0;
   if (own_capture_stream && !h->cap) IBMG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
   if (!h->flags_h) {
-    // the per-iteration flags of FGMRES go straight to host memory: no copy
-    // is enqueued between the Givens step and the host's decision
+    // the per-iteration flags of FGMRES go straight to host memory (two
+    // slots, for the iteration being read and the one enqueued after it): no
+    // copy is enqueued between the Givens step and the host's decision
     IBMG_HIP(hipHostMalloc((void**)&h->flags_h, 8 * sizeof(double), hipHostMallocDefault));
     IBMG_HIP(hipHostGetDevicePointer((void**)&h->flags_d, h->flags_h, 0));
+    for (auto& e : h->flag_ev) IBMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   // dynamic LDS of the V-cycle tail (levels of at most kSmallLevel cells per side)
   if (prepare_tail(tail_lds(h, sizeof(double))) != 0) return IBMG_EHIP;
@@ -713,6 +741,8 @@ int ibmg_destroy(ibmg_handle* h) {
   if (h->graph) (void)hipGraphDestroy(h->graph);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->flags_h) (void)hipHostFree(h->flags_h);
+  for (auto e : h->flag_ev)
+    if (e) (void)hipEventDestroy(e);
   delete h;
   return IBMG_OK;
 }

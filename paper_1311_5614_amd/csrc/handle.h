@@ -64,6 +64,7 @@ struct ibmg_handle {
   hipStream_t cap = nullptr;
   double* flags_h = nullptr;   // pinned host memory the Givens kernel writes its flags into
   double* flags_d = nullptr;   // the same memory as the device addresses it
+  hipEvent_t flag_ev[2] = {nullptr, nullptr};   // marks each slot's flags as written
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   double graph_dt = -1.0;
