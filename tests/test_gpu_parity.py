@@ -272,6 +272,28 @@ def test_solve_parity_equal_iterations(K, fac, box):
     assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < tol
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lookahead_leaves_iterates_unchanged(prec):
+    """FGMRES enqueues iteration j + 1 before it reads iteration j's flags and
+    discards it when the cycle stops at j; with phase timing on it does not
+    look ahead (and the V-cycle runs eagerly instead of from its graph).  Both
+    solves of the same system agree bit for bit, iteration counts included
+    (FP64 and FP32 V-cycles)."""
+    w, dt, s = make(N=64, levels=4, M=160, K=1e5, dt_factor=100.0, n_fibers=2, prec=prec, rtol=1e-10)
+    _setup(s, w, dt)
+    rng = np.random.default_rng(14)
+    b = s.rhs(tdev(rng.standard_normal((64, 64))), tdev(rng.standard_normal((64, 64))))
+    x1 = torch.zeros(3 * 4096, dtype=torch.float64, device=DEV)
+    st1 = s.solve(b, x1)
+    s.set_timing(True)
+    x2 = torch.zeros(3 * 4096, dtype=torch.float64, device=DEV)
+    st2 = s.solve(b, x2)
+    s.set_timing(False)
+    assert st1["converged"] == 1 and st2["converged"] == 1
+    assert st1["iters"] == st2["iters"] and st1["iters"] > 2
+    assert torch.equal(x1, x2)
+
+
 def test_multistep_trajectory_and_determinism():
     from paper_1311_5614_amd import ibmg
     N = 32
