@@ -183,7 +183,7 @@ void sweep(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r,
 
 // z = MGV(0, r) on level 0 (Algorithm 1), vectors in precision T.
 template <typename T>
-void vcycle(ibmg_handle* h, const T* b0, T* w0) {
+void vcycle(ibmg_handle* h, const T* b0, T* w0, bool w0_zero = false) {
   const int Lv = h->levels;
   hipStream_t s = h->stream;
   T* w[IBMG_MAX_LEVELS];
@@ -200,7 +200,7 @@ void vcycle(ibmg_handle* h, const T* b0, T* w0) {
   // one LDS-resident workgroup; a tail of the coarsest level alone is its
   // matrix-vector product, spread over the grid
   const int ls = tail_start(h);
-  if (ls > 0) {
+  if (ls > 0 && !w0_zero) {   // w0_zero: the caller's input pass has cleared w[0]
     const size_t n3 = 3 * (size_t)v[0].N * v[0].N;
     k_fill<T><<<nblk(n3), 256, 0, s>>>(w[0], n3, T(0));
   }
@@ -229,8 +229,9 @@ int capture_vcycle(ibmg_handle* h) {
   hipStream_t user = h->stream;
   h->stream = h->cap;
   IBMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-  if (h->prec == IBMG_FP32) vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f));
-  else vcycle<double>(h, h->p<double>(h->b0g), h->p<double>(h->w0g));
+  // the graph starts after precond's input pass, which also clears w0
+  if (h->prec == IBMG_FP32) vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f), true);
+  else vcycle<double>(h, h->p<double>(h->b0g), h->p<double>(h->w0g), true);
   const hipError_t e = hipStreamEndCapture(h->cap, &h->graph);
   h->stream = user;
   if (e != hipSuccess || h->launch_error) return IBMG_EHIP;
@@ -250,17 +251,16 @@ void precond(ibmg_handle* h, const double* r, double* z) {
   if (h->prec == IBMG_FP32 && h->fb64) {
     vcycle_fp64(h, r, z);
   } else if (h->prec == IBMG_FP32) {
-    k_convert<double, float><<<nblk(n0), 256, 0, h->stream>>>(r, h->p<float>(h->b0f), n0);
+    k_vcycle_in<float><<<nblk(n0), 256, 0, h->stream>>>(r, h->p<float>(h->b0f), h->p<float>(h->w0f), n0);
     if (graph) {
       if (hipGraphLaunch(h->gexec, h->stream) != hipSuccess) h->launch_error = true;
     } else {
-      vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f));
+      vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f), true);
     }
     k_convert<float, double><<<nblk(n0), 256, 0, h->stream>>>(h->p<float>(h->w0f), z, n0);
   } else if (graph) {
-    if (hipMemcpyAsync(h->p<double>(h->b0g), r, n0 * sizeof(double), hipMemcpyDeviceToDevice, h->stream) !=
-            hipSuccess ||
-        hipGraphLaunch(h->gexec, h->stream) != hipSuccess ||
+    k_vcycle_in<double><<<nblk(n0), 256, 0, h->stream>>>(r, h->p<double>(h->b0g), h->p<double>(h->w0g), n0);
+    if (hipGraphLaunch(h->gexec, h->stream) != hipSuccess ||
         hipMemcpyAsync(z, h->p<double>(h->w0g), n0 * sizeof(double), hipMemcpyDeviceToDevice, h->stream) !=
             hipSuccess)
       h->launch_error = true;

@@ -19,6 +19,18 @@ __global__ void __launch_bounds__(256) k_convert(const S* __restrict__ a, D* __r
   if (i < n) b[i] = (D)a[i];
 }
 
+// The V-cycle's level-0 input in its own precision (b = r) and its initial
+// iterate (w = 0), one pass.
+template <typename D>
+__global__ void __launch_bounds__(256) k_vcycle_in(const double* __restrict__ r, D* __restrict__ b, D* __restrict__ w,
+                                                   size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    b[i] = (D)r[i];
+    w[i] = D(0);
+  }
+}
+
 namespace ibmg {
 
 inline unsigned nblk(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
