@@ -87,7 +87,8 @@ typedef struct {
   int32_t box;         /* box edge n in cells: 1, 2 or 4; every smoothed level needs
                           N_l >= max(4, 2n) (colour classes of boxes stay disjoint)  */
   int32_t nu1, nu2;    /* pre- and post-smoothing sweeps (Algorithm 1)              */
-  int32_t maxit;       /* FGMRES iteration cap (no restart below it), 1..200        */
+  int32_t maxit;       /* FGMRES iteration cap over all cycles: 1..200 when restart
+                          is 0, 1..1000000 otherwise                                */
   double rtol;         /* stop when ||b - A w||_2 <= rtol ||b||_2                   */
   int32_t vcycle_prec; /* IBMG_FP64 or IBMG_FP32 (V-cycle fields and stencils)      */
   int32_t guess;       /* IBMG_GUESS_ZERO or IBMG_GUESS_PREV (step only)            */
@@ -102,6 +103,11 @@ typedef struct {
                           then as a grid-wide matrix-vector product).  Changes
                           the launch schedule and the summation order of the
                           elastic rows, not the method.                         */
+  int32_t restart;     /* FGMRES(m) restart length m, the Krylov basis size
+                          (Sec. 3.3 leaves it open): 0 = no restart below maxit
+                          (m = maxit), else 1..200.  A cycle that ends without
+                          meeting rtol updates the iterate and starts the next
+                          cycle from its true residual.                         */
 } ibmg_opts;
 
 typedef struct {

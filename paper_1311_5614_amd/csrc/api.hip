@@ -104,7 +104,7 @@ void layout(ibmg_handle* h) {
   take(cur, h->loc, scan_n * sizeof(int));
   take(cur, h->bsum, (scan_n / 1024 + 2) * sizeof(int));
   take(cur, h->meta, 8 * sizeof(int));
-  const size_t n0 = h->n0(), m = h->maxit;
+  const size_t n0 = h->n0(), m = h->mb;
   take(cur, h->V, (m + 1) * n0 * sizeof(double));
   take(cur, h->Z, m * n0 * sizeof(double));
   take(cur, h->H, (m + 1) * (m + 1) * sizeof(double));
@@ -251,6 +251,7 @@ void precond(ibmg_handle* h, const double* r, double* z) {
   if (h->prec == IBMG_FP32 && h->fb64) {
     vcycle_fp64(h, r, z);
   } else if (h->prec == IBMG_FP32) {
+    yib_for_fp32(h);
     k_vcycle_in<float><<<nblk(n0), 256, 0, h->stream>>>(r, h->p<float>(h->b0f), h->p<float>(h->w0f), n0);
     if (graph) {
       if (hipGraphLaunch(h->gexec, h->stream) != hipSuccess) h->launch_error = true;
@@ -296,6 +297,7 @@ int setup_launch(ibmg_handle* h, double dt, const double* X) {
   hipStream_t s = h->stream;
   h->dt = dt;
   h->setup_ok = false;
+  h->yib64 = false;   // the elastic-row buffers are cleared below
   const int M = h->M, Lv = h->levels;
   h->has_ib = M > 0 && h->K != 0.0;
   int* meta = h->p<int>(h->meta);
@@ -422,7 +424,7 @@ int do_setup(ibmg_handle* h, double dt, const double* X) {
 int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
   hipStream_t s = h->stream;
   const size_t n0 = h->n0();
-  const int m = h->maxit, ldh = m + 1;
+  const int m = h->mb, ldh = m + 1, cap = h->maxit;
   double* V = h->p<double>(h->V);
   double* Z = h->p<double>(h->Z);
   double* H = h->p<double>(h->H);
@@ -469,9 +471,9 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
     if (beta <= target) { st->converged = 1; break; }
     if (beta < best) {
       best = beta;
-      if (total < m) IBMG_HIP(hipMemcpyAsync(xbest, x, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (total < cap) IBMG_HIP(hipMemcpyAsync(xbest, x, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    if (total >= m) {
+    if (total >= cap) {
       if (beta > best) {           // give back the best iterate
         IBMG_HIP(hipMemcpyAsync(x, xbest, n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
         st->rel_resid_true = best / bnorm;
@@ -515,12 +517,12 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
     const bool lookahead = !h->timing;
     int j = 0;
     bool queued = false;   // iteration j is enqueued
-    if (j < m && total < m) {
+    if (j < m && total < cap) {
       if ((rc = enqueue(0))) return rc;
       queued = true;
     }
     while (queued) {
-      const bool ahead = lookahead && j + 1 < m && total + 1 < m;
+      const bool ahead = lookahead && j + 1 < m && total + 1 < cap;
       if (ahead && (rc = enqueue(j + 1))) return rc;
       IBMG_HIP(hipEventSynchronize(h->flag_ev[j & 1]));
       for (int q = 0; q < 3; ++q) hs[q] = reinterpret_cast<volatile double*>(h->flags_h)[4 * (j & 1) + q];
@@ -538,7 +540,7 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
       if (hs[1] != 0.0) break;
       ++j;
       if (!ahead) {
-        queued = j < m && total < m;
+        queued = j < m && total < cap;
         if (queued && (rc = enqueue(j))) return rc;
       }
     }
@@ -601,15 +603,33 @@ int bind(ibmg_handle* h, void* dev, size_t bytes, bool own_capture_stream) {
   return IBMG_OK;
 }
 
+// Zero the elastic-row buffers of every level (they must be zero off the
+// active rows, in whichever precision the next V-cycle reads them).
+void clear_yib(ibmg_handle* h) {
+  for (int l = 0; l < h->levels; ++l) {
+    const size_t ny = 2 * (size_t)h->L[l].N * h->L[l].N;
+    k_fill<double><<<nblk(ny), 256, 0, h->stream>>>(h->p<double>(h->L[l].yib), ny, 0.0);
+  }
+}
+
 void vcycle_fp64(ibmg_handle* h, const double* r, double* z) {
   // on an FP32 handle the elastic-row buffers hold FP32 values: read as FP64
-  // off the active rows they would not be zero, so clear them first
-  if (h->prec == IBMG_FP32 && h->has_ib)
-    for (int l = 0; l < h->levels; ++l) {
-      const size_t ny = 2 * (size_t)h->L[l].N * h->L[l].N;
-      k_fill<double><<<nblk(ny), 256, 0, h->stream>>>(h->p<double>(h->L[l].yib), ny, 0.0);
-    }
+  // off the active rows they would not be zero, so clear them first (and once
+  // more before the next FP32 V-cycle, which would read these FP64 values)
+  if (h->prec == IBMG_FP32 && h->has_ib) {
+    if (!h->yib64) clear_yib(h);
+    h->yib64 = true;
+  }
   vcycle<double>(h, r, z);
+}
+
+// Before an FP32 V-cycle or smoothing pass: undo what an FP64 fallback
+// V-cycle left in the elastic-row buffers.
+void yib_for_fp32(ibmg_handle* h) {
+  if (h->prec == IBMG_FP32 && h->has_ib && h->yib64) {
+    clear_yib(h);
+    h->yib64 = false;
+  }
 }
 
 // Right-hand side (a4) into bvec and the initial iterate into xvec.
@@ -687,7 +707,10 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
     const int Nl = N >> l;
     if (Nl < 4 || Nl < 2 * op->box) return IBMG_ESHAPE;
   }
-  if (op->nu1 < 0 || op->nu2 < 0 || op->maxit < 1 || op->maxit > 200 || !(op->rtol > 0)) return IBMG_EINVAL;
+  if (op->nu1 < 0 || op->nu2 < 0 || !(op->rtol > 0)) return IBMG_EINVAL;
+  if (op->restart < 0 || op->restart > kMaxBasis || op->maxit < 1 ||
+      op->maxit > (op->restart == 0 ? kMaxBasis : kMaxIters))
+    return IBMG_EINVAL;
   if (op->vcycle_prec != IBMG_FP64 && op->vcycle_prec != IBMG_FP32) return IBMG_EINVAL;
   if (op->guess != IBMG_GUESS_ZERO && op->guess != IBMG_GUESS_PREV) return IBMG_EINVAL;
   if (op->colours != 2 && op->colours != 4) return IBMG_EINVAL;
@@ -700,6 +723,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   h->N = N; h->M = pr->n_points; h->nfib = pr->n_fibers; h->kind = pr->delta;
   h->rho = pr->rho; h->mu = pr->mu; h->K = pr->K;
   h->levels = op->levels; h->n = op->box; h->nu1 = op->nu1; h->nu2 = op->nu2; h->maxit = op->maxit;
+  h->mb = op->restart == 0 ? op->maxit : std::min(op->restart, op->maxit);
   h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess; h->ncol = op->colours;
   h->tail_max = op->tail_max ? op->tail_max : kSmallLevel;
   h->stream = (hipStream_t)stream;
@@ -953,6 +977,7 @@ int single_op(ibmg_handle* h, int which, int level, const double* a, const doubl
   LevelView<T> v = view<T>(h, level);
   const size_t n3 = 3 * (size_t)v.N * v.N;
   const bool f32 = sizeof(T) == sizeof(float);
+  if (f32) yib_for_fp32(h);
   // staging: FP32 handles convert through the level's r and w buffers (level 0: w0f, b0f)
   auto stage = [&](const double* src, const Buf& bf) -> T* {
     T* d = h->p<T>(bf);

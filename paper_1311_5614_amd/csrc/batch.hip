@@ -672,7 +672,7 @@ void fill_tables(ibmg_batch* B) {
     q.partial = h->p<double>(h->partial);
     q.b0 = b0; q.w0 = w0;
     q.n0 = (long long)h->n0();
-    q.ldh = h->maxit + 1; q.m = h->maxit;
+    q.ldh = h->mb + 1; q.m = h->mb;
     q.nibx = ib_blocks(h->L[0].maxact);
     q.target = 0.0;   // set by the solve once ||b|| is known
   }
@@ -841,7 +841,7 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
     for (int p : S.p) {
       PState& q = ps[p];
       ibmg_handle* hp = B->h[p];
-      const int m = hp->maxit;
+      const int m = hp->maxit;   // iteration cap over all cycles
       const size_t xb = hp->n0() * sizeof(double);
       q.k_end = -1;
       const double beta = std::sqrt(B->gather_h[4 * p]);
@@ -869,7 +869,7 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
     }
     for (int p : I.p) {
       PState& q = ps[p];
-      const int m = B->h[p]->maxit;
+      const int m = B->h[p]->mb, cap = B->h[p]->maxit;
       q.begin = false;
       ++q.total;
       const double* f = B->gather_h + 4 * p + 1;
@@ -884,7 +884,7 @@ int batch_solve(ibmg_batch* B, std::vector<PState>& ps) {
         q.state = ST_START;
         continue;
       }
-      if (f[1] != 0.0 || q.j + 1 >= m || q.total >= m) {
+      if (f[1] != 0.0 || q.j + 1 >= m || q.total >= cap) {
         q.k_end = q.j + 1;
         q.state = ST_START;
       } else {

@@ -13,6 +13,8 @@ constexpr int kPW = 16;          // panel width of the coarse Gauss-Jordan (dens
 constexpr int kDotBlocks = 256;  // workgroups of the deterministic dot products
 constexpr int kMaxTimed = 8192;  // timed phase launches per solve
 constexpr int kFallbackWindow = 20;  // FP32 V-cycle stall test: < 10% progress over this many iterations
+constexpr int kMaxBasis = 200;      // largest Krylov basis (restart length)
+constexpr int kMaxIters = 1000000;  // largest iteration cap with restarts
 constexpr int kSmallLevel = 32;  // default (and largest) level size run in one workgroup per V-cycle leg
 
 struct Buf {
@@ -40,6 +42,7 @@ struct ibmg_handle {
   // problem and options
   int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 2, nu2 = 2, maxit = 100, prec = 0, guess = 0;
   int ncol = 2;
+  int mb = 100;   // Krylov basis size: the FGMRES(m) restart length (maxit caps the iterations of all cycles)
   int tail_max = ibmg::kSmallLevel;   // largest level size run by the LDS-resident tail
   double rho = 1, mu = 1, K = 0, rtol = 1e-8;
   std::vector<int> prev, next;
@@ -60,6 +63,7 @@ struct ibmg_handle {
   // state
   bool setup_ok = false, has_ib = false, launch_error = false;
   bool fb64 = false;   // this solve continues with the FP64 V-cycle (FP32 stalled)
+  bool yib64 = false;  // FP32 handle: the FP64 V-cycle left FP64 values in the elastic-row buffers
   // the V-cycle as a captured graph (fixed buffers b0g -> w0g), rebuilt when dt changes
   hipStream_t cap = nullptr;
   double* flags_h = nullptr;   // pinned host memory the Givens kernel writes its flags into
@@ -164,5 +168,8 @@ int step_begin(ibmg_handle* h, double dt, const double* u, const double* v, cons
 int step_end(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X);
 // z = MGV(0, r) with the FP64 V-cycle, launched eagerly on the handle's stream.
 void vcycle_fp64(ibmg_handle* h, const double* r, double* z);
+// Before an FP32 V-cycle or smoothing pass on an FP32 handle: clears the
+// elastic-row buffers if an FP64 fallback V-cycle has used them since setup.
+void yib_for_fp32(ibmg_handle* h);
 
 }  // namespace ibmg

@@ -48,7 +48,8 @@ class ibmg_problem(C.Structure):
 class ibmg_opts(C.Structure):
     _fields_ = [("levels", C.c_int32), ("box", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("maxit", C.c_int32), ("rtol", C.c_double), ("vcycle_prec", C.c_int32),
-                ("guess", C.c_int32), ("colours", C.c_int32), ("tail_max", C.c_int32)]
+                ("guess", C.c_int32), ("colours", C.c_int32), ("tail_max", C.c_int32),
+                ("restart", C.c_int32)]
 
 
 class ibmg_stats(C.Structure):
@@ -169,6 +170,7 @@ class Config:
     guess: int = IBMG_GUESS_ZERO
     colours: int = 2
     tail_max: int = 0
+    restart: int = 0
 
 
 def _problem(cfg: Config, fiber_offsets):
@@ -179,7 +181,7 @@ def _problem(cfg: Config, fiber_offsets):
     prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, M, max(0, len(offs) - 1),
                         C.cast(arr, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
     opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
-                     cfg.guess, cfg.colours, cfg.tail_max)
+                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart)
     return prob, opts, arr, M
 
 

@@ -6,7 +6,9 @@ short trajectory.
 Tolerances: the GPU accumulates in FP32 and the oracle in FP64 on the same
 BF16-rounded weights and activations, so a hidden activation can round to a
 neighbouring BF16 value (relative step 2^-8); outputs and gradients are
-compared in relative L2 norm at 2e-2, the loss at 1e-3."""
+compared in relative L2 norm (whole tensor, and per output channel), the
+loss relatively.  Each bound is the measured error times a margin of about
+3 (measured values printed by the tests)."""
 import numpy as np
 import pytest
 import torch
@@ -17,6 +19,12 @@ pytestmark = pytest.mark.gpu
 
 import ibgen  # noqa: E402
 from oracle import cnn as ocnn  # noqa: E402
+
+FWD_TOL = 2e-2       # network output, whole and per channel
+LOSS_TOL = 1e-3      # loss, relative
+GRAD_TOL = 2e-2      # weight and bias gradient of a layer
+GRAD_CH_TOL = 2e-2   # weight gradient of one output channel
+ADAM_TOL = 5e-2      # parameter change of two Adam steps
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -51,7 +59,10 @@ def test_forward_matches_oracle(N):
     x = np.random.default_rng(5).standard_normal((5, N, N))
     y = tnp(c.infer(tdev(x)))
     _, yo = ocnn.forward(th, x, emulate_bf16=True)
-    assert _rel(y, yo) < 2e-2
+    e = _rel(y, yo)
+    ec = [_rel(y[k], yo[k]) for k in range(3)]
+    print(f"N={N}: forward error {e:.2e}, per output channel {[f'{x:.2e}' for x in ec]}")
+    assert e < FWD_TOL and max(ec) < FWD_TOL
 
 
 def test_loss_and_gradient_match_oracle():
@@ -62,11 +73,19 @@ def test_loss_and_gradient_match_oracle():
     t = rng.standard_normal((3, N, N)) * 0.1
     loss, g = c.loss_grad(tdev(x), tdev(t))
     Lo, go = ocnn.loss_grad(th, x, t, emulate_bf16=True)
-    assert abs(loss - Lo) <= 1e-3 * Lo
+    print(f"loss error {abs(loss - Lo) / Lo:.2e}")
+    assert abs(loss - Lo) <= LOSS_TOL * Lo
     off = 0
-    for ci, co in ocnn.LAYERS:
+    for li, (ci, co) in enumerate(ocnn.LAYERS):
         n = co * ci * 9 + co
-        assert _rel(g[off:off + n], go[off:off + n]) < 2e-2, (ci, co)
+        gw, gwo = g[off:off + n - co].reshape(co, -1), go[off:off + n - co].reshape(co, -1)
+        ew = _rel(gw, gwo)
+        eb = _rel(g[off + n - co:off + n], go[off + n - co:off + n])
+        # every output channel's weight gradient on its own (an error in one
+        # channel must not hide in the layer's norm)
+        ech = max(_rel(gw[k], gwo[k]) for k in range(co) if np.linalg.norm(gwo[k]) > 0)
+        print(f"layer {li} ({ci}->{co}): weight gradient {ew:.2e} (worst channel {ech:.2e}), bias {eb:.2e}")
+        assert ew < GRAD_TOL and eb < GRAD_TOL and ech < GRAD_CH_TOL, (ci, co)
         off += n
 
 
@@ -88,7 +107,9 @@ def test_adam_training_step_matches_oracle():
         _, g = ocnn.loss_grad(ref, x, t, emulate_bf16=True)
         ref, m, v = ocnn.adam(ref, m, v, g, k + 1, lr)
     step_gpu, step_ref = got - th, ref - th
-    assert _rel(step_gpu, step_ref) < 5e-2
+    e = _rel(step_gpu, step_ref)
+    print(f"Adam step error {e:.2e}")
+    assert e < ADAM_TOL
 
 
 def test_training_lowers_the_loss_and_scales_are_rms():

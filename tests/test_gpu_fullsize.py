@@ -152,39 +152,78 @@ def test_c5_network_forward_full_size():
     assert np.array_equal(ys, np.roll(y, (37, -5), axis=(1, 2)))
 
 
-def test_c5_fp32_trajectory_through_a_stalled_step():
-    """The 512x512 warm-start trajectory with the FP32 V-cycle: at step 44 the
-    FP32-preconditioned solve stalls (the FP64 V-cycle alone needs about 190
-    iterations there).  The solve restarts from its current iterate with the
-    FP64 V-cycle and keeps its best iterate.  Step 18 converges slowly without
-    stalling (198 to 200 iterations, depending on the FP32 summation order of
-    the elastic windows).  Only those two steps may end at the 200-iteration
-    cap, with a relative residual below 1e-3, and once the initial relaxation
-    is over (points then move about 0.13 cells per step) no step moves a
-    point by a cell."""
+def test_c5_fp32_trajectory_every_step_at_rtol():
+    """The 512x512 warm-start trajectory with the FP32 V-cycle: every one of
+    the first 46 steps meets rtol 1e-8.  At step 44 the FP32-preconditioned
+    solve stalls (the FP64 V-cycle alone needs about 190 iterations there)
+    and restarts from its current iterate with the FP64 V-cycle; step 18
+    converges slowly (about 200 iterations).  FGMRES(200) with an iteration
+    cap of 1000 lets both finish.  Every step is judged by its true FP64
+    residual (the library's operator, which matches the oracle's to 1e-12);
+    steps 18, 44 and 45 are also judged in the oracle's own operator, and the
+    new positions against the oracle's interpolation of the GPU velocity.
+    Once the initial relaxation is over no step moves a point by a cell."""
     from paper_1311_5614_amd import ibmg
     w = ibgen.config_c5()
     dt = _dts("c5")[0]
     N = w.N
-    cfg = ibmg.Config(N=N, levels=7, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2, maxit=200, rtol=w.rtol,
-                      prec=ibmg.IBMG_FP32, guess=ibmg.IBMG_GUESS_PREV, tail_max=1)
+    cfg = ibmg.Config(N=N, levels=7, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2, maxit=1000, restart=200,
+                      rtol=w.rtol, prec=ibmg.IBMG_FP32, guess=ibmg.IBMG_GUESS_PREV, tail_max=1)
     s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
     z = torch.zeros(N, N, dtype=torch.float64, device=DEV)
     u, v, p, X = z.clone(), z.clone(), z.clone(), tdev(w.X)
     gu, gv = tdev(w.g_u), tdev(w.g_v)
-    fallbacks, capped = 0, []
+    fallbacks = 0
     for n in range(46):
         X_old = X.clone()
+        state = [tnp(a).copy() for a in (u, v, p)] if n in (18, 44, 45) else None
         st = s.step(dt, u, v, p, X, gu, gv)
-        print(n, st["iters"], st["converged"], st["fallback"], f"{st['rel_resid_true']:.2e}")
-        if st["converged"] != 1:
-            capped.append(n)
-            assert st["iters"] == 200 and st["rel_resid_true"] <= 1e-3, (n, st)
-        else:
-            assert st["rel_resid_true"] <= w.rtol, (n, st)
+        print(n, st["iters"], st["converged"], st["fallback"], f"{st['rel_resid_true']:.2e}", flush=True)
+        assert st["converged"] == 1 and st["rel_resid_true"] <= w.rtol, (n, st)
+        if state is not None:
+            Xn = tnp(X_old)
+            lv = system.hierarchy(N, 1, w.rho, w.mu, dt, Xn, w.fiber_offsets, w.K, 0)
+            b = system.rhs(state[0], state[1], Xn, w.fiber_offsets, w.K, dt, w.rho, g_u=w.g_u, g_v=w.g_v)
+            sol = np.concatenate([tnp(u).ravel(), tnp(v).ravel(), tnp(p).ravel()])
+            rr = np.linalg.norm(b - lv[0].A @ sol) / np.linalg.norm(b)
+            assert rr <= 1.02 * w.rtol, (n, rr)
+            U = ib.interp(Xn, tnp(u), tnp(v), 0)
+            assert np.max(np.abs(tnp(X) - (Xn + dt * U))) <= 1e-12 * max(1.0, np.max(np.abs(Xn))), n
         if n >= 10:
             assert float((X - X_old).abs().max()) * N < 1.0, n
         fallbacks += st["fallback"]
     assert fallbacks >= 1      # the stalled step is on this stretch of the trajectory
-    assert set(capped) <= {18, 44}, capped
+    s.close()
+
+
+def test_c3_step_meets_tolerance_in_oracle_norm():
+    """One step of the 1024x1024 eight-ring workload (16384 points, K = 1e6,
+    dt = 500 x the explicit limit, 7 levels) with the schedule the benchmark
+    times for it, FP32 V-cycle inside FP64 FGMRES: the GPU velocity and
+    pressure meet rtol 1e-8 in the oracle's operator, the positions move by
+    the oracle's interpolation of the GPU velocity, and the pressure has
+    zero mean."""
+    from paper_1311_5614_amd import ibmg
+    w = ibgen.config_c3()
+    dt = _dts("c3")[0]
+    sch = _schedule("c3", "1024")
+    cfg = ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, box=sch["box"], nu1=sch["nu1"], nu2=sch["nu2"],
+                      maxit=sch.get("maxit", 200), restart=sch.get("restart", 0), rtol=w.rtol,
+                      prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"])
+    s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    z = torch.zeros(w.N, w.N, dtype=torch.float64, device=DEV)
+    u, v, p, X = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    st = s.step(dt, u, v, p, X)
+    print(f"c3 step: {st['iters']} iterations, true residual {st['rel_resid_true']:.2e}")
+    assert st["converged"] == 1
+    lv = system.hierarchy(w.N, 1, 1.0, 1.0, dt, w.X, w.fiber_offsets, w.K, 0)
+    zz = np.zeros((w.N, w.N))
+    b = system.rhs(zz, zz, w.X, w.fiber_offsets, w.K, dt, 1.0)
+    sol = np.concatenate([tnp(u).ravel(), tnp(v).ravel(), tnp(p).ravel()])
+    rr = np.linalg.norm(b - lv[0].A @ sol) / np.linalg.norm(b)
+    print(f"c3 step: residual in the oracle's operator {rr:.3e}")
+    assert rr <= 1.02 * w.rtol, rr
+    U = ib.interp(w.X, tnp(u), tnp(v), 0)
+    assert np.max(np.abs(tnp(X) - (w.X + dt * U))) <= 1e-12 * max(1.0, np.max(np.abs(w.X)))
+    assert abs(tnp(p).mean()) < 1e-12 * max(1.0, np.max(np.abs(tnp(p))))
     s.close()

@@ -484,3 +484,69 @@ def test_concurrent_trajectories_match_sequential():
     for a, b in zip(seq, con):
         for x, y in zip(a[2], b[2]):
             assert torch.equal(x, y)
+
+
+def test_fp32_solve_after_fallback_matches_fresh_setup():
+    """A solve that fell back to the FP64 V-cycle leaves FP64 values in the
+    elastic-row buffers of an FP32 handle; the next FP32 V-cycle on the same
+    setup (another solve, a V-cycle, a smoothing pass) must not read them.
+    Each is compared bit for bit with the same call on a fresh setup."""
+    w, dt, s = make(N=64, levels=5, M=160, K=1e2, dt_factor=10.0, seed=16, box=1, prec=1, maxit=200, rtol=1e-9)
+    _, _, s2 = make(N=64, levels=5, M=160, K=1e2, dt_factor=10.0, seed=16, box=1, prec=1, maxit=200, rtol=1e-9)
+    z = torch.zeros(64, 64, dtype=torch.float64, device=DEV)
+    _setup(s, w, dt)
+    b = s.rhs(z, z)
+    x = torch.zeros_like(b)
+    st = s.solve(b, x)
+    assert st["fallback"] == 1 and st["converged"] == 1
+    r = torch.as_tensor(np.random.default_rng(40).standard_normal(3 * 4096), device=DEV)
+    zv = s.vcycle(r)
+    _setup(s2, w, dt)
+    zv2 = s2.vcycle(r)
+    assert torch.isfinite(zv).all() and torch.equal(zv, zv2)
+    xs = torch.zeros_like(b)
+    xs2 = torch.zeros_like(b)
+    sa = s.smooth(0, b, xs, 2)
+    sb = s2.smooth(0, b, xs2, 2)
+    assert torch.equal(sa, sb)
+    x_again = torch.zeros_like(b)
+    st_again = s.solve(b, x_again)
+    x_fresh = torch.zeros_like(b)
+    st_fresh = s2.solve(b, x_fresh)
+    assert st_again["iters"] == st_fresh["iters"] and torch.equal(x_again, x_fresh)
+
+
+@pytest.mark.parametrize("restart,prec", [(8, 0), (15, 1)])
+def test_restarted_fgmres_matches_oracle(restart, prec):
+    """FGMRES(m): cycles of m iterations, each from the true residual of the
+    iterate the previous one left (Sec. 3.3 leaves the restart open).  Against
+    the oracle's FGMRES with the same restart length: iteration counts within
+    one, the GPU solution meets rtol in the oracle's operator, and at equal
+    counts the iterates agree (FP64 V-cycle)."""
+    K, fac = 1e6, 200.0
+    w, dt, s = make(N=64, levels=4, M=160, K=K, dt_factor=fac, n_fibers=2, rtol=1e-10, prec=prec)
+    from paper_1311_5614_amd import ibmg
+    s.close()
+    cfg = ibmg.Config(N=64, levels=4, K=K, rtol=1e-10, prec=prec, maxit=400, restart=restart)
+    s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    _setup(s, w, dt)
+    lv, V = ostep.build(64, 4, 1.0, 1.0, dt, w.X, w.fiber_offsets, K)
+    rng = np.random.default_rng(41)
+    u = rng.standard_normal((64, 64))
+    v = rng.standard_normal((64, 64))
+    bo = system.rhs(u, v, w.X, w.fiber_offsets, K, dt, 1.0)
+    res = krylov.fgmres(lv[0].A, bo, V, rtol=1e-10, maxit=400, restart=restart)
+    b = s.rhs(tdev(u), tdev(v))
+    x = torch.zeros(3 * 4096, dtype=torch.float64, device=DEV)
+    st = s.solve(b, x)
+    xg = tnp(x)
+    print(f"restart {restart} prec {prec}: gpu iters {st['iters']} oracle iters {res.iters}")
+    assert st["converged"] == 1 and res.converged
+    assert st["iters"] > restart            # at least one restart happened
+    assert abs(st["iters"] - res.iters) <= (1 if prec == 0 else 3)
+    assert np.linalg.norm(bo - lv[0].A @ xg) / np.linalg.norm(bo) <= 1e-10
+    if prec == 0 and st["iters"] == res.iters:
+        xo = res.x.copy()
+        xo[2 * 4096:] -= xo[2 * 4096:].mean()
+        xg[2 * 4096:] -= xg[2 * 4096:].mean()
+        assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-9

@@ -137,6 +137,54 @@ def test_restrict_u_full_weighting_weights():
     assert np.array_equal(row, expect)
 
 
+def _swap_axes(N):
+    """Permutation T with (T f)[j][i] = f[i][j] on an N x N field: the
+    reflection x <-> y of the periodic square.  It maps the v faces
+    ((i + 1/2) h, j h) onto the u faces (j h, (i + 1/2) h) and back, so the
+    MAC discretisation is invariant under it with u and v exchanged."""
+    idx = np.arange(N * N).reshape(N, N).T.ravel()
+    return sp.csr_matrix((np.ones(N * N), (np.arange(N * N), idx)), shape=(N * N, N * N))
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_restrict_v_is_the_reflection_of_restrict_u(N):
+    """Sec. 3.1 gives R_v as R_u with the roles of x and y exchanged: under
+    the reflection x <-> y, restricting a v field equals restricting the
+    reflected field as u and reflecting back.  Together with the explicit
+    R_u weights above this fixes every weight of R_v; R_u's own rule applied
+    to v faces fails it."""
+    T, Tc = _swap_axes(N), _swap_axes(N // 2)
+    assert abs(mac.restrict_v(N) - Tc @ mac.restrict_u(N) @ T).max() == 0.0
+    assert abs(mac.prolong_v(N) - T @ mac.prolong_u(N) @ Tc).max() == 0.0
+    assert abs(mac.restrict_u(N) - Tc @ mac.restrict_u(N) @ T).max() > 0.1   # u's rule is not symmetric
+
+
+@pytest.mark.parametrize("comp", ["u", "v"])
+def test_restriction_exact_on_linear_fields(comp):
+    """Each face restriction is a weighted mean of fine faces whose centroid is
+    the coarse face centre, so a field linear in x and y, sampled at the fine
+    faces of its family, restricts to its values at the coarse faces (away
+    from the periodic seam).  A rule centred on the wrong face family (R_u's
+    stencil on v faces, or a shifted row pair) misses the coarse centre."""
+    N = 16
+    Nc, h, H = N // 2, 1.0 / N, 2.0 / N
+    f = lambda x, y: 0.3 + 1.7 * x - 2.1 * y
+    j, i = np.mgrid[0:N, 0:N]
+    J, I = np.mgrid[0:Nc, 0:Nc]
+    if comp == "u":
+        R = mac.restrict_u(N)
+        fine = f(i * h, (j + 0.5) * h)
+        ex = f(I * H, (J + 0.5) * H)
+        inner = (I >= 1) & (I < Nc - 1)
+    else:
+        R = mac.restrict_v(N)
+        fine = f((i + 0.5) * h, j * h)
+        ex = f((I + 0.5) * H, J * H)
+        inner = (J >= 1) & (J < Nc - 1)
+    out = (R @ fine.ravel()).reshape(Nc, Nc)
+    assert np.max(np.abs(out - ex)[inner]) < 1e-13
+
+
 # ---------------------------------------------------------------- spreading / interpolation
 
 def _pts(M=30, N=16, seed=3):
