@@ -421,7 +421,7 @@ int do_setup(ibmg_handle* h, double dt, const double* X) {
 
 // ---------------------------------------------------------------- FGMRES
 
-int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
+int do_solve_impl(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
   hipStream_t s = h->stream;
   const size_t n0 = h->n0();
   const int m = h->mb, ldh = m + 1, cap = h->maxit;
@@ -562,6 +562,14 @@ int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
     }
   }
   return st->converged ? IBMG_OK : IBMG_NOT_CONVERGED;
+}
+
+// The FP64 fallback belongs to one solve: whatever way the solve ends, later
+// V-cycles (the next solve, ibmg_vcycle) run in the handle's precision.
+int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
+  const int rc = do_solve_impl(h, b, x, st);
+  h->fb64 = false;
+  return rc;
 }
 
 double now_ms() {
