@@ -225,6 +225,20 @@ int ibmg_spread(ibmg_handle* h, const double* X, const double* G, double* f_u, d
 /* U = S^* (u, v) = h^2 S_0^T (u, v).  U: M x 2. */
 int ibmg_interp(ibmg_handle* h, const double* X, const double* u, const double* v, double* U);
 
+/* ibmg_spread without a handle and without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  f_u, f_v (N x N each) = S_0 G for
+ * points X (M x 2) with forces G (M x 2), same kernels and bit-identical
+ * results as ibmg_spread (delta kernel `delta`).  Scratch memory is a 16 MiB
+ * array in device memory that each GPU holds for the life of the process,
+ * shared by every call on that GPU: calls that overlap on one GPU (several
+ * streams or threads) race.  Enqueued on `stream` (hipStream_t, NULL =
+ * default), not synchronised.  Limits: N a power of two, 16 <= N <= 512;
+ * 0 <= M <= 8192.  Errors: EINVAL (sizes beyond these limits, null pointers,
+ * bad delta), EHIP. */
+int ibmg_spread_noalloc(int32_t N, int32_t delta, int32_t M, const double* X, const double* G, double* f_u,
+                        double* f_v, void* stream);
+
 /* --- Batched form: many independent problems, each with its own grid,
  *     structure, stiffness, dt and options, advanced together.  Every
  *     problem runs the same method as ibmg_step (Sec. 2.3.2 step, FGMRES of

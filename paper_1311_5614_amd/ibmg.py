@@ -35,7 +35,7 @@ EXPORTS = [
     "ibmg_batch_set_graph", "ibmg_batch_rounds", "ibmg_batch_destroy", "ibmg_step_x0",
     "ibmg_cnn_create", "ibmg_cnn_workspace_bytes", "ibmg_cnn_bind_workspace", "ibmg_cnn_set_params",
     "ibmg_cnn_get_params", "ibmg_cnn_set_scales", "ibmg_cnn_get_scales", "ibmg_cnn_record", "ibmg_cnn_pairs",
-    "ibmg_cnn_train", "ibmg_cnn_infer", "ibmg_cnn_loss_grad", "ibmg_cnn_destroy",
+    "ibmg_cnn_train", "ibmg_cnn_infer", "ibmg_cnn_loss_grad", "ibmg_cnn_destroy", "ibmg_spread_noalloc",
 ]
 
 
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ibmg_cnn_infer": [vp, vp, vp],
         "ibmg_cnn_loss_grad": [vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)],
         "ibmg_cnn_destroy": [vp],
+        "ibmg_spread_noalloc": [i32, i32, i32, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
