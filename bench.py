@@ -1,30 +1,30 @@
 """Benchmark: implicit IB time steps per second on one MI355X.
 
-Workload (default): the 256x256 single-ellipse stiffness sweep -- one
-perturbed ellipse of 1024 points, a smooth random body force (16 Fourier
-modes per component), springs K in {1e2, 1e4, 1e6, 1e8} and dt in {100, 1000}
-x the explicit stability limit: 8 independent trajectories.  One bench step
-advances every trajectory by one implicit time step (FGMRES to relative
-residual 1e-8, at most 200 iterations, 4x4 boxes).  Timed from the same
-initial state in four forms:
+Headline workload (default, --workload c3): the 1024x1024 eight-ring
+instance -- 8 elastic rings of 2048 points (16384 Lagrangian points), K = 1e6,
+dt = 500 x the explicit stability limit, 7 multigrid levels, every solve to
+relative residual 1e-8.  One bench step is one implicit time step of that
+trajectory (setup, right-hand side, FGMRES solve, position update).  Two forms
+are timed from the same initial state, each `--repeats` times (median
+reported):
 
-  plain  FP64 V-cycle, default schedule (V(2,2), checkerboard boxes, levels
-         down to 4x4, LDS tail from 32x32);
-  fp32   FP32 V-cycle inside FP64 FGMRES, default schedule;
-  tuned  per case the schedule and V-cycle precision picked by the
-         autotuner on calibration problems (schedules.json in the package);
-  concurrent  (chosen) the tuned form with the eight trajectories advanced
-         at the same time, each on its own stream and host thread.
+  plain   FP64 V-cycle inside FP64 FGMRES, default schedule (4x4 boxes,
+          checkerboard order, V(2,2), no restart below the 200 cap);
+  chosen  the schedule the autotuner table gives for this workload
+          (schedules.json: FP32 V-cycle inside FP64 FGMRES, box order,
+          sweeps, tail, restart), the value reported.
 
-`value` is the chosen form's whole-job rate in time steps per second; inputs
-are resident in HBM before timing starts.  --workload c4 runs the 64-problem
-batch (forms batch / batch64 / plain / fp32 / tuned).
+Inputs are resident in HBM before timing starts; every timed step includes
+its setup.  Also reported: iterations per solve and steps that missed rtol
+per form, the HIP-event roofline of the dominant kernel, the 4096x4096 plain
+V-cycle bandwidth probe, the oracle timed on the host on a bounded sample of
+the same workload, and (unless --no-extras) the 256x256 stiffness sweep and
+the 64-problem batch as extra keys.
 
-Also reported: iterations per solve for every form, the HIP-event roofline of
-the box-relaxation kernel k_box, and the CPU oracle timed on a bounded sample
-on the host.
+Other workloads: --workload c2 (256x256 sweep, forms concurrent / plain /
+fp32 / tuned), c4 (64-problem batch), c5 (512x512 learned warm start), c1.
 
-python bench.py [--gpus 1] [--steps 20] [--warmup 1] [--workload c2|c1|c5|c3|c4]
+python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload c3|c2|c4|c5|c1]
 """
 import argparse
 import json
@@ -36,13 +36,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MAXIT = 200   # FGMRES iteration cap (no restart below it)
+MAXIT = 200          # Krylov basis size: no restart below 200 iterations
+MAXIT_TOTAL = 1000   # iteration cap of the sweep's and the batch's solves (FGMRES(200) restarts past 200)
 BOX_REPS = 200   # back-to-back box launches timed for the roofline
 METRIC = "IB time-steps/sec and FGMRES iters/solve at rel resid 1e-8, plain vs chosen"
 
 
 BOX_SOURCES = ("paper_1311_5614_amd/csrc/level_ops.h", "paper_1311_5614_amd/csrc/mg.hip",
-               "paper_1311_5614_amd/csrc/common.h")
+               "paper_1311_5614_amd/csrc/common.h", "paper_1311_5614_amd/csrc/krylov.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_box_traffic.txt")
 
 
@@ -129,8 +130,8 @@ class Run:
         from paper_1311_5614_amd import ibmg
         self.w, self.dt = w, dt
         cfg = ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
-                          nu2=w.nu2, maxit=MAXIT, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
-                          tail_max=getattr(w, "tail_max", 0))
+                          nu2=w.nu2, maxit=MAXIT_TOTAL, restart=MAXIT, rtol=w.rtol, prec=prec,
+                          colours=getattr(w, "colours", 2), tail_max=getattr(w, "tail_max", 0))
         self.s = ibmg.Solver(cfg, w.fiber_offsets, dev, stream=stream)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
         self.X0 = t(w.X)
@@ -158,8 +159,8 @@ class BatchRun:
         from paper_1311_5614_amd import ibmg
         self.ws, self.dts = ws, dts
         cfgs = [ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
-                            nu2=w.nu2, maxit=MAXIT, rtol=w.rtol, prec=prec, colours=getattr(w, "colours", 2),
-                            tail_max=getattr(w, "tail_max", 0))
+                            nu2=w.nu2, maxit=MAXIT_TOTAL, restart=MAXIT, rtol=w.rtol, prec=prec,
+                            colours=getattr(w, "colours", 2), tail_max=getattr(w, "tail_max", 0))
                 for w in ws]
         self.b = ibmg.Batch(cfgs, [w.fiber_offsets for w in ws], dev)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
@@ -342,14 +343,15 @@ def cpu_baseline(w, dt, budget_note, steps=3):
 
 
 def run_learned(args, dev):
-    """The 512x512 learned-warm-start trajectory.  Steps 1..H run from w^n
-    (guess PREV) and record (features, target) pairs, the target being the
-    change of the step increment, Dw^n - Dw^{n-1}; the network is trained on
-    the GPU; then steps H+1..2H run four ways from the same state at step H:
-    learned (x0 = w^n + Dw^{n-1} + net(features), guarded by the minimal-
-    residual weight alpha), extrapolation alone (x0 = w^n + Dw^{n-1}, same
-    guard: what the network adds is the difference of the two), from w^n,
-    and from zero."""
+    """The 512x512 learned-warm-start trajectory.  Steps 1..H start from w^n
+    and record (features, target) pairs in the network handle (the target
+    being the change of the step increment, dw^n - dw^{n-1}); the network is
+    trained on the GPU; then steps H+1..2H run four ways from the same state
+    at step H: learned (x0 = w^n + dw^{n-1} + net(features), guarded by the
+    minimal-residual weight alpha), extrapolation alone (x0 = w^n + dw^{n-1},
+    same guard: what the network adds is the difference of the two), from
+    w^n, and from zero.  Features, proposals, increments and targets are
+    formed inside the library (ibmg_guess_step)."""
     import torch
     from paper_1311_5614_amd import ibmg
     import ibgen
@@ -357,7 +359,8 @@ def run_learned(args, dev):
     dt = load_dt("c5")[0]["dt"]
     H = args.steps or 200        # half-trajectory length (default 200 of 400)
     N = w.N
-    cfg = lambda guess: ibmg.Config(N=N, levels=7, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2, maxit=MAXIT,
+    cfg = lambda guess: ibmg.Config(N=N, levels=7, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2,
+                                    maxit=MAXIT_TOTAL, restart=MAXIT,
                                     rtol=w.rtol, prec=ibmg.IBMG_FP32, guess=guess, tail_max=1)
     s = ibmg.Solver(cfg(ibmg.IBMG_GUESS_PREV), w.fiber_offsets, dev)
     s0 = ibmg.Solver(cfg(ibmg.IBMG_GUESS_ZERO), w.fiber_offsets, dev)
@@ -367,23 +370,12 @@ def run_learned(args, dev):
     gu, gv = t(w.g_u), t(w.g_v)
     z = torch.zeros(N, N, dtype=torch.float64, device=dev)
     u, v, p, X = z.clone(), z.clone(), z.clone(), t(w.X)
-
-    def features(U, V, Pp, XX):
-        G = s.fiber_force(XX)
-        fu, fv = s.spread(XX, G)
-        return torch.stack([U, V, Pp, fu, fv]).contiguous()
-
     t0 = time.perf_counter()
     its_train = []
-    dprev = torch.zeros(3, N, N, dtype=torch.float64, device=dev)
+    net.reset()
     for n in range(H):
-        f = features(u, v, p, X)
-        old = torch.stack([u, v, p]).clone()
-        st = s.step(dt, u, v, p, X, gu, gv)
+        st = s.guess_step(net, ibmg.IBMG_GUESS_RECORD, dt, u, v, p, X, gu, gv)
         its_train.append(st["iters"])
-        d = torch.stack([u, v, p]) - old
-        net.record(f, (d - dprev).contiguous())
-        dprev = d
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -391,21 +383,19 @@ def run_learned(args, dev):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     start = [a.clone() for a in (u, v, p, X)]
-    dstart = dprev.clone()
+    dstart = net.get_increment()          # dw^{H-1}: every form starts from it
     res = {}
     for form in ("learned", "extrap", "prev", "zero"):
         u, v, p, X = (a.clone() for a in start)
-        dprev = dstart.clone()
+        net.set_increment(dstart)
         its, conv, alphas = [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for n in range(H):
-            old = torch.stack([u, v, p])
             if form in ("learned", "extrap"):
-                q = dprev + net.infer(features(u, v, p, X)) if form == "learned" else dprev
-                st = s.step_x0(dt, u, v, p, X, (old + q).reshape(-1).contiguous(), gu, gv)
+                mode = ibmg.IBMG_GUESS_LEARNED if form == "learned" else ibmg.IBMG_GUESS_EXTRAP
+                st = s.guess_step(net, mode, dt, u, v, p, X, gu, gv)
                 alphas.append(st["guess_alpha"])
-                dprev = torch.stack([u, v, p]) - old
             elif form == "prev":
                 st = s.step(dt, u, v, p, X, gu, gv)
             else:
@@ -436,10 +426,252 @@ def run_learned(args, dev):
     }
     print(json.dumps(out))
 
+def c3_schedule():
+    """The chosen schedule of the 1024x1024 eight-ring workload (autotuner table)."""
+    from paper_1311_5614_amd import autotune
+    return autotune.load()["c3"]["1024"]
+
+
+def c3_config(form):
+    """Solver options of a form on the 1024x1024 workload."""
+    from paper_1311_5614_amd import ibmg
+    import ibgen
+    w = ibgen.config_c3()
+    if form == "plain":
+        return ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2,
+                           maxit=MAXIT_TOTAL, restart=MAXIT, rtol=w.rtol, prec=ibmg.IBMG_FP64, colours=2, tail_max=0)
+    sch = c3_schedule()
+    return ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, rho=w.rho, mu=w.mu, box=sch["box"], nu1=sch["nu1"],
+                       nu2=sch["nu2"], maxit=sch.get("maxit", MAXIT_TOTAL), restart=sch.get("restart", MAXIT), rtol=w.rtol,
+                       prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"])
+
+
+def describe(cfg):
+    from paper_1311_5614_amd import ibmg
+    rs = f"FGMRES({cfg.restart}), cap {cfg.maxit}" if cfg.restart else f"FGMRES, cap {cfg.maxit}"
+    return (f"{'FP32' if cfg.prec == ibmg.IBMG_FP32 else 'FP64'} V({cfg.nu1},{cfg.nu2}) V-cycle, {cfg.levels} levels, "
+            f"{cfg.box}x{cfg.box} boxes, {cfg.colours} colours, tail {cfg.tail_max or 32}, {rs}, FP64 Krylov")
+
+
+def timed_trajectory(s, w, dt, dev, steps, warmup, repeats):
+    """`warmup` untimed steps, then `repeats` runs of `steps` steps, each from
+    the workload's initial state (u = v = p = 0, X^0), bracketed by device
+    synchronisations.  Returns the per-run seconds and the per-step stats of
+    every run."""
+    import torch
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+    X0 = t(w.X)
+    z = torch.zeros(w.N, w.N, dtype=torch.float64, device=dev)
+    u, v, p, X = z.clone(), z.clone(), z.clone(), X0.clone()
+    for _ in range(warmup):
+        s.step(dt, u, v, p, X)
+    times, stats = [], []
+    for _ in range(repeats):
+        u.zero_(); v.zero_(); p.zero_(); X.copy_(X0)
+        torch.cuda.synchronize()
+        run = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run.append(s.step(dt, u, v, p, X))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        stats.append(run)
+    return times, stats
+
+
+def form_summary(cfg, times, stats, steps):
+    import statistics
+    med = statistics.median(times)
+    its = [st["iters"] for run in stats for st in run]
+    res = [st["rel_resid_true"] for run in stats for st in run]
+    conv = [st["converged"] for run in stats for st in run]
+    return {"schedule": describe(cfg), "rate": steps / med, "ms_per_step": 1e3 * med / steps,
+            "runs_s": [round(x, 4) for x in times], "iters_mean": sum(its) / len(its), "iters_max": max(its),
+            "steps_timed": len(its), "converged": sum(conv), "missed_rtol": len(its) - sum(conv),
+            "rel_resid_max": max(res), "fallbacks": sum(st["fallback"] for run in stats for st in run)}
+
+
+def cpu_leg_c3(iters=2):
+    """Oracle sample of the 1024x1024 workload (run in a child process): step
+    1's setup (level hierarchy with the Galerkin elasticity operators, box
+    factorisations, bordered coarsest LU, right-hand side) and the first
+    `iters` FGMRES iterations with the chosen schedule's box order and
+    sweeps; one thread.  Prints one JSON line."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import ibgen
+    from oracle import krylov, mg, system
+    w = ibgen.config_c3()
+    dt = load_dt("c3")[0]["dt"]
+    sch = c3_schedule()
+    mode = "colour2" if sch["colours"] == 2 else "colour"
+    z = np.zeros((w.N, w.N))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        lv = system.hierarchy(w.N, sch["levels"], w.rho, w.mu, dt, w.X, w.fiber_offsets, w.K)
+        b = system.rhs(z, z, w.X, w.fiber_offsets, w.K, dt, w.rho)
+        V = mg.VCycle(lv, sch["box"], sch["nu1"], sch["nu2"], mode)
+        t1 = time.perf_counter()
+        krylov.fgmres(lv[0].A, b, V, rtol=w.rtol, maxit=iters)
+        t2 = time.perf_counter()
+    print(json.dumps({"setup_s": t1 - t0, "iter_s": (t2 - t1) / iters, "iters_run": iters,
+                      "schedule": f"box {sch['box']}, V({sch['nu1']},{sch['nu2']}), {mode}"}), flush=True)
+
+
+def start_cpu_leg():
+    """The oracle leg in a child process on one host core, started before
+    the GPU timing so that the two overlap."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cores = sorted(os.sched_getaffinity(0))
+    p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-leg"], stdout=subprocess.PIPE,
+                         stderr=subprocess.PIPE, env=env, text=True,
+                         preexec_fn=(lambda: os.sched_setaffinity(0, {cores[-1]})) if len(cores) > 1 else None)
+    return p, cores
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def finish_cpu_leg(p, cores, iters_per_step, timeout_s=900):
+    try:
+        out, err = p.communicate(timeout=timeout_s)
+    except Exception as e:   # noqa: BLE001
+        p.kill()
+        return {"error": f"cpu leg did not finish: {type(e).__name__}"}
+    if p.returncode != 0:
+        return {"error": f"cpu leg failed: {err.strip()[-300:]}"}
+    d = json.loads(out.strip().splitlines()[-1])
+    t_step = d["setup_s"] + iters_per_step * d["iter_s"]
+    return {"value": 1.0 / t_step, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"1024x1024 eight-ring workload, step 1: oracle setup ({d['setup_s']:.1f} s) and "
+                       f"{d['iters_run']} FGMRES iterations ({d['iter_s']:.2f} s each, {d['schedule']}), "
+                       f"extrapolated to one step at {iters_per_step:.1f} iterations (the GPU chosen form's "
+                       f"mean); one thread (numpy/scipy, no BLAS threads)"),
+            "host": {"nproc": len(cores), "cpu_model": cpu_model()}, "setup_s": d["setup_s"],
+            "iter_s": d["iter_s"]}
+
+
+def c3_roofline(s, cfg, w, dt, dev, iters_mean, reps=BOX_REPS):
+    """HIP-event timing of the hot kernels of the chosen form on the state the
+    timed runs left (setup at the current positions, the last solve's Krylov
+    basis): the box relaxation and the residual pass of one colour phase on
+    the finest level, and one Gram-Schmidt dot pass and update pass at the
+    solve's mean basis size.  Each is `reps` launches replayed from a graph
+    on the solver's stream.  The dominant kernel (the largest estimated time
+    per step: launches per step times mean launch time) is the roofline
+    entry; all four are listed."""
+    import torch
+    from paper_1311_5614_amd import ibmg
+    X = torch.as_tensor(w.X, dtype=torch.float64, device=dev).contiguous()
+    s.setup(dt, X)
+    nvec = max(1, min(int(round(iters_mean / 2)) + 1, cfg.restart or cfg.maxit))
+    sweeps = (cfg.nu1 + cfg.nu2) * cfg.colours * iters_mean        # finest-level phases per step
+    cand = {
+        "k_box": (ibmg.IBMG_KERNEL_BOX, 0, 0, sweeps, "box relaxation of one colour phase, finest level"),
+        "k_res_ib": (ibmg.IBMG_KERNEL_RES, 0, 0, sweeps, "residual pass of one colour phase, finest level"),
+        "k_multidot": (ibmg.IBMG_KERNEL_MULTIDOT, 0, nvec, 2 * iters_mean,
+                       f"Gram-Schmidt dot pass over {nvec} basis vectors"),
+        "k_update_acc": (ibmg.IBMG_KERNEL_UPDATE, 0, nvec, 2 * iters_mean,
+                         f"Gram-Schmidt update pass over {nvec} basis vectors"),
+    }
+    out = {}
+    for name, (k, level, arg, per_step, what) in cand.items():
+        us, by = s.kernel_bench(k, level, arg, reps)
+        gbs = by / (us * 1e-6) / 1e9
+        out[name] = {"what": what, "avg_us": us, "bytes": by, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                     "launches_per_step": per_step, "est_ms_per_step": per_step * us * 1e-3}
+        print(f"[bench] {name}: {us:.2f} us, {by / 1e6:.2f} MB -> {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f} %)",
+              file=sys.stderr, flush=True)
+    dom = max(out, key=lambda k: out[k]["est_ms_per_step"])
+    d = out[dom]
+    return {"kernel": f"{dom} ({d['what']})", "bound": "hbm", "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": d["frac"], "traffic": measured_traffic_c3(dom, d),
+            "launch": {"avg_us": d["avg_us"], "bytes": d["bytes"], "reps": reps, "prec": "fp32" if
+                       cfg.prec == ibmg.IBMG_FP32 else "fp64"},
+            "kernels": out}
+
+
+def measured_traffic_c3(name, d):
+    """HBM bytes per launch of kernel `name` from the committed rocprofv3
+    counter summary (profiles/<name>_1024x1024_traffic.txt: FETCH_SIZE and
+    WRITE_SIZE scaled by a copy-kernel calibration), or None when there is no
+    summary, it was taken for another launch size, or the kernel's sources
+    changed since."""
+    path = os.path.join(ROOT, "profiles", f"{name}_1024x1024_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.strip().split("=", 1)
+                kv[k] = v
+    if kv.get("kernel_source_sha1") != box_source_hash():
+        return None
+    if abs(float(kv.get("algorithmic_bytes", -1)) - d["bytes"]) > 1e-6 * d["bytes"]:
+        return None
+    return float(kv["traffic_bytes"])
+
+
+def run_c3(args, dev):
+    """The 1024x1024 eight-ring workload, plain and chosen forms."""
+    import torch
+    import ibgen
+    from paper_1311_5614_amd import ibmg
+    leg = None if args.no_cpu else start_cpu_leg()
+    w = ibgen.config_c3()
+    dt = load_dt("c3")[0]["dt"]
+    forms = [f for f in args.forms.split(",") if f in ("plain", "chosen")] or ["chosen", "plain"]
+    res, solvers = {}, {}
+    for form in forms:
+        cfg = c3_config(form)
+        s = ibmg.Solver(cfg, w.fiber_offsets, dev)
+        times, stats = timed_trajectory(s, w, dt, dev, args.steps, args.warmup, args.repeats)
+        res[form] = form_summary(cfg, times, stats, args.steps)
+        r = res[form]
+        print(f"[bench] c3 {form}: {r['rate']:.3f} steps/s (runs {r['runs_s']} s), iters mean "
+              f"{r['iters_mean']:.1f} max {r['iters_max']}, missed rtol {r['missed_rtol']}/{r['steps_timed']}",
+              file=sys.stderr, flush=True)
+        solvers[form] = (s, cfg)
+    chosen = "chosen" if "chosen" in res else forms[0]
+    rc = res[chosen]
+    s, cfg = solvers[chosen]
+    roof = c3_roofline(s, cfg, w, dt, dev, rc["iters_mean"])
+    for f, (sv, _) in solvers.items():
+        sv.close()
+    del solvers
+    torch.cuda.empty_cache()
+    out = {
+        "metric": METRIC, "value": rc["rate"], "unit": "time-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rc["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32" if cfg.prec == ibmg.IBMG_FP32 else "f64", "data": "synthetic",
+        "config": {"workload": (f"1024x1024 periodic grid, 8 elastic rings x 2048 points (16384), K 1e6, "
+                                f"dt 500 x explicit limit, {cfg.levels} levels, rtol 1e-8; chosen form: "
+                                f"{describe(cfg)}"),
+                   "grid": w.N, "points": w.M, "rings": 8, "K": w.K, "dt_factor": w.dt_factor,
+                   "repeats": args.repeats, "timing": "median of the repeats"},
+        "forms": res,
+        "iters_per_solve": {f: round(r["iters_mean"], 2) for f, r in res.items()},
+        "roofline": roof,
+    }
+    if "plain" in res and chosen != "plain":
+        out["speedup_vs_plain"] = rc["rate"] / res["plain"]["rate"]
+    return out, leg
+
+
 PROBE_N = 4096   # bandwidth probe: plain V(2,2) with no structure on this grid
 
 
-def vcycle_probe(dev, N=PROBE_N, reps=10):
+def vcycle_probe(dev, N=PROBE_N, reps=10, colours=2):
     """Plain FP64 V(2,2) with 4x4 boxes and no structure on an N x N grid
     (coarsest 16 x 16), large enough to be bandwidth-bound rather than
     latency-bound.  Times `reps` V-cycles (one captured graph each) between
@@ -452,7 +684,7 @@ def vcycle_probe(dev, N=PROBE_N, reps=10):
     import torch
     from paper_1311_5614_amd import ibmg
     levels = int(math.log2(N // 16)) + 1
-    cfg = ibmg.Config(N=N, levels=levels, K=0.0, box=4, nu1=2, nu2=2, maxit=4, prec=ibmg.IBMG_FP64)
+    cfg = ibmg.Config(N=N, levels=levels, K=0.0, box=4, nu1=2, nu2=2, maxit=4, prec=ibmg.IBMG_FP64, colours=colours)
     s = ibmg.Solver(cfg, None, dev)
     try:
         s.setup(1.0 / N, None)
@@ -472,7 +704,7 @@ def vcycle_probe(dev, N=PROBE_N, reps=10):
         us, by = s.box_bench(0, 0, BOX_REPS)
         gbs = alg / (ms * 1e-3) / 1e9
         kb = by / (us * 1e-6) / 1e9
-        out = {"workload": f"{N}x{N}, {levels} levels, plain FP64 V(2,2), 4x4 boxes, 2 colours, no structure",
+        out = {"workload": f"{N}x{N}, {levels} levels, plain FP64 V(2,2), 4x4 boxes, {colours} colours, no structure",
                "vcycle_ms": ms, "vcycle_bytes": alg, "vcycle_GBs": gbs, "vcycle_frac": gbs / HBM_PEAK_GBS,
                "k_box_us": us, "k_box_bytes": by, "k_box_GBs": kb, "k_box_frac": kb / HBM_PEAK_GBS}
         print(f"[bench] probe {N}x{N}: V-cycle {ms:.3f} ms -> {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f} %), "
@@ -484,50 +716,12 @@ def vcycle_probe(dev, N=PROBE_N, reps=10):
         torch.cuda.empty_cache()
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; c5: half-trajectory 200)")
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="concurrent,plain,fp32,tuned")
-    ap.add_argument("--levels", type=int, default=0, help="override the workload's level count")
-    ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
-    ap.add_argument("--colours", type=int, default=2)
-    ap.add_argument("--box", type=int, default=0, help="override the box edge (1, 2, 4 or 8 cells)")
-    ap.add_argument("--tail-max", type=int, default=0, help="override the V-cycle tail size")
-    ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs of the warm-start network")
-    ap.add_argument("--lr", type=float, default=1e-3, help="c5: Adam learning rate")
-    ap.add_argument("--no-probe", action="store_true", help="skip the 4096x4096 bandwidth probe")
-    ap.add_argument("--probe-only", action="store_true", help="run only the 4096x4096 bandwidth probe")
-    ap.add_argument("--probe-n", type=int, default=PROBE_N, help="grid of the bandwidth probe")
-    ap.add_argument("--copy-probe", type=int, default=0,
-                    help="only copy a device buffer of this many MiB, 5 times (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.copy_probe:
-        import torch
-        a = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 5}))
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md, not implemented)"}))
-        sys.exit(2)
+def run_sweep(args, dev, workload, forms, steps, warmup):
+    """The 256x256 stiffness sweep (c2) or the 64-problem batch (c4) in the
+    given forms; returns the result line without probe and CPU leg."""
     import torch
     from paper_1311_5614_amd import ibmg
-    dev = "cuda:0"
-    if args.probe_only:
-        print(json.dumps({"probe": vcycle_probe(dev, args.probe_n)}))
-        return
-    if args.workload == "c5":
-        return run_learned(args, dev)
-    args.steps = args.steps or 20
-    cases, dts = workloads(args.workload)
+    cases, dts = workloads(workload)
     for c in cases:
         if args.levels:
             c.levels = args.levels
@@ -538,7 +732,7 @@ def main():
             c.box = args.box
         if args.tail_max:
             c.tail_max = args.tail_max
-    forms = args.forms.split(",")
+    forms = list(forms)
     res = {}
     for form in forms:
         # plain: FP64 V-cycle, default schedule.  fp32: FP32 V-cycle, default
@@ -547,10 +741,10 @@ def main():
         # schedules, FP32 / FP64 V-cycle).
         if form.startswith("batch"):
             prec = ibmg.IBMG_FP64 if form == "batch64" else ibmg.IBMG_FP32
-            bcases, _ = tuned(args.workload, cases)
+            bcases, _ = tuned(workload, cases)
             br = BatchRun(bcases, dts, prec, dev)
-            t, its, conv, rounds = timed_batch(br, args.steps, args.warmup)
-            n = args.steps * len(cases)
+            t, its, conv, rounds = timed_batch(br, steps, warmup)
+            n = steps * len(cases)
             res[form] = dict(time_s=t, timesteps=n, rate=n / t, iters_mean=sum(its) / len(its), iters_max=max(its),
                              converged=sum(conv), rounds=rounds, phase=None)
             print(f"[bench] {form}: {n} steps in {t:.3f} s -> {n / t:.2f} steps/s, iters mean "
@@ -560,7 +754,7 @@ def main():
             torch.cuda.empty_cache()
             continue
         if form in ("tuned", "concurrent"):
-            fcases, precs = tuned(args.workload, cases)
+            fcases, precs = tuned(workload, cases)
         else:
             fcases = cases
             precs = [ibmg.IBMG_FP32 if form == "fp32" else ibmg.IBMG_FP64] * len(cases)
@@ -573,17 +767,17 @@ def main():
             # their own.  The form runs first in the default order, before
             # other forms' streams come and go.
             from paper_1311_5614_amd import autotune
-            table = autotune.load().get(args.workload, {})
-            cost = [table.get(schedule_key(args.workload, w), {}).get("ms_per_step", 0.0) for w in cases]
+            table = autotune.load().get(workload, {})
+            cost = [table.get(schedule_key(workload, w), {}).get("ms_per_step", 0.0) for w in cases]
             streams = [None] * len(cases)
             for k in sorted(range(len(cases)), key=lambda k: -cost[k]):
                 streams[k] = torch.cuda.Stream(dev)
             runs = [Run(w, dt, pr, dev, stream=st) for w, dt, pr, st in zip(fcases, dts, precs, streams)]
             torch.cuda.synchronize()
-            t, its, conv, _ = timed_concurrent(runs, args.steps, args.warmup)
+            t, its, conv, _ = timed_concurrent(runs, steps, warmup)
         else:
             runs = [Run(w, dt, pr, dev) for w, dt, pr in zip(fcases, dts, precs)]
-            t, its, conv, _ = timed(runs, args.steps, args.warmup, timing=False)
+            t, its, conv, _ = timed(runs, steps, warmup, timing=False)
         failed = dict(timed.failed)
         per_case = [round(sum(x) / max(1, len(x)), 1) for x in timed.per_case]
         # roofline of the box kernel: on the finest level of the first
@@ -621,9 +815,9 @@ def main():
         "value": rc["rate"],
         "unit": "time-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * rc["time_s"] / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * rc["time_s"] / steps,
         "ms_per_timestep": 1e3 * rc["time_s"] / rc["timesteps"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -654,6 +848,85 @@ def main():
             "launch": ph,
         },
     }
+    out["_cases"] = (cases, dts)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; c5: half-trajectory 200)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=3, help="c3: timed runs per form (median reported)")
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-extras", action="store_true", help="c3: skip the 256x256 sweep and the batch")
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="", help="c3: chosen,plain; c2: concurrent,plain,fp32,tuned")
+    ap.add_argument("--levels", type=int, default=0, help="override the workload's level count")
+    ap.add_argument("--nu", default="", help="override smoothing sweeps, e.g. 1,1")
+    ap.add_argument("--colours", type=int, default=2)
+    ap.add_argument("--box", type=int, default=0, help="override the box edge (1, 2, 4 or 8 cells)")
+    ap.add_argument("--tail-max", type=int, default=0, help="override the V-cycle tail size")
+    ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs of the warm-start network")
+    ap.add_argument("--lr", type=float, default=1e-3, help="c5: Adam learning rate")
+    ap.add_argument("--no-probe", action="store_true", help="skip the 4096x4096 bandwidth probe")
+    ap.add_argument("--probe-only", action="store_true", help="run only the 4096x4096 bandwidth probe")
+    ap.add_argument("--probe-n", type=int, default=PROBE_N, help="grid of the bandwidth probe")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy a device buffer of this many MiB, 5 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.cpu_leg:
+        return cpu_leg_c3()
+    if not args.forms:
+        args.forms = "chosen,plain" if args.workload == "c3" else "concurrent,plain,fp32,tuned"
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 5}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import torch
+    from paper_1311_5614_amd import ibmg
+    dev = "cuda:0"
+    if args.probe_only:
+        print(json.dumps({"probe": vcycle_probe(dev, args.probe_n, colours=args.colours)}))
+        return
+    if args.workload == "c5":
+        return run_learned(args, dev)
+    args.steps = args.steps or 20
+    if args.workload == "c3":
+        out, leg = run_c3(args, dev)
+        if not args.no_extras:
+            extra = {}
+            for wl, forms, steps in (("c2", ("concurrent", "plain"), 20), ("c4", ("batch",), 10)):
+                try:
+                    r = run_sweep(args, dev, wl, forms, steps, 1)
+                    r.pop("_cases", None)
+                    extra[wl] = {k: r[k] for k in ("value", "unit", "ms_per_step", "config", "forms")}
+                except Exception as e:   # noqa: BLE001  (extra figures; the headline stands without them)
+                    extra[wl] = {"error": f"{type(e).__name__}: {e}"}
+            out["extra_workloads"] = extra
+        if not args.no_probe:
+            try:
+                out["probe"] = vcycle_probe(dev)
+            except Exception as e:   # the probe is an extra figure; the workload's line stands without it
+                out["probe"] = {"error": f"{type(e).__name__}: {e}"}
+        if leg is not None:
+            out["cpu_baseline"] = finish_cpu_leg(*leg, iters_per_step=out["forms"]["chosen"]["iters_mean"]
+                                                 if "chosen" in out["forms"] else 100.0)
+        print(json.dumps(out))
+        return
+    steps = args.steps or 20
+    out = run_sweep(args, dev, args.workload, args.forms.split(","), steps, args.warmup)
+    cases, dts = out.pop("_cases")
     if not args.no_probe:
         try:
             out["probe"] = vcycle_probe(dev)

@@ -87,7 +87,7 @@ typedef struct {
   int32_t box;         /* box edge n in cells: 1, 2 or 4; every smoothed level needs
                           N_l >= max(4, 2n) (colour classes of boxes stay disjoint)  */
   int32_t nu1, nu2;    /* pre- and post-smoothing sweeps (Algorithm 1)              */
-  int32_t maxit;       /* FGMRES iteration cap over all cycles: 1..200 when restart
+  int32_t maxit;       /* FGMRES iteration cap over all cycles: 1..1000 when restart
                           is 0, 1..1000000 otherwise                                */
   double rtol;         /* stop when ||b - A w||_2 <= rtol ||b||_2                   */
   int32_t vcycle_prec; /* IBMG_FP64 or IBMG_FP32 (V-cycle fields and stencils)      */
@@ -105,9 +105,13 @@ typedef struct {
                           elastic rows, not the method.                         */
   int32_t restart;     /* FGMRES(m) restart length m, the Krylov basis size
                           (Sec. 3.3 leaves it open): 0 = no restart below maxit
-                          (m = maxit), else 1..200.  A cycle that ends without
+                          (m = maxit), else 1..1000 (the workspace holds 2m + 1
+                          vectors of 3 N^2 doubles).  A cycle that ends without
                           meeting rtol updates the iterate and starts the next
                           cycle from its true residual.                         */
+  int32_t colours_from;/* 0: every smoothed level uses `colours`; k >= 1: levels
+                          k and coarser use the checkerboard (2 colours), the
+                          finer ones `colours` (the order may differ per level) */
 } ibmg_opts;
 
 typedef struct {
@@ -154,6 +158,20 @@ int ibmg_set_timing(ibmg_handle* h, int on);
  * of a box with elastic rows once).  Needs a setup.  Synchronises. */
 int ibmg_box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, double* bytes);
 int ibmg_phase_timing(ibmg_handle* h, double* total_ms, int64_t* launches, double* bytes);
+/* Kernel timing of one hot-path kernel on the current setup, `reps` launches
+ * replayed from a captured graph between two HIP events on the handle's
+ * stream (as ibmg_box_bench).  kernel / level / arg:
+ *   IBMG_KERNEL_BOX       box relaxation on `level`, colour `arg` (= ibmg_box_bench);
+ *   IBMG_KERNEL_RES       the colour phase's residual pass on `level` (Stokes
+ *                         rows of every unknown and the elastic rows);
+ *   IBMG_KERNEL_MULTIDOT  one classical Gram-Schmidt dot pass of FGMRES: the
+ *                         first `arg` basis vectors against basis vector `arg`;
+ *   IBMG_KERNEL_UPDATE    one Gram-Schmidt update pass with `arg` vectors.
+ * The Krylov kernels run on the basis left by the last solve (1 <= arg <= the
+ * restart length; results are not used).  avg_us: mean time per launch;
+ * bytes: the launch's algorithmic bytes.  Needs a setup.  Synchronises. */
+enum { IBMG_KERNEL_BOX = 0, IBMG_KERNEL_RES = 1, IBMG_KERNEL_MULTIDOT = 2, IBMG_KERNEL_UPDATE = 3 };
+int ibmg_kernel_bench(ibmg_handle* h, int kernel, int level, int arg, int reps, double* avg_us, double* bytes);
 
 /* Operator setup at positions X (Sec. 2.3.2 lags S at X^n; Sec. 3.2 builds the
  * coarse elasticity operators by Galerkin products; Sec. 8 notes the box
@@ -310,6 +328,34 @@ int ibmg_cnn_infer(ibmg_cnn* c, const double* in5, double* dw3);
 /* Loss and gradient (HOST FP32 [39331]) of one pair, no update.  Synchronises. */
 int ibmg_cnn_loss_grad(ibmg_cnn* c, const double* in5, const double* dw3, float* loss, float* grad);
 int ibmg_cnn_destroy(ibmg_cnn* c);
+
+/* --- The learned initial iterate bound to the solver (Sec. 3.3 leaves the
+ *     FGMRES initial iterate free).  The network handle c (same N and the
+ *     same stream as the solver handle h) keeps the trajectory's previous
+ *     increment dw^{n-1} = w^n - w^{n-1} (zero after binding or
+ *     ibmg_guess_reset).  ibmg_guess_step is one implicit step (as ibmg_step,
+ *     same arguments) whose initial iterate depends on mode:
+ *       IBMG_GUESS_RECORD   from w^n; afterwards the training pair
+ *                           (features of step n, dw^n - dw^{n-1}) is stored
+ *                           in c (ibmg_cnn_record);
+ *       IBMG_GUESS_EXTRAP   x0 = w^n + dw^{n-1} (first-order extrapolation);
+ *       IBMG_GUESS_LEARNED  x0 = w^n + dw^{n-1} + F(features), F the
+ *                           network (scales must be set, e.g. by training).
+ *     Both proposals go through ibmg_step_x0's guard (the minimal-residual
+ *     point on the line from w^n through x0), and the solve runs to rtol as
+ *     always.  Features: (u^n, v^n, p^n, S_0 G^n on u faces, on v faces),
+ *     formed on the device from the step's setup.  Every mode updates
+ *     dw^{n-1}.  Synchronises.  Errors: as ibmg_step; EINVAL for a network of
+ *     another size or stream, ESTATE (learned) when the scales are unset. --- */
+enum { IBMG_GUESS_RECORD = 0, IBMG_GUESS_EXTRAP = 1, IBMG_GUESS_LEARNED = 2 };
+int ibmg_guess_step(ibmg_handle* h, ibmg_cnn* c, int mode, double dt, double* u, double* v, double* p, double* X,
+                    const double* g_u, const double* g_v, ibmg_stats* out);
+/* Forget the previous increment (the next step starts a trajectory). */
+int ibmg_guess_reset(ibmg_cnn* c);
+/* Copy the previous increment dw^{n-1} (3 N^2, device) out of / into the
+ * network handle, e.g. to run several forms of a trajectory from one state. */
+int ibmg_guess_get_increment(ibmg_cnn* c, double* dw3);
+int ibmg_guess_set_increment(ibmg_cnn* c, const double* dw3);
 
 #ifdef __cplusplus
 }

@@ -21,9 +21,16 @@ from .smoother import BoxSmoother
 
 class VCycle:
     def __init__(self, levels, box=4, nu1=2, nu2=2, mode="colour2"):
-        """levels: list of system.Level, finest first."""
+        """levels: list of system.Level, finest first.  mode: the box order of
+        every smoothed level (a string), or one order per smoothed level (a
+        sequence; Algorithm 1 fixes no order, so levels may differ)."""
         self.levels = levels
-        self.nu1, self.nu2, self.mode = nu1, nu2, mode
+        self.nu1, self.nu2 = nu1, nu2
+        nsm = len(levels) - 1
+        self.modes = [mode] * nsm if isinstance(mode, str) else list(mode)[:nsm]
+        if len(self.modes) != nsm:
+            raise ValueError("one box order per smoothed level")
+        self.mode = mode
         self.smoothers = [BoxSmoother(lv.A, lv.N, box) for lv in levels[:-1]]
         Ac = levels[-1].A.toarray()
         Nc = levels[-1].N
@@ -46,12 +53,12 @@ class VCycle:
             return self.coarse_solve(b)
         sm = self.smoothers[l]
         for _ in range(self.nu1):
-            w = sm.sweep(w, b, self.mode)
+            w = sm.sweep(w, b, self.modes[l])
         r2 = lv.R @ (b - lv.A @ w)
         e2 = self.mgv(np.zeros_like(r2), r2, l + 1)
         w = w + lv.P @ e2
         for _ in range(self.nu2):
-            w = sm.sweep(w, b, self.mode)
+            w = sm.sweep(w, b, self.modes[l])
         return w
 
     def __call__(self, r):

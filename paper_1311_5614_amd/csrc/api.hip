@@ -158,11 +158,15 @@ template <typename T>
 void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r, int colour,
                  bool from_zero) {
   LevelView<T> vb = v;
+  // four colours: the boxes form their own Stokes residuals, one launch per
+  // phase (plus the elastic-row pass); otherwise the residual pass first
+  const bool fused = !from_zero && phase_fusable(v.ncol, v.n);
   if (from_zero) vb.yib = nullptr;
-  else launch_res<T>(h->stream, v, b, w, r, h->has_ib);
+  else if (!fused) launch_res<T>(h->stream, v, b, w, r, h->has_ib);
   const bool t = h->timing && h->ev_used + 2 <= (int)h->ev.size();
   if (t) (void)hipEventRecord(h->ev[h->ev_used], h->stream);
-  launch_box<T>(h->stream, vb, from_zero ? b : r, w, colour, h->has_ib);
+  if (fused) launch_phase_fused<T>(h->stream, v, b, w, colour, h->has_ib);
+  else launch_box<T>(h->stream, vb, from_zero ? b : r, w, colour, h->has_ib);
   if (t) {
     (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
     // algorithmic bytes of one box launch: per unknown of the colour's boxes
@@ -178,7 +182,7 @@ void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w,
 
 template <typename T>
 void sweep(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w, T* r, bool from_zero = false) {
-  for (int c = 0; c < h->ncol; ++c) phase_timed<T>(h, v, l, b, w, r, c, from_zero && c == 0);
+  for (int c = 0; c < v.ncol; ++c) phase_timed<T>(h, v, l, b, w, r, c, from_zero && c == 0);
 }
 
 // z = MGV(0, r) on level 0 (Algorithm 1), vectors in precision T.
@@ -226,9 +230,10 @@ void vcycle(ibmg_handle* h, const T* b0, T* w0, bool w0_zero = false) {
 int capture_vcycle(ibmg_handle* h) {
   if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
   if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+  std::lock_guard<std::mutex> capture_lock(capture_mutex());
+  IBMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
   hipStream_t user = h->stream;
   h->stream = h->cap;
-  IBMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
   // the graph starts after precond's input pass, which also clears w0
   if (h->prec == IBMG_FP32) vcycle<float>(h, h->p<float>(h->b0f), h->p<float>(h->w0f), true);
   else vcycle<double>(h, h->p<double>(h->b0g), h->p<double>(h->w0g), true);
@@ -338,7 +343,7 @@ int setup_launch(ibmg_handle* h, double dt, const double* X) {
   }
   for (int l = 0; l + 1 < Lv; ++l) {
     LevelBufs& B = h->L[l];
-    launch_box_classes(s, B.N, h->n, B.nb, h->ncol, h->has_ib ? h->p<int>(B.act) : nullptr, h->p<int>(B.boxflag),
+    launch_box_classes(s, B.N, h->n, B.nb, h->ncol_l[l], h->has_ib ? h->p<int>(B.act) : nullptr, h->p<int>(B.boxflag),
                        h->p<int>(B.ib_index), h->p<int>(B.ib_boxes), h->p<int>(B.info));
   }
   // read back counts: boxes with elastic rows per colour, active rows, flags
@@ -722,6 +727,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   if (op->vcycle_prec != IBMG_FP64 && op->vcycle_prec != IBMG_FP32) return IBMG_EINVAL;
   if (op->guess != IBMG_GUESS_ZERO && op->guess != IBMG_GUESS_PREV) return IBMG_EINVAL;
   if (op->colours != 2 && op->colours != 4) return IBMG_EINVAL;
+  if (op->colours_from < 0 || op->colours_from > op->levels) return IBMG_EINVAL;
   if (op->tail_max != 0 && (op->tail_max < 1 || op->tail_max > kSmallLevel || (op->tail_max & (op->tail_max - 1))))
     return IBMG_EINVAL;
   if (pr->n_points < 0 || pr->n_fibers < 0) return IBMG_EINVAL;
@@ -733,6 +739,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   h->levels = op->levels; h->n = op->box; h->nu1 = op->nu1; h->nu2 = op->nu2; h->maxit = op->maxit;
   h->mb = op->restart == 0 ? op->maxit : std::min(op->restart, op->maxit);
   h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess; h->ncol = op->colours;
+  for (int l = 0; l < IBMG_MAX_LEVELS; ++l) h->ncol_l[l] = (op->colours_from > 0 && l >= op->colours_from) ? 2 : op->colours;
   h->tail_max = op->tail_max ? op->tail_max : kSmallLevel;
   h->stream = (hipStream_t)stream;
   h->prev.assign(h->M, 0);
@@ -815,8 +822,16 @@ int box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, d
   if (!h->cap) return IBMG_ESTATE;
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
+  std::lock_guard<std::mutex> capture_lock(capture_mutex());
   IBMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-  for (int q = 0; q < reps; ++q) launch_box<T>(h->cap, v, r, w, colour, h->has_ib);
+  // the box launch the V-cycle makes: on four-colour levels the one that forms
+  // its own Stokes residuals from b (the elastic rows as last evaluated)
+  const bool fused = phase_fusable(v.ncol, v.n);
+  const T* b = (level == 0 && h->prec == IBMG_FP64) ? h->p<T>(h->b0g) : h->p<T>(h->L[level].b);
+  for (int q = 0; q < reps; ++q) {
+    if (fused) launch_phase_fused<T>(h->cap, v, b, w, colour, h->has_ib, false);
+    else launch_box<T>(h->cap, v, r, w, colour, h->has_ib);
+  }
   IBMG_HIP(hipStreamEndCapture(h->cap, &g));
   if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
     (void)hipGraphDestroy(g);
@@ -839,11 +854,73 @@ int box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, d
   if (e != hipSuccess) return IBMG_EHIP;
   if (avg_us) *avg_us = 1e3 * (double)ms / reps;
   if (bytes) {
+    // per box: read the residual (or b) and the iterate, write the iterate at
+    // every unknown; a fused launch also reads the iterate on the box's
+    // one-cell halo (10 n + 4 values: the x and y neighbours of its u and v
+    // faces and the pressures left and below)
     const double boxes = colour_count(v.ncol, v.nb);
-    double by = boxes * v.ndof * 3.0 * sizeof(T) + (double)v.ndof * v.ndof * sizeof(T);
+    const double per_box = v.ndof * 3.0 + (fused ? 10.0 * v.n + 4.0 : 0.0);
+    double by = boxes * per_box * sizeof(T) + (double)v.ndof * v.ndof * sizeof(T);
     if (h->has_ib) by += (double)h->n_ib[level][colour] * v.ndof * v.ndof * sizeof(double);
     *bytes = by;
   }
+  return IBMG_OK;
+}
+
+// Graph-replayed timing of one hot-path kernel (see ibmg_kernel_bench):
+// `reps` launches captured on the capture stream, replayed once to warm up,
+// then once between two HIP events on the handle's stream.
+template <typename F>
+int replay_time(ibmg_handle* h, int reps, F launch, double* avg_us) {
+  if (!h->cap) return IBMG_ESTATE;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  std::lock_guard<std::mutex> capture_lock(capture_mutex());
+  IBMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  for (int q = 0; q < reps; ++q) launch(h->cap);
+  IBMG_HIP(hipStreamEndCapture(h->cap, &g));
+  if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return IBMG_EHIP;
+  }
+  hipEvent_t e0, e1;
+  IBMG_HIP(hipEventCreate(&e0));
+  IBMG_HIP(hipEventCreate(&e1));
+  IBMG_HIP(hipGraphLaunch(ge, h->stream));
+  IBMG_HIP(hipEventRecord(e0, h->stream));
+  IBMG_HIP(hipGraphLaunch(ge, h->stream));
+  IBMG_HIP(hipEventRecord(e1, h->stream));
+  IBMG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  const hipError_t e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(ge);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return IBMG_EHIP;
+  *avg_us = 1e3 * (double)ms / reps;
+  return IBMG_OK;
+}
+
+// The fused residual pass of a colour phase on level `level` (k_res_ib), in
+// the handle's V-cycle precision, on the level's V-cycle vectors.
+template <typename T>
+int res_bench(ibmg_handle* h, int level, int reps, double* avg_us, double* bytes) {
+  LevelView<T> v = view<T>(h, level);
+  T* w = (level == 0 && h->prec == IBMG_FP64) ? h->p<T>(h->w0g) : h->p<T>(h->L[level].w);
+  const T* b = (level == 0 && h->prec == IBMG_FP64) ? h->p<T>(h->b0g) : h->p<T>(h->L[level].b);
+  T* r = h->p<T>(h->L[level].r);
+  const int rc = replay_time(h, reps, [&](hipStream_t s) { launch_res<T>(s, v, b, w, r, h->has_ib); }, avg_us);
+  if (rc) return rc;
+  // read w and b, write r on every unknown; per active elastic row its window
+  // (121 coefficients) and the window's iterate values, and the row's result
+  const double n3 = 3.0 * v.N * v.N;
+  double by = 3.0 * n3 * sizeof(T);
+  if (h->has_ib) {
+    const double rows = (double)h->rb_nact[2 * level] + h->rb_nact[2 * level + 1];
+    by += rows * (IBMG_WS * sizeof(T) + sizeof(int) + sizeof(T));
+  }
+  *bytes = by;
   return IBMG_OK;
 }
 
@@ -851,10 +928,52 @@ int box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, d
 
 extern "C" {
 
+int ibmg_kernel_bench(ibmg_handle* h, int kernel, int level, int arg, int reps, double* avg_us, double* bytes) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  if (!h->setup_ok) return IBMG_ESTATE;
+  if (reps < 1 || !avg_us || !bytes) return IBMG_EINVAL;
+  const size_t n0 = h->n0();
+  double* V = h->p<double>(h->V);
+  switch (kernel) {
+    case IBMG_KERNEL_BOX:
+      return ibmg_box_bench(h, level, arg, reps, avg_us, bytes);
+    case IBMG_KERNEL_RES:
+      if (level < 0 || level + 1 >= h->levels) return IBMG_EINVAL;
+      return h->prec == IBMG_FP32 ? res_bench<float>(h, level, reps, avg_us, bytes)
+                                  : res_bench<double>(h, level, reps, avg_us, bytes);
+    case IBMG_KERNEL_MULTIDOT: {
+      // <V_i, v_arg> for i < arg over the FGMRES basis (one Gram-Schmidt pass)
+      if (arg < 1 || arg > h->mb) return IBMG_EINVAL;
+      double* part = h->p<double>(h->partial);
+      const int rc = replay_time(
+          h, reps, [&](hipStream_t s) { launch_multidot(s, V, n0, arg, V + (size_t)arg * n0, n0, part, kDotBlocks); },
+          avg_us);
+      // the arg basis vectors once, the new vector once per group of eight
+      *bytes = ((double)arg + (arg + 7) / 8) * n0 * sizeof(double);
+      return rc;
+    }
+    case IBMG_KERNEL_UPDATE: {
+      // v_arg -= sum_{i < arg} c_i V_i with c = the Hessenberg column (values
+      // as left by the last solve; the timing does not depend on them)
+      if (arg < 1 || arg > h->mb) return IBMG_EINVAL;
+      const double* c = h->p<double>(h->hc);
+      const int rc = replay_time(
+          h, reps, [&](hipStream_t s) { launch_update_acc(s, V, n0, arg, c, V + (size_t)arg * n0, n0, nullptr); },
+          avg_us);
+      // the arg basis vectors, read and write the updated vector
+      *bytes = ((double)arg + 2.0) * n0 * sizeof(double);
+      return rc;
+    }
+    default:
+      return IBMG_EINVAL;
+  }
+}
+
 int ibmg_box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, double* bytes) {
   if (!ready(h)) return IBMG_ENOMEM;
   if (!h->setup_ok) return IBMG_ESTATE;
-  if (level < 0 || level + 1 >= h->levels || colour < 0 || colour >= h->ncol || reps < 1) return IBMG_EINVAL;
+  if (level < 0 || level + 1 >= h->levels || colour < 0 || colour >= h->ncol_l[level] || reps < 1)
+    return IBMG_EINVAL;
   return h->prec == IBMG_FP32 ? box_bench<float>(h, level, colour, reps, avg_us, bytes)
                               : box_bench<double>(h, level, colour, reps, avg_us, bytes);
 }
@@ -900,12 +1019,13 @@ namespace {
 // One implicit step; x0 (nullable) is a proposed initial iterate, used only
 // when its residual is below that of w^n.
 int step_impl(ibmg_handle* h, double dt, double* u, double* v, double* p, double* X, const double* gu,
-              const double* gv, const double* x0, ibmg_stats* out) {
+              const double* gv, const double* x0, ibmg_stats* out, double t_setup_ms = -1.0) {
   if (!ready(h)) return IBMG_ENOMEM;
   if (!u || !v || !p || (h->M > 0 && !X)) return IBMG_EINVAL;
   ibmg_stats st{};
-  const double t0 = now_ms();
-  int rc = do_setup(h, dt, X);
+  // t_setup_ms >= 0: the caller has set up at (dt, X) already and took that long
+  const double t0 = now_ms() - (t_setup_ms >= 0.0 ? t_setup_ms : 0.0);
+  int rc = t_setup_ms >= 0.0 ? IBMG_OK : do_setup(h, dt, X);
   if (rc) return rc;
   const double t1 = now_ms();
   if ((rc = step_begin(h, dt, u, v, p, gu, gv))) return rc;
@@ -970,6 +1090,57 @@ int ibmg_step_x0(ibmg_handle* h, double dt, double* u, double* v, double* p, dou
                  const double* gv, const double* x0, ibmg_stats* out) {
   if (!x0) return IBMG_EINVAL;
   return step_impl(h, dt, u, v, p, X, gu, gv, x0, out);
+}
+
+int ibmg_guess_step(ibmg_handle* h, ibmg_cnn* c, int mode, double dt, double* u, double* v, double* p, double* X,
+                    const double* gu, const double* gv, ibmg_stats* out) {
+  if (!ready(h)) return IBMG_ENOMEM;
+  CnnTraj T;
+  if (!c || cnn_traj(c, &T) != IBMG_OK) return IBMG_ENOMEM;
+  if (T.N != h->N || T.stream != h->stream) return IBMG_EINVAL;
+  if (mode != IBMG_GUESS_RECORD && mode != IBMG_GUESS_EXTRAP && mode != IBMG_GUESS_LEARNED) return IBMG_EINVAL;
+  if (!u || !v || !p || (h->M > 0 && !X)) return IBMG_EINVAL;
+  hipStream_t s = h->stream;
+  const size_t NN = (size_t)h->N * h->N, n3 = 3 * NN;
+  const double t0 = now_ms();
+  int rc = do_setup(h, dt, X);   // S at X^n: the features use it
+  if (rc) return rc;
+  // features (u^n, v^n, p^n, S_0 G^n on u and v faces) and w^n
+  double* const w_in[3] = {u, v, p};
+  for (int k = 0; k < 3; ++k) {
+    IBMG_HIP(hipMemcpyAsync(T.feat + k * NN, w_in[k], NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(T.wold + k * NN, w_in[k], NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  launch_rhs(s, points(h), 0.0, (double)NN, nullptr, nullptr, nullptr, nullptr,
+             h->M > 0 ? h->p<double>(h->G) : nullptr, T.feat + 3 * NN);
+  const double* x0 = nullptr;
+  const int guess = h->guess;
+  if (mode == IBMG_GUESS_RECORD) {
+    h->guess = IBMG_GUESS_PREV;
+  } else {
+    // x0 = w^n + dw^{n-1} (+ the network's correction)
+    if (mode == IBMG_GUESS_LEARNED) {
+      if ((rc = ibmg_cnn_infer(c, T.feat, T.x0)) != IBMG_OK) return rc;
+      k_lincomb<<<nblk(n3), 256, 0, s>>>(T.x0, T.wold, T.dprev, 1.0, T.x0, 1.0, n3);
+    } else {
+      k_lincomb<<<nblk(n3), 256, 0, s>>>(T.x0, T.wold, T.dprev, 1.0, nullptr, 0.0, n3);
+    }
+    x0 = T.x0;
+  }
+  rc = step_impl(h, dt, u, v, p, X, gu, gv, x0, out, now_ms() - t0);
+  h->guess = guess;
+  if (rc < 0) return rc;
+  // dw^n = w^{n+1} - w^n; recording: the pair (features, dw^n - dw^{n-1})
+  for (int k = 0; k < 3; ++k)
+    k_lincomb<<<nblk(NN), 256, 0, s>>>(T.dw + k * NN, w_in[k], T.wold + k * NN, -1.0, nullptr, 0.0, NN);
+  if (mode == IBMG_GUESS_RECORD) {
+    k_lincomb<<<nblk(n3), 256, 0, s>>>(T.x0, T.dw, T.dprev, -1.0, nullptr, 0.0, n3);
+    const int rr = ibmg_cnn_record(c, T.feat, T.x0);
+    if (rr != IBMG_OK) return rr;
+  }
+  IBMG_HIP(hipMemcpyAsync(T.dprev, T.dw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  IBMG_HIP(hipStreamSynchronize(s));
+  return rc;
 }
 
 }  // extern "C"

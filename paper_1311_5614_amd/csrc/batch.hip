@@ -299,7 +299,8 @@ __global__ void __launch_bounds__(256) kb_update_acc(BSet S, const BKry* __restr
   const double* coef = pass == 1 ? col : q.hc;
   double* acc = pass == 1 ? nullptr : col;
   const size_t e = (size_t)blk * 256 + threadIdx.x;
-  if (acc && blk == 0 && (int)threadIdx.x < nvec) acc[threadIdx.x] += coef[threadIdx.x];
+  if (acc && blk == 0)
+    for (int t = threadIdx.x; t < nvec; t += blockDim.x) acc[t] += coef[t];
   if (e >= n) return;
   double sum = 0.0;
   // unrolled so that eight basis loads are in flight; the sum keeps its order
@@ -350,7 +351,8 @@ __global__ void __launch_bounds__(256) kb_start(BSet S, const BKry* __restrict__
   const size_t e = (size_t)blk * 256 + threadIdx.x;
   const double nrm = sqrt(q.scal[0]);
   if (e < n) q.V[e] = nrm > 0.0 ? q.V[e] / nrm : 0.0;
-  if (blk == 0 && (int)threadIdx.x < q.m + 2) q.g[threadIdx.x] = threadIdx.x == 0 ? S.beta[s] : 0.0;
+  if (blk == 0)
+    for (int t = threadIdx.x; t < q.m + 2; t += blockDim.x) q.g[t] = t == 0 ? S.beta[s] : 0.0;
 }
 
 // y = R^{-1} g over the leading k x k block, one thread per problem.
@@ -566,13 +568,13 @@ void build_schedule(ibmg_batch* B) {
         const LevelBufs& L = hp->L[l];
         const size_t NN = (size_t)L.N * L.N;
         const bool ib = hp->M > 0 && hp->K != 0.0;
-        const bool in_sweep = sweep < (post ? hp->nu2 : hp->nu1) && colour < hp->ncol;
+        const bool in_sweep = sweep < (post ? hp->nu2 : hp->nu1) && colour < hp->ncol_l[l];
         switch (kind) {
           case OP_RES:
             nb = in_sweep ? (int)nblk(3 * NN) + (ib ? 2 * ib_blocks(L.maxact) : 0) : 0;
             break;
-          case OP_BOX: nb = in_sweep && hp->n <= 4 ? colour_count(hp->ncol, L.nb) : 0; break;
-          case OP_BOX8: nb = in_sweep && hp->n == 8 ? colour_count(hp->ncol, L.nb) * kBigBoxRowBlocks : 0; break;
+          case OP_BOX: nb = in_sweep && hp->n <= 4 ? colour_count(hp->ncol_l[l], L.nb) : 0; break;
+          case OP_BOX8: nb = in_sweep && hp->n == 8 ? colour_count(hp->ncol_l[l], L.nb) * kBigBoxRowBlocks : 0; break;
           case OP_RESID: nb = (int)nblk(3 * NN) + (ib ? 2 * ib_blocks(L.maxact) : 0); break;
           case OP_RESTRICT: nb = (int)nblk(3 * NN / 4); break;
           case OP_PROLONG: nb = (int)nblk(3 * NN); break;
@@ -689,6 +691,7 @@ int upload_tables(ibmg_batch* B) {
 }
 
 int capture(ibmg_batch* B) {
+  std::lock_guard<std::mutex> capture_lock(capture_mutex());
   IBMG_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
   if (B->prec == IBMG_FP32) bvcycle<float>(B, B->cap);
   else bvcycle<double>(B, B->cap);

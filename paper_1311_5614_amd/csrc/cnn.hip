@@ -345,6 +345,7 @@ struct ibmg_cnn {
   size_t o_theta = 0, o_m = 0, o_v = 0, o_grad = 0, o_wf[kLayers] = {}, o_wb[kLayers] = {}, o_bias[kLayers] = {};
   size_t o_act[kLayers] = {}, o_dz[2] = {}, o_y = 0, o_part = 0, o_partb = 0, o_lpart = 0, o_loss = 0;
   size_t o_scale = 0, o_sumsq = 0, o_pairs = 0;
+  size_t o_traj = 0;   // features (6 planes), w^n, dw^{n-1}, proposal, dw^n (3 planes each), FP64
   template <typename T> T* d(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   WeightViews views() const {
     WeightViews V;
@@ -416,7 +417,51 @@ int compute_scales(ibmg_cnn* C) {
 
 }  // namespace
 
+namespace ibmg {
+
+int cnn_traj(ibmg_cnn* C, CnnTraj* t) {
+  if (!C || !C->ws || !t) return IBMG_ENOMEM;
+  const size_t P = C->P;
+  double* base = C->d<double>(C->o_traj);
+  t->N = C->N;
+  t->stream = C->stream;
+  t->feat = base;
+  t->wold = base + 6 * P;
+  t->dprev = base + 9 * P;
+  t->x0 = base + 12 * P;
+  t->dw = base + 15 * P;
+  return IBMG_OK;
+}
+
+}  // namespace ibmg
+
 extern "C" {
+
+int ibmg_guess_reset(ibmg_cnn* C) {
+  if (!C || !C->ws) return IBMG_ENOMEM;
+  // a new trajectory: no previous increment
+  k_fill<double><<<nblk(3 * (size_t)C->P), 256, 0, C->stream>>>(C->d<double>(C->o_traj) + 9 * (size_t)C->P,
+                                                                 3 * (size_t)C->P, 0.0);
+  IBMG_HIP(hipGetLastError());
+  return IBMG_OK;
+}
+
+int ibmg_guess_get_increment(ibmg_cnn* C, double* dw3) {
+  if (!C || !C->ws) return IBMG_ENOMEM;
+  if (!dw3) return IBMG_EINVAL;
+  IBMG_HIP(hipMemcpyAsync(dw3, C->d<double>(C->o_traj) + 9 * (size_t)C->P, 3 * (size_t)C->P * sizeof(double),
+                          hipMemcpyDeviceToDevice, C->stream));
+  IBMG_HIP(hipStreamSynchronize(C->stream));
+  return IBMG_OK;
+}
+
+int ibmg_guess_set_increment(ibmg_cnn* C, const double* dw3) {
+  if (!C || !C->ws) return IBMG_ENOMEM;
+  if (!dw3) return IBMG_EINVAL;
+  IBMG_HIP(hipMemcpyAsync(C->d<double>(C->o_traj) + 9 * (size_t)C->P, dw3, 3 * (size_t)C->P * sizeof(double),
+                          hipMemcpyDeviceToDevice, C->stream));
+  return IBMG_OK;
+}
 
 int ibmg_cnn_create(ibmg_cnn** out, int32_t N, int32_t max_pairs, void* stream) {
   if (!out) return IBMG_EINVAL;
@@ -457,6 +502,7 @@ int ibmg_cnn_create(ibmg_cnn** out, int32_t N, int32_t max_pairs, void* stream) 
   C->o_loss = take(4 * sizeof(float));
   C->o_scale = take(8 * sizeof(float));
   C->o_sumsq = take(8 * sizeof(double));
+  C->o_traj = take(18 * P * sizeof(double));   // zeroed at bind: dw^{-1} = 0
   C->o_pairs = take((size_t)max_pairs * 8 * P * sizeof(float));
   C->need = cur + 256;
   *out = C;

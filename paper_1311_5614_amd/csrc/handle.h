@@ -2,6 +2,7 @@
 // the batched ABI (batch.hip): the handle, its workspace layout and the
 // level views handed to the kernels.
 #pragma once
+#include <mutex>
 #include <vector>
 
 #include "../../include/ibmg.h"
@@ -13,7 +14,7 @@ constexpr int kPW = 16;          // panel width of the coarse Gauss-Jordan (dens
 constexpr int kDotBlocks = 256;  // workgroups of the deterministic dot products
 constexpr int kMaxTimed = 8192;  // timed phase launches per solve
 constexpr int kFallbackWindow = 20;  // FP32 V-cycle stall test: < 10% progress over this many iterations
-constexpr int kMaxBasis = 200;      // largest Krylov basis (restart length)
+constexpr int kMaxBasis = 1000;     // largest Krylov basis (restart length)
 constexpr int kMaxIters = 1000000;  // largest iteration cap with restarts
 constexpr int kSmallLevel = 32;  // default (and largest) level size run in one workgroup per V-cycle leg
 
@@ -42,6 +43,7 @@ struct ibmg_handle {
   // problem and options
   int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 2, nu2 = 2, maxit = 100, prec = 0, guess = 0;
   int ncol = 2;
+  int ncol_l[IBMG_MAX_LEVELS] = {};   // colour classes of each level's sweeps
   int mb = 100;   // Krylov basis size: the FGMRES(m) restart length (maxit caps the iterations of all cycles)
   int tail_max = ibmg::kSmallLevel;   // largest level size run by the LDS-resident tail
   double rho = 1, mu = 1, K = 0, rtol = 1e-8;
@@ -99,7 +101,7 @@ inline LevelView<T> view(const ibmg_handle* h, int l) {
   v.nb = B.nb;
   v.n = h->n;
   v.ndof = h->ndof;
-  v.ncol = h->ncol;
+  v.ncol = h->ncol_l[l];
   const double hl = 1.0 / B.N;
   v.c = (T)(h->rho / h->dt);
   v.muh2 = (T)(h->mu / (hl * hl));
@@ -157,6 +159,18 @@ inline size_t tail_lds(const ibmg_handle* h, size_t elem) {
   size_t lds = ls < h->levels - 1 ? (size_t)h->ndof * h->ndof * elem : 0;
   for (int l = ls; l < h->levels; ++l) lds += 9 * (size_t)h->L[l].N * h->L[l].N * elem;
   return lds;
+}
+
+// Graph capture and instantiation are serialised over the process: handles
+// driven from several host threads (one stream each) then never capture or
+// instantiate at the same time.  The HIP runtime allows concurrent
+// thread-local captures, but a kernel-tracing profiler that intercepts the
+// capture and instantiate calls faulted on the host when eight threads did so
+// together; the lock costs nothing outside that moment (captures happen once
+// per time-step size or when the active set outgrows a captured launch).
+inline std::mutex& capture_mutex() {
+  static std::mutex m;
+  return m;
 }
 
 void layout(ibmg_handle* h);

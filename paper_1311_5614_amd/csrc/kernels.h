@@ -31,9 +31,36 @@ __global__ void __launch_bounds__(256) k_vcycle_in(const double* __restrict__ r,
   }
 }
 
+// out = a + sb b (+ sc c when c is given), elementwise over n: the FP64
+// vector sums of the learned initial iterate (proposal, increment, target).
+// (out may be c: each lane reads its entries before it writes)
+__global__ void __launch_bounds__(256) static k_lincomb(double* out, const double* __restrict__ a,
+                                                       const double* __restrict__ b, double sb, const double* c,
+                                                       double sc, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = a[i] + sb * b[i];
+  if (c) x += sc * c[i];
+  out[i] = x;
+}
+
+struct ibmg_cnn;
+
 namespace ibmg {
 
 inline unsigned nblk(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// Trajectory state a warm-start network handle keeps for ibmg_guess_step
+// (device FP64 planes of N x N): the step's features (u, v, p, then the spread
+// elastic force on u and v faces, and a sixth plane the spreading pass also
+// writes), w^n, the previous increment dw^{n-1}, the proposal and the new
+// increment.
+struct CnnTraj {
+  int N = 0;
+  hipStream_t stream = nullptr;
+  double *feat = nullptr, *wold = nullptr, *dprev = nullptr, *x0 = nullptr, *dw = nullptr;
+};
+int cnn_traj(ibmg_cnn* c, CnnTraj* t);
 
 // ib_setup.hip
 void launch_fiber_force(hipStream_t s, int M, const int* prev, const int* next, double K,
@@ -72,6 +99,12 @@ template <typename T> void launch_residual(hipStream_t s, const LevelView<T>& L,
                                            bool ib);
 template <typename T> void launch_res(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r, bool ib);
 template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, const T* r, T* w, int colour, bool ib);
+// ib_rows: evaluate the elastic rows first (false only to time the box launch alone)
+template <typename T> void launch_phase_fused(hipStream_t s, const LevelView<T>& L, const T* b, T* w, int colour,
+                                              bool ib, bool ib_rows = true);
+// A colour phase may run as one box launch that forms its own Stokes residuals
+// (launch_phase_fused) when boxes of one colour are two boxes apart.
+inline bool phase_fusable(int ncol, int n) { return ncol == 4 && (n == 2 || n == 4); }
 // yf (nullable): elastic term of the fine residual (rf - yf is restricted)
 template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero,
                                            const T* yf = nullptr);

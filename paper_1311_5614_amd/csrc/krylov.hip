@@ -162,7 +162,8 @@ __global__ void __launch_bounds__(256)
 k_update_acc(const double* __restrict__ V, size_t ldv, int nvec, const double* __restrict__ coef,
              double* __restrict__ w, size_t n, double* __restrict__ acc) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (acc && blockIdx.x == 0 && (int)threadIdx.x < nvec) acc[threadIdx.x] += coef[threadIdx.x];
+  if (acc && blockIdx.x == 0)
+    for (int t = threadIdx.x; t < nvec; t += blockDim.x) acc[t] += coef[t];
   if (e >= n) return;
   double s = 0.0;
   // unrolled so that eight basis loads are in flight; the sum keeps its order
@@ -177,7 +178,7 @@ k_update_acc(const double* __restrict__ V, size_t ldv, int nvec, const double* _
 // rotations are first staged in LDS by the whole workgroup, so the serial
 // chain of rotations (thread 0, same operations in the same order as
 // k_givens) reads LDS instead of waiting on a global load per rotation.
-constexpr int kGivensMax = 256;   // >= the largest Krylov dimension + 2
+constexpr int kGivensMax = 1024;  // >= the largest Krylov dimension + 2
 __global__ void __launch_bounds__(256)
 k_scale_givens(double* __restrict__ w, size_t n, const double* __restrict__ nrm2, double* __restrict__ H, int ldh,
                double* __restrict__ g, double* __restrict__ cs, double* __restrict__ sn, int j,

@@ -146,7 +146,16 @@ constexpr int kBoxWavesMax = 4;          // waves per workgroup on the large lev
 constexpr int kBoxWaveTarget = 16384;    // waves per launch beyond which a wave takes several groups of boxes
 constexpr int kBoxGroupMin = 16384;      // boxes per colour from which a wave takes 4x4 boxes four at a time (levels without elastic rows)
 
-template <typename T, int NB, int W = 1, int B = 1>
+// F (fused): r is the level's right-hand side b, and each lane forms the
+// Stokes residual of its unknown itself, b - (Stokes part of A) w, from the
+// iterate at the start of the phase -- the same expression the residual pass
+// evaluates, so the result is bitwise that of the two-launch phase.  Valid
+// only where no box of the colour reads an unknown another box of the colour
+// writes: four colours ((bx mod 2, by mod 2)) and boxes of at least 2 x 2
+// cells put two boxes' width between boxes of one colour, more than the
+// one-cell reach of the stencil.  The elastic rows still come from the
+// elastic-row pass before the phase (their windows reach farther).
+template <typename T, int NB, int W = 1, int B = 1, bool F = false>
 __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
                                   int q0, int nper = 1, int cnt = 0x7fffffff) {
   constexpr int ND = 2 * NB * (NB + 1) + NB * NB;
@@ -190,7 +199,8 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
         int i, j;
         box_dof(lane, bx, by, NB, N, comp, i, j);
         g[b] = (size_t)comp * NN + (size_t)j * N + i;
-        y[b] = r[g[b]];
+        if constexpr (F) y[b] = r[g[b]] - stokes_row(L, w, comp, i, j);
+        else y[b] = r[g[b]];
         wv[b] = w[g[b]];
         // zero off the active rows.  One box per wave: loaded whatever the
         // box's class, so that no load waits for another (the launch is

@@ -39,11 +39,11 @@ k_res_ib(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* __
 // W waves per workgroup: several on the large levels (fewer workgroups to
 // dispatch), one where the colour has too few boxes to fill the chip that way.
 // Each wave takes B nper consecutive boxes of the colour, B at a time.
-template <typename T, int NB, int W, int B = 1>
+template <typename T, int NB, int W, int B = 1, bool F = false>
 __global__ void __launch_bounds__(64 * W)
 k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour, int cnt, int nper) {
   const int q = (xcd_remap(blockIdx.x, gridDim.x) * W + (int)(threadIdx.x >> 6)) * nper * B;
-  if (q < cnt) box_body_n<T, NB, W, B>(L, r, w, colour, q, nper, cnt);
+  if (q < cnt) box_body_n<T, NB, W, B, F>(L, r, w, colour, q, nper, cnt);
 }
 template <typename T>
 __global__ void __launch_bounds__(kBigBoxLanes)
@@ -161,6 +161,32 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
     else k_box<T, 1, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt, 1);
   }
 }
+// A colour phase in one box launch (plus the elastic-row pass on levels with
+// elastic rows): the boxes form their Stokes residuals themselves from b and
+// the iterate (box_body_n with F).  For four colours and 2 x 2 or 4 x 4 boxes.
+template <typename T> void launch_phase_fused(hipStream_t s, const LevelView<T>& L, const T* b, T* w, int colour,
+                                              bool ib, bool ib_rows) {
+  LevelView<T> V = L;
+  if (ib && ib_rows) k_ib_rows<T><<<dim3(ib_blocks(L.rowhint), 2), 256, 0, s>>>(L, w, nullptr, 0);
+  if (!ib) V.ib_index = nullptr;
+  const int cnt = colour_count(L.ncol, L.nb);
+  if (cnt >= kBoxWavesMax * 512) {
+    const int B = (L.n == 4 && !ib && cnt >= kBoxGroupMin) ? 4 : 1;
+    const int groups = (cnt + B - 1) / B;
+    const int nper = (B > 1 && groups > kBoxWaveTarget) ? groups / kBoxWaveTarget : 1;
+    const int waves = (groups + nper - 1) / nper;
+    const int grid = (waves + kBoxWavesMax - 1) / kBoxWavesMax;
+    if (L.n == 4) {
+      if (B == 4) k_box<T, 4, kBoxWavesMax, 4, true><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, b, w, colour, cnt, nper);
+      else k_box<T, 4, kBoxWavesMax, 1, true><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, b, w, colour, cnt, nper);
+    } else {
+      k_box<T, 2, kBoxWavesMax, 1, true><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, b, w, colour, cnt, nper);
+    }
+  } else {
+    if (L.n == 4) k_box<T, 4, 1, 1, true><<<cnt, 64, 0, s>>>(V, b, w, colour, cnt, 1);
+    else k_box<T, 2, 1, 1, true><<<cnt, 64, 0, s>>>(V, b, w, colour, cnt, 1);
+  }
+}
 template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero, const T* yf) {
   k_restrict<T><<<nblk(3 * (size_t)(Nf / 2) * (Nf / 2)), 256, 0, s>>>(Nf, rf, rc, wc_zero, yf);
 }
@@ -207,6 +233,7 @@ void launch_interp(hipStream_t s, const PointView& P, const double* u, const dou
   template void launch_residual<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, bool);     \
   template void launch_res<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, bool);         \
   template void launch_box<T>(hipStream_t, const LevelView<T>&, const T*, T*, int, bool);             \
+  template void launch_phase_fused<T>(hipStream_t, const LevelView<T>&, const T*, T*, int, bool, bool);  \
   template void launch_restrict<T>(hipStream_t, int, const T*, T*, T*, const T*);                                 \
   template void launch_prolong_add<T>(hipStream_t, int, const T*, T*);                                  \
   template int launch_tail<T>(hipStream_t, const LevelView<T>*, int, int, int, int, bool, int, const T*, T*,   \

@@ -24,6 +24,8 @@ IBMG_EINVAL, IBMG_ESHAPE, IBMG_EHIP, IBMG_ENOMEM, IBMG_ENONFINITE, IBMG_ESTATE =
 IBMG_DELTA_IB4, IBMG_DELTA_COS4 = 0, 1
 IBMG_FP64, IBMG_FP32 = 0, 1
 IBMG_GUESS_ZERO, IBMG_GUESS_PREV = 0, 1
+IBMG_KERNEL_BOX, IBMG_KERNEL_RES, IBMG_KERNEL_MULTIDOT, IBMG_KERNEL_UPDATE = 0, 1, 2, 3
+IBMG_GUESS_RECORD, IBMG_GUESS_EXTRAP, IBMG_GUESS_LEARNED = 0, 1, 2
 
 EXPORTS = [
     "ibmg_create", "ibmg_workspace_bytes", "ibmg_bind_workspace", "ibmg_destroy",
@@ -36,6 +38,8 @@ EXPORTS = [
     "ibmg_cnn_create", "ibmg_cnn_workspace_bytes", "ibmg_cnn_bind_workspace", "ibmg_cnn_set_params",
     "ibmg_cnn_get_params", "ibmg_cnn_set_scales", "ibmg_cnn_get_scales", "ibmg_cnn_record", "ibmg_cnn_pairs",
     "ibmg_cnn_train", "ibmg_cnn_infer", "ibmg_cnn_loss_grad", "ibmg_cnn_destroy", "ibmg_spread_noalloc",
+    "ibmg_kernel_bench", "ibmg_guess_step", "ibmg_guess_reset", "ibmg_guess_get_increment",
+    "ibmg_guess_set_increment",
 ]
 
 
@@ -49,7 +53,7 @@ class ibmg_opts(C.Structure):
     _fields_ = [("levels", C.c_int32), ("box", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("maxit", C.c_int32), ("rtol", C.c_double), ("vcycle_prec", C.c_int32),
                 ("guess", C.c_int32), ("colours", C.c_int32), ("tail_max", C.c_int32),
-                ("restart", C.c_int32)]
+                ("restart", C.c_int32), ("colours_from", C.c_int32)]
 
 
 class ibmg_stats(C.Structure):
@@ -114,6 +118,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ibmg_cnn_loss_grad": [vp, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)],
         "ibmg_cnn_destroy": [vp],
         "ibmg_spread_noalloc": [i32, i32, i32, vp, vp, vp, vp, vp],
+        "ibmg_kernel_bench": [vp, i32, i32, i32, i32, C.POINTER(dbl), C.POINTER(dbl)],
+        "ibmg_guess_step": [vp, vp, i32, dbl, vp, vp, vp, vp, vp, vp, C.POINTER(ibmg_stats)],
+        "ibmg_guess_reset": [vp],
+        "ibmg_guess_get_increment": [vp, vp],
+        "ibmg_guess_set_increment": [vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -172,6 +181,7 @@ class Config:
     colours: int = 2
     tail_max: int = 0
     restart: int = 0
+    colours_from: int = 0
 
 
 def _problem(cfg: Config, fiber_offsets):
@@ -182,7 +192,7 @@ def _problem(cfg: Config, fiber_offsets):
     prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, M, max(0, len(offs) - 1),
                         C.cast(arr, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
     opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
-                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart)
+                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart, cfg.colours_from)
     return prob, opts, arr, M
 
 
@@ -232,6 +242,16 @@ class Solver:
         st = ibmg_stats()
         code = _check(lib().ibmg_step_x0(self.h, float(dt), _ptr(u), _ptr(v), _ptr(p), _ptr(X),
                                          _ptr(g_u), _ptr(g_v), _ptr(x0), C.byref(st)), "ibmg_step_x0")
+        d = st.as_dict()
+        d["status"] = code
+        return d
+
+    def guess_step(self, net, mode, dt, u, v, p, X, g_u=None, g_v=None):
+        """One step with the learned-iterate machinery of `net` (ibmg_guess_step;
+        mode IBMG_GUESS_RECORD / _EXTRAP / _LEARNED)."""
+        st = ibmg_stats()
+        code = _check(lib().ibmg_guess_step(self.h, net.h, int(mode), float(dt), _ptr(u), _ptr(v), _ptr(p),
+                                            _ptr(X), _ptr(g_u), _ptr(g_v), C.byref(st)), "ibmg_guess_step")
         d = st.as_dict()
         d["status"] = code
         return d
@@ -313,6 +333,14 @@ class Solver:
     def box_bench(self, level, colour, reps):
         us, by = C.c_double(), C.c_double()
         _check(lib().ibmg_box_bench(self.h, level, colour, reps, C.byref(us), C.byref(by)), "ibmg_box_bench")
+        return us.value, by.value
+
+    def kernel_bench(self, kernel, level, arg, reps):
+        """(mean microseconds per launch, algorithmic bytes per launch) of one
+        hot-path kernel replayed `reps` times (ibmg_kernel_bench)."""
+        us, by = C.c_double(), C.c_double()
+        _check(lib().ibmg_kernel_bench(self.h, kernel, level, arg, reps, C.byref(us), C.byref(by)),
+               "ibmg_kernel_bench")
         return us.value, by.value
 
     def set_timing(self, on=True):
@@ -414,6 +442,18 @@ class Cnn:
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         _check(L.ibmg_cnn_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value),
                "ibmg_cnn_bind_workspace")
+
+    def reset(self):
+        """Forget the previous step increment (ibmg_guess_reset)."""
+        _check(lib().ibmg_guess_reset(self.h), "ibmg_guess_reset")
+
+    def get_increment(self):
+        dw = torch.empty(3 * self.N * self.N, dtype=torch.float64, device=self.device)
+        _check(lib().ibmg_guess_get_increment(self.h, _ptr(dw)), "ibmg_guess_get_increment")
+        return dw
+
+    def set_increment(self, dw):
+        _check(lib().ibmg_guess_set_increment(self.h, _ptr(dw)), "ibmg_guess_set_increment")
 
     def close(self):
         if getattr(self, "h", None):

@@ -162,48 +162,98 @@ def test_guarded_step():
     assert float((u2 - u0).abs().max()) <= 1e-9 * float(u0.abs().max())
 
 
-def test_learned_guess_gain_on_a_trajectory():
-    """Train on the first steps of a 64x64 trajectory, then compare the
-    remaining steps started from w^n + alpha Dw against the same steps started
-    from w^n: the guard keeps every start at or below the residual of w^n, and
-    the solves need no more iterations in total."""
+def _traj_case():
     from paper_1311_5614_amd import ibmg
+    from oracle import dtexp
     N, M = 64, 160
     w = ibgen.small_case(N=N, M=M, K=1e5, seed=21, levels=5, with_force=True)
-    from oracle import dtexp
     dt = 200.0 * dtexp.dt_explicit(w.X, w.fiber_offsets, N, 1e5)
     cfg = ibmg.Config(N=N, levels=5, K=1e5, rtol=1e-8, maxit=200, guess=ibmg.IBMG_GUESS_PREV)
     s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    return w, dt, s
+
+
+def test_guess_step_matches_its_definition():
+    """ibmg_guess_step forms its features, proposals, increments and targets
+    on the device; the same step built by hand from the C ABI's pieces (the
+    spreading of the fibre force, the network's inference, ibmg_step_x0, and
+    vector sums in the same association) gives bit for bit the same state:
+    recording mode = a step from w^n, extrapolation = x0 = w^n + dw^{n-1},
+    learned = x0 = (w^n + dw^{n-1}) + F(u, v, p, S_0 G^n)."""
+    from paper_1311_5614_amd import ibmg
+    w, dt, s = _traj_case()
+    N = w.N
+    net = ibmg.Cnn(N, 8, DEV)
+    net.set_params(ibgen.cnn_init(5))
+    z = torch.zeros(N, N, dtype=torch.float64, device=DEV)
+    gu, gv = tdev(w.g_u), tdev(w.g_v)
+    a = [z.clone(), z.clone(), z.clone(), tdev(w.X)]     # through ibmg_guess_step
+    b = [z.clone(), z.clone(), z.clone(), tdev(w.X)]     # by hand
+    net.reset()
+    dprev = torch.zeros(3 * N * N, dtype=torch.float64, device=DEV)
+    feats = []
+    for n in range(3):                                    # recording from w^n
+        G = s.fiber_force(b[3])
+        fu, fv = s.spread(b[3], G)
+        feats.append(torch.stack([b[0], b[1], b[2], fu, fv]).contiguous())
+        old = torch.cat([t.reshape(-1) for t in b[:3]])
+        sa = s.guess_step(net, ibmg.IBMG_GUESS_RECORD, dt, *a, gu, gv)
+        sb = s.step(dt, *b, gu, gv)
+        assert sa["iters"] == sb["iters"]
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+        dprev = torch.cat([t.reshape(-1) for t in b[:3]]) - old
+    assert net.pairs() == 3
+    assert torch.equal(net.get_increment(), dprev)
+    net.train(2, 1e-3)                                    # sets the scales
+    for mode in (ibmg.IBMG_GUESS_EXTRAP, ibmg.IBMG_GUESS_LEARNED):
+        old = torch.cat([t.reshape(-1) for t in b[:3]])
+        x0 = old + dprev
+        if mode == ibmg.IBMG_GUESS_LEARNED:
+            G = s.fiber_force(b[3])
+            fu, fv = s.spread(b[3], G)
+            x0 = x0 + net.infer(torch.stack([b[0], b[1], b[2], fu, fv]).contiguous()).reshape(-1)
+        sa = s.guess_step(net, mode, dt, *a, gu, gv)
+        sb = s.step_x0(dt, *b, x0.contiguous(), gu, gv)
+        assert sa["iters"] == sb["iters"] and sa["guess_alpha"] == sb["guess_alpha"]
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+        dprev = torch.cat([t.reshape(-1) for t in b[:3]]) - old
+        assert torch.equal(net.get_increment(), dprev)
+
+
+def test_learned_guess_against_extrapolation_on_a_trajectory():
+    """Train on the first 30 steps of a 64x64 trajectory (pairs recorded by
+    ibmg_guess_step), then run the next 10 steps three ways from the same
+    state: learned (w^n + dw^{n-1} + network), extrapolation alone
+    (w^n + dw^{n-1}) and from w^n.  The guard keeps every proposal's start
+    at or below the residual of w^n, so both warm starts need no more
+    iterations than w^n in total; what the network adds over extrapolation is
+    printed (the honest comparison: it may be nothing) and bounded by a
+    small loss."""
+    from paper_1311_5614_amd import ibmg
+    w, dt, s = _traj_case()
+    N = w.N
     net = ibmg.Cnn(N, 40, DEV)
     net.set_params(ibgen.cnn_init(5))
     z = torch.zeros(N, N, dtype=torch.float64, device=DEV)
-    u, v, p, X = z.clone(), z.clone(), z.clone(), tdev(w.X)
+    st0 = [z.clone(), z.clone(), z.clone(), tdev(w.X)]
     gu, gv = tdev(w.g_u), tdev(w.g_v)
-
-    def features():
-        G = s.fiber_force(X)
-        fu, fv = s.spread(X, G)
-        return torch.stack([u, v, p, fu, fv]).contiguous()
-
+    net.reset()
     for _ in range(30):
-        f = features()
-        old = torch.stack([u, v, p]).clone()
-        s.step(dt, u, v, p, X, gu, gv)
-        net.record(f, (torch.stack([u, v, p]) - old).contiguous())
+        s.guess_step(net, ibmg.IBMG_GUESS_RECORD, dt, *st0, gu, gv)
     lf, ll = net.train(30, 1e-3)
-    assert ll < lf
-    it_prev, it_cnn, rejected, alphas = 0, 0, 0, []
-    for _ in range(10):
-        f = features()
-        state = [t.clone() for t in (u, v, p, X)]
-        st = s.step(dt, *state, gu, gv)           # started from w^n
-        it_prev += st["iters"]
-        x0 = (torch.stack([u, v, p]) + net.infer(f)).reshape(-1).contiguous()
-        st2 = s.step_x0(dt, u, v, p, X, x0, gu, gv)
-        it_cnn += st2["iters"]
-        rejected += st2["guess_rejected"]
-        alphas.append(round(st2["guess_alpha"], 3))
-        assert st2["converged"] == 1
-    print(f"learned guess: iterations {it_cnn} vs {it_prev} from w^n, {rejected}/10 proposals dropped, "
-          f"alpha {alphas}, loss {lf:.3e} -> {ll:.3e}")
-    assert it_cnn <= it_prev
+    d0 = net.get_increment()
+    its = {}
+    for form, mode in (("learned", ibmg.IBMG_GUESS_LEARNED), ("extrap", ibmg.IBMG_GUESS_EXTRAP), ("prev", None)):
+        state = [t.clone() for t in st0]
+        net.set_increment(d0)
+        its[form] = 0
+        for _ in range(10):
+            st = s.step(dt, *state, gu, gv) if mode is None else s.guess_step(net, mode, dt, *state, gu, gv)
+            assert st["converged"] == 1
+            its[form] += st["iters"]
+    print(f"iterations over 10 steps: learned {its['learned']}, extrapolation {its['extrap']}, from w^n "
+          f"{its['prev']}; training loss {lf:.3e} -> {ll:.3e}")
+    assert its["learned"] <= its["prev"] and its["extrap"] <= its["prev"]
+    assert its["learned"] <= its["extrap"] + 5

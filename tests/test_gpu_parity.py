@@ -550,3 +550,22 @@ def test_restarted_fgmres_matches_oracle(restart, prec):
         xo[2 * 4096:] -= xo[2 * 4096:].mean()
         xg[2 * 4096:] -= xg[2 * 4096:].mean()
         assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-9
+
+
+@pytest.mark.parametrize("colours_from,levels", [(1, 4), (2, 5)])
+def test_vcycle_parity_per_level_colours(colours_from, levels):
+    """Four colours on the finer levels and the checkerboard from level
+    `colours_from` on (Algorithm 1 fixes no box order per level), against the
+    oracle's VCycle with the same order per level."""
+    from paper_1311_5614_amd import ibmg
+    w, dt, s = make(N=64, levels=levels, M=150, K=1e5, dt_factor=100.0)
+    s.close()
+    cfg = ibmg.Config(N=64, levels=levels, K=1e5, colours=4, colours_from=colours_from, tail_max=1, rtol=1e-10)
+    s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    _setup(s, w, dt)
+    lv = oracle_levels(w, dt, levels, 1e5)
+    modes = ["colour" if l < colours_from else "colour2" for l in range(levels - 1)]
+    V = mg.VCycle(lv, 4, 2, 2, modes)
+    r = np.random.default_rng(42).standard_normal(3 * 64 * 64)
+    r[2 * 4096:] -= r[2 * 4096:].mean()
+    assert rel(tnp(s.vcycle(tdev(r))), V(r)) < 1e-11

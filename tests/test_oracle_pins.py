@@ -444,6 +444,29 @@ def test_coarse_bordered_solve():
     assert abs(x[2 * Nc * Nc:].mean()) < 1e-13
 
 
+def test_vcycle_box_order_per_level():
+    """A box order given per level applies level by level: one order for every
+    level repeats the single-order V-cycle bit for bit, and a mixed one equals
+    the V-cycle assembled from the two by hand (level 0's sweeps of the first
+    order around a coarse correction whose sweeps take the second)."""
+    w, dt, lv = _small(N=16, levels=3)
+    r = rng.standard_normal(3 * 256)
+    r[512:] -= r[512:].mean()
+    a = mg.VCycle(lv, 2, 1, 1, "colour")(r)
+    b = mg.VCycle(lv, 2, 1, 1, ["colour", "colour"])(r)
+    assert np.array_equal(a, b)
+    mixed = mg.VCycle(lv, 2, 1, 1, ["colour", "colour2"])
+    one = mg.VCycle(lv, 2, 1, 1, "colour")
+    two = mg.VCycle(lv, 2, 1, 1, "colour2")
+    w0 = one.smoothers[0].sweep(np.zeros_like(r), r, "colour")
+    r1 = lv[0].R @ (r - lv[0].A @ w0)
+    e1 = two.mgv(np.zeros_like(r1), r1, 1)
+    ref = one.smoothers[0].sweep(w0 + lv[0].P @ e1, r, "colour")
+    assert np.array_equal(mixed(r), ref)
+    with pytest.raises(ValueError):
+        mg.VCycle(lv, 2, 1, 1, ["colour"])
+
+
 @pytest.mark.parametrize("mode", ["colour2", "colour", "paper"])
 def test_mg_iteration_matrix_contracts(mode):
     """Spectral radius of the V-cycle iteration matrix on the mean-zero
