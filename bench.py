@@ -36,8 +36,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MAXIT = 200          # Krylov basis size: no restart below 200 iterations
-MAXIT_TOTAL = 1000   # iteration cap of the sweep's and the batch's solves (FGMRES(200) restarts past 200)
+MAXIT = 200          # Krylov basis of the batch and the learned trajectory: FGMRES(200)
+MAXIT_TOTAL = 1000   # iteration cap of every solve; the 256x256 sweep keeps a basis of this size (no
+                     # restart: restarted FGMRES stagnates on its hardest steps)
+C3_BASIS = 600       # Krylov basis of both 1024x1024 forms (30 GB with the preconditioned directions)
 BOX_REPS = 200   # back-to-back box launches timed for the roofline
 METRIC = "IB time-steps/sec and FGMRES iters/solve at rel resid 1e-8, plain vs chosen"
 
@@ -130,8 +132,9 @@ class Run:
         from paper_1311_5614_amd import ibmg
         self.w, self.dt = w, dt
         cfg = ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=w.box, nu1=w.nu1,
-                          nu2=w.nu2, maxit=MAXIT_TOTAL, restart=MAXIT, rtol=w.rtol, prec=prec,
-                          colours=getattr(w, "colours", 2), tail_max=getattr(w, "tail_max", 0))
+                          nu2=w.nu2, maxit=MAXIT_TOTAL, restart=0, rtol=w.rtol, prec=prec,
+                          colours=getattr(w, "colours", 2), tail_max=getattr(w, "tail_max", 0),
+                          colours_from=getattr(w, "colours_from", 0))
         self.s = ibmg.Solver(cfg, w.fiber_offsets, dev, stream=stream)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
         self.X0 = t(w.X)
@@ -432,25 +435,42 @@ def c3_schedule():
     return autotune.load()["c3"]["1024"]
 
 
+C3_FORMS = ("chosen", "plain", "chosen_zero_start", "chosen_fp32")
+
+
 def c3_config(form):
-    """Solver options of a form on the 1024x1024 workload."""
+    """Solver options of a form on the 1024x1024 workload: plain (FP64 V-cycle,
+    default schedule, zero start), chosen (the autotuned schedule and its
+    start rule), and for attribution the chosen schedule from a zero start and
+    with the FP32 V-cycle."""
+    import dataclasses
     from paper_1311_5614_amd import ibmg
     import ibgen
+    if form == "chosen_zero_start":
+        return dataclasses.replace(c3_config("chosen"), guess=ibmg.IBMG_GUESS_ZERO)
+    if form == "chosen_fp32":
+        return dataclasses.replace(c3_config("chosen"), prec=ibmg.IBMG_FP32)
     w = ibgen.config_c3()
     if form == "plain":
         return ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2,
-                           maxit=MAXIT_TOTAL, restart=MAXIT, rtol=w.rtol, prec=ibmg.IBMG_FP64, colours=2, tail_max=0)
+                           maxit=MAXIT_TOTAL, restart=C3_BASIS, rtol=w.rtol, prec=ibmg.IBMG_FP64, colours=2,
+                           tail_max=0)
     sch = c3_schedule()
     return ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, rho=w.rho, mu=w.mu, box=sch["box"], nu1=sch["nu1"],
-                       nu2=sch["nu2"], maxit=sch.get("maxit", MAXIT_TOTAL), restart=sch.get("restart", MAXIT), rtol=w.rtol,
-                       prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"])
+                       nu2=sch["nu2"], maxit=sch.get("maxit", MAXIT_TOTAL), restart=sch.get("restart", C3_BASIS), rtol=w.rtol,
+                       prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"],
+                       colours_from=sch.get("colours_from", 0), guess=sch.get("guess", 0))
 
 
 def describe(cfg):
     from paper_1311_5614_amd import ibmg
     rs = f"FGMRES({cfg.restart}), cap {cfg.maxit}" if cfg.restart else f"FGMRES, cap {cfg.maxit}"
+    order = (f"{cfg.colours} colours on levels 0-{cfg.colours_from - 1}, checkerboard below" if cfg.colours_from
+             else f"{cfg.colours} colours")
+    start = "previous step's solution" if cfg.guess == ibmg.IBMG_GUESS_PREV else "zero"
     return (f"{'FP32' if cfg.prec == ibmg.IBMG_FP32 else 'FP64'} V({cfg.nu1},{cfg.nu2}) V-cycle, {cfg.levels} levels, "
-            f"{cfg.box}x{cfg.box} boxes, {cfg.colours} colours, tail {cfg.tail_max or 32}, {rs}, FP64 Krylov")
+            f"{cfg.box}x{cfg.box} boxes, {order}, tail {cfg.tail_max or 32}, {rs}, FP64 Krylov, "
+            f"initial iterate {start}")
 
 
 def timed_trajectory(s, w, dt, dev, steps, warmup, repeats):
@@ -630,7 +650,7 @@ def run_c3(args, dev):
     leg = None if args.no_cpu else start_cpu_leg()
     w = ibgen.config_c3()
     dt = load_dt("c3")[0]["dt"]
-    forms = [f for f in args.forms.split(",") if f in ("plain", "chosen")] or ["chosen", "plain"]
+    forms = [f for f in args.forms.split(",") if f in C3_FORMS] or ["chosen", "plain"]
     res, solvers = {}, {}
     for form in forms:
         cfg = c3_config(form)
@@ -641,7 +661,12 @@ def run_c3(args, dev):
         print(f"[bench] c3 {form}: {r['rate']:.3f} steps/s (runs {r['runs_s']} s), iters mean "
               f"{r['iters_mean']:.1f} max {r['iters_max']}, missed rtol {r['missed_rtol']}/{r['steps_timed']}",
               file=sys.stderr, flush=True)
-        solvers[form] = (s, cfg)
+        if form == "chosen" or len(forms) == 1:
+            solvers[form] = (s, cfg)
+        else:
+            s.close()          # only the chosen form's state is timed further (its workspace is 30 GB)
+            del s
+            torch.cuda.empty_cache()
     chosen = "chosen" if "chosen" in res else forms[0]
     rc = res[chosen]
     s, cfg = solvers[chosen]
@@ -666,6 +691,85 @@ def run_c3(args, dev):
     if "plain" in res and chosen != "plain":
         out["speedup_vs_plain"] = rc["rate"] / res["plain"]["rate"]
     return out, leg
+
+
+def run_efficiency(args, dev, steps=20, probe_steps=60, sample=100):
+    """Implicit against explicit time stepping on the 256x256 single-ellipse
+    geometry (Sec. 7's comparison, on the periodic workload): per stiffness,
+    the wall time per unit of simulated time of the implicit method at
+    100 x dt_exp (tuned schedule) and of the explicit method (Sec. 2.3.1: the
+    force at X^n, a Stokes solve per step) at the largest multiple of dt_exp
+    among 1, 2, 4 whose run of `probe_steps` steps stays bounded, timed over
+    `sample` steps.  The ratio is the efficiency factor of Sec. 7 measured in
+    wall time on this GPU."""
+    import torch
+    from paper_1311_5614_amd import ibmg
+    cases, dts = workloads("c2")
+    tcases, precs = tuned("c2", cases)
+    out = {}
+    for k in (2, 4):                        # K = 1e4 and 1e6 at 100 x dt_exp
+        w, dt, prec = tcases[k], dts[k], precs[k]
+        dte = dt / w.dt_factor
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+        gu, gv = t(w.g_u), t(w.g_v)
+
+        def fresh():
+            z = torch.zeros(w.N, w.N, dtype=torch.float64, device=dev)
+            return z.clone(), z.clone(), z.clone(), t(w.X)
+
+        r = Run(w, dt, prec, dev)
+        for _ in range(2):
+            r.step()
+        r.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its_i = [r.step()["iters"] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t_imp = (time.perf_counter() - t0) / steps
+        r.s.close()
+        del r
+        cfg = ibmg.Config(N=w.N, levels=w.levels, K=w.K, rho=w.rho, mu=w.mu, box=4, nu1=2, nu2=2, maxit=200,
+                          rtol=w.rtol, prec=ibmg.IBMG_FP64, colours=2, scheme=ibmg.IBMG_EXPLICIT)
+        se = ibmg.Solver(cfg, w.fiber_offsets, dev)
+        f_ok = None
+        for f in (1.0, 2.0, 4.0):
+            u, v, p, X = fresh()
+            X0 = X.clone()
+            try:
+                for _ in range(probe_steps):
+                    se.step(f * dte, u, v, p, X, gu, gv)
+                bounded = float((X - X0).abs().max()) * w.N < 0.25 * w.N
+            except ibmg.IBMGError:
+                bounded = False
+            if not bounded:
+                break
+            f_ok = f
+        if f_ok is None:
+            out[f"K{w.K:.0e}"] = {"error": "explicit method unstable at dt_exp"}
+            se.close()
+            continue
+        u, v, p, X = fresh()
+        se.step(f_ok * dte, u, v, p, X, gu, gv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its_e = [se.step(f_ok * dte, u, v, p, X, gu, gv)["iters"] for _ in range(sample)]
+        torch.cuda.synchronize()
+        t_exp = (time.perf_counter() - t0) / sample
+        se.close()
+        per_time_imp = t_imp / dt                 # wall seconds per unit simulated time
+        per_time_exp = t_exp / (f_ok * dte)
+        out[f"K{w.K:.0e}"] = {
+            "implicit": {"dt_over_dt_exp": w.dt_factor, "ms_per_step": 1e3 * t_imp,
+                         "iters_mean": sum(its_i) / len(its_i), "schedule": "tuned (schedules.json c2)"},
+            "explicit": {"dt_over_dt_exp": f_ok, "ms_per_step": 1e3 * t_exp, "iters_mean": sum(its_e) / len(its_e),
+                         "stability": f"bounded over {probe_steps} steps at {f_ok:g} x dt_exp, "
+                                      f"{'not tried' if f_ok == 4.0 else 'unbounded'} above"},
+            "efficiency_factor": per_time_exp / per_time_imp}
+        print(f"[bench] efficiency K={w.K:.0e}: implicit {1e3 * t_imp:.2f} ms/step at {w.dt_factor:g} dt_exp, "
+              f"explicit {1e3 * t_exp:.2f} ms/step at {f_ok:g} dt_exp -> factor "
+              f"{out[f'K{w.K:.0e}']['efficiency_factor']:.1f}", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    return out
 
 
 PROBE_N = 4096   # bandwidth probe: plain V(2,2) with no structure on this grid
@@ -879,7 +983,7 @@ def main():
     if args.cpu_leg:
         return cpu_leg_c3()
     if not args.forms:
-        args.forms = "chosen,plain" if args.workload == "c3" else "concurrent,plain,fp32,tuned"
+        args.forms = ",".join(C3_FORMS) if args.workload == "c3" else "concurrent,plain,fp32,tuned"
     if args.copy_probe:
         import torch
         a = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
@@ -901,6 +1005,9 @@ def main():
         return
     if args.workload == "c5":
         return run_learned(args, dev)
+    if args.workload == "efficiency":
+        print(json.dumps({"efficiency": run_efficiency(args, dev)}))
+        return
     args.steps = args.steps or 20
     if args.workload == "c3":
         out, leg = run_c3(args, dev)
@@ -913,6 +1020,10 @@ def main():
                     extra[wl] = {k: r[k] for k in ("value", "unit", "ms_per_step", "config", "forms")}
                 except Exception as e:   # noqa: BLE001  (extra figures; the headline stands without them)
                     extra[wl] = {"error": f"{type(e).__name__}: {e}"}
+            try:
+                extra["implicit_vs_explicit"] = run_efficiency(args, dev)
+            except Exception as e:   # noqa: BLE001
+                extra["implicit_vs_explicit"] = {"error": f"{type(e).__name__}: {e}"}
             out["extra_workloads"] = extra
         if not args.no_probe:
             try:

@@ -71,6 +71,7 @@ enum { IBMG_DELTA_IB4 = 0,  /* Peskin's standard 4-point kernel                 
        IBMG_DELTA_COS4 = 1  /* cosine 4-point kernel printed in Sec. 2.2           */ };
 enum { IBMG_FP64 = 0, IBMG_FP32 = 1 };
 enum { IBMG_GUESS_ZERO = 0, IBMG_GUESS_PREV = 1 };
+enum { IBMG_IMPLICIT = 0, IBMG_EXPLICIT = 1 };
 
 typedef struct {
   int32_t N;                     /* cells per side, power of two >= 4               */
@@ -112,6 +113,11 @@ typedef struct {
   int32_t colours_from;/* 0: every smoothed level uses `colours`; k >= 1: levels
                           k and coarser use the checkerboard (2 colours), the
                           finer ones `colours` (the order may differ per level) */
+  int32_t scheme;      /* IBMG_IMPLICIT (the method: the elasticity operator in
+                          the system) or IBMG_EXPLICIT (Sec. 2.3.1: the force at
+                          X^n on the right-hand side only, the system is the
+                          Stokes operator; stable below the explicit limit of
+                          Sec. 4.1, the comparison of Sec. 7)                   */
 } ibmg_opts;
 
 typedef struct {

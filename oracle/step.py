@@ -1,4 +1,4 @@
-"""One implicit immersed-boundary time step (oracle, FP64).
+"""One implicit (or explicit) immersed-boundary time step (oracle, FP64).
 
 Sec. 2.3.2: with S^n = S[X^n] lagged, solve the Eulerian system for
 (u^{n+1}, p^{n+1}) (forces at the new positions eliminated), then move the
@@ -6,6 +6,11 @@ structure, X^{n+1} = X^n + dt S^{n*} u^{n+1}.  The solve is multigrid-
 preconditioned FGMRES (Sec. 3.3) with the hybrid coarse operators of
 Sec. 3.2 and box smoothing of Sec. 5-6.  The output pressure is shifted to
 zero mean (it is defined only up to a constant).
+
+The explicit method (Sec. 2.3.1, the comparison of Sec. 7) takes the
+elastic force at X^n on the right-hand side only: the same Eulerian solve
+without the elasticity operator M_0 in the matrix, then the same position
+update.  It is stable only below the explicit limit (Sec. 4.1).
 """
 from __future__ import annotations
 
@@ -31,16 +36,20 @@ class StepResult:
 
 
 def build(N, levels, rho, mu, dt, X, fiber_offsets, K, box=4, nu1=2, nu2=2,
-          mode="colour2", kind=ib.DELTA_IB4):
-    lv = system.hierarchy(N, levels, rho, mu, dt, X, fiber_offsets, K, kind)
+          mode="colour2", kind=ib.DELTA_IB4, scheme="implicit"):
+    # the explicit method's matrix is the Stokes operator alone
+    K_op = K if scheme == "implicit" else 0.0
+    lv = system.hierarchy(N, levels, rho, mu, dt, X, fiber_offsets, K_op, kind)
     return lv, VCycle(lv, box, nu1, nu2, mode)
 
 
 def step(u, v, p, X, fiber_offsets, K, dt, levels, rho=1.0, mu=1.0, box=4, nu1=2,
          nu2=2, rtol=1e-8, maxit=100, g_u=None, g_v=None, guess="zero",
-         mode="colour2", orth="cgs2", kind=ib.DELTA_IB4):
+         mode="colour2", orth="cgs2", kind=ib.DELTA_IB4, scheme="implicit"):
     N = u.shape[0]
-    lv, mg = build(N, levels, rho, mu, dt, X, fiber_offsets, K, box, nu1, nu2, mode, kind)
+    if scheme not in ("implicit", "explicit"):
+        raise ValueError(scheme)
+    lv, mg = build(N, levels, rho, mu, dt, X, fiber_offsets, K, box, nu1, nu2, mode, kind, scheme)
     b = system.rhs(u, v, X, fiber_offsets, K, dt, rho, g_u, g_v, kind)
     x0 = None
     if guess == "prev":

@@ -1,7 +1,9 @@
 """Schedule autotuner for the multigrid preconditioner.
 
 For each problem class of a workload (the 256x256 stiffness sweep: one class
-per (K, dt) case; the batch: one class per grid size) it times candidate
+per (K, dt) case; the batch: one class per grid size; the 1024x1024
+eight-ring trajectory: one class, timed over a dozen steps because its later
+steps are the hard ones) it times candidate
 V-cycle schedules on seeded calibration problems -- same class, geometry
 drawn with other seeds than the benchmark's -- and keeps, per class, the
 fastest schedule whose steps all reach the tolerance.  A schedule is
@@ -10,7 +12,8 @@ fastest schedule whose steps all reach the tolerance.  A schedule is
     levels    multigrid depth (coarsest 4^2, 8^2 or 16^2),
     tail_max  largest level run by the LDS-resident one-workgroup tail,
     nu1, nu2  smoothing sweeps (Algorithm 1),
-    colours   box colour classes of a sweep (2 or 4),
+    colours   box colour classes of a sweep (2 or 4), and colours_from, the
+              level from which the checkerboard order takes over,
     prec      V-cycle precision (FP32, or FP64 where FP32 is slower or stalls),
 
 inside FP64 FGMRES.  The result is written as JSON
@@ -18,7 +21,7 @@ inside FP64 FGMRES.  The result is written as JSON
 use the dt values stored for the workload (tests/golden/workload_dt.json,
 written by the oracle's explicit-limit estimate) for the class.
 
-python -m paper_1311_5614_amd.autotune [--workload c2|c4|all] [--steps 2]
+python -m paper_1311_5614_amd.autotune [--workload c2|c4|c3|all] [--steps 2]
 """
 from __future__ import annotations
 
@@ -35,6 +38,7 @@ OUT = os.path.join(HERE, "schedules.json")
 CAL_INSTANCE = 900   # seeds 1311000 + 100 * config + 900 + k are calibration-only
 CAL_GEOMETRIES = 2   # calibration geometries per class of the 256x256 sweep
 MAXIT = 200          # FGMRES iteration cap (no restart), as in the benchmark
+C3_BASIS, C3_CAP = 600, 1000   # the 1024x1024 trajectory: FGMRES(600), at most 1000 iterations
 
 
 def _dt_table():
@@ -74,9 +78,26 @@ def classes(workload):
                                1e5, case.dt_factor, rtol=case.rtol, seed=ibgen.seed_for(4, CAL_INSTANCE))
             # dt of the class: the stored dt of this grid size rescaled from its K to 1e5
             out.append((str(case.N), [w], d["dt"] * case.K / 1e5))
+    elif workload == "c3":
+        c3 = ibgen.config_c3()
+        X, offs, _ = ibgen.rings(np.random.default_rng(ibgen.seed_for(3, CAL_INSTANCE)), 8, 2048, c3.N)
+        w = ibgen.Workload("cal-1024", c3.N, c3.levels, X, offs, c3.K, c3.dt_factor, rtol=c3.rtol,
+                           seed=ibgen.seed_for(3, CAL_INSTANCE))
+        out.append(("1024", [w], dts["c3"][0]["dt"]))
     else:
         raise SystemExit(f"unknown workload {workload}")
     return out
+
+
+def candidates_c3(w):
+    """The eight-ring trajectory: FP64 V-cycles of 4 x 4 boxes down to 16^2,
+    the coarsest solve spread over the grid (tail 1), over box orders (four
+    colours on every level, on the two finest only, or the checkerboard
+    throughout) and sweeps.  FP32 V-cycles are tried on the best of these in
+    the second stage."""
+    for (col, cf), nu in itertools.product(((4, 0), (4, 2), (4, 3), (2, 0)), ((2, 2), (3, 3), (3, 2), (2, 1))):
+        yield dict(box=4, levels=w.levels, tail_max=1, nu1=nu[0], nu2=nu[1], colours=col, colours_from=cf, prec=0,
+                   maxit=C3_CAP, restart=C3_BASIS)
 
 
 def candidates(w, boxes=(4,)):
@@ -104,8 +125,9 @@ def tails(w, sch):
 def time_schedule(w, dt, sch, steps, dev):
     import torch
     from . import ibmg
-    cfg = ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, box=sch["box"], nu1=sch["nu1"], nu2=sch["nu2"], maxit=MAXIT,
-                      rtol=w.rtol, prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"])
+    cfg = ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, box=sch["box"], nu1=sch["nu1"], nu2=sch["nu2"],
+                      maxit=sch.get("maxit", MAXIT), restart=sch.get("restart", 0), rtol=w.rtol, prec=sch["prec"],
+                      colours=sch["colours"], colours_from=sch.get("colours_from", 0), tail_max=sch["tail_max"])
     s = ibmg.Solver(cfg, w.fiber_offsets, dev)
     t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
     gu = t(w.g_u) if w.g_u is not None else None
@@ -153,7 +175,7 @@ def tune(workload, steps, dev="cuda:0"):
     for key, ws, dt in classes(workload):
         w = ws[0]
         scored, failed = [], []
-        for sch in candidates(w, boxes):
+        for sch in (candidates_c3(w) if workload == "c3" else candidates(w, boxes)):
             r = _try(ws, dt, sch, steps, dev, workload, key)
             if r is None:
                 continue
@@ -167,7 +189,7 @@ def tune(workload, steps, dev="cuda:0"):
             best, conv = failed[0], False
             top = failed[:1]
         for _, sch, _ in top:
-            for cand in tails(w, sch):
+            for cand in ([dict(sch, prec=1)] if workload == "c3" else tails(w, sch)):
                 if cand == sch:
                     continue
                 r = _try(ws, dt, cand, steps, dev, workload, key)
@@ -195,10 +217,15 @@ def main():
     ap.add_argument("--out", default=OUT)
     args = ap.parse_args()
     data = load(args.out) if os.path.exists(args.out) else {}
-    for wl in (("c2", "c4") if args.workload == "all" else (args.workload,)):
+    for wl in (("c2", "c4", "c3") if args.workload == "all" else (args.workload,)):
         data[wl] = tune(wl, args.steps)
-    data["meta"] = {"form": "V-cycle (prec 1 = fp32, 0 = fp64) in fp64 FGMRES", "c2_geometries": CAL_GEOMETRIES,
-                    "steps_timed": args.steps, "calibration_instance": CAL_INSTANCE, "maxit": MAXIT}
+    meta = data.get("meta", {})
+    meta.update({"form": "V-cycle (prec 1 = fp32, 0 = fp64) in fp64 FGMRES", "c2_geometries": CAL_GEOMETRIES,
+                 "calibration_instance": CAL_INSTANCE, "maxit": MAXIT})
+    meta.pop("steps_timed", None)
+    for wl in (("c2", "c4", "c3") if args.workload == "all" else (args.workload,)):
+        meta[f"steps_timed_{wl}"] = args.steps
+    data["meta"] = meta
     with open(args.out, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     print(f"[autotune] wrote {args.out}")

@@ -304,7 +304,8 @@ int setup_launch(ibmg_handle* h, double dt, const double* X) {
   h->setup_ok = false;
   h->yib64 = false;   // the elastic-row buffers are cleared below
   const int M = h->M, Lv = h->levels;
-  h->has_ib = M > 0 && h->K != 0.0;
+  // the explicit method keeps the elastic force on the right-hand side only
+  h->has_ib = M > 0 && h->K != 0.0 && h->scheme == IBMG_IMPLICIT;
   int* meta = h->p<int>(h->meta);
   k_fill_i32<<<1, 256, 0, s>>>(meta, 8, 0);
   if (M > 0) {
@@ -728,6 +729,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   if (op->guess != IBMG_GUESS_ZERO && op->guess != IBMG_GUESS_PREV) return IBMG_EINVAL;
   if (op->colours != 2 && op->colours != 4) return IBMG_EINVAL;
   if (op->colours_from < 0 || op->colours_from > op->levels) return IBMG_EINVAL;
+  if (op->scheme != IBMG_IMPLICIT && op->scheme != IBMG_EXPLICIT) return IBMG_EINVAL;
   if (op->tail_max != 0 && (op->tail_max < 1 || op->tail_max > kSmallLevel || (op->tail_max & (op->tail_max - 1))))
     return IBMG_EINVAL;
   if (pr->n_points < 0 || pr->n_fibers < 0) return IBMG_EINVAL;
@@ -738,6 +740,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   h->rho = pr->rho; h->mu = pr->mu; h->K = pr->K;
   h->levels = op->levels; h->n = op->box; h->nu1 = op->nu1; h->nu2 = op->nu2; h->maxit = op->maxit;
   h->mb = op->restart == 0 ? op->maxit : std::min(op->restart, op->maxit);
+  h->scheme = op->scheme;
   h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess; h->ncol = op->colours;
   for (int l = 0; l < IBMG_MAX_LEVELS; ++l) h->ncol_l[l] = (op->colours_from > 0 && l >= op->colours_from) ? 2 : op->colours;
   h->tail_max = op->tail_max ? op->tail_max : kSmallLevel;

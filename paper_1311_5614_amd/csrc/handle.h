@@ -44,6 +44,7 @@ struct ibmg_handle {
   int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 2, nu2 = 2, maxit = 100, prec = 0, guess = 0;
   int ncol = 2;
   int ncol_l[IBMG_MAX_LEVELS] = {};   // colour classes of each level's sweeps
+  int scheme = 0; // IBMG_IMPLICIT or IBMG_EXPLICIT
   int mb = 100;   // Krylov basis size: the FGMRES(m) restart length (maxit caps the iterations of all cycles)
   int tail_max = ibmg::kSmallLevel;   // largest level size run by the LDS-resident tail
   double rho = 1, mu = 1, K = 0, rtol = 1e-8;

@@ -155,9 +155,17 @@ constexpr int kBoxGroupMin = 16384;      // boxes per colour from which a wave t
 // cells put two boxes' width between boxes of one colour, more than the
 // one-cell reach of the stencil.  The elastic rows still come from the
 // elastic-row pass before the phase (their windows reach farther).
-template <typename T, int NB, int W = 1, int B = 1, bool F = false>
+//
+// LI, sinv (one box per wave): the shared plain inverse staged in LDS by
+// the whole workgroup (k_box does it before any wave starts), read from
+// there by every box of every wave -- column c of lane r at sinv[c ND + r],
+// the same values in the same order as the register column, so the result
+// does not change; the waves then take `nper` boxes each.  Without it a
+// one-box wave reads the whole inverse from L2 for its single box (25 KB in
+// FP64 against the box's own 1.3 KB).
+template <typename T, int NB, int W = 1, int B = 1, bool F = false, bool LI = false>
 __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r, T* __restrict__ w, int colour,
-                                  int q0, int nper = 1, int cnt = 0x7fffffff) {
+                                  int q0, int nper = 1, int cnt = 0x7fffffff, const T* sinv = nullptr) {
   constexpr int ND = 2 * NB * (NB + 1) + NB * NB;
   __shared__ double res_all[W][B][64];
   double (*res)[64] = res_all[W == 1 ? 0 : threadIdx.x >> 6];
@@ -173,10 +181,10 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
       for (int c = 0; c < ND; ++c) a[c] = L.ainv_plain[c * ND + lane];
     }
   }
-  // one box per wave always comes with one group per wave: a compile-time
-  // single pass leaves the column dead on the path of boxes with elastic
-  // rows, whose inverse loads then all issue together
-  const int np = B == 1 ? 1 : nper;
+  // one box per wave comes with one group per wave unless the inverse is in
+  // LDS: a compile-time single pass leaves the column dead on the path of
+  // boxes with elastic rows, whose inverse loads then all issue together
+  const int np = (B == 1 && !LI) ? 1 : nper;
   for (int k = 0; k < np; ++k) {
     const int qb = q0 + k * B;
     if (qb >= cnt) break;   // uniform over the wave
@@ -213,7 +221,7 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
         }
       }
     }
-    if (B == 1 && k == 0 && lane < ND) {
+    if (B == 1 && !LI && k == 0 && lane < ND) {
 #pragma unroll
       for (int c = 0; c < ND; ++c) a[c] = L.ainv_plain[c * ND + lane];
     }
@@ -240,6 +248,11 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
 #pragma unroll
           for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[b][c];
           w[g[b]] = wv[b] + (T)z;
+        } else if constexpr (LI) {
+          T z = T(0);
+#pragma unroll
+          for (int c = 0; c < ND; ++c) z += sinv[c * ND + lane] * (T)res[b][c];
+          w[g[b]] = wv[b] + z;
         } else {
           T z = T(0);
 #pragma unroll

@@ -43,7 +43,17 @@ template <typename T, int NB, int W, int B = 1, bool F = false>
 __global__ void __launch_bounds__(64 * W)
 k_box(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour, int cnt, int nper) {
   const int q = (xcd_remap(blockIdx.x, gridDim.x) * W + (int)(threadIdx.x >> 6)) * nper * B;
-  if (q < cnt) box_body_n<T, NB, W, B, F>(L, r, w, colour, q, nper, cnt);
+  if constexpr (W > 1 && B == 1) {
+    // several one-box waves: the shared plain inverse goes to LDS once per
+    // workgroup, before any wave leaves (every lane takes part in the barrier)
+    constexpr int ND = 2 * NB * (NB + 1) + NB * NB;
+    __shared__ T sinv[ND * ND];
+    for (int e = threadIdx.x; e < ND * ND; e += 64 * W) sinv[e] = L.ainv_plain[e];
+    __syncthreads();
+    if (q < cnt) box_body_n<T, NB, W, B, F, true>(L, r, w, colour, q, nper, cnt, sinv);
+  } else {
+    if (q < cnt) box_body_n<T, NB, W, B, F>(L, r, w, colour, q, nper, cnt);
+  }
 }
 template <typename T>
 __global__ void __launch_bounds__(kBigBoxLanes)

@@ -24,6 +24,7 @@ IBMG_EINVAL, IBMG_ESHAPE, IBMG_EHIP, IBMG_ENOMEM, IBMG_ENONFINITE, IBMG_ESTATE =
 IBMG_DELTA_IB4, IBMG_DELTA_COS4 = 0, 1
 IBMG_FP64, IBMG_FP32 = 0, 1
 IBMG_GUESS_ZERO, IBMG_GUESS_PREV = 0, 1
+IBMG_IMPLICIT, IBMG_EXPLICIT = 0, 1
 IBMG_KERNEL_BOX, IBMG_KERNEL_RES, IBMG_KERNEL_MULTIDOT, IBMG_KERNEL_UPDATE = 0, 1, 2, 3
 IBMG_GUESS_RECORD, IBMG_GUESS_EXTRAP, IBMG_GUESS_LEARNED = 0, 1, 2
 
@@ -53,7 +54,7 @@ class ibmg_opts(C.Structure):
     _fields_ = [("levels", C.c_int32), ("box", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("maxit", C.c_int32), ("rtol", C.c_double), ("vcycle_prec", C.c_int32),
                 ("guess", C.c_int32), ("colours", C.c_int32), ("tail_max", C.c_int32),
-                ("restart", C.c_int32), ("colours_from", C.c_int32)]
+                ("restart", C.c_int32), ("colours_from", C.c_int32), ("scheme", C.c_int32)]
 
 
 class ibmg_stats(C.Structure):
@@ -182,6 +183,7 @@ class Config:
     tail_max: int = 0
     restart: int = 0
     colours_from: int = 0
+    scheme: int = 0
 
 
 def _problem(cfg: Config, fiber_offsets):
@@ -192,7 +194,7 @@ def _problem(cfg: Config, fiber_offsets):
     prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, M, max(0, len(offs) - 1),
                         C.cast(arr, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
     opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
-                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart, cfg.colours_from)
+                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart, cfg.colours_from, cfg.scheme)
     return prob, opts, arr, M
 
 

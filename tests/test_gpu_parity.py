@@ -569,3 +569,44 @@ def test_vcycle_parity_per_level_colours(colours_from, levels):
     r = np.random.default_rng(42).standard_normal(3 * 64 * 64)
     r[2 * 4096:] -= r[2 * 4096:].mean()
     assert rel(tnp(s.vcycle(tdev(r))), V(r)) < 1e-11
+
+
+def test_explicit_step_parity_and_stability():
+    """The explicit method (Sec. 2.3.1; the comparison of Sec. 7): the force at
+    X^n on the right-hand side only and the Stokes operator alone in the
+    system.  Three steps against the oracle's explicit steps, then the
+    explicit limit in practice: 60 steps just below the computed limit stay
+    bounded, 20 steps at four times it blow up."""
+    from paper_1311_5614_amd import ibmg
+    N = 32
+    w = ibgen.small_case(N=N, M=80, K=2e4, seed=12, with_force=True)
+    dte = dtexp.dt_explicit(w.X, w.fiber_offsets, N, w.K)
+    cfg = ibmg.Config(N=N, levels=3, K=w.K, rtol=1e-11, scheme=ibmg.IBMG_EXPLICIT)
+    s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    z = np.zeros((N, N))
+    u, v, p, X = tdev(z), tdev(z), tdev(z), tdev(w.X)
+    uo, vo, po, Xo = z, z, z, w.X
+    for _ in range(3):
+        st = s.step(0.9 * dte, u, v, p, X, tdev(w.g_u), tdev(w.g_v))
+        o = ostep.step(uo, vo, po, Xo, w.fiber_offsets, w.K, 0.9 * dte, 3, rtol=1e-11, g_u=w.g_u, g_v=w.g_v,
+                       scheme="explicit")
+        uo, vo, po, Xo = o.u, o.v, o.p, o.X
+        assert st["converged"] == 1
+    assert rel(tnp(u), uo) < 1e-9 and rel(tnp(X), Xo) < 1e-12
+
+    def run(fac, n):
+        uu, vv, pp, XX = tdev(z), tdev(z), tdev(z), tdev(w.X)
+        try:
+            for _ in range(n):
+                s.step(fac * dte, uu, vv, pp, XX)
+        except ibmg.IBMGError:        # a non-finite iterate: the explicit run has blown up
+            return float("inf")
+        return float((XX - tdev(w.X)).abs().max()) * N      # displacement in cells
+    # the limit computed with the steady Stokes operator (Sec. 4.1) is
+    # conservative for the unsteady scheme: at 2 x it still holds here (the
+    # oracle's explicit steps relax by 1.4 cells at 0.95 x and 2 x, and blow
+    # up within 12 steps at 4 x)
+    stable, unstable = run(0.95, 60), run(4.0, 20)
+    print(f"explicit method: max displacement {stable:.3g} cells after 60 steps at 0.95 dt_exp, "
+          f"{unstable:.3g} cells after 20 steps at 4 dt_exp")
+    assert stable < 3.0 and unstable > 1e3

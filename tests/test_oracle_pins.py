@@ -687,3 +687,29 @@ def test_step_energy_decays_without_forcing():
         E.append(_energy(u, v, X, w.fiber_offsets, w.K, 1.0, h))
     assert all(E[k + 1] <= E[k] * (1 + 1e-10) for k in range(3))
     assert E[-1] < E[0]
+
+
+# ---------------------------------------------------------------- explicit method (Sec. 2.3.1, Sec. 7)
+
+def test_explicit_step_is_a_stokes_solve_with_the_force_at_x_n():
+    """The explicit step's velocity is the periodic unsteady Stokes solution
+    (an independent FFT solve) for the right-hand side (rho/dt) u^n + S_0 G^n
+    + g, and the positions move with the interpolated new velocity."""
+    N = 16
+    w = ibgen.small_case(N=N, M=40, K=2e3, seed=4, with_force=True)
+    dt = 0.5 * dtexp.dt_explicit(w.X, w.fiber_offsets, N, w.K)
+    r = np.random.default_rng(12)
+    u0, v0 = r.standard_normal((N, N)), r.standard_normal((N, N))
+    o = step.step(u0, v0, np.zeros((N, N)), w.X, w.fiber_offsets, w.K, dt, 2, rtol=1e-13, g_u=w.g_u, g_v=w.g_v,
+                  scheme="explicit")
+    b = system.rhs(u0, v0, w.X, w.fiber_offsets, w.K, dt, 1.0, w.g_u, w.g_v)
+    fu, fv, _ = system.split(b, N)
+    uf, vf, pf = stokes_fft.solve(fu, fv, 1.0 / dt, 1.0)
+    assert np.max(np.abs(o.u - uf)) < 1e-10 * np.max(np.abs(uf))
+    assert np.max(np.abs(o.v - vf)) < 1e-10 * np.max(np.abs(vf))
+    U = ib.interp(w.X, uf, vf)
+    assert np.max(np.abs(o.X - (w.X + dt * U))) < 1e-12
+    # with no springs the two schemes are the same step
+    oi = step.step(u0, v0, np.zeros((N, N)), w.X, w.fiber_offsets, 0.0, dt, 2, rtol=1e-13)
+    oe = step.step(u0, v0, np.zeros((N, N)), w.X, w.fiber_offsets, 0.0, dt, 2, rtol=1e-13, scheme="explicit")
+    assert np.array_equal(oi.u, oe.u) and np.array_equal(oi.X, oe.X)
