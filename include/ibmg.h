@@ -72,6 +72,7 @@ enum { IBMG_DELTA_IB4 = 0,  /* Peskin's standard 4-point kernel                 
 enum { IBMG_FP64 = 0, IBMG_FP32 = 1 };
 enum { IBMG_GUESS_ZERO = 0, IBMG_GUESS_PREV = 1 };
 enum { IBMG_IMPLICIT = 0, IBMG_EXPLICIT = 1 };
+enum { IBMG_SOLVER_FGMRES = 0, IBMG_SOLVER_MG = 1 };
 
 typedef struct {
   int32_t N;                     /* cells per side, power of two >= 4               */
@@ -118,6 +119,12 @@ typedef struct {
                           X^n on the right-hand side only, the system is the
                           Stokes operator; stable below the explicit limit of
                           Sec. 4.1, the comparison of Sec. 7)                   */
+  int32_t solver;      /* IBMG_SOLVER_FGMRES (multigrid-preconditioned FGMRES,
+                          Sec. 3.3) or IBMG_SOLVER_MG (multigrid alone, Sec. 5.1:
+                          w <- w + MGV(0, b - A w) until the same rtol or
+                          maxit V-cycles; stats.iters counts V-cycles)          */
+  double omega;        /* weight of each box correction, w[box] += omega z_box:
+                          0 or 1 = the paper's undamped boxes, else (0, 1]     */
 } ibmg_opts;
 
 typedef struct {

@@ -20,12 +20,14 @@ from .smoother import BoxSmoother
 
 
 class VCycle:
-    def __init__(self, levels, box=4, nu1=2, nu2=2, mode="colour2"):
+    def __init__(self, levels, box=4, nu1=2, nu2=2, mode="colour2", omega=1.0):
         """levels: list of system.Level, finest first.  mode: the box order of
         every smoothed level (a string), or one order per smoothed level (a
-        sequence; Algorithm 1 fixes no order, so levels may differ)."""
+        sequence; Algorithm 1 fixes no order, so levels may differ).  omega:
+        the box correction's weight (1 = the paper's undamped boxes)."""
         self.levels = levels
         self.nu1, self.nu2 = nu1, nu2
+        self.omega = omega
         nsm = len(levels) - 1
         self.modes = [mode] * nsm if isinstance(mode, str) else list(mode)[:nsm]
         if len(self.modes) != nsm:
@@ -53,14 +55,48 @@ class VCycle:
             return self.coarse_solve(b)
         sm = self.smoothers[l]
         for _ in range(self.nu1):
-            w = sm.sweep(w, b, self.modes[l])
+            w = sm.sweep(w, b, self.modes[l], self.omega)
         r2 = lv.R @ (b - lv.A @ w)
         e2 = self.mgv(np.zeros_like(r2), r2, l + 1)
         w = w + lv.P @ e2
         for _ in range(self.nu2):
-            w = sm.sweep(w, b, self.modes[l])
+            w = sm.sweep(w, b, self.modes[l], self.omega)
         return w
 
     def __call__(self, r):
         """Preconditioner z = MGV(0, r) on the finest level."""
         return self.mgv(np.zeros_like(r), r, 0)
+
+
+def mg_solve(A, b, vcycle, x0=None, rtol=1e-8, maxit=100):
+    """Multigrid as the solver (Sec. 5.1): x <- x + MGV(0, b - A x) until
+    ||b - A x|| <= rtol ||b|| or maxit V-cycles (stopping early once the
+    residual has grown by 1e12: the iteration diverges).  Returns
+    (x, V-cycles applied, converged, relative residual history)."""
+    x = np.zeros_like(b) if x0 is None else np.array(x0, float)
+    bnorm = float(np.linalg.norm(b))
+    hist = []
+    if bnorm == 0.0:
+        return np.zeros_like(b), 0, True, hist
+    its = 0
+    while True:
+        r = b - A @ x
+        beta = float(np.linalg.norm(r))
+        hist.append(beta / bnorm)
+        if beta <= rtol * bnorm:
+            return x, its, True, hist
+        if its >= maxit or beta > 1e12 * bnorm:
+            return x, its, False, hist
+        x = x + vcycle(r)
+        its += 1
+
+
+def iteration_matrix(A, vcycle, n):
+    """The multigrid iteration matrix T = I - M A (M the V-cycle as a linear
+    map, the error propagator of one mg_solve step), column by column."""
+    T = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        T[:, k] = e - vcycle(A @ e)
+    return T

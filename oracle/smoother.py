@@ -21,6 +21,11 @@ The coloured orderings are different (equally valid) smoothers from the
 paper's lexicographic one.
 
 The local solve uses a pivoted dense LU of the extracted block.
+
+Damping: the paper states none (omega = 1, every default here).  An optional
+omega scales each box correction, w[box] += omega A_box^{-1} (b - A w)[box]
+-- the damped block relaxation that weights a smoother's correction, an
+option of this build (a schedule parameter), not the paper's method.
 """
 from __future__ import annotations
 
@@ -60,7 +65,7 @@ def box_dof_table(N, n):
     return np.concatenate([u, v, p], axis=1).astype(np.int64)
 
 
-def sweep_shared(A, N, n, w, b, mode="colour2"):
+def sweep_shared(A, N, n, w, b, mode="colour2", omega=1.0):
     """One coloured sweep (Jacobi within a colour, colour order as
     BoxSmoother.sweep_colour2 / sweep_colour) on a level without elastic
     rows.  The periodic Stokes operator is invariant under translation, so
@@ -83,7 +88,7 @@ def sweep_shared(A, N, n, w, b, mode="colour2"):
     for sel in classes:
         r = b - A @ w
         Dc = D[sel]
-        w[Dc] += sla.lu_solve(lu, r[Dc].T).T
+        w[Dc] += omega * sla.lu_solve(lu, r[Dc].T).T
     return w
 
 
@@ -109,7 +114,7 @@ class BoxSmoother:
         d = self.dofs[(bx, by)]
         return self.A[d][:, d].toarray()
 
-    def sweep_colour(self, w, b):
+    def sweep_colour(self, w, b, omega=1.0):
         """One sweep in colour order with Jacobi-within-colour semantics."""
         w = w.copy()
         for cx, cy in COLOURS:
@@ -120,10 +125,10 @@ class BoxSmoother:
                     d = self.dofs[(bx, by)]
                     upd.append((d, sla.lu_solve(self.lu[(bx, by)], r[d])))
             for d, z in upd:
-                w[d] += z
+                w[d] += omega * z
         return w
 
-    def sweep_colour2(self, w, b):
+    def sweep_colour2(self, w, b, omega=1.0):
         """One checkerboard sweep: colour (bx + by) mod 2 = 0, then 1, each
         from the residual at the start of the colour."""
         w = w.copy()
@@ -137,24 +142,24 @@ class BoxSmoother:
                     d = self.dofs[(bx, by)]
                     upd.append((d, sla.lu_solve(self.lu[(bx, by)], r[d])))
             for d, z in upd:
-                w[d] += z
+                w[d] += omega * z
         return w
 
-    def sweep_paper(self, w, b):
+    def sweep_paper(self, w, b, omega=1.0):
         """One lexicographic block Gauss-Seidel sweep (the paper's order)."""
         w = w.copy()
         for by in range(self.nb):
             for bx in range(self.nb):
                 d = self.dofs[(bx, by)]
                 r = b[d] - self.A[d] @ w
-                w[d] += sla.lu_solve(self.lu[(bx, by)], r)
+                w[d] += omega * sla.lu_solve(self.lu[(bx, by)], r)
         return w
 
-    def sweep(self, w, b, mode="colour2"):
+    def sweep(self, w, b, mode="colour2", omega=1.0):
         if mode == "colour2":
-            return self.sweep_colour2(w, b)
+            return self.sweep_colour2(w, b, omega)
         if mode == "colour":
-            return self.sweep_colour(w, b)
+            return self.sweep_colour(w, b, omega)
         if mode == "paper":
-            return self.sweep_paper(w, b)
+            return self.sweep_paper(w, b, omega)
         raise ValueError(mode)

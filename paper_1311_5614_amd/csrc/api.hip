@@ -570,10 +570,54 @@ int do_solve_impl(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
   return st->converged ? IBMG_OK : IBMG_NOT_CONVERGED;
 }
 
+// Multigrid as the solver (Sec. 5.1): w <- w + MGV(0, b - A w), the V-cycle
+// of the handle's precision applied to the FP64 residual, until
+// ||b - A w|| <= rtol ||b|| or maxit V-cycles.  A diverging iteration (the
+// paper's MG alone at high stiffness) stops once the residual has grown by
+// 1e12 and reports IBMG_NOT_CONVERGED.
+int do_solve_mg(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
+  hipStream_t s = h->stream;
+  const size_t n0 = h->n0();
+  double* r = h->p<double>(h->V);
+  double* z = h->p<double>(h->Z);
+  double* scal = h->p<double>(h->scal);
+  double hs[1];
+  st->iters = 0;
+  st->converged = 0;
+  st->fallback = 0;
+  dot(h, b, b, scal);
+  int rc = read_doubles(h, scal, hs, 1);
+  if (rc) return rc;
+  const double bnorm = std::sqrt(hs[0]);
+  if (!std::isfinite(bnorm)) return IBMG_ENONFINITE;
+  st->bnorm = bnorm;
+  if (bnorm == 0.0) {
+    k_fill<double><<<nblk(n0), 256, 0, s>>>(x, n0, 0.0);
+    st->converged = 1;
+    return sync(h);
+  }
+  const double target = h->rtol * bnorm;
+  for (;;) {
+    apply0(h, x, r, b);   // r = b - A w
+    dot(h, r, r, scal);
+    if ((rc = read_doubles(h, scal, hs, 1))) return rc;
+    const double beta = std::sqrt(hs[0]);
+    if (!std::isfinite(beta)) return IBMG_ENONFINITE;
+    st->rel_resid_true = st->rel_resid_est = beta / bnorm;
+    if (beta <= target) { st->converged = 1; break; }
+    if (st->iters >= h->maxit || beta > 1e12 * bnorm) break;
+    precond(h, r, z);
+    if (h->launch_error) return IBMG_EHIP;
+    k_lincomb<<<nblk(n0), 256, 0, s>>>(x, x, z, 1.0, nullptr, 0.0, n0);
+    ++st->iters;
+  }
+  return st->converged ? IBMG_OK : IBMG_NOT_CONVERGED;
+}
+
 // The FP64 fallback belongs to one solve: whatever way the solve ends, later
 // V-cycles (the next solve, ibmg_vcycle) run in the handle's precision.
 int do_solve(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
-  const int rc = do_solve_impl(h, b, x, st);
+  const int rc = h->solver == IBMG_SOLVER_MG ? do_solve_mg(h, b, x, st) : do_solve_impl(h, b, x, st);
   h->fb64 = false;
   return rc;
 }
@@ -730,6 +774,8 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   if (op->colours != 2 && op->colours != 4) return IBMG_EINVAL;
   if (op->colours_from < 0 || op->colours_from > op->levels) return IBMG_EINVAL;
   if (op->scheme != IBMG_IMPLICIT && op->scheme != IBMG_EXPLICIT) return IBMG_EINVAL;
+  if (op->solver != IBMG_SOLVER_FGMRES && op->solver != IBMG_SOLVER_MG) return IBMG_EINVAL;
+  if (!(op->omega >= 0.0 && op->omega <= 1.0)) return IBMG_EINVAL;
   if (op->tail_max != 0 && (op->tail_max < 1 || op->tail_max > kSmallLevel || (op->tail_max & (op->tail_max - 1))))
     return IBMG_EINVAL;
   if (pr->n_points < 0 || pr->n_fibers < 0) return IBMG_EINVAL;
@@ -741,6 +787,8 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   h->levels = op->levels; h->n = op->box; h->nu1 = op->nu1; h->nu2 = op->nu2; h->maxit = op->maxit;
   h->mb = op->restart == 0 ? op->maxit : std::min(op->restart, op->maxit);
   h->scheme = op->scheme;
+  h->solver = op->solver;
+  h->omega = op->omega == 0.0 ? 1.0 : op->omega;
   h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess; h->ncol = op->colours;
   for (int l = 0; l < IBMG_MAX_LEVELS; ++l) h->ncol_l[l] = (op->colours_from > 0 && l >= op->colours_from) ? 2 : op->colours;
   h->tail_max = op->tail_max ? op->tail_max : kSmallLevel;

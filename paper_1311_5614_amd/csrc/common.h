@@ -32,6 +32,7 @@ struct LevelView {
   T c;            // rho / dt
   T muh2;         // mu / h_l^2
   T invh;         // 1 / h_l
+  T omega;        // weight of a box correction (1: the undamped boxes of the paper)
   int reach;      // window reach on this level
   int maxact;     // row capacity of the window store per component
   int rowhint;    // launch size of the elastic-row passes: expected active rows per component (<= maxact;

@@ -45,6 +45,8 @@ struct ibmg_handle {
   int ncol = 2;
   int ncol_l[IBMG_MAX_LEVELS] = {};   // colour classes of each level's sweeps
   int scheme = 0; // IBMG_IMPLICIT or IBMG_EXPLICIT
+  int solver = 0; // IBMG_SOLVER_FGMRES or IBMG_SOLVER_MG
+  double omega = 1.0;  // box correction weight
   int mb = 100;   // Krylov basis size: the FGMRES(m) restart length (maxit caps the iterations of all cycles)
   int tail_max = ibmg::kSmallLevel;   // largest level size run by the LDS-resident tail
   double rho = 1, mu = 1, K = 0, rtol = 1e-8;
@@ -107,6 +109,7 @@ inline LevelView<T> view(const ibmg_handle* h, int l) {
   v.c = (T)(h->rho / h->dt);
   v.muh2 = (T)(h->mu / (hl * hl));
   v.invh = (T)(1.0 / hl);
+  v.omega = (T)h->omega;
   v.reach = B.reach;
   v.maxact = B.maxact;
   v.rowhint = B.rowhint > 0 ? B.rowhint : B.maxact;

@@ -33,10 +33,9 @@ __global__ void __launch_bounds__(256) k_vcycle_in(const double* __restrict__ r,
 
 // out = a + sb b (+ sc c when c is given), elementwise over n: the FP64
 // vector sums of the learned initial iterate (proposal, increment, target).
-// (out may be c: each lane reads its entries before it writes)
-__global__ void __launch_bounds__(256) static k_lincomb(double* out, const double* __restrict__ a,
-                                                       const double* __restrict__ b, double sb, const double* c,
-                                                       double sc, size_t n) {
+// (out may be a or c: each lane reads its entries before it writes)
+__global__ void __launch_bounds__(256) static k_lincomb(double* out, const double* a, const double* __restrict__ b,
+                                                       double sb, const double* c, double sc, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double x = a[i] + sb * b[i];

@@ -247,17 +247,17 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
           double z = 0.0;
 #pragma unroll
           for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[b][c];
-          w[g[b]] = wv[b] + (T)z;
+          w[g[b]] = wv[b] + L.omega * (T)z;
         } else if constexpr (LI) {
           T z = T(0);
 #pragma unroll
           for (int c = 0; c < ND; ++c) z += sinv[c * ND + lane] * (T)res[b][c];
-          w[g[b]] = wv[b] + z;
+          w[g[b]] = wv[b] + L.omega * z;
         } else {
           T z = T(0);
 #pragma unroll
           for (int c = 0; c < ND; ++c) z += a[c] * (T)res[b][c];
-          w[g[b]] = wv[b] + z;
+          w[g[b]] = wv[b] + L.omega * z;
         }
       }
     }
@@ -277,7 +277,7 @@ constexpr int kBigBoxLanes = 256, kBigBoxRowBlocks = 4;
 
 template <typename T, typename A>
 __device__ inline void big_box_rows(const A* __restrict__ inv, T y, int row, int rr, int q, bool act, size_t gr,
-                                    T wv, T* __restrict__ w, double* res, double (*part)[52]) {
+                                    T wv, T* __restrict__ w, double* res, double (*part)[52], T omega) {
   constexpr int ND = 208, CP = 52;
   A a[CP];
   if (act) {
@@ -295,7 +295,7 @@ __device__ inline void big_box_rows(const A* __restrict__ inv, T y, int row, int
   __syncthreads();
   if (act && q == 0) {
     const A z = (((A)part[0][rr] + (A)part[1][rr]) + (A)part[2][rr]) + (A)part[3][rr];
-    w[gr] = wv + (T)z;
+    w[gr] = wv + omega * (T)z;
   }
 }
 
@@ -333,9 +333,9 @@ __device__ inline void box_body_big(const LevelView<T>& L, const T* __restrict__
   }
   if (ibx >= 0) {
     if (comp < 2) y -= yb;
-    big_box_rows<T, double>(L.ainv_ib + (size_t)ibx * ND * ND, y, row, rr, q, act, gr, wv, w, res, part);
+    big_box_rows<T, double>(L.ainv_ib + (size_t)ibx * ND * ND, y, row, rr, q, act, gr, wv, w, res, part, L.omega);
   } else {
-    big_box_rows<T, T>(L.ainv_plain, y, row, rr, q, act, gr, wv, w, res, part);
+    big_box_rows<T, T>(L.ainv_plain, y, row, rr, q, act, gr, wv, w, res, part, L.omega);
   }
 }
 
@@ -508,12 +508,12 @@ __device__ void small_sweep(const LevelView<T>& L, const T* __restrict__ b, T* _
           double z = 0.0;
 #pragma unroll
           for (int c = 0; c < nd; ++c) z += A[c * nd + lane] * res[wave][c];
-          w[g] += (T)z;
+          w[g] += L.omega * (T)z;
         } else {
           T z = T(0);
 #pragma unroll 8
           for (int c = 0; c < nd; ++c) z += Ap[c * nd + lane] * (T)res[wave][c];
-          w[g] += z;
+          w[g] += L.omega * z;
         }
       }
       __syncthreads();

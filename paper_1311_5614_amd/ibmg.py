@@ -25,6 +25,7 @@ IBMG_DELTA_IB4, IBMG_DELTA_COS4 = 0, 1
 IBMG_FP64, IBMG_FP32 = 0, 1
 IBMG_GUESS_ZERO, IBMG_GUESS_PREV = 0, 1
 IBMG_IMPLICIT, IBMG_EXPLICIT = 0, 1
+IBMG_SOLVER_FGMRES, IBMG_SOLVER_MG = 0, 1
 IBMG_KERNEL_BOX, IBMG_KERNEL_RES, IBMG_KERNEL_MULTIDOT, IBMG_KERNEL_UPDATE = 0, 1, 2, 3
 IBMG_GUESS_RECORD, IBMG_GUESS_EXTRAP, IBMG_GUESS_LEARNED = 0, 1, 2
 
@@ -54,7 +55,8 @@ class ibmg_opts(C.Structure):
     _fields_ = [("levels", C.c_int32), ("box", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("maxit", C.c_int32), ("rtol", C.c_double), ("vcycle_prec", C.c_int32),
                 ("guess", C.c_int32), ("colours", C.c_int32), ("tail_max", C.c_int32),
-                ("restart", C.c_int32), ("colours_from", C.c_int32), ("scheme", C.c_int32)]
+                ("restart", C.c_int32), ("colours_from", C.c_int32), ("scheme", C.c_int32),
+                ("solver", C.c_int32), ("omega", C.c_double)]
 
 
 class ibmg_stats(C.Structure):
@@ -184,6 +186,8 @@ class Config:
     restart: int = 0
     colours_from: int = 0
     scheme: int = 0
+    solver: int = 0
+    omega: float = 1.0
 
 
 def _problem(cfg: Config, fiber_offsets):
@@ -194,7 +198,7 @@ def _problem(cfg: Config, fiber_offsets):
     prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, M, max(0, len(offs) - 1),
                         C.cast(arr, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
     opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
-                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart, cfg.colours_from, cfg.scheme)
+                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart, cfg.colours_from, cfg.scheme, cfg.solver, cfg.omega)
     return prob, opts, arr, M
 
 

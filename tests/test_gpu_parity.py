@@ -610,3 +610,61 @@ def test_explicit_step_parity_and_stability():
     print(f"explicit method: max displacement {stable:.3g} cells after 60 steps at 0.95 dt_exp, "
           f"{unstable:.3g} cells after 20 steps at 4 dt_exp")
     assert stable < 3.0 and unstable > 1e3
+
+
+def test_mg_solver_and_iteration_matrix_parity():
+    """Multigrid as the solver (Sec. 5.1): the same V-cycle counts as the
+    oracle's mg_solve and the same iterate; and the iteration matrix
+    T = I - M A of Sec. 5.2, assembled column by column through the C ABI
+    (ibmg_apply, ibmg_vcycle), against the oracle's, element by element, with
+    its spectral radius on the zero-mean-pressure space."""
+    from paper_1311_5614_amd import ibmg
+    N, K = 16, 1e3
+    w = ibgen.small_case(N=N, M=40, K=K, seed=9)
+    dt = 20.0 * dtexp.dt_explicit(w.X, w.fiber_offsets, N, K)
+    cfg = ibmg.Config(N=N, levels=2, K=K, box=2, nu1=1, nu2=1, colours=4, rtol=1e-10, maxit=300,
+                      solver=ibmg.IBMG_SOLVER_MG)
+    s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    _setup(s, w, dt)
+    lv = oracle_levels(w, dt, 2, K)
+    V = mg.VCycle(lv, 2, 1, 1, "colour")
+    n = 3 * N * N
+    b = np.random.default_rng(33).standard_normal(n)
+    b[2 * N * N:] -= b[2 * N * N:].mean()
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    st = s.solve(tdev(b), x)
+    xo, its, ok, _ = mg.mg_solve(lv[0].A, b, V, rtol=1e-10, maxit=300)
+    assert st["converged"] == 1 and ok and st["iters"] == its
+    assert rel(tnp(x), xo) < 1e-9
+    T = np.zeros((n, n))
+    for k in range(n):
+        e = torch.zeros(n, dtype=torch.float64, device=DEV)
+        e[k] = 1.0
+        T[:, k] = tnp(e - s.vcycle(s.apply(0, e)))
+    To = mg.iteration_matrix(lv[0].A, V, n)
+    assert np.max(np.abs(T - To)) < 1e-10 * np.max(np.abs(To))
+    q = np.zeros(n)
+    q[2 * N * N:] = 1.0 / N
+    Pm = np.eye(n) - np.outer(q, q)
+    rg = np.max(np.abs(np.linalg.eigvals(Pm @ T @ Pm)))
+    ro = np.max(np.abs(np.linalg.eigvals(Pm @ To @ Pm)))
+    print(f"spectral radius of the iteration matrix: gpu {rg:.6f} oracle {ro:.6f}")
+    assert abs(rg - ro) < 1e-8
+
+
+@pytest.mark.parametrize("omega,colours", [(0.8, 2), (0.7, 4)])
+def test_damped_vcycle_parity(omega, colours):
+    """Box corrections weighted by omega (an option of this build; the paper's
+    boxes are undamped) in every sweep, against the oracle's VCycle with the
+    same weight."""
+    from paper_1311_5614_amd import ibmg
+    w, dt, s = make(N=64, levels=4, M=150, K=1e5, dt_factor=100.0)
+    s.close()
+    cfg = ibmg.Config(N=64, levels=4, K=1e5, colours=colours, omega=omega, tail_max=1, rtol=1e-10)
+    s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
+    _setup(s, w, dt)
+    lv = oracle_levels(w, dt, 4, 1e5)
+    V = mg.VCycle(lv, 4, 2, 2, "colour2" if colours == 2 else "colour", omega=omega)
+    r = np.random.default_rng(43).standard_normal(3 * 64 * 64)
+    r[2 * 4096:] -= r[2 * 4096:].mean()
+    assert rel(tnp(s.vcycle(tdev(r))), V(r)) < 1e-11

@@ -375,6 +375,29 @@ def test_paper_mode_box_residual_zero_after_update():
     assert np.max(np.abs(r)) < 1e-11 * np.max(np.abs(b - A @ x))
 
 
+@pytest.mark.parametrize("mode", ["paper", "colour", "colour2"])
+def test_damped_box_correction(mode):
+    """A right-hand side carried only by unknowns that belong to the last box
+    alone (its interior pressures) leaves every earlier box with a zero
+    residual, so one damped sweep updates that box once: the iterate is omega
+    times the undamped one and the box's residual drops to (1 - omega) of
+    the right-hand side there, for omega = 0.6."""
+    N, n = 8, 4
+    lv = system.hierarchy(N, 2, 1.0, 1.0, 0.05)
+    A = lv[0].A
+    sm = smoother.BoxSmoother(A, N, n)
+    b = np.zeros(3 * N * N)
+    last = (1, 0) if mode == "colour2" else (1, 1)     # a box of the sweep's last colour
+    d = sm.dofs[last]
+    interior = [k for k in d if k >= 2 * N * N]          # the box's pressures
+    b[interior] = rng.standard_normal(len(interior))
+    x1 = sm.sweep(np.zeros_like(b), b, mode)
+    xw = sm.sweep(np.zeros_like(b), b, mode, omega=0.6)
+    assert np.max(np.abs(xw - 0.6 * x1)) < 1e-14 * np.max(np.abs(x1))
+    r = (b - A @ xw)[d]
+    assert np.max(np.abs(r - 0.4 * b[d])) < 1e-12 * np.max(np.abs(b))
+
+
 @pytest.mark.parametrize("n", [2, 4])
 def test_colour_phase_exact_without_elasticity(n):
     """Without the elastic term, same-colour boxes do not couple for n >= 2,
@@ -713,3 +736,63 @@ def test_explicit_step_is_a_stokes_solve_with_the_force_at_x_n():
     oi = step.step(u0, v0, np.zeros((N, N)), w.X, w.fiber_offsets, 0.0, dt, 2, rtol=1e-13)
     oe = step.step(u0, v0, np.zeros((N, N)), w.X, w.fiber_offsets, 0.0, dt, 2, rtol=1e-13, scheme="explicit")
     assert np.array_equal(oi.u, oe.u) and np.array_equal(oi.X, oe.X)
+
+
+# ---------------------------------------------------------------- multigrid as the solver (Sec. 5.1-5.2)
+
+def _mg_case(N=16, K=1e3, fac=5.0):
+    w = ibgen.small_case(N=N, M=40, K=K, seed=9)
+    dt = fac * dtexp.dt_explicit(w.X, w.fiber_offsets, N, K)
+    lv = system.hierarchy(N, 2, 1.0, 1.0, dt, w.X, w.fiber_offsets, K)
+    return lv, mg.VCycle(lv, 2, 1, 1, "colour")
+
+
+def test_mg_iteration_matrix_is_the_error_propagator():
+    """One multigrid step x1 = x0 + MGV(0, b - A x0) moves the error by the
+    iteration matrix: x1 - x* = T (x0 - x*), with x* the exact solution (dense
+    bordered solve; errors compared with their pressure means removed)."""
+    lv, V = _mg_case()
+    A = lv[0].A
+    n = A.shape[0]
+    N = lv[0].N
+    T = mg.iteration_matrix(A, V, n)
+    r = np.random.default_rng(31)
+    b = r.standard_normal(n)
+    b[2 * N * N:] -= b[2 * N * N:].mean()
+    B = np.zeros((n + 1, n + 1))
+    B[:n, :n] = A.toarray()
+    B[2 * N * N:n, n] = 1.0
+    B[n, 2 * N * N:n] = 1.0
+    xs = np.linalg.solve(B, np.concatenate([b, [0.0]]))[:n]
+    x0 = r.standard_normal(n)
+    x1, its, _, _ = mg.mg_solve(A, b, V, x0=x0, rtol=0.0, maxit=1)
+    assert its == 1
+
+    def zm(e):
+        e = e.copy()
+        e[2 * N * N:] -= e[2 * N * N:].mean()
+        return e
+    e1, Te0 = zm(x1 - xs), zm(T @ (x0 - xs))
+    assert np.max(np.abs(e1 - Te0)) < 1e-10 * np.max(np.abs(e1))
+
+
+def test_mg_solver_converges_at_the_spectral_radius():
+    """The residual of the multigrid solver falls, asymptotically, by the
+    spectral radius of the iteration matrix per V-cycle (on the space of
+    zero-mean pressure), and the solver meets its tolerance."""
+    lv, V = _mg_case(K=1e3, fac=20.0)
+    A = lv[0].A
+    n = A.shape[0]
+    N = lv[0].N
+    T = mg.iteration_matrix(A, V, n)
+    q = np.zeros(n)
+    q[2 * N * N:] = 1.0 / N
+    Pm = np.eye(n) - np.outer(q, q)
+    rho = float(np.max(np.abs(np.linalg.eigvals(Pm @ T @ Pm))))
+    assert 0.05 < rho < 0.9
+    b = np.random.default_rng(32).standard_normal(n)
+    b[2 * N * N:] -= b[2 * N * N:].mean()
+    x, its, ok, hist = mg.mg_solve(A, b, V, rtol=1e-12, maxit=400)
+    assert ok and np.linalg.norm(b - A @ x) <= 1e-12 * np.linalg.norm(b)
+    late = [hist[k + 1] / hist[k] for k in range(len(hist) - 6, len(hist) - 1)]
+    assert abs(np.exp(np.mean(np.log(late))) - rho) < 0.1 * rho, (late, rho)
