@@ -36,7 +36,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "schedules.json")
 CAL_INSTANCE = 900   # seeds 1311000 + 100 * config + 900 + k are calibration-only
-CAL_GEOMETRIES = 2   # calibration geometries per class of the 256x256 sweep
+CAL_GEOMETRIES = 2   # calibration geometries per class (256x256 sweep, 1024x1024 rings)
 MAXIT = 200          # FGMRES iteration cap (no restart), as in the benchmark
 C3_BASIS, C3_CAP = 600, 1000   # the 1024x1024 trajectory: FGMRES(600), at most 1000 iterations
 
@@ -227,6 +227,7 @@ def main():
         data[wl] = tune(wl, args.steps)
     meta = data.get("meta", {})
     meta.update({"form": "V-cycle (prec 1 = fp32, 0 = fp64) in fp64 FGMRES", "c2_geometries": CAL_GEOMETRIES,
+                 "c3_geometries": CAL_GEOMETRIES,
                  "calibration_instance": CAL_INSTANCE, "maxit": MAXIT})
     meta.pop("steps_timed", None)
     for wl in (("c2", "c4", "c3") if args.workload == "all" else (args.workload,)):
