@@ -546,18 +546,23 @@ def cpu_leg_c3(iters=2):
     w = ibgen.config_c3()
     dt = load_dt("c3")[0]["dt"]
     sch = c3_schedule()
-    mode = "colour2" if sch["colours"] == 2 else "colour"
+    # box order per smoothed level: four colours below colours_from (0: every level), the checkerboard
+    # from there on; two-colour schedules use the checkerboard throughout
+    cf = sch.get("colours_from", 0) or sch["levels"]
+    modes = ["colour" if sch["colours"] == 4 and l < cf else "colour2" for l in range(sch["levels"] - 1)]
+    mode = "/".join(sorted(set(modes)))
+    omega = sch.get("omega", 1.0)
     z = np.zeros((w.N, w.N))
     with threadpool_limits(1):
         t0 = time.perf_counter()
         lv = system.hierarchy(w.N, sch["levels"], w.rho, w.mu, dt, w.X, w.fiber_offsets, w.K)
         b = system.rhs(z, z, w.X, w.fiber_offsets, w.K, dt, w.rho)
-        V = mg.VCycle(lv, sch["box"], sch["nu1"], sch["nu2"], mode)
+        V = mg.VCycle(lv, sch["box"], sch["nu1"], sch["nu2"], modes, omega)
         t1 = time.perf_counter()
         krylov.fgmres(lv[0].A, b, V, rtol=w.rtol, maxit=iters)
         t2 = time.perf_counter()
     print(json.dumps({"setup_s": t1 - t0, "iter_s": (t2 - t1) / iters, "iters_run": iters,
-                      "schedule": f"box {sch['box']}, V({sch['nu1']},{sch['nu2']}), {mode}"}), flush=True)
+                      "schedule": f"box {sch['box']}, V({sch['nu1']},{sch['nu2']}), {mode}, omega {omega:g}"}), flush=True)
 
 
 def start_cpu_leg():
