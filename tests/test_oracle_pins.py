@@ -551,6 +551,35 @@ def test_fgmres_mgs_and_cgs2_agree():
     assert r1.rel_resid_true < 1e-10 and r2.rel_resid_true < 1e-10
 
 
+def test_fgmres_dcgs2_equals_cgs2():
+    """The delayed second Gram-Schmidt pass is a reordering of CGS2: after the
+    same number of iterations the iterates agree to rounding (stiff 16^2 case,
+    500 x dt_exp, pressure compared without its mean), converged solves take
+    the same count, and so do restarted ones."""
+    N, K = 16, 1e6
+    w = ibgen.small_case(N=N, M=48, K=K, seed=11, levels=2)
+    dt = 500 * dtexp.dt_explicit(w.X, w.fiber_offsets, N, K)
+    lv, V = step.build(N, 3, 1.0, 1.0, dt, w.X, w.fiber_offsets, K, box=2, nu1=1, nu2=1)
+    b = system.rhs(rng.standard_normal((N, N)), rng.standard_normal((N, N)), w.X, w.fiber_offsets, K, dt, 1.0)
+    n2 = 2 * N * N
+    for k in (1, 2, 9, 30):
+        r1 = krylov.fgmres(lv[0].A, b, V, rtol=1e-30, maxit=k, orth="cgs2")
+        r2 = krylov.fgmres(lv[0].A, b, V, rtol=1e-30, maxit=k, orth="dcgs2")
+        assert r1.iters == r2.iters == k
+        x1, x2 = r1.x.copy(), r2.x.copy()
+        x1[n2:] -= x1[n2:].mean()
+        x2[n2:] -= x2[n2:].mean()
+        assert np.linalg.norm(x1 - x2) <= 1e-10 * np.linalg.norm(x1)
+        assert np.allclose(r1.history, r2.history, rtol=1e-8, atol=0)
+    r1 = krylov.fgmres(lv[0].A, b, V, rtol=1e-10, maxit=200, orth="cgs2")
+    r2 = krylov.fgmres(lv[0].A, b, V, rtol=1e-10, maxit=200, orth="dcgs2")
+    assert r1.converged and r2.converged and r1.iters == r2.iters
+    assert r2.rel_resid_true <= 1e-10
+    r1 = krylov.fgmres(lv[0].A, b, V, rtol=1e-6, maxit=400, restart=20, orth="cgs2")
+    r2 = krylov.fgmres(lv[0].A, b, V, rtol=1e-6, maxit=400, restart=20, orth="dcgs2")
+    assert r1.iters == r2.iters and abs(r1.rel_resid_true - r2.rel_resid_true) <= 1e-6 * r1.rel_resid_true
+
+
 def test_fgmres_zero_rhs_and_maxit():
     lv = system.hierarchy(8, 2, 1.0, 1.0, 0.1)
     V = mg.VCycle(lv, 2, 1, 1)
