@@ -481,7 +481,8 @@ def c3_config(form):
     return ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, rho=w.rho, mu=w.mu, box=sch["box"], nu1=sch["nu1"],
                        nu2=sch["nu2"], maxit=sch.get("maxit", MAXIT_TOTAL), restart=sch.get("restart", C3_BASIS), rtol=w.rtol,
                        prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"],
-                       colours_from=sch.get("colours_from", 0), guess=sch.get("guess", 0))
+                       colours_from=sch.get("colours_from", 0), guess=sch.get("guess", 0),
+                       omega=sch.get("omega", 1.0), orth=sch.get("orth", ibmg.IBMG_ORTH_CGS2))
 
 
 def describe(cfg):
@@ -490,9 +491,10 @@ def describe(cfg):
     order = (f"{cfg.colours} colours on levels 0-{cfg.colours_from - 1}, checkerboard below" if cfg.colours_from
              else f"{cfg.colours} colours")
     start = "previous step's solution" if cfg.guess == ibmg.IBMG_GUESS_PREV else "zero"
+    orth = "delayed CGS2" if cfg.orth == ibmg.IBMG_ORTH_DCGS2 else "CGS2"
     return (f"{'FP32' if cfg.prec == ibmg.IBMG_FP32 else 'FP64'} V({cfg.nu1},{cfg.nu2}) V-cycle, {cfg.levels} levels, "
-            f"{cfg.box}x{cfg.box} boxes, {order}, tail {cfg.tail_max or 32}, {rs}, FP64 Krylov, "
-            f"initial iterate {start}")
+            f"{cfg.box}x{cfg.box} boxes, {order}, box weight {cfg.omega:g}, tail {cfg.tail_max or 32}, {rs}, "
+            f"FP64 Krylov ({orth}), initial iterate {start}")
 
 
 def timed_trajectory(s, w, dt, dev, steps, warmup, repeats):
@@ -620,16 +622,23 @@ def c3_roofline(s, cfg, w, dt, dev, iters_mean, reps=BOX_REPS):
     from paper_1311_5614_amd import ibmg
     X = torch.as_tensor(w.X, dtype=torch.float64, device=dev).contiguous()
     s.setup(dt, X)
-    nvec = max(1, min(int(round(iters_mean / 2)) + 1, cfg.restart or cfg.maxit))
+    basis = cfg.restart or cfg.maxit
+    nvec = max(1, min(int(round(iters_mean / 2)) + 1, basis - 1))
     sweeps = (cfg.nu1 + cfg.nu2) * cfg.colours * iters_mean        # finest-level phases per step
     cand = {
         "k_box": (ibmg.IBMG_KERNEL_BOX, 0, 0, sweeps, "box relaxation of one colour phase, finest level"),
         "k_res_ib": (ibmg.IBMG_KERNEL_RES, 0, 0, sweeps, "residual pass of one colour phase, finest level"),
-        "k_multidot": (ibmg.IBMG_KERNEL_MULTIDOT, 0, nvec, 2 * iters_mean,
-                       f"Gram-Schmidt dot pass over {nvec} basis vectors"),
-        "k_update_acc": (ibmg.IBMG_KERNEL_UPDATE, 0, nvec, 2 * iters_mean,
-                         f"Gram-Schmidt update pass over {nvec} basis vectors"),
     }
+    if cfg.orth == ibmg.IBMG_ORTH_DCGS2:     # one product pass and one update pass per iteration
+        cand["k_multidot2"] = (ibmg.IBMG_KERNEL_DOT2, 0, nvec, iters_mean,
+                               f"delayed Gram-Schmidt product pass over {nvec + 1} basis vectors, two vectors")
+        cand["k_dcgs2_update"] = (ibmg.IBMG_KERNEL_UPDATE2, 0, nvec, iters_mean,
+                                  f"delayed Gram-Schmidt update pass over {nvec} basis vectors")
+    else:                                    # two of each
+        cand["k_multidot"] = (ibmg.IBMG_KERNEL_MULTIDOT, 0, nvec, 2 * iters_mean,
+                              f"Gram-Schmidt dot pass over {nvec} basis vectors")
+        cand["k_update_acc"] = (ibmg.IBMG_KERNEL_UPDATE, 0, nvec, 2 * iters_mean,
+                                f"Gram-Schmidt update pass over {nvec} basis vectors")
     out = {}
     for name, (k, level, arg, per_step, what) in cand.items():
         us, by = s.kernel_bench(k, level, arg, reps)

@@ -73,6 +73,7 @@ enum { IBMG_FP64 = 0, IBMG_FP32 = 1 };
 enum { IBMG_GUESS_ZERO = 0, IBMG_GUESS_PREV = 1 };
 enum { IBMG_IMPLICIT = 0, IBMG_EXPLICIT = 1 };
 enum { IBMG_SOLVER_FGMRES = 0, IBMG_SOLVER_MG = 1 };
+enum { IBMG_ORTH_CGS2 = 0, IBMG_ORTH_DCGS2 = 1 };
 
 typedef struct {
   int32_t N;                     /* cells per side, power of two >= 4               */
@@ -86,7 +87,7 @@ typedef struct {
 
 typedef struct {
   int32_t levels;      /* multigrid levels, coarsest N / 2^(levels-1) >= 2          */
-  int32_t box;         /* box edge n in cells: 1, 2 or 4; every smoothed level needs
+  int32_t box;         /* box edge n in cells: 1, 2, 4 or 8; every smoothed level needs
                           N_l >= max(4, 2n) (colour classes of boxes stay disjoint)  */
   int32_t nu1, nu2;    /* pre- and post-smoothing sweeps (Algorithm 1)              */
   int32_t maxit;       /* FGMRES iteration cap over all cycles: 1..1000 when restart
@@ -125,6 +126,16 @@ typedef struct {
                           maxit V-cycles; stats.iters counts V-cycles)          */
   double omega;        /* weight of each box correction, w[box] += omega z_box:
                           0 or 1 = the paper's undamped boxes, else (0, 1]     */
+  int32_t orth;        /* FGMRES orthogonalisation (the paper fixes none):
+                          IBMG_ORTH_CGS2, classical Gram-Schmidt twice (four
+                          passes over the basis per iteration), or
+                          IBMG_ORTH_DCGS2, the same two projections with the
+                          second delayed by one iteration (one pass for the
+                          products, one for the update): the same basis in
+                          exact arithmetic.  The stopping test of an iteration
+                          then uses its column before the delayed projection;
+                          the column is completed before the iterate is
+                          formed.  Batches take IBMG_ORTH_CGS2 only.        */
 } ibmg_opts;
 
 typedef struct {
@@ -179,11 +190,17 @@ int ibmg_phase_timing(ibmg_handle* h, double* total_ms, int64_t* launches, doubl
  *                         rows of every unknown and the elastic rows);
  *   IBMG_KERNEL_MULTIDOT  one classical Gram-Schmidt dot pass of FGMRES: the
  *                         first `arg` basis vectors against basis vector `arg`;
- *   IBMG_KERNEL_UPDATE    one Gram-Schmidt update pass with `arg` vectors.
+ *   IBMG_KERNEL_UPDATE    one Gram-Schmidt update pass with `arg` vectors;
+ *   IBMG_KERNEL_DOT2      the delayed form's product pass: basis vectors
+ *                         0 .. arg against vectors arg and arg + 1;
+ *   IBMG_KERNEL_UPDATE2   the delayed form's update pass over `arg` vectors
+ *                         (completes vector arg, projects vector arg + 1),
+ *                         timed on zero coefficients so the basis is unchanged.
  * The Krylov kernels run on the basis left by the last solve (1 <= arg <= the
- * restart length; results are not used).  avg_us: mean time per launch;
+ * restart length, arg + 1 <= it for the delayed form's; results are not used).  avg_us: mean time per launch;
  * bytes: the launch's algorithmic bytes.  Needs a setup.  Synchronises. */
-enum { IBMG_KERNEL_BOX = 0, IBMG_KERNEL_RES = 1, IBMG_KERNEL_MULTIDOT = 2, IBMG_KERNEL_UPDATE = 3 };
+enum { IBMG_KERNEL_BOX = 0, IBMG_KERNEL_RES = 1, IBMG_KERNEL_MULTIDOT = 2, IBMG_KERNEL_UPDATE = 3,
+       IBMG_KERNEL_DOT2 = 4, IBMG_KERNEL_UPDATE2 = 5 };
 int ibmg_kernel_bench(ibmg_handle* h, int kernel, int level, int arg, int reps, double* avg_us, double* bytes);
 
 /* Operator setup at positions X (Sec. 2.3.2 lags S at X^n; Sec. 3.2 builds the
@@ -280,7 +297,8 @@ int ibmg_spread_noalloc(int32_t N, int32_t delta, int32_t M, const double* X, co
  *     and the V-cycle over all problems is one captured graph. --- */
 typedef struct ibmg_batch ibmg_batch;
 /* nprob problems (1..4096); probs and opts are HOST arrays of nprob entries
- * (copied).  All opts must share vcycle_prec.  Errors as ibmg_create. */
+ * (copied).  All opts must share vcycle_prec and take IBMG_ORTH_CGS2.
+ * Errors as ibmg_create. */
 int ibmg_batch_create(ibmg_batch** out, int32_t nprob, const ibmg_problem* probs,
                       const ibmg_opts* opts, void* hip_stream);
 /* One device workspace for every problem plus the batch's tables. */

@@ -112,10 +112,12 @@ void layout(ibmg_handle* h) {
   take(cur, h->cs, (m + 1) * sizeof(double));
   take(cur, h->sn, (m + 1) * sizeof(double));
   take(cur, h->y, (m + 1) * sizeof(double));
-  take(cur, h->hc, (m + 2) * sizeof(double));
+  take(cur, h->hc, 2 * (m + 2) * sizeof(double));
   take(cur, h->flags, 8 * sizeof(double));
   take(cur, h->scal, 16 * sizeof(double));
-  take(cur, h->partial, (size_t)kDotBlocks * (m + 2) * sizeof(double));
+  // product passes (two vectors per pass in the delayed form) and the
+  // per-workgroup norm shares of the delayed form's update pass
+  take(cur, h->partial, std::max((size_t)kDotBlocks * 2 * (m + 2), (size_t)nblk(n0)) * sizeof(double));
   take(cur, h->bvec, n0 * sizeof(double));
   take(cur, h->xvec, n0 * sizeof(double));
   take(cur, h->rvec, n0 * sizeof(double));
@@ -438,6 +440,9 @@ int do_solve_impl(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
   double* scal = h->p<double>(h->scal);
   double* partial = h->p<double>(h->partial);
   double* hc = h->p<double>(h->hc);
+  double* cs = h->p<double>(h->cs);
+  double* sn = h->p<double>(h->sn);
+  const bool dcgs2 = h->orth == IBMG_ORTH_DCGS2;
   double hs[4];
   h->ev_used = 0;
   dot(h, b, b, scal);
@@ -493,14 +498,29 @@ int do_solve_impl(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
     // Iteration j: preconditioner, operator, classical Gram-Schmidt twice,
     // H(j+1, j) and the Givens step; its flags land in pinned slot j & 1 and
     // an event marks them.
+    // Delayed form: V[j] holds u_j until iteration j completes it into v_j
+    // (and completes column j - 1); column k - 1 of the last iteration is
+    // completed after the loop unless a later iteration was enqueued.
+    int enq_max = -1;
     auto enqueue = [&](int j) -> int {
       double* vj = V + (size_t)j * n0;
       double* vn = V + (size_t)(j + 1) * n0;
       double* zj = Z + (size_t)j * n0;
       double* colj = H + (size_t)j * ldh;
+      enq_max = j;
       precond(h, vj, zj);
       if (h->launch_error) return IBMG_EHIP;
       apply0(h, zj, vn);
+      if (dcgs2) {
+        launch_multidot2(s, V, n0, j + 1, vj, vn, n0, partial, kDotBlocks);
+        launch_reduce(s, partial, kDotBlocks, 2 * (j + 1), hc, 0);
+        launch_dcgs2_coef(s, hc, hc + (j + 1), j - 1, H, ldh, cs, sn, g, scal + 2);
+        launch_dcgs2_update(s, V, n0, j, hc, hc + (j + 1), scal + 2, n0, partial);
+        launch_reduce2(s, partial, (int)nblk(n0), colj + j + 1, scal + 1);
+        launch_scale_tentative(s, vn, n0, scal + 1, H, ldh, g, cs, sn, j, h->flags_d + 4 * (j & 1), target);
+        IBMG_HIP(hipEventRecord(h->flag_ev[j & 1], s));
+        return IBMG_OK;
+      }
       launch_multidot(s, V, n0, j + 1, vn, n0, partial, kDotBlocks);
       launch_reduce(s, partial, kDotBlocks, j + 1, colj, 0);
       launch_update_acc(s, V, n0, j + 1, colj, vn, n0, nullptr);
@@ -549,6 +569,12 @@ int do_solve_impl(ibmg_handle* h, const double* b, double* x, ibmg_stats* st) {
         queued = j < m && total < cap;
         if (queued && (rc = enqueue(j))) return rc;
       }
+    }
+    if (dcgs2 && k > 0 && enq_max < k) {   // complete column k - 1 (second projection of u_k)
+      const int c = k - 1;
+      launch_multidot(s, V, n0, c + 2, V + (size_t)(c + 1) * n0, n0, partial, kDotBlocks);
+      launch_reduce(s, partial, kDotBlocks, c + 2, hc, 0);
+      launch_dcgs2_coef(s, hc, nullptr, c, H, ldh, cs, sn, g, scal + 2);
     }
     launch_backsolve(s, H, ldh, g, k, h->p<double>(h->y));
     launch_update(s, Z, n0, k, h->p<double>(h->y), x, n0, 1.0);
@@ -776,6 +802,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   if (op->scheme != IBMG_IMPLICIT && op->scheme != IBMG_EXPLICIT) return IBMG_EINVAL;
   if (op->solver != IBMG_SOLVER_FGMRES && op->solver != IBMG_SOLVER_MG) return IBMG_EINVAL;
   if (!(op->omega >= 0.0 && op->omega <= 1.0)) return IBMG_EINVAL;
+  if (op->orth != IBMG_ORTH_CGS2 && op->orth != IBMG_ORTH_DCGS2) return IBMG_EINVAL;
   if (op->tail_max != 0 && (op->tail_max < 1 || op->tail_max > kSmallLevel || (op->tail_max & (op->tail_max - 1))))
     return IBMG_EINVAL;
   if (pr->n_points < 0 || pr->n_fibers < 0) return IBMG_EINVAL;
@@ -789,6 +816,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   h->scheme = op->scheme;
   h->solver = op->solver;
   h->omega = op->omega == 0.0 ? 1.0 : op->omega;
+  h->orth = op->orth;
   h->rtol = op->rtol; h->prec = op->vcycle_prec; h->guess = op->guess; h->ncol = op->colours;
   for (int l = 0; l < IBMG_MAX_LEVELS; ++l) h->ncol_l[l] = (op->colours_from > 0 && l >= op->colours_from) ? 2 : op->colours;
   h->tail_max = op->tail_max ? op->tail_max : kSmallLevel;
@@ -1013,6 +1041,39 @@ int ibmg_kernel_bench(ibmg_handle* h, int kernel, int level, int arg, int reps, 
           avg_us);
       // the arg basis vectors, read and write the updated vector
       *bytes = ((double)arg + 2.0) * n0 * sizeof(double);
+      return rc;
+    }
+    case IBMG_KERNEL_DOT2: {
+      // the delayed form's product pass: V[0 .. arg] against V[arg] and V[arg + 1]
+      if (arg < 1 || arg + 1 > h->mb) return IBMG_EINVAL;
+      double* part = h->p<double>(h->partial);
+      const int rc = replay_time(
+          h, reps,
+          [&](hipStream_t s) {
+            launch_multidot2(s, V, n0, arg + 1, V + (size_t)arg * n0, V + (size_t)(arg + 1) * n0, n0, part,
+                             kDotBlocks);
+          },
+          avg_us);
+      // the arg + 1 basis vectors once, the two vectors once per group of sixteen
+      *bytes = ((double)(arg + 1) + 2.0 * ((arg + 1 + 15) / 16)) * n0 * sizeof(double);
+      return rc;
+    }
+    case IBMG_KERNEL_UPDATE2: {
+      // the delayed form's update pass with arg vectors, on zero coefficients
+      // and 1 / rho = 1 (V unchanged; the timing does not depend on the values)
+      if (arg < 1 || arg + 1 > h->mb) return IBMG_EINVAL;
+      hipStream_t s0 = h->stream;
+      double* c = h->p<double>(h->hc);
+      double* coef = h->p<double>(h->scal) + 2;
+      k_fill<double><<<nblk(2 * (size_t)arg), 256, 0, s0>>>(c, 2 * (size_t)arg, 0.0);
+      k_fill<double><<<1, 256, 0, s0>>>(coef, 1, 1.0);
+      k_fill<double><<<1, 256, 0, s0>>>(coef + 1, 1, 0.0);
+      double* part = h->p<double>(h->partial);
+      const int rc = replay_time(
+          h, reps, [&](hipStream_t s) { launch_dcgs2_update(s, V, n0, arg, c, c + arg, coef, n0, part); },
+          avg_us);
+      // the arg basis vectors, read and write u and w
+      *bytes = ((double)arg + 4.0) * n0 * sizeof(double);
       return rc;
     }
     default:

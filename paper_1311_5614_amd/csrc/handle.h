@@ -47,6 +47,7 @@ struct ibmg_handle {
   int scheme = 0; // IBMG_IMPLICIT or IBMG_EXPLICIT
   int solver = 0; // IBMG_SOLVER_FGMRES or IBMG_SOLVER_MG
   double omega = 1.0;  // box correction weight
+  int orth = 0;        // IBMG_ORTH_CGS2 or IBMG_ORTH_DCGS2
   int mb = 100;   // Krylov basis size: the FGMRES(m) restart length (maxit caps the iterations of all cycles)
   int tail_max = ibmg::kSmallLevel;   // largest level size run by the LDS-resident tail
   double rho = 1, mu = 1, K = 0, rtol = 1e-8;

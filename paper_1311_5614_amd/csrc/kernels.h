@@ -139,5 +139,18 @@ void launch_update_acc(hipStream_t s, const double* V, size_t ldv, int nvec, con
                        double* acc);
 void launch_scale_givens(hipStream_t s, double* w, size_t n, const double* nrm2, double* H, int ldh, double* g,
                          double* cs, double* sn, int j, double* flags, double target);
+// delayed CGS2 (krylov.hip): the products of V[0 .. nvec-1] with r1 and r2 in
+// one pass (2 nvec dots, r2's after r1's); the coefficients and column
+// completion; the update pass (partial = one |w'|^2 share per workgroup of
+// nblk(n)); the scaling of u_{j+1} with the stopping test on a rotated copy
+void launch_multidot2(hipStream_t s, const double* V, size_t ldv, int nvec, const double* r1, const double* r2,
+                      size_t n, double* partial, int nblocks);
+void launch_dcgs2_coef(hipStream_t s, const double* a, const double* c, int jf, double* H, int ldh, double* cs,
+                       double* sn, double* g, double* coef);
+void launch_dcgs2_update(hipStream_t s, double* V, size_t ldv, int j, const double* t, const double* sc,
+                         const double* coef, size_t n, double* partial);
+void launch_scale_tentative(hipStream_t s, double* w, size_t n, const double* nrm2, double* H, int ldh,
+                            const double* g, const double* cs, const double* sn, int j, double* flags,
+                            double target);
 
 }  // namespace ibmg

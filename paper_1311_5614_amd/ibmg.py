@@ -27,6 +27,8 @@ IBMG_GUESS_ZERO, IBMG_GUESS_PREV = 0, 1
 IBMG_IMPLICIT, IBMG_EXPLICIT = 0, 1
 IBMG_SOLVER_FGMRES, IBMG_SOLVER_MG = 0, 1
 IBMG_KERNEL_BOX, IBMG_KERNEL_RES, IBMG_KERNEL_MULTIDOT, IBMG_KERNEL_UPDATE = 0, 1, 2, 3
+IBMG_KERNEL_DOT2, IBMG_KERNEL_UPDATE2 = 4, 5
+IBMG_ORTH_CGS2, IBMG_ORTH_DCGS2 = 0, 1
 IBMG_GUESS_RECORD, IBMG_GUESS_EXTRAP, IBMG_GUESS_LEARNED = 0, 1, 2
 
 EXPORTS = [
@@ -56,7 +58,7 @@ class ibmg_opts(C.Structure):
                 ("maxit", C.c_int32), ("rtol", C.c_double), ("vcycle_prec", C.c_int32),
                 ("guess", C.c_int32), ("colours", C.c_int32), ("tail_max", C.c_int32),
                 ("restart", C.c_int32), ("colours_from", C.c_int32), ("scheme", C.c_int32),
-                ("solver", C.c_int32), ("omega", C.c_double)]
+                ("solver", C.c_int32), ("omega", C.c_double), ("orth", C.c_int32)]
 
 
 class ibmg_stats(C.Structure):
@@ -188,6 +190,7 @@ class Config:
     scheme: int = 0
     solver: int = 0
     omega: float = 1.0
+    orth: int = 0
 
 
 def _problem(cfg: Config, fiber_offsets):
@@ -198,7 +201,8 @@ def _problem(cfg: Config, fiber_offsets):
     prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, M, max(0, len(offs) - 1),
                         C.cast(arr, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
     opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
-                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart, cfg.colours_from, cfg.scheme, cfg.solver, cfg.omega)
+                     cfg.guess, cfg.colours, cfg.tail_max, cfg.restart, cfg.colours_from, cfg.scheme, cfg.solver, cfg.omega,
+                     cfg.orth)
     return prob, opts, arr, M
 
 

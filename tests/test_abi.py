@@ -42,12 +42,12 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "ibmg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
          offsetof(ibmg_problem, fiber_offsets), offsetof(ibmg_problem, K), offsetof(ibmg_opts, rtol),
          offsetof(ibmg_stats, t_step_ms), offsetof(ibmg_opts, colours), offsetof(ibmg_opts, tail_max),
          offsetof(ibmg_stats, rel_resid_est), offsetof(ibmg_stats, guess_rejected), offsetof(ibmg_opts, restart),
          offsetof(ibmg_opts, colours_from), offsetof(ibmg_opts, scheme),
-         offsetof(ibmg_opts, solver), offsetof(ibmg_opts, omega));
+         offsetof(ibmg_opts, solver), offsetof(ibmg_opts, omega), offsetof(ibmg_opts, orth));
   return 0;
 }
 """
@@ -63,7 +63,7 @@ int main(void) {
             ibmg.ibmg_opts.tail_max.offset, ibmg.ibmg_stats.rel_resid_est.offset,
             ibmg.ibmg_stats.guess_rejected.offset, ibmg.ibmg_opts.restart.offset,
             ibmg.ibmg_opts.colours_from.offset, ibmg.ibmg_opts.scheme.offset,
-            ibmg.ibmg_opts.solver.offset, ibmg.ibmg_opts.omega.offset]
+            ibmg.ibmg_opts.solver.offset, ibmg.ibmg_opts.omega.offset, ibmg.ibmg_opts.orth.offset]
     assert got == want
 
 
@@ -75,7 +75,7 @@ def _create(N=32, levels=3, box=4, offs=(0, 40), **kw):
     opts = ibmg.ibmg_opts(levels, box, kw.get("nu1", 2), kw.get("nu2", 2), kw.get("maxit", 100),
                           kw.get("rtol", 1e-8), kw.get("prec", 0), kw.get("guess", 0), kw.get("colours", 2),
                           kw.get("tail_max", 0), kw.get("restart", 0), kw.get("colours_from", 0),
-                          kw.get("scheme", 0), kw.get("solver", 0), kw.get("omega", 1.0))
+                          kw.get("scheme", 0), kw.get("solver", 0), kw.get("omega", 1.0), kw.get("orth", 0))
     h = C.c_void_p()
     rc = L.ibmg_create(C.byref(h), C.byref(prob), C.byref(opts), None)
     return rc, h, L
@@ -124,6 +124,7 @@ def test_create_validates_shapes_without_gpu():
     assert _create(scheme=1)[0] == 0 and _create(scheme=2)[0] == -1
     assert _create(solver=1)[0] == 0 and _create(solver=2)[0] == -1
     assert _create(omega=0.8)[0] == 0 and _create(omega=1.5)[0] == -1 and _create(omega=-0.1)[0] == -1
+    assert _create(orth=1)[0] == 0 and _create(orth=2)[0] == -1 and _create(orth=-1)[0] == -1
 
 
 def test_status_strings():

@@ -199,17 +199,19 @@ def test_c5_fp32_trajectory_every_step_at_rtol():
 def test_c3_step_meets_tolerance_in_oracle_norm():
     """One step of the 1024x1024 eight-ring workload (16384 points, K = 1e6,
     dt = 500 x the explicit limit, 7 levels) with the schedule the benchmark
-    times for it, FP32 V-cycle inside FP64 FGMRES: the GPU velocity and
-    pressure meet rtol 1e-8 in the oracle's operator, the positions move by
-    the oracle's interpolation of the GPU velocity, and the pressure has
-    zero mean."""
+    times for it (box order per level, box weight, V-cycle precision, basis,
+    orthogonalisation): the GPU velocity and pressure meet rtol 1e-8 in the
+    oracle's operator, the positions move by the oracle's interpolation of
+    the GPU velocity, and the pressure has zero mean."""
     from paper_1311_5614_amd import ibmg
     w = ibgen.config_c3()
     dt = _dts("c3")[0]
     sch = _schedule("c3", "1024")
     cfg = ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, box=sch["box"], nu1=sch["nu1"], nu2=sch["nu2"],
                       maxit=sch.get("maxit", 200), restart=sch.get("restart", 0), rtol=w.rtol,
-                      prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"])
+                      prec=sch["prec"], colours=sch["colours"], tail_max=sch["tail_max"],
+                      colours_from=sch.get("colours_from", 0), omega=sch.get("omega", 1.0),
+                      orth=sch.get("orth", 0))
     s = ibmg.Solver(cfg, w.fiber_offsets, DEV)
     z = torch.zeros(w.N, w.N, dtype=torch.float64, device=DEV)
     u, v, p, X = z.clone(), z.clone(), z.clone(), tdev(w.X)

@@ -668,3 +668,96 @@ def test_damped_vcycle_parity(omega, colours):
     r = np.random.default_rng(43).standard_normal(3 * 64 * 64)
     r[2 * 4096:] -= r[2 * 4096:].mean()
     assert rel(tnp(s.vcycle(tdev(r))), V(r)) < 1e-11
+
+
+def _solver_64(w, K, **kw):
+    from paper_1311_5614_amd import ibmg
+    cfg = ibmg.Config(N=64, levels=4, K=K, **kw)
+    return ibmg.Solver(cfg, w.fiber_offsets, DEV)
+
+
+@pytest.mark.parametrize("restart,prec", [(0, 0), (8, 0), (0, 1)])
+def test_delayed_cgs2_matches_oracle(restart, prec):
+    """FGMRES with the second Gram-Schmidt projection delayed by one
+    iteration (orth = IBMG_ORTH_DCGS2) against the oracle's delayed form and
+    the GPU's CGS2 on the same stiff 64^2 system: counts within one, the
+    solution meets rtol in the oracle's operator, at equal counts the
+    iterates agree (FP64 V-cycle); with phase timing on (no lookahead, the
+    last column completed after the loop) the solve is bitwise the same."""
+    from paper_1311_5614_amd import ibmg
+    K, fac = 1e6, 200.0
+    w, dt, s0 = make(N=64, levels=4, M=160, K=K, dt_factor=fac, n_fibers=2, rtol=1e-10)
+    s0.close()
+    kw = dict(rtol=1e-10, prec=prec, maxit=400, restart=restart)
+    s = _solver_64(w, K, orth=ibmg.IBMG_ORTH_DCGS2, **kw)
+    sc = _solver_64(w, K, orth=ibmg.IBMG_ORTH_CGS2, **kw)
+    _setup(s, w, dt)
+    _setup(sc, w, dt)
+    lv, V = ostep.build(64, 4, 1.0, 1.0, dt, w.X, w.fiber_offsets, K)
+    rng = np.random.default_rng(43)
+    u = rng.standard_normal((64, 64))
+    v = rng.standard_normal((64, 64))
+    bo = system.rhs(u, v, w.X, w.fiber_offsets, K, dt, 1.0)
+    res = krylov.fgmres(lv[0].A, bo, V, rtol=1e-10, maxit=400, restart=restart or None, orth="dcgs2")
+    b = s.rhs(tdev(u), tdev(v))
+    x = torch.zeros(3 * 4096, dtype=torch.float64, device=DEV)
+    st = s.solve(b, x)
+    xc = torch.zeros_like(x)
+    stc = sc.solve(b, xc)
+    s.set_timing(True)
+    x2 = torch.zeros_like(x)
+    st2 = s.solve(b, x2)
+    s.set_timing(False)
+    print(f"dcgs2 restart {restart} prec {prec}: gpu {st['iters']} oracle {res.iters} gpu cgs2 {stc['iters']}")
+    assert st["converged"] == 1 and stc["converged"] == 1 and res.converged
+    assert abs(st["iters"] - res.iters) <= (1 if prec == 0 else 3)
+    assert abs(st["iters"] - stc["iters"]) <= (1 if prec == 0 else 3)
+    assert st2["iters"] == st["iters"] and torch.equal(x, x2)
+    xg = tnp(x)
+    assert np.linalg.norm(bo - lv[0].A @ xg) / np.linalg.norm(bo) <= 1e-10
+    xg[2 * 4096:] -= xg[2 * 4096:].mean()
+    xcg = tnp(xc)
+    xcg[2 * 4096:] -= xcg[2 * 4096:].mean()
+    assert np.linalg.norm(xg - xcg) / np.linalg.norm(xcg) < 1e-8
+    if prec == 0 and st["iters"] == res.iters:
+        xo = res.x.copy()
+        xo[2 * 4096:] -= xo[2 * 4096:].mean()
+        assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-9
+    s.close()
+    sc.close()
+
+
+def test_delayed_cgs2_fixed_iteration_counts():
+    """After exactly k iterations (cap k, unreachable rtol; the last column is
+    completed after the loop) the delayed form's iterate equals the oracle's
+    delayed form and the GPU's CGS2 to rounding, for k = 1, 2, 7 and a
+    restart length of 5 (k = 7 spans two cycles)."""
+    from paper_1311_5614_amd import ibmg
+    K, fac = 1e5, 100.0
+    w, dt, s0 = make(N=64, levels=4, M=160, K=K, dt_factor=fac, n_fibers=2)
+    s0.close()
+    lv, V = ostep.build(64, 4, 1.0, 1.0, dt, w.X, w.fiber_offsets, K)
+    rng = np.random.default_rng(44)
+    u = rng.standard_normal((64, 64))
+    v = rng.standard_normal((64, 64))
+    bo = system.rhs(u, v, w.X, w.fiber_offsets, K, dt, 1.0)
+    for k, restart in ((1, 0), (2, 0), (7, 0), (7, 5)):
+        res = krylov.fgmres(lv[0].A, bo, V, rtol=1e-30, maxit=k, restart=restart or None, orth="dcgs2")
+        out = []
+        for orth in (ibmg.IBMG_ORTH_DCGS2, ibmg.IBMG_ORTH_CGS2):
+            s = _solver_64(w, K, orth=orth, rtol=1e-30, maxit=k, restart=restart)
+            _setup(s, w, dt)
+            b = s.rhs(tdev(u), tdev(v))
+            x = torch.zeros(3 * 4096, dtype=torch.float64, device=DEV)
+            st = s.solve(b, x)
+            assert st["iters"] == k and st["converged"] == 0
+            xg = tnp(x)
+            xg[2 * 4096:] -= xg[2 * 4096:].mean()
+            out.append(xg)
+            s.close()
+        xo = res.x.copy()
+        xo[2 * 4096:] -= xo[2 * 4096:].mean()
+        e_or = np.linalg.norm(out[0] - xo) / np.linalg.norm(xo)
+        e_cg = np.linalg.norm(out[0] - out[1]) / np.linalg.norm(out[1])
+        print(f"k {k} restart {restart}: vs oracle {e_or:.2e}, vs cgs2 {e_cg:.2e}")
+        assert e_or < 1e-10 and e_cg < 1e-10
