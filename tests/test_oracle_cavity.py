@@ -1,0 +1,223 @@
+"""Pins of the walled test problem of the paper (oracle/cavity.py, CPU):
+the printed alpha_exp of Table 1, closed forms of the walled MAC operators
+and transfers, and the walled hierarchy's consistency."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cavity, ib, mac
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+rng = np.random.default_rng(7)
+
+
+def _table1():
+    with open(os.path.join(ROOT, "tests", "golden", "table1_alpha_exp.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_alpha_exp_table1(idx):
+    """Table 1: alpha_exp to the printed digits (N = 32, 64, 128; N = 256 gives
+    2.2855 against the printed 2.28 and takes minutes, so it is not run here).
+    Fails for the periodic domain (6.03 at N = 32), Peskin's IB4 delta (6.10)
+    and the node-area spreading weight ds1 ds2 (6.04)."""
+    t = _table1()
+    N, want = t["N"][idx], t["alpha_exp"][idx]
+    got = cavity.alpha_exp(N)
+    assert abs(got - want) <= 0.005, (N, got, want)
+
+
+def test_annulus_sizes():
+    """Sec. 4: M1 = 19 N / 8, M2 = 3 N / 32 + 1, node spacing about 2/3 h."""
+    for N in (32, 64, 128):
+        a = cavity.annulus(N)
+        assert (a.M1, a.M2) == (19 * N // 8, 3 * N // 32 + 1)
+        assert a.X.shape == (a.M1 * a.M2, 2)
+        assert abs(a.ds1 * N - 0.6614) < 1e-3 and abs(a.ds2 * N - 2.0 / 3.0) < 1e-12
+        r = np.hypot(a.X[:, 0] - 0.5, a.X[:, 1] - 0.5)
+        assert abs(r.min() - 0.25) < 1e-14 and abs(r.max() - 0.3125) < 1e-14
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_walled_operators_closed_forms(N):
+    """D = -G^T on the interior, D G = the cell Laplacian with homogeneous
+    Neumann walls (pressure), wall rows and columns decoupled, and the walled
+    Laplacian symmetric and negative definite on interior faces."""
+    Gx, Gy = cavity.gradient(N)
+    Dx, Dy = cavity.divergence(N)
+    assert abs(Dx + Gx.T).max() == 0 and abs(Dy + Gy.T).max() == 0
+    h = 1.0 / N
+    P = (Dx @ Gx + Dy @ Gy).toarray()
+    # Neumann cell Laplacian: each cell couples to its in-domain neighbours
+    for j in range(N):
+        for i in range(N):
+            k = j * N + i
+            nb = [(i + 1, j), (i - 1, j), (i, j + 1), (i, j - 1)]
+            nb = [(a, b) for a, b in nb if 0 <= a < N and 0 <= b < N]
+            assert abs(P[k, k] + len(nb) / h**2) < 1e-9
+            for a, b in nb:
+                assert abs(P[k, b * N + a] - 1 / h**2) < 1e-9
+    wu, wv = cavity.wall_u(N).ravel(), cavity.wall_v(N).ravel()
+    for comp, w in ((0, wu), (1, wv)):
+        L = cavity.laplacian_face(N, comp).toarray()
+        assert np.all(L[w] == 0) and np.all(L[:, w] == 0)
+        Li = L[~w][:, ~w]
+        assert np.allclose(Li, Li.T)
+        assert np.max(np.linalg.eigvalsh(Li)) < 0
+    assert np.all(Gx.toarray()[wu] == 0) and np.all(Dx.toarray()[:, wu] == 0)
+    assert np.all(Gy.toarray()[wv] == 0) and np.all(Dy.toarray()[:, wv] == 0)
+
+
+def test_walled_laplacian_ghost_on_linear_profile():
+    """The ghost reading (wall value = average of the face and its ghost) is
+    exact for a profile linear in y: u = y has zero second difference in
+    every row of u faces away from the x walls, including the row next to
+    y = 0; in the row next to y = 1 the homogeneous operator misses exactly
+    the ghost's wall term 2 g / h^2 with g = u(1) = 1."""
+    N = 16
+    h = 1.0 / N
+    j, i = np.mgrid[0:N, 0:N]
+    u = (j + 0.5) * h
+    u[:, 0] = 0.0
+    Lu = (cavity.laplacian_face(N, 0) @ u.ravel()).reshape(N, N)
+    inner = (i >= 2) & (i <= N - 2)
+    assert np.max(np.abs(Lu[inner & (j < N - 1)])) < 1e-9
+    assert np.max(np.abs(Lu[inner & (j == N - 1)] + 2.0 / h**2)) < 1e-9
+
+
+def test_walled_transfers():
+    """Restriction of constants away from walls and zero rows on coarse wall
+    faces; prolongation of an interior coarse field reproduces bilinear
+    values, with 1/2 weight on the fine row next to a tangential wall and
+    nothing on fine wall faces; pressure transfers unchanged."""
+    N, Nc = 16, 8
+    Ru, Rv = cavity.restrict_u(N), cavity.restrict_v(N)
+    Pu, Pv = cavity.prolong_u(N), cavity.prolong_v(N)
+    one = np.ones(N * N)
+    ru = (Ru @ one).reshape(Nc, Nc)
+    assert np.all(ru[:, 0] == 0) and np.allclose(ru[:, 1:], 1.0)
+    rv = (Rv @ one).reshape(Nc, Nc)
+    assert np.all(rv[0, :] == 0) and np.allclose(rv[1:, :], 1.0)
+    e = np.zeros((Nc, Nc))
+    e[0, 3] = 1.0      # coarse u face I = 3 in the row next to y = 0
+    f = (Pu @ e.ravel()).reshape(N, N)
+    assert abs(f[0, 6] - 0.5) < 1e-15 and abs(f[1, 6] - 0.75) < 1e-15 and abs(f[2, 6] - 0.25) < 1e-15
+    assert abs(f[0, 5] - 0.25) < 1e-15 and abs(f[0, 7] - 0.25) < 1e-15
+    assert np.all(f[:, 0] == 0)
+    ec = rng.standard_normal((Nc, Nc))
+    ec[:, 0] = 0.0
+    assert np.all((Pu @ ec.ravel()).reshape(N, N)[:, 0] == 0)
+    assert np.all((Pv @ ec.T.ravel()).reshape(N, N)[0, :] == 0)
+
+
+def test_walled_hierarchy_consistent():
+    """The fine elasticity block is symmetric positive semidefinite; on every
+    level the elasticity blocks leave the wall faces alone (zero rows and
+    columns); the pressure constant is the only null vector of the coarsest
+    operator (bordered system non-singular)."""
+    N = 32
+    a = cavity.annulus(N)
+    lv = cavity.hierarchy(N, 3, 60.0, a)
+    for M in (lv[0].M_u, lv[0].M_v):
+        Md = M.toarray()
+        assert np.allclose(Md, Md.T, atol=1e-12 * abs(Md).max())
+        assert np.min(np.linalg.eigvalsh(Md)) > -1e-9 * abs(Md).max()
+    for l in lv:
+        for M, w in ((l.M_u, cavity.wall_u(l.N).ravel()), (l.M_v, cavity.wall_v(l.N).ravel())):
+            Md = M.toarray()
+            assert np.all(Md[w] == 0) and np.all(Md[:, w] == 0)
+        assert abs(l.M_u).max() > 0
+    A = lv[-1].A.toarray()
+    n = A.shape[0]
+    Nl = lv[-1].N
+    q = np.zeros(n)
+    q[2 * Nl * Nl:] = 1.0
+    assert np.max(np.abs(A @ q)) < 1e-12
+    B = np.zeros((n + 1, n + 1))
+    B[:n, :n] = A
+    B[2 * Nl * Nl:n, n] = 1
+    B[n, 2 * Nl * Nl:n] = 1
+    assert np.linalg.matrix_rank(B) == n + 1
+
+
+# ---------------------------------------------------------------- printed iteration counts
+
+def _counts():
+    with open(os.path.join(ROOT, "tests", "golden", "solver_counts.json")) as f:
+        return json.load(f)
+
+
+_AEXP = {}
+
+
+def _alpha_exp(N):
+    if N not in _AEXP:
+        _AEXP[N] = cavity.alpha_exp(N)
+    return _AEXP[N]
+
+
+def _cavity_levels(N, box, ratio):
+    from oracle import mg
+    a = cavity.annulus(N)
+    levels = int(np.log2(N // max(4, box))) + 1      # coarsest max(4, b) (Sec. 6.1)
+    lv = cavity.hierarchy(N, levels, ratio * _alpha_exp(N), a)
+    return lv, mg
+
+
+def _gmres_count(N, box, nu, ratio):
+    from oracle import krylov
+    lv, mg = _cavity_levels(N, box, ratio)
+    V = mg.VCycle(lv, box, nu[0], nu[1], "paper")
+    r = krylov.fgmres(lv[0].A, cavity.rhs(N, None, 0.0), V, rtol=1e-6, maxit=100)
+    return r.iters
+
+
+@pytest.mark.parametrize("ratio", [1, 10, 100])
+def test_fig3_mg_gmres_counts(ratio):
+    """Sec. 5.1: MG-preconditioned GMRES on the cavity, h = 2^-5, single-cell
+    boxes in the paper's lexicographic order, V(1,1), zero start, residual
+    reduced by 1e-6: the printed counts (8 flat to relative stiffness 10, 30
+    at 100) within 2.  The right-hand side is the lid alone (the reading that
+    reproduces the text's counts)."""
+    want = _counts()["fig3"]["mg_gmres"][str(ratio)]
+    got = _gmres_count(32, 1, (1, 1), float(ratio))
+    assert abs(got - want) <= 2, (ratio, got, want)
+
+
+@pytest.mark.parametrize("ratio", [1, 100])
+def test_fig3_mg_solver_counts(ratio):
+    """Sec. 5.1: multigrid alone, same problem: 9 V-cycles at low stiffness,
+    62 at relative stiffness 100 (within 2)."""
+    lv, mg = _cavity_levels(32, 1, float(ratio))
+    V = mg.VCycle(lv, 1, 1, 1, "paper")
+    x, its, conv, hist = mg.mg_solve(lv[0].A, cavity.rhs(32, None, 0.0), V, rtol=1e-6, maxit=200)
+    want = _counts()["fig3"]["mg"][str(ratio)]
+    assert conv and abs(its - want) <= 2, (ratio, its, want)
+
+
+@pytest.mark.parametrize("box", [4, 8])
+def test_table2_counts_big_boxes(box):
+    """Table 2 (Sec. 6.3), h = 2^-6, boxes of 4 x 4 and 8 x 8 cells: all
+    twelve counts of each box size (four sweep pairs x three relative
+    stiffnesses) within 2 of the printed ones.  The single-cell rows take
+    minutes and run with IBMG_FULL_TABLES=1 (test_table2_counts_single_cell)."""
+    c = _counts()
+    for nu_key, want_row in c["table2"][str(box)].items():
+        nu = tuple(int(x) for x in nu_key.split(","))
+        for ratio, want in zip(c["ratios"], want_row):
+            got = _gmres_count(64, box, nu, float(ratio))
+            assert abs(got - want) <= 2, (box, nu, ratio, got, want)
+
+
+@pytest.mark.skipif(not os.environ.get("IBMG_FULL_TABLES"), reason="minutes of CPU; set IBMG_FULL_TABLES=1")
+def test_table2_counts_single_cell():
+    """Table 2's single-cell rows (the 100 entry means the cap was reached)."""
+    c = _counts()
+    for nu_key, want_row in c["table2"]["1"].items():
+        nu = tuple(int(x) for x in nu_key.split(","))
+        for ratio, want in zip(c["ratios"], want_row):
+            got = _gmres_count(64, 1, nu, float(ratio))
+            assert abs(got - want) <= 2, (nu, ratio, got, want)
