@@ -70,6 +70,7 @@ typedef enum {
 enum { IBMG_DELTA_IB4 = 0,  /* Peskin's standard 4-point kernel                    */
        IBMG_DELTA_COS4 = 1  /* cosine 4-point kernel printed in Sec. 2.2           */ };
 enum { IBMG_FP64 = 0, IBMG_FP32 = 1 };
+enum { IBMG_PERIODIC = 0, IBMG_CAVITY = 1 };
 enum { IBMG_GUESS_ZERO = 0, IBMG_GUESS_PREV = 1 };
 enum { IBMG_IMPLICIT = 0, IBMG_EXPLICIT = 1 };
 enum { IBMG_SOLVER_FGMRES = 0, IBMG_SOLVER_MG = 1 };
@@ -83,6 +84,18 @@ typedef struct {
   const int32_t* fiber_offsets;  /* HOST, n_fibers + 1 CSR offsets into [0, M]      */
   double K;                      /* nodal spring stiffness, force G = K L X         */
   int32_t delta;                 /* IBMG_DELTA_IB4 or IBMG_DELTA_COS4               */
+  int32_t domain;                /* IBMG_PERIODIC (rho > 0) or IBMG_CAVITY: the unit
+                                    square with walls on all four sides (Sec. 4), the
+                                    velocity zero on them except the tangential
+                                    velocity (1 - cos 2 pi x) / 2 of the top wall;
+                                    rho >= 0 (0: the steady form).  Layout as
+                                    periodic: the faces u[j][0] and v[0][i] lie on
+                                    the walls (standing for x = 1 and y = 1 too),
+                                    carry zero and are identity rows of the system;
+                                    a face next to a wall parallel to it sees the
+                                    ghost 2 g - u across it.  Needs opts.tail_max = 1
+                                    (every smoothed level as grid-wide launches);
+                                    batches take IBMG_PERIODIC only.               */
 } ibmg_problem;
 
 typedef struct {
@@ -297,7 +310,8 @@ int ibmg_spread_noalloc(int32_t N, int32_t delta, int32_t M, const double* X, co
  *     and the V-cycle over all problems is one captured graph. --- */
 typedef struct ibmg_batch ibmg_batch;
 /* nprob problems (1..4096); probs and opts are HOST arrays of nprob entries
- * (copied).  All opts must share vcycle_prec and take IBMG_ORTH_CGS2.
+ * (copied).  All opts must share vcycle_prec and take IBMG_ORTH_CGS2, all
+ * problems IBMG_PERIODIC.
  * Errors as ibmg_create. */
 int ibmg_batch_create(ibmg_batch** out, int32_t nprob, const ibmg_problem* probs,
                       const ibmg_opts* opts, void* hip_stream);

@@ -70,7 +70,8 @@ void layout(ibmg_handle* h) {
       take(cur, B.info, 8 * sizeof(int));
       take(cur, B.ainv_plain, nd2 * sizeof(double));
       take(cur, B.ainv_plain_f, nd2 * sizeof(float));
-      B.max_ib = ib ? (int)std::min<size_t>(nbox, (size_t)M * bpp) : 0;
+      // boxes with elastic rows, plus with walls the 4 (nb - 1) boxes along them
+      B.max_ib = (int)std::min<size_t>(nbox, (ib ? (size_t)M * bpp : 0) + (h->walls ? 4 * (size_t)B.nb : 0));
       take(cur, B.ainv_ib, std::max<size_t>(1, (size_t)B.max_ib) * nd2 * sizeof(double));
     }
   }
@@ -167,8 +168,8 @@ void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w,
   else if (!fused) launch_res<T>(h->stream, v, b, w, r, h->has_ib);
   const bool t = h->timing && h->ev_used + 2 <= (int)h->ev.size();
   if (t) (void)hipEventRecord(h->ev[h->ev_used], h->stream);
-  if (fused) launch_phase_fused<T>(h->stream, v, b, w, colour, h->has_ib);
-  else launch_box<T>(h->stream, vb, from_zero ? b : r, w, colour, h->has_ib);
+  if (fused) launch_phase_fused<T>(h->stream, v, b, w, colour, h->own_boxes());
+  else launch_box<T>(h->stream, vb, from_zero ? b : r, w, colour, h->own_boxes());
   if (t) {
     (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
     // algorithmic bytes of one box launch: per unknown of the colour's boxes
@@ -176,7 +177,7 @@ void phase_timed(ibmg_handle* h, const LevelView<T>& v, int l, const T* b, T* w,
     // box with elastic rows once
     const double boxes = colour_count(v.ncol, v.nb);
     double bytes = boxes * v.ndof * 3.0 * sizeof(T) + (double)v.ndof * v.ndof * sizeof(T);
-    if (h->has_ib) bytes += (double)h->n_ib[l][colour] * v.ndof * v.ndof * sizeof(double);
+    if (h->own_boxes()) bytes += (double)h->n_ib[l][colour] * v.ndof * v.ndof * sizeof(double);
     h->ev_bytes[h->ev_used / 2] = bytes;
     h->ev_used += 2;
   }
@@ -216,14 +217,15 @@ void vcycle(ibmg_handle* h, const T* b0, T* w0, bool w0_zero = false) {
     // Stokes residual and the elastic term in one pass; the restriction
     // subtracts the elastic term (also zeroes w[l+1])
     launch_res<T>(s, v[l], b[l], w[l], r[l], h->has_ib);
-    launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b), w[l + 1], h->has_ib ? v[l].yib : nullptr);
+    launch_restrict<T>(s, v[l].N, r[l], h->p<T>(h->L[l + 1].b), w[l + 1], h->has_ib ? v[l].yib : nullptr,
+                       h->walls);
   }
   if (ls == Lv - 1)
     launch_coarse_apply<T>(s, h->p<double>(h->cainv), h->nr, b[ls], w[ls]);
   else if (launch_tail<T>(s, v, ls, Lv, h->nu1, h->nu2, h->has_ib, h->nr, b[ls], w[ls], h->p<double>(h->cainv)) != 0)
     h->launch_error = true;
   for (int l = ls - 1; l >= 0; --l) {
-    launch_prolong_add<T>(s, v[l].N, w[l + 1], w[l]);
+    launch_prolong_add<T>(s, v[l].N, w[l + 1], w[l], h->walls);
     for (int q = 0; q < h->nu2; ++q) sweep<T>(h, v[l], l, b[l], w[l], r[l]);
   }
 }
@@ -334,7 +336,7 @@ int setup_launch(ibmg_handle* h, double dt, const double* X) {
       else
         launch_windows_coarse(s, B.N, h->p<int>(h->L[l - 1].act), h->p<double>(h->L[l - 1].win),
                               h->L[l - 1].maxact, h->L[l - 1].reach, h->p<int>(B.rows), h->p<int>(B.nact),
-                              B.maxact, B.reach, h->p<double>(B.win), meta);
+                              B.maxact, B.reach, h->p<double>(B.win), meta, h->walls ? 1 : 0);
       if (h->prec == IBMG_FP32) {
         const size_t nw = 2 * (size_t)B.maxact * IBMG_WS;
         k_convert<double, float><<<nblk(nw), 256, 0, s>>>(h->p<double>(B.win), h->p<float>(B.winf), nw);
@@ -346,7 +348,8 @@ int setup_launch(ibmg_handle* h, double dt, const double* X) {
   }
   for (int l = 0; l + 1 < Lv; ++l) {
     LevelBufs& B = h->L[l];
-    launch_box_classes(s, B.N, h->n, B.nb, h->ncol_l[l], h->has_ib ? h->p<int>(B.act) : nullptr, h->p<int>(B.boxflag),
+    launch_box_classes(s, B.N, h->n, B.nb, h->ncol_l[l], h->has_ib ? h->p<int>(B.act) : nullptr, h->walls ? 1 : 0,
+                       h->p<int>(B.boxflag),
                        h->p<int>(B.ib_index), h->p<int>(B.ib_boxes), h->p<int>(B.info));
   }
   // read back counts: boxes with elastic rows per colour, active rows, flags
@@ -389,7 +392,7 @@ int setup_finish(ibmg_handle* h) {
   F.nl = Lv - 1;
   int nfb = 0;
   for (int l = 0; l + 1 < Lv; ++l) {
-    for (int c = 0; c < 5; ++c) h->n_ib[l][c] = h->has_ib ? info[8 * l + c] : 0;
+    for (int c = 0; c < 5; ++c) h->n_ib[l][c] = h->own_boxes() ? info[8 * l + c] : 0;
     if (h->n_ib[l][4] > h->L[l].max_ib) return IBMG_ENOMEM;
     F.v[l] = view<double>(h, l);
     F.ib_boxes[l] = h->p<int>(h->L[l].ib_boxes);
@@ -724,7 +727,7 @@ int step_begin(ibmg_handle* h, double dt, const double* u, const double* v, cons
   double* b = h->p<double>(h->bvec);
   double* x = h->p<double>(h->xvec);
   launch_rhs(s, points(h), h->rho / dt, (double)h->N * h->N, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr,
-             b);
+             b, h->walls ? 1 : 0, h->mu);
   if (h->guess == IBMG_GUESS_PREV) {
     IBMG_HIP(hipMemcpyAsync(x, u, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
     IBMG_HIP(hipMemcpyAsync(x + NN, v, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -781,7 +784,12 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   *out = nullptr;
   const int N = pr->N;
   if (N < 4 || (N & (N - 1)) != 0) return IBMG_ESHAPE;
-  if (!(pr->rho > 0) || !(pr->mu > 0) || !std::isfinite(pr->K) || pr->K < 0) return IBMG_EINVAL;
+  if (pr->domain != IBMG_PERIODIC && pr->domain != IBMG_CAVITY) return IBMG_EINVAL;
+  const bool cavity = pr->domain == IBMG_CAVITY;
+  // periodic: rho > 0 (the steady periodic problem leaves the velocity's mean free)
+  if (!(pr->rho > 0 || (cavity && pr->rho == 0)) || !(pr->mu > 0) || !std::isfinite(pr->K) || pr->K < 0)
+    return IBMG_EINVAL;
+  if (cavity && op->tail_max != 1) return IBMG_EINVAL;
   if (pr->delta != IBMG_DELTA_IB4 && pr->delta != IBMG_DELTA_COS4) return IBMG_EINVAL;
   if (op->box != 1 && op->box != 2 && op->box != 4 && op->box != 8) return IBMG_ESHAPE;
   if (op->levels < 1 || op->levels > IBMG_MAX_LEVELS) return IBMG_ESHAPE;
@@ -811,6 +819,7 @@ int ibmg_create(ibmg_handle** out, const ibmg_problem* pr, const ibmg_opts* op, 
   if (!h) return IBMG_EINVAL;
   h->N = N; h->M = pr->n_points; h->nfib = pr->n_fibers; h->kind = pr->delta;
   h->rho = pr->rho; h->mu = pr->mu; h->K = pr->K;
+  h->walls = cavity;
   h->levels = op->levels; h->n = op->box; h->nu1 = op->nu1; h->nu2 = op->nu2; h->maxit = op->maxit;
   h->mb = op->restart == 0 ? op->maxit : std::min(op->restart, op->maxit);
   h->scheme = op->scheme;
@@ -908,8 +917,8 @@ int box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, d
   const bool fused = phase_fusable(v.ncol, v.n);
   const T* b = (level == 0 && h->prec == IBMG_FP64) ? h->p<T>(h->b0g) : h->p<T>(h->L[level].b);
   for (int q = 0; q < reps; ++q) {
-    if (fused) launch_phase_fused<T>(h->cap, v, b, w, colour, h->has_ib, false);
-    else launch_box<T>(h->cap, v, r, w, colour, h->has_ib);
+    if (fused) launch_phase_fused<T>(h->cap, v, b, w, colour, h->own_boxes(), false);
+    else launch_box<T>(h->cap, v, r, w, colour, h->own_boxes());
   }
   IBMG_HIP(hipStreamEndCapture(h->cap, &g));
   if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
@@ -940,7 +949,7 @@ int box_bench(ibmg_handle* h, int level, int colour, int reps, double* avg_us, d
     const double boxes = colour_count(v.ncol, v.nb);
     const double per_box = v.ndof * 3.0 + (fused ? 10.0 * v.n + 4.0 : 0.0);
     double by = boxes * per_box * sizeof(T) + (double)v.ndof * v.ndof * sizeof(T);
-    if (h->has_ib) by += (double)h->n_ib[level][colour] * v.ndof * v.ndof * sizeof(double);
+    if (h->own_boxes()) by += (double)h->n_ib[level][colour] * v.ndof * v.ndof * sizeof(double);
     *bytes = by;
   }
   return IBMG_OK;
@@ -1100,7 +1109,8 @@ int ibmg_rhs(ibmg_handle* h, const double* u, const double* v, const double* gu,
   if (!h->setup_ok) return IBMG_ESTATE;
   if (!b) return IBMG_EINVAL;
   const double inv_h2 = (double)h->N * h->N;
-  launch_rhs(h->stream, points(h), h->rho / h->dt, inv_h2, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr, b);
+  launch_rhs(h->stream, points(h), h->rho / h->dt, inv_h2, u, v, gu, gv, h->M > 0 ? h->p<double>(h->G) : nullptr, b,
+             h->walls ? 1 : 0, h->mu);
   IBMG_HIP(hipGetLastError());
   return IBMG_OK;
 }
@@ -1307,11 +1317,11 @@ int single_op(ibmg_handle* h, int which, int level, const double* a, const doubl
       if (f32) {
         T* f = stage(a, h->L[level].r);
         T* c = h->p<T>(h->L[level + 1].b);
-        launch_restrict<T>(s, v.N, f, c, (T*)nullptr);
+        launch_restrict<T>(s, v.N, f, c, (T*)nullptr, nullptr, h->walls);
         const size_t nc3 = n3 / 4;
         k_convert<T, double><<<nblk(nc3), 256, 0, s>>>(c, out, nc3);
       } else {
-        launch_restrict<T>(s, v.N, (const T*)a, (T*)out, (T*)nullptr);
+        launch_restrict<T>(s, v.N, (const T*)a, (T*)out, (T*)nullptr, nullptr, h->walls);
       }
       break;
     }
@@ -1322,10 +1332,10 @@ int single_op(ibmg_handle* h, int which, int level, const double* a, const doubl
         T* c = h->p<T>(h->L[level + 1].w);
         k_convert<double, T><<<nblk(nc3), 256, 0, s>>>(a, c, nc3);
         T* f = stage(out, wb);
-        launch_prolong_add<T>(s, v.N, c, f);
+        launch_prolong_add<T>(s, v.N, c, f, h->walls);
         k_convert<T, double><<<nblk(n3), 256, 0, s>>>(f, out, n3);
       } else {
-        launch_prolong_add<T>(s, v.N, (const T*)a, (T*)out);
+        launch_prolong_add<T>(s, v.N, (const T*)a, (T*)out, h->walls);
       }
       break;
     }

@@ -919,7 +919,7 @@ int ibmg_batch_create(ibmg_batch** out, int32_t nprob, const ibmg_problem* probs
   B->prec = opts[0].vcycle_prec;
   for (int p = 0; p < nprob; ++p) {
     ibmg_handle* h = nullptr;
-    int rc = (opts[p].vcycle_prec != B->prec || opts[p].orth != IBMG_ORTH_CGS2)
+    int rc = (opts[p].vcycle_prec != B->prec || opts[p].orth != IBMG_ORTH_CGS2 || probs[p].domain != IBMG_PERIODIC)
                  ? IBMG_EINVAL
                  : ibmg_create(&h, &probs[p], &opts[p], stream);
     if (rc) {

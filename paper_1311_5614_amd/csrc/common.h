@@ -33,6 +33,10 @@ struct LevelView {
   T muh2;         // mu / h_l^2
   T invh;         // 1 / h_l
   T omega;        // weight of a box correction (1: the undamped boxes of the paper)
+  int walls;      // 0: periodic; 1: walls on all four sides (the cavity of Sec. 4).  With walls the
+                  // faces u[j][0] (x = 0, standing for x = 1 too) and v[0][i] (y = 0 and y = 1) are
+                  // identity rows that no other row reads; a face next to a wall parallel to it sees
+                  // the ghost -u across it (the wall value is the average of face and ghost)
   int reach;      // window reach on this level
   int maxact;     // row capacity of the window store per component
   int rowhint;    // launch size of the elastic-row passes: expected active rows per component (<= maxact;
@@ -124,8 +128,37 @@ __device__ inline int box_local(int comp, int i, int j, int bx, int by, int n, i
 
 // (A_l w) at one unknown without the elasticity term: unsteady Stokes on the
 // MAC grid (Sec. 2.2) -- momentum c u - mu Lap u + G p, continuity -D u.
+// With walls (L.walls): the walled rows described at LevelView::walls.
+template <typename T>
+__device__ inline T stokes_row_walls(const LevelView<T>& L, const T* __restrict__ w, int comp, int i, int j) {
+  const int N = L.N, NN = N * N;
+  const T* u = w;
+  const T* v = w + NN;
+  const T* p = w + 2 * NN;
+  if (comp == 2) {
+    const T ue = i + 1 < N ? u[j * N + i + 1] : T(0), uw = i > 0 ? u[j * N + i] : T(0);
+    const T vn = j + 1 < N ? v[(j + 1) * N + i] : T(0), vs = j > 0 ? v[j * N + i] : T(0);
+    return -((ue - uw) + (vn - vs)) * L.invh;
+  }
+  // a: index along the face normal (i for u), t: along the tangent
+  const T* f = comp == 0 ? u : v;
+  const int a = comp == 0 ? i : j, t = comp == 0 ? j : i;
+  const int sa = comp == 0 ? 1 : N, st = comp == 0 ? N : 1;   // strides along a and t
+  const int k = j * N + i;
+  if (a == 0) return f[k];                                    // wall face: identity row
+  const T c0 = f[k];
+  T nb = T(0), ghosts = T(0);
+  if (a + 1 < N) nb += f[k + sa];
+  if (a - 1 > 0) nb += f[k - sa];
+  if (t + 1 < N) nb += f[k + st]; else ghosts += T(1);
+  if (t > 0) nb += f[k - st]; else ghosts += T(1);
+  const T grad = (p[k] - p[k - sa]) * L.invh;
+  return (L.c + (T(4) + ghosts) * L.muh2) * c0 - L.muh2 * nb + grad;
+}
+
 template <typename T>
 __device__ inline T stokes_row(const LevelView<T>& L, const T* __restrict__ w, int comp, int i, int j) {
+  if (L.walls) return stokes_row_walls(L, w, comp, i, j);
   const int N = L.N, NN = N * N;
   const T* u = w;
   const T* v = w + NN;

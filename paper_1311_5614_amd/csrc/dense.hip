@@ -34,6 +34,39 @@ k_coarse_assemble(LevelView<double> L, double* __restrict__ aug, int nr) {
   const int j = rem / N, i = rem - j * N;
   const int ip = wrapi(i + 1, N), im = wrapi(i - 1, N), jp = wrapi(j + 1, N), jm = wrapi(j - 1, N);
   const int base = comp * NN;
+  if (L.walls) {   // the walled rows of stokes_row_walls
+    if (comp < 2) {
+      const int an = comp == 0 ? i : j, at = comp == 0 ? j : i;
+      const int sa = comp == 0 ? 1 : N, st = comp == 0 ? N : 1;
+      const int k = j * N + i;
+      if (an == 0) {
+        row[r] += 1.0;
+        return;
+      }
+      const int ghosts = (at + 1 < N ? 0 : 1) + (at > 0 ? 0 : 1);
+      row[r] += L.c + (4.0 + ghosts) * L.muh2;
+      if (an + 1 < N) row[base + k + sa] -= L.muh2;
+      if (an - 1 > 0) row[base + k - sa] -= L.muh2;
+      if (at + 1 < N) row[base + k + st] -= L.muh2;
+      if (at > 0) row[base + k - st] -= L.muh2;
+      row[2 * NN + k] += L.invh;
+      row[2 * NN + k - sa] -= L.invh;
+      const int ar = L.act ? L.act[comp * NN + k] : -1;
+      if (ar >= 0) {
+        const double* cw = L.win + ((size_t)comp * L.maxact + ar) * IBMG_WS;
+        for (int dy = -L.reach; dy <= L.reach; ++dy)
+          for (int dx = -L.reach; dx <= L.reach; ++dx)
+            row[base + ((j + dy) & msk) * N + ((i + dx) & msk)] += cw[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR];
+      }
+    } else {
+      if (i + 1 < N) row[j * N + i + 1] -= L.invh;
+      if (i > 0) row[j * N + i] += L.invh;
+      if (j + 1 < N) row[NN + (j + 1) * N + i] -= L.invh;
+      if (j > 0) row[NN + j * N + i] += L.invh;
+      row[nr - 1] = 1.0;          // border column
+    }
+    return;
+  }
   if (comp < 2) {
     row[r] += L.c + 4.0 * L.muh2;
     row[base + j * N + ip] -= L.muh2;

@@ -68,6 +68,10 @@ struct ibmg_handle {
   int nr = 0, ndof = 0;
   // state
   bool setup_ok = false, has_ib = false, launch_error = false;
+  bool walls = false;   // IBMG_CAVITY: walls on all four sides, the top one moving (Sec. 4)
+  // boxes that take their own inverse: those with elastic rows, and with
+  // walls the boxes touching a wall
+  bool own_boxes() const { return has_ib || walls; }
   bool fb64 = false;   // this solve continues with the FP64 V-cycle (FP32 stalled)
   bool yib64 = false;  // FP32 handle: the FP64 V-cycle left FP64 values in the elastic-row buffers
   // the V-cycle as a captured graph (fixed buffers b0g -> w0g), rebuilt when dt changes
@@ -111,6 +115,7 @@ inline LevelView<T> view(const ibmg_handle* h, int l) {
   v.muh2 = (T)(h->mu / (hl * hl));
   v.invh = (T)(1.0 / hl);
   v.omega = (T)h->omega;
+  v.walls = h->walls ? 1 : 0;
   v.reach = B.reach;
   v.maxact = B.maxact;
   v.rowhint = B.rowhint > 0 ? B.rowhint : B.maxact;

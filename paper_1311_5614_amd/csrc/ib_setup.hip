@@ -333,12 +333,23 @@ k_win0(PointView P, const int* __restrict__ rows, const int* __restrict__ nact, 
 // tangential 2G-1..2G+2), fine rows in stencil order and g in row-major
 // order within each.  flags[0] |= 2 if a contribution falls outside the
 // coarse window.
+// With walls the transfers are the walled ones: coarse wall faces (normal
+// index 0, or Nc for the far wall) and faces outside the domain neither
+// restrict nor receive (their row and column of R M P are zero), fine faces
+// outside the domain do not exist, and the fine row next to a wall parallel
+// to the face prolongs from its coarse row with weight 1/2 (the coarse
+// field's ghost across the wall is -e).
 __device__ inline double win_coarse_entry(int comp, int FX, int FY, int ox, int oy, const int* __restrict__ af,
-                                          const double* __restrict__ win_f, int maxact_f, int reach_f, int Nf) {
-  const int mf = Nf - 1;
+                                          const double* __restrict__ win_f, int maxact_f, int reach_f, int Nf,
+                                          int walls) {
+  const int mf = Nf - 1, Nc = Nf / 2;
   const double wr[3] = {0.125, 0.25, 0.125};
   const int GX = FX + ox, GY = FY + oy;
   const int gn0 = 2 * (comp == 0 ? GX : GY), gt0 = 2 * (comp == 0 ? GY : GX);
+  if (walls) {
+    const int Fn = comp == 0 ? FX : FY, Gn = comp == 0 ? GX : GY, Gt = comp == 0 ? GY : GX;
+    if (Fn == 0 || Gn <= 0 || Gn >= Nc || Gt < 0 || Gt >= Nc) return 0.0;
+  }
   double acc = 0.0;
   for (int d = -1; d <= 1; ++d)
     for (int e = 0; e <= 1; ++e) {
@@ -361,7 +372,11 @@ __device__ inline double win_coarse_entry(int comp, int FX, int FY, int ox, int 
           if (val == 0.0) continue;
           const int gn = comp == 0 ? gx : gy, gt = comp == 0 ? gy : gx;
           const double wn = gn == gn0 ? 1.0 : 0.5;
-          const double wt = (gt == gt0 || gt == gt0 + 1) ? 0.75 : 0.25;
+          double wt = (gt == gt0 || gt == gt0 + 1) ? 0.75 : 0.25;
+          if (walls) {
+            if (gn <= 0 || gn >= Nf || gt < 0 || gt >= Nf) continue;
+            if (gt == 0 || gt == Nf - 1) wt = 0.5;
+          }
           acc += val * wn * wt;
         }
       }
@@ -372,7 +387,7 @@ __device__ inline double win_coarse_entry(int comp, int FX, int FY, int ox, int 
 __global__ void __launch_bounds__(256)
 k_win_coarse(int Nc, const int* __restrict__ act_f, const double* __restrict__ win_f, int maxact_f, int reach_f,
              const int* __restrict__ rows, const int* __restrict__ nact, int maxact, int reach,
-             double* __restrict__ win, int* __restrict__ flags) {
+             double* __restrict__ win, int* __restrict__ flags, int walls) {
   const int comp = blockIdx.y;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -387,9 +402,9 @@ k_win_coarse(int Nc, const int* __restrict__ act_f, const double* __restrict__ w
   const int dx1 = q1 % IBMG_WW - IBMG_WR, dy1 = q1 / IBMG_WW - IBMG_WR;
   double acc0 = 0.0, acc1 = 0.0;
   if (dx0 >= -reach && dx0 <= reach && dy0 >= -reach && dy0 <= reach)
-    acc0 = win_coarse_entry(comp, FX, FY, dx0, dy0, af, win_f, maxact_f, reach_f, Nf);
+    acc0 = win_coarse_entry(comp, FX, FY, dx0, dy0, af, win_f, maxact_f, reach_f, Nf, walls);
   if (has1 && dx1 >= -reach && dx1 <= reach && dy1 >= -reach && dy1 <= reach)
-    acc1 = win_coarse_entry(comp, FX, FY, dx1, dy1, af, win_f, maxact_f, reach_f, Nf);
+    acc1 = win_coarse_entry(comp, FX, FY, dx1, dy1, af, win_f, maxact_f, reach_f, Nf, walls);
   double* o = win + ((size_t)comp * maxact + row) * IBMG_WS;
   o[lane] = acc0;
   if (has1) o[q1] = acc1;
@@ -416,13 +431,16 @@ k_win_coarse(int Nc, const int* __restrict__ act_f, const double* __restrict__ w
 }
 
 // ---------------------------------------------------------------- boxes with elastic rows
+// A box takes its own inverse if one of its faces has elastic rows (act
+// given) or, with walls, if it touches a wall (its block differs from the
+// interior boxes' shared one).
 __global__ void __launch_bounds__(256)
-k_box_flag(int N, int n, int nb, const int* __restrict__ act, int* __restrict__ flag) {
+k_box_flag(int N, int n, int nb, const int* __restrict__ act, int walls, int* __restrict__ flag) {
   const int box = blockIdx.x * blockDim.x + threadIdx.x;
   if (box >= nb * nb) return;
   const int bx = box % nb, by = box / nb, NN = N * N;
-  int any = 0;
-  for (int lj = 0; lj <= n && !any; ++lj)
+  int any = walls && (bx == 0 || by == 0 || bx == nb - 1 || by == nb - 1);
+  for (int lj = 0; act && lj <= n && !any; ++lj)
     for (int li = 0; li <= n; ++li) {
       if (lj < n) any |= act[wrapi(by * n + lj, N) * N + wrapi(bx * n + li, N)] >= 0;           // u
       if (li < n) any |= act[NN + wrapi(by * n + lj, N) * N + wrapi(bx * n + li, N)] >= 0;      // v
@@ -496,6 +514,40 @@ __device__ void assemble_box(const LevelView<double>& L, int bx, int by, bool wi
     double* row = a + (size_t)r * ld;
     const int ip = wrapi(i + 1, N), im = wrapi(i - 1, N), jp = wrapi(j + 1, N), jm = wrapi(j - 1, N);
     int col;
+    if (L.walls) {   // the walled rows of stokes_row_walls
+      if (comp < 2) {
+        const int an = comp == 0 ? i : j, at = comp == 0 ? j : i;
+        if (an == 0) {   // wall face: identity row
+          row[r] += 1.0;
+          continue;
+        }
+        const int ghosts = (at + 1 < N ? 0 : 1) + (at > 0 ? 0 : 1);
+        row[r] += L.c + (4.0 + ghosts) * L.muh2;
+        // (normal +1, normal -1, tangent +1, tangent -1) neighbours inside the walls
+        const bool ok[4] = {an + 1 < N, an - 1 > 0, at + 1 < N, at > 0};
+        const int nbi[4] = {comp == 0 ? i + 1 : i, comp == 0 ? i - 1 : i, comp == 0 ? i : i + 1, comp == 0 ? i : i - 1};
+        const int nbj[4] = {comp == 0 ? j : j + 1, comp == 0 ? j : j - 1, comp == 0 ? j + 1 : j, comp == 0 ? j - 1 : j};
+        for (int q = 0; q < 4; ++q)
+          if (ok[q] && (col = box_local(comp, nbi[q], nbj[q], bx, by, n, N)) >= 0) row[col] -= L.muh2;
+        if ((col = box_local(2, i, j, bx, by, n, N)) >= 0) row[col] += L.invh;
+        if ((col = box_local(2, comp == 0 ? i - 1 : i, comp == 0 ? j : j - 1, bx, by, n, N)) >= 0)
+          row[col] -= L.invh;
+        const int ar = with_ib ? L.act[comp * NN + j * N + i] : -1;
+        if (ar >= 0) {
+          const double* cw = L.win + ((size_t)comp * L.maxact + ar) * IBMG_WS;
+          for (int dy = -L.reach; dy <= L.reach; ++dy)
+            for (int dx = -L.reach; dx <= L.reach; ++dx)
+              if ((col = box_local(comp, wrapi(i + dx, N), wrapi(j + dy, N), bx, by, n, N)) >= 0)
+                row[col] += cw[(dy + IBMG_WR) * IBMG_WW + dx + IBMG_WR];
+        }
+      } else {
+        if (i + 1 < N && (col = box_local(0, i + 1, j, bx, by, n, N)) >= 0) row[col] -= L.invh;
+        if (i > 0 && (col = box_local(0, i, j, bx, by, n, N)) >= 0) row[col] += L.invh;
+        if (j + 1 < N && (col = box_local(1, i, j + 1, bx, by, n, N)) >= 0) row[col] -= L.invh;
+        if (j > 0 && (col = box_local(1, i, j, bx, by, n, N)) >= 0) row[col] += L.invh;
+      }
+      continue;
+    }
     if (comp < 2) {
       row[r] += L.c + 4.0 * L.muh2;
       const int nbi[4] = {ip, im, i, i}, nbj[4] = {j, j, jp, jm};
@@ -550,6 +602,9 @@ __global__ void __launch_bounds__(128) k_box_factor(ibmg::BoxFactorLevels F) {
     const int box = F.ib_boxes[lv][blk - 1];
     bx = box % L.nb;
     by = box / L.nb;
+  } else if (L.walls && L.nb >= 3) {   // the shared block is an interior box's
+    bx = 1;
+    by = 1;
   }
   for (int idx = threadIdx.x; idx < nd * ld; idx += blockDim.x) {
     const int i = idx / ld, c = idx - i * ld;
@@ -582,6 +637,9 @@ __global__ void __launch_bounds__(kGjLanes) k_box_factor_big(ibmg::BoxFactorLeve
     const int box = F.ib_boxes[lv][blk - 1];
     bx = box % L.nb;
     by = box / L.nb;
+  } else if (L.walls && L.nb >= 3) {
+    bx = 1;
+    by = 1;
   }
   double* slot = plain ? F.ainv_plain[lv] : F.ainv_ib[lv] + (size_t)(blk - 1) * nd * nd;
   for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) slot[idx] = 0.0;
@@ -666,14 +724,15 @@ void launch_windows0(hipStream_t s, const PointView& P, const int* rows, const i
 }
 
 void launch_windows_coarse(hipStream_t s, int Nc, const int* act_f, const double* win_f, int maxact_f, int reach_f,
-                           const int* rows, const int* nact, int maxact, int reach, double* win, int* flags) {
+                           const int* rows, const int* nact, int maxact, int reach, double* win, int* flags,
+                           int walls) {
   dim3 g((unsigned)((maxact + 3) / 4), 2);
-  k_win_coarse<<<g, 256, 0, s>>>(Nc, act_f, win_f, maxact_f, reach_f, rows, nact, maxact, reach, win, flags);
+  k_win_coarse<<<g, 256, 0, s>>>(Nc, act_f, win_f, maxact_f, reach_f, rows, nact, maxact, reach, win, flags, walls);
 }
 
-void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int* flag, int* ib_index,
-                        int* ib_boxes, int* info) {
-  if (act) k_box_flag<<<nblk(nb * nb), 256, 0, s>>>(N, n, nb, act, flag);
+void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int walls, int* flag,
+                        int* ib_index, int* ib_boxes, int* info) {
+  if (act || walls) k_box_flag<<<nblk(nb * nb), 256, 0, s>>>(N, n, nb, act, walls, flag);
   else k_fill_i32<<<nblk(nb * nb), 256, 0, s>>>(flag, nb * nb, 0);
   k_ib_index<<<1, 1024, 0, s>>>(nb, ncol, flag, ib_index, ib_boxes, info);
 }

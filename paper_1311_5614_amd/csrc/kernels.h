@@ -74,9 +74,10 @@ void launch_active(hipStream_t s, int level, int M, int N, const int* org, const
 void launch_windows0(hipStream_t s, const PointView& P, const int* rows, const int* nact, int maxact, double kappa,
                      int reach, double* win, int* flags);
 void launch_windows_coarse(hipStream_t s, int Nc, const int* act_f, const double* win_f, int maxact_f, int reach_f,
-                           const int* rows, const int* nact, int maxact, int reach, double* win, int* flags);
-void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int* flag, int* ib_index,
-                        int* ib_boxes, int* info);
+                           const int* rows, const int* nact, int maxact, int reach, double* win, int* flags,
+                           int walls = 0);
+void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int walls, int* flag,
+                        int* ib_index, int* ib_boxes, int* info);
 // Box inverses of every non-coarsest level in one launch: level l owns blocks
 // first[l] .. first[l + 1] - 1, the first of them its plain block and the
 // others its boxes with elastic rows (ib_boxes[l]).
@@ -97,8 +98,11 @@ void launch_box_matrix(hipStream_t s, const LevelView<double>& L, int bx, int by
 template <typename T> void launch_residual(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r,
                                            bool ib);
 template <typename T> void launch_res(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r, bool ib);
+// ib: boxes listed in L.ib_index take their own inverse (boxes with elastic
+// rows, and with walls the boxes touching a wall)
 template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, const T* r, T* w, int colour, bool ib);
-// ib_rows: evaluate the elastic rows first (false only to time the box launch alone)
+// ib_rows: evaluate the elastic rows first when the level has them (false
+// only to time the box launch alone)
 template <typename T> void launch_phase_fused(hipStream_t s, const LevelView<T>& L, const T* b, T* w, int colour,
                                               bool ib, bool ib_rows = true);
 // A colour phase may run as one box launch that forms its own Stokes residuals
@@ -106,13 +110,14 @@ template <typename T> void launch_phase_fused(hipStream_t s, const LevelView<T>&
 inline bool phase_fusable(int ncol, int n) { return ncol == 4 && (n == 2 || n == 4); }
 // yf (nullable): elastic term of the fine residual (rf - yf is restricted)
 template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero,
-                                           const T* yf = nullptr);
-template <typename T> void launch_prolong_add(hipStream_t s, int Nf, const T* ec, T* wf);
+                                           const T* yf = nullptr, int walls = 0);
+template <typename T> void launch_prolong_add(hipStream_t s, int Nf, const T* ec, T* wf, int walls = 0);
 int prepare_tail(size_t lds);
 template <typename T> int launch_tail(hipStream_t s, const LevelView<T>* views, int ls, int L, int nu1, int nu2,
                                       bool ib, int nr, const T* b_in, T* w_out, const double* cainv);
+// walls: the cavity's wall faces and lid term (mu the viscosity); 0: periodic
 void launch_rhs(hipStream_t s, const PointView& P, double c, double inv_h2, const double* u, const double* v,
-                const double* gu, const double* gv, const double* G, double* b);
+                const double* gu, const double* gv, const double* G, double* b, int walls = 0, double mu = 0.0);
 void launch_interp(hipStream_t s, const PointView& P, const double* u, const double* v, double* U,
                    double* X, double dt);
 

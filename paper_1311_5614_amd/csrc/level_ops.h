@@ -358,9 +358,11 @@ __device__ inline T res_at(const T* __restrict__ rf, const T* __restrict__ yf, s
   return yf ? rf[i] - yf[i] : rf[i];
 }
 
+// walls: the coarse wall faces (u: I = 0, v: J = 0) restrict to zero; the
+// other coarse faces read only interior fine faces.
 template <typename T>
 __device__ inline void restrict_body(int Nf, const T* __restrict__ rf, T* __restrict__ rc, T* __restrict__ wz,
-                                     int blk, const T* __restrict__ yf = nullptr) {
+                                     int blk, const T* __restrict__ yf = nullptr, int walls = 0) {
   const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf, mf = Nf - 1, lgc = __builtin_ctz(Nc);
   const int idx = blk * 256 + threadIdx.x;
   if (idx >= 3 * NNc) return;
@@ -385,6 +387,7 @@ __device__ inline void restrict_body(int Nf, const T* __restrict__ rf, T* __rest
     s = T(0.25) * (f[2 * J * Nf + 2 * I] + f[2 * J * Nf + 2 * I + 1] + f[(2 * J + 1) * Nf + 2 * I] +
                    f[(2 * J + 1) * Nf + 2 * I + 1]);
   }
+  if (walls && ((comp == 0 && I == 0) || (comp == 1 && J == 0))) s = T(0);
   rc[idx] = s;
   if (wz) wz[idx] = T(0);
 }
@@ -406,8 +409,31 @@ __device__ inline T bilinear(const T* c, int Nc, int in, int it, bool normal_is_
   return s;
 }
 
+// Bilinear prolongation with walls: coarse wall faces (normal index 0; Nc
+// stands for the wall at the far side) contribute nothing, and across a
+// wall parallel to the face the coarse field's ghost is -e, so the fine row
+// next to the wall takes 3/4 - 1/4 = 1/2 of its coarse row.  Fine wall faces
+// get nothing.
 template <typename T>
-__device__ inline void prolong_body(int Nf, const T* __restrict__ ec, T* __restrict__ wf, int blk) {
+__device__ inline T bilinear_walls(const T* c, int Nc, int in, int it, bool normal_is_x) {
+  if (in == 0) return T(0);
+  auto at = [&](int a, int b) -> T { return normal_is_x ? c[b * Nc + a] : c[a * Nc + b]; };
+  const int t0 = it >> 1;
+  const int t1 = (it & 1) == 0 ? t0 - 1 : t0 + 1;
+  const bool t1in = t1 >= 0 && t1 < Nc;
+  auto tang = [&](int n) -> T {   // the tangential pair of coarse normal index n
+    return t1in ? T(0.75) * at(n, t0) + T(0.25) * at(n, t1) : T(0.5) * at(n, t0);
+  };
+  if ((in & 1) == 0) return tang(in >> 1);
+  const int n0 = (in - 1) >> 1, n1 = (in + 1) >> 1;
+  T s = T(0);
+  if (n0 > 0) s += T(0.5) * tang(n0);
+  if (n1 < Nc) s += T(0.5) * tang(n1);
+  return s;
+}
+
+template <typename T>
+__device__ inline void prolong_body(int Nf, const T* __restrict__ ec, T* __restrict__ wf, int blk, int walls = 0) {
   const int Nc = Nf / 2, NNc = Nc * Nc, NNf = Nf * Nf, lgf = __builtin_ctz(Nf);
   const int idx = blk * 256 + threadIdx.x;
   if (idx >= 3 * NNf) return;
@@ -415,8 +441,8 @@ __device__ inline void prolong_body(int Nf, const T* __restrict__ ec, T* __restr
   const int j = rem >> lgf, i = rem & (Nf - 1);
   const T* c = ec + (size_t)comp * NNc;
   T add;
-  if (comp == 0) add = bilinear(c, Nc, i, j, true);
-  else if (comp == 1) add = bilinear(c, Nc, j, i, false);
+  if (comp == 0) add = walls ? bilinear_walls(c, Nc, i, j, true) : bilinear(c, Nc, i, j, true);
+  else if (comp == 1) add = walls ? bilinear_walls(c, Nc, j, i, false) : bilinear(c, Nc, j, i, false);
   else add = c[(j >> 1) * Nc + (i >> 1)];
   wf[idx] += add;
 }

@@ -63,12 +63,13 @@ k_box_big(LevelView<T> L, const T* __restrict__ r, T* __restrict__ w, int colour
 }
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int Nf, const T* __restrict__ rf, T* __restrict__ rc,
-                                                  T* __restrict__ wz, const T* __restrict__ yf) {
-  restrict_body<T>(Nf, rf, rc, wz, blockIdx.x, yf);
+                                                  T* __restrict__ wz, const T* __restrict__ yf, int walls) {
+  restrict_body<T>(Nf, rf, rc, wz, blockIdx.x, yf, walls);
 }
 template <typename T>
-__global__ void __launch_bounds__(256) k_prolong_add(int Nf, const T* __restrict__ ec, T* __restrict__ wf) {
-  prolong_body<T>(Nf, ec, wf, blockIdx.x);
+__global__ void __launch_bounds__(256) k_prolong_add(int Nf, const T* __restrict__ ec, T* __restrict__ wf,
+                                                     int walls) {
+  prolong_body<T>(Nf, ec, wf, blockIdx.x, walls);
 }
 template <typename T, int NB>
 __global__ void __launch_bounds__(1024) k_tail(TailArgs<T> A) {
@@ -78,17 +79,20 @@ __global__ void __launch_bounds__(1024) k_tail(TailArgs<T> A) {
 // ---------------------------------------------------------------- a4: right-hand side
 // b = [(rho/dt) u^n + S_0 G + g_u; (rho/dt) v^n + S_0 G + g_v; 0].  The spread
 // force at a face sums, in ascending point order, W_k(face) G_k / h^2 over
-// the points binned to the face's box.
+// the points binned to the face's box.  walls (the cavity of Sec. 4): wall
+// faces get 0 (prescribed normal velocity), and the top row of u faces the
+// lid's ghost term 2 mu g(x) / h^2, g(x) = (1 - cos 2 pi x) / 2.
 __global__ void __launch_bounds__(256)
 k_rhs(PointView P, double c, double inv_h2, const double* __restrict__ u, const double* __restrict__ v,
       const double* __restrict__ gu, const double* __restrict__ gv, const double* __restrict__ G,
-      double* __restrict__ b) {
+      double* __restrict__ b, int walls, double mu) {
   const int N = P.N, NN = N * N, msk = N - 1;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 3 * NN) return;
   const int comp = idx / NN, rem = idx - comp * NN;
   if (comp == 2) { b[idx] = 0.0; return; }
   const int j = rem / N, i = rem - j * N;
+  if (walls && (comp == 0 ? i : j) == 0) { b[idx] = 0.0; return; }
   double val = 0.0;
   const double* f0 = comp == 0 ? u : v;
   const double* g0 = comp == 0 ? gu : gv;
@@ -106,6 +110,7 @@ k_rhs(PointView P, double c, double inv_h2, const double* __restrict__ u, const 
   }
   val += sp * inv_h2;
   if (g0) val += g0[rem];
+  if (walls && comp == 0 && j == N - 1) val += mu * (1.0 - cospi(2.0 * i / N)) * inv_h2;
   b[idx] = val;
 }
 
@@ -177,7 +182,7 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
 template <typename T> void launch_phase_fused(hipStream_t s, const LevelView<T>& L, const T* b, T* w, int colour,
                                               bool ib, bool ib_rows) {
   LevelView<T> V = L;
-  if (ib && ib_rows) k_ib_rows<T><<<dim3(ib_blocks(L.rowhint), 2), 256, 0, s>>>(L, w, nullptr, 0);
+  if (ib && ib_rows && L.act) k_ib_rows<T><<<dim3(ib_blocks(L.rowhint), 2), 256, 0, s>>>(L, w, nullptr, 0);
   if (!ib) V.ib_index = nullptr;
   const int cnt = colour_count(L.ncol, L.nb);
   if (cnt >= kBoxWavesMax * 512) {
@@ -197,11 +202,12 @@ template <typename T> void launch_phase_fused(hipStream_t s, const LevelView<T>&
     else k_box<T, 2, 1, 1, true><<<cnt, 64, 0, s>>>(V, b, w, colour, cnt, 1);
   }
 }
-template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero, const T* yf) {
-  k_restrict<T><<<nblk(3 * (size_t)(Nf / 2) * (Nf / 2)), 256, 0, s>>>(Nf, rf, rc, wc_zero, yf);
+template <typename T> void launch_restrict(hipStream_t s, int Nf, const T* rf, T* rc, T* wc_zero, const T* yf,
+                                           int walls) {
+  k_restrict<T><<<nblk(3 * (size_t)(Nf / 2) * (Nf / 2)), 256, 0, s>>>(Nf, rf, rc, wc_zero, yf, walls);
 }
-template <typename T> void launch_prolong_add(hipStream_t s, int Nf, const T* ec, T* wf) {
-  k_prolong_add<T><<<nblk(3 * (size_t)Nf * Nf), 256, 0, s>>>(Nf, ec, wf);
+template <typename T> void launch_prolong_add(hipStream_t s, int Nf, const T* ec, T* wf, int walls) {
+  k_prolong_add<T><<<nblk(3 * (size_t)Nf * Nf), 256, 0, s>>>(Nf, ec, wf, walls);
 }
 template <typename T> int launch_tail(hipStream_t s, const LevelView<T>* views, int ls, int L, int nu1, int nu2,
                                       bool ib, int nr, const T* b_in, T* w_out, const double* cainv) {
@@ -231,8 +237,8 @@ int prepare_tail(size_t lds) {
 }
 
 void launch_rhs(hipStream_t s, const PointView& P, double c, double inv_h2, const double* u, const double* v,
-                const double* gu, const double* gv, const double* G, double* b) {
-  k_rhs<<<nblk(3 * (size_t)P.N * P.N), 256, 0, s>>>(P, c, inv_h2, u, v, gu, gv, G, b);
+                const double* gu, const double* gv, const double* G, double* b, int walls, double mu) {
+  k_rhs<<<nblk(3 * (size_t)P.N * P.N), 256, 0, s>>>(P, c, inv_h2, u, v, gu, gv, G, b, walls, mu);
 }
 void launch_interp(hipStream_t s, const PointView& P, const double* u, const double* v, double* U,
                    double* X, double dt) {
@@ -244,8 +250,8 @@ void launch_interp(hipStream_t s, const PointView& P, const double* u, const dou
   template void launch_res<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, bool);         \
   template void launch_box<T>(hipStream_t, const LevelView<T>&, const T*, T*, int, bool);             \
   template void launch_phase_fused<T>(hipStream_t, const LevelView<T>&, const T*, T*, int, bool, bool);  \
-  template void launch_restrict<T>(hipStream_t, int, const T*, T*, T*, const T*);                                 \
-  template void launch_prolong_add<T>(hipStream_t, int, const T*, T*);                                  \
+  template void launch_restrict<T>(hipStream_t, int, const T*, T*, T*, const T*, int);                            \
+  template void launch_prolong_add<T>(hipStream_t, int, const T*, T*, int);                             \
   template int launch_tail<T>(hipStream_t, const LevelView<T>*, int, int, int, int, bool, int, const T*, T*,   \
                               const double*);
 IBMG_INST(double)

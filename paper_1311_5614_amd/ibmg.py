@@ -29,6 +29,7 @@ IBMG_SOLVER_FGMRES, IBMG_SOLVER_MG = 0, 1
 IBMG_KERNEL_BOX, IBMG_KERNEL_RES, IBMG_KERNEL_MULTIDOT, IBMG_KERNEL_UPDATE = 0, 1, 2, 3
 IBMG_KERNEL_DOT2, IBMG_KERNEL_UPDATE2 = 4, 5
 IBMG_ORTH_CGS2, IBMG_ORTH_DCGS2 = 0, 1
+IBMG_PERIODIC, IBMG_CAVITY = 0, 1
 IBMG_GUESS_RECORD, IBMG_GUESS_EXTRAP, IBMG_GUESS_LEARNED = 0, 1, 2
 
 EXPORTS = [
@@ -50,7 +51,8 @@ EXPORTS = [
 class ibmg_problem(C.Structure):
     _fields_ = [("N", C.c_int32), ("rho", C.c_double), ("mu", C.c_double),
                 ("n_points", C.c_int32), ("n_fibers", C.c_int32),
-                ("fiber_offsets", C.POINTER(C.c_int32)), ("K", C.c_double), ("delta", C.c_int32)]
+                ("fiber_offsets", C.POINTER(C.c_int32)), ("K", C.c_double), ("delta", C.c_int32),
+                ("domain", C.c_int32)]
 
 
 class ibmg_opts(C.Structure):
@@ -191,6 +193,7 @@ class Config:
     solver: int = 0
     omega: float = 1.0
     orth: int = 0
+    domain: int = 0
 
 
 def _problem(cfg: Config, fiber_offsets):
@@ -199,7 +202,7 @@ def _problem(cfg: Config, fiber_offsets):
     M = offs[-1] if len(offs) > 1 else 0
     arr = (C.c_int32 * len(offs))(*offs)
     prob = ibmg_problem(cfg.N, cfg.rho, cfg.mu, M, max(0, len(offs) - 1),
-                        C.cast(arr, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
+                        C.cast(arr, C.POINTER(C.c_int32)), cfg.K, cfg.delta, cfg.domain)
     opts = ibmg_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.prec,
                      cfg.guess, cfg.colours, cfg.tail_max, cfg.restart, cfg.colours_from, cfg.scheme, cfg.solver, cfg.omega,
                      cfg.orth)

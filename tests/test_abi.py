@@ -42,12 +42,13 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "ibmg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg_problem), sizeof(ibmg_opts), sizeof(ibmg_stats),
          offsetof(ibmg_problem, fiber_offsets), offsetof(ibmg_problem, K), offsetof(ibmg_opts, rtol),
          offsetof(ibmg_stats, t_step_ms), offsetof(ibmg_opts, colours), offsetof(ibmg_opts, tail_max),
          offsetof(ibmg_stats, rel_resid_est), offsetof(ibmg_stats, guess_rejected), offsetof(ibmg_opts, restart),
          offsetof(ibmg_opts, colours_from), offsetof(ibmg_opts, scheme),
-         offsetof(ibmg_opts, solver), offsetof(ibmg_opts, omega), offsetof(ibmg_opts, orth));
+         offsetof(ibmg_opts, solver), offsetof(ibmg_opts, omega), offsetof(ibmg_opts, orth),
+         offsetof(ibmg_problem, domain));
   return 0;
 }
 """
@@ -63,7 +64,8 @@ int main(void) {
             ibmg.ibmg_opts.tail_max.offset, ibmg.ibmg_stats.rel_resid_est.offset,
             ibmg.ibmg_stats.guess_rejected.offset, ibmg.ibmg_opts.restart.offset,
             ibmg.ibmg_opts.colours_from.offset, ibmg.ibmg_opts.scheme.offset,
-            ibmg.ibmg_opts.solver.offset, ibmg.ibmg_opts.omega.offset, ibmg.ibmg_opts.orth.offset]
+            ibmg.ibmg_opts.solver.offset, ibmg.ibmg_opts.omega.offset, ibmg.ibmg_opts.orth.offset,
+            ibmg.ibmg_problem.domain.offset]
     assert got == want
 
 
@@ -71,7 +73,8 @@ def _create(N=32, levels=3, box=4, offs=(0, 40), **kw):
     ibmg, L = _lib()
     o = (C.c_int32 * len(offs))(*offs)
     prob = ibmg.ibmg_problem(N, kw.get("rho", 1.0), kw.get("mu", 1.0), offs[-1], len(offs) - 1,
-                             C.cast(o, C.POINTER(C.c_int32)), kw.get("K", 1e3), kw.get("delta", 0))
+                             C.cast(o, C.POINTER(C.c_int32)), kw.get("K", 1e3), kw.get("delta", 0),
+                             kw.get("domain", 0))
     opts = ibmg.ibmg_opts(levels, box, kw.get("nu1", 2), kw.get("nu2", 2), kw.get("maxit", 100),
                           kw.get("rtol", 1e-8), kw.get("prec", 0), kw.get("guess", 0), kw.get("colours", 2),
                           kw.get("tail_max", 0), kw.get("restart", 0), kw.get("colours_from", 0),
@@ -125,6 +128,10 @@ def test_create_validates_shapes_without_gpu():
     assert _create(solver=1)[0] == 0 and _create(solver=2)[0] == -1
     assert _create(omega=0.8)[0] == 0 and _create(omega=1.5)[0] == -1 and _create(omega=-0.1)[0] == -1
     assert _create(orth=1)[0] == 0 and _create(orth=2)[0] == -1 and _create(orth=-1)[0] == -1
+    # the walled cavity: steady form allowed, grid-wide levels only
+    assert _create(domain=1, tail_max=1)[0] == 0 and _create(domain=1, tail_max=1, rho=0.0)[0] == 0
+    assert _create(domain=1)[0] == -1 and _create(domain=2, tail_max=1)[0] == -1
+    assert _create(rho=0.0, tail_max=1)[0] == -1
 
 
 def test_status_strings():

@@ -1,0 +1,210 @@
+"""GPU parity on the paper's walled test problem (Sec. 4): the lid-driven
+cavity with the thick annulus, steady Stokes, cosine delta, against the
+oracle's walled operators (oracle/cavity.py), element by element: the level
+operators with their Galerkin elasticity blocks, the walled transfers, the
+box blocks of boxes along the walls and inside, coloured sweeps, the
+coarsest solve, V-cycles, the right-hand side with the lid, and FGMRES and
+multigrid-alone solves (iteration counts and the solution in the oracle's
+operator).  Tolerances as in the periodic parity tests."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import DEV, rel, tdev, tnp
+
+pytestmark = pytest.mark.gpu
+
+from oracle import cavity, krylov, mg, smoother  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_5614_amd import ibmg  # noqa: F401  (raises if the library is missing)
+
+
+_AEXP = {}
+
+
+def _alpha_exp(N):
+    if N not in _AEXP:
+        _AEXP[N] = cavity.alpha_exp(N)
+    return _AEXP[N]
+
+
+def cav(N, levels, ratio, box=4, nu=(1, 1), colours=2, prec=0, rtol=1e-10, maxit=200, solver=0):
+    """GPU solver and oracle hierarchy of the cavity at relative stiffness
+    alpha / alpha_exp = ratio (dt = 1, so the nodal stiffness K = alpha)."""
+    from paper_1311_5614_amd import ibmg
+    a = cavity.annulus(N)
+    alpha = ratio * _alpha_exp(N)
+    cfg = ibmg.Config(N=N, levels=levels, K=alpha, rho=0.0, box=box, nu1=nu[0], nu2=nu[1], maxit=maxit, rtol=rtol,
+                      prec=prec, colours=colours, tail_max=1, delta=ibmg.IBMG_DELTA_COS4,
+                      domain=ibmg.IBMG_CAVITY, solver=solver)
+    s = ibmg.Solver(cfg, a.fiber_offsets, DEV)
+    s.setup(1.0, tdev(a.X))
+    lv = cavity.hierarchy(N, levels, alpha, a)
+    return a, alpha, s, lv
+
+
+def _zero_walls(x, N):
+    x = x.copy()
+    n = N * N
+    x[:n].reshape(N, N)[:, 0] = 0.0
+    x[n:2 * n].reshape(N, N)[0, :] = 0.0
+    return x
+
+
+@pytest.mark.parametrize("N,levels,box,ratio", [(32, 4, 1, 100.0), (64, 5, 4, 500.0)])
+def test_cavity_operator_every_level(N, levels, box, ratio):
+    a, alpha, s, lv = cav(N, levels, ratio, box=box)
+    rng = np.random.default_rng(50)
+    for l, L in enumerate(lv):
+        x = rng.standard_normal(3 * L.N * L.N)
+        y = tnp(s.apply(l, tdev(x)))
+        assert rel(y, L.A @ x) < 1e-12, l
+        b = rng.standard_normal(3 * L.N * L.N)
+        r = tnp(s.residual(l, tdev(b), tdev(x)))
+        assert np.max(np.abs(r - (b - L.A @ x))) < 1e-12 * np.max(np.abs(L.A @ x)), l
+        assert abs(L.M_u).max() > 0     # the structure reaches every level
+    s.close()
+
+
+def test_cavity_transfers():
+    a, alpha, s, lv = cav(32, 4, 10.0, box=1)
+    rng = np.random.default_rng(51)
+    for l, N in enumerate((32, 16, 8)):
+        f = rng.standard_normal(3 * N * N)
+        c = tnp(s.restrict(l, tdev(f)))
+        assert rel(c, cavity.restrict_w(N) @ f) < 1e-14, l
+        cc = rng.standard_normal(3 * (N // 2) ** 2)
+        base = rng.standard_normal(3 * N * N)
+        out = tnp(s.prolong_add(l, tdev(cc), tdev(base.copy())))
+        assert rel(out, base + cavity.prolong_w(N) @ cc) < 1e-14, l
+    s.close()
+
+
+@pytest.mark.parametrize("N,levels,box", [(32, 4, 1), (32, 4, 2), (64, 5, 4), (64, 4, 8)])
+def test_cavity_box_matrices(N, levels, box):
+    """Every box block on the two finest levels: boxes along the walls (own
+    inverse: identity rows of the wall faces, ghost diagonals) and inside."""
+    a, alpha, s, lv = cav(N, levels, 100.0, box=box)
+    for l in (0, 1):
+        sm = smoother.BoxSmoother(lv[l].A, lv[l].N, box)
+        nb = lv[l].N // box
+        for bx in range(nb):
+            for by in range(nb):
+                A = tnp(s.box_matrix(l, bx, by))
+                Ao = sm.box_matrix(bx, by)
+                assert np.max(np.abs(A - Ao)) < 1e-12 * np.max(np.abs(Ao)), (l, bx, by)
+    s.close()
+
+
+@pytest.mark.parametrize("box,colours", [(1, 2), (1, 4), (2, 2), (4, 2), (4, 4), (8, 2)])
+def test_cavity_smooth(box, colours):
+    N = 64
+    levels = 4 if box == 8 else 5
+    a, alpha, s, lv = cav(N, levels, 100.0, box=box, colours=colours)
+    rng = np.random.default_rng(52)
+    mode = "colour2" if colours == 2 else "colour"
+    for l in (0, 1, 2):
+        Nl = lv[l].N
+        if Nl < 2 * box:
+            continue
+        b = _zero_walls(rng.standard_normal(3 * Nl * Nl), Nl)
+        x = _zero_walls(rng.standard_normal(3 * Nl * Nl), Nl)
+        sm = smoother.BoxSmoother(lv[l].A, Nl, box)
+        xo = sm.sweep(sm.sweep(x, b, mode), b, mode)
+        xg = tnp(s.smooth(l, tdev(b), tdev(x.copy()), 2))
+        assert rel(xg, xo) < 1e-11, (box, colours, l)
+    s.close()
+
+
+@pytest.mark.parametrize("N,levels,box", [(32, 4, 1), (64, 4, 8)])
+def test_cavity_coarse_solve(N, levels, box):
+    a, alpha, s, lv = cav(N, levels, 100.0, box=box)
+    V = mg.VCycle(lv, box, 1, 1)
+    Nc = lv[-1].N
+    b = _zero_walls(np.random.default_rng(53).standard_normal(3 * Nc * Nc), Nc)
+    b[2 * Nc * Nc:] -= b[2 * Nc * Nc:].mean()
+    z = tnp(s.coarse_solve(tdev(b)))
+    zo = V.coarse_solve(b)
+    assert rel(z, zo) < 1e-11
+    assert np.max(np.abs(lv[-1].A @ z - b)) < 1e-10 * np.max(np.abs(b))
+    s.close()
+
+
+@pytest.mark.parametrize("N,levels,box,nu,colours", [(32, 4, 1, (1, 1), 2), (64, 5, 4, (2, 1), 4),
+                                                      (64, 4, 8, (1, 1), 2)])
+def test_cavity_vcycle(N, levels, box, nu, colours):
+    a, alpha, s, lv = cav(N, levels, 100.0, box=box, nu=nu, colours=colours)
+    V = mg.VCycle(lv, box, nu[0], nu[1], "colour2" if colours == 2 else "colour")
+    r = _zero_walls(np.random.default_rng(54).standard_normal(3 * N * N), N)
+    r[2 * N * N:] -= r[2 * N * N:].mean()
+    z = tnp(s.vcycle(tdev(r)))
+    zo = V(r)
+    assert rel(z, zo) < 1e-11
+    s.close()
+
+
+def test_cavity_rhs_with_lid_and_force():
+    """b = lid term + spread elastic force of the annulus at rest (u^n = 0,
+    steady: no inertia term)."""
+    N = 64
+    a, alpha, s, lv = cav(N, 5, 10.0)
+    z = torch.zeros(N, N, dtype=torch.float64, device=DEV)
+    b = tnp(s.rhs(z, z))
+    bo = cavity.rhs(N, a, alpha)
+    assert rel(b, bo) < 1e-13
+    s.close()
+
+
+@pytest.mark.parametrize("ratio,box,colours", [(1.0, 1, 2), (100.0, 1, 4), (100.0, 4, 2), (500.0, 8, 2)])
+def test_cavity_fgmres_matches_oracle(ratio, box, colours):
+    """MG-preconditioned FGMRES on the lid-driven cavity (zero initial guess,
+    V(1,1), the lid as right-hand side): iteration counts within one of the
+    oracle's with the same box order, the solution meets rtol in the
+    oracle's operator, and at equal counts the iterates agree."""
+    N = 64 if box > 1 else 32
+    levels = int(np.log2(N // max(4, box))) + 1
+    a, alpha, s, lv = cav(N, levels, ratio, box=box, colours=colours, rtol=1e-8)
+    bo = cavity.rhs(N, None, 0.0)
+    V = mg.VCycle(lv, box, 1, 1, "colour2" if colours == 2 else "colour")
+    res = krylov.fgmres(lv[0].A, bo, V, rtol=1e-8, maxit=200)
+    x = torch.zeros(3 * N * N, dtype=torch.float64, device=DEV)
+    st = s.solve(tdev(bo), x)
+    xg = tnp(x)
+    print(f"cavity N {N} box {box} colours {colours} ratio {ratio}: gpu {st['iters']} oracle {res.iters}")
+    assert st["converged"] == 1 and res.converged
+    assert abs(st["iters"] - res.iters) <= 1
+    assert np.linalg.norm(bo - lv[0].A @ xg) / np.linalg.norm(bo) <= 1e-8
+    n2 = 2 * N * N
+    if st["iters"] == res.iters:
+        xo = res.x.copy()
+        xo[n2:] -= xo[n2:].mean()
+        xg[n2:] -= xg[n2:].mean()
+        assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("ratio", [1.0, 10.0])
+def test_cavity_mg_solver_matches_oracle(ratio):
+    """Multigrid alone (Sec. 5.1) on the cavity with the checkerboard box
+    order: the V-cycle count and the outcome equal the oracle's.  At relative
+    stiffness 1 both converge; at 10 this order (Jacobi within a colour)
+    diverges where the paper's lexicographic order still converges, and both
+    stop at the same V-cycle once the residual has grown by 1e12."""
+    N = 32
+    a, alpha, s, lv = cav(N, 4, ratio, box=1, rtol=1e-6, maxit=300, solver=1)
+    bo = cavity.rhs(N, None, 0.0)
+    V = mg.VCycle(lv, 1, 1, 1, "colour2")
+    xo, its, conv, hist = mg.mg_solve(lv[0].A, bo, V, rtol=1e-6, maxit=300)
+    x = torch.zeros(3 * N * N, dtype=torch.float64, device=DEV)
+    st = s.solve(tdev(bo), x)
+    print(f"cavity mg solver ratio {ratio}: gpu {st['iters']} converged {st['converged']}, oracle {its} {conv}")
+    assert st["iters"] == its and bool(st["converged"]) == bool(conv)
+    if conv:
+        xg = tnp(x)
+        assert np.linalg.norm(bo - lv[0].A @ xg) / np.linalg.norm(bo) <= 1e-6
+    s.close()
