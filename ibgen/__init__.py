@@ -134,6 +134,20 @@ def fourier_force(rng: np.random.Generator, N: int, n_modes: int = 16, kmax: int
     return out[0], out[1]
 
 
+def annulus(N: int, xc: float = 0.5, yc: float = 0.5, r: float = 0.25, width: float = 1.0 / 16):
+    """The thick annulus of the paper's test problem (Sec. 4) as input
+    positions: M2 = 3 N / 32 + 1 concentric rings of M1 = 19 N / 8 points,
+    ring l at radius r + l width / (M2 - 1), point k at angle 2 pi k / M1.
+    Returns (X of shape (M1 M2, 2), fibre offsets, M1, M2).  Deterministic."""
+    if N % 32:
+        raise ValueError("N must be a multiple of 32")
+    M1, M2 = 19 * N // 8, 3 * N // 32 + 1
+    th = 2.0 * np.pi * np.arange(M1) / M1
+    X = np.concatenate([np.stack([xc + (r + l * width / (M2 - 1)) * np.cos(th),
+                                  yc + (r + l * width / (M2 - 1)) * np.sin(th)], 1) for l in range(M2)])
+    return X, np.arange(M2 + 1, dtype=np.int32) * M1, M1, M2
+
+
 def config_c1() -> Workload:
     """32x32, 4 levels, one perturbed ellipse of 128 points, K=1e4,
     dt = 100 x explicit limit, V(2,2), box 4, rtol 1e-10, one step."""

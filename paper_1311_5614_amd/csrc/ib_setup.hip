@@ -532,7 +532,9 @@ __device__ void assemble_box(const LevelView<double>& L, int bx, int by, bool wi
         if ((col = box_local(2, i, j, bx, by, n, N)) >= 0) row[col] += L.invh;
         if ((col = box_local(2, comp == 0 ? i - 1 : i, comp == 0 ? j : j - 1, bx, by, n, N)) >= 0)
           row[col] -= L.invh;
-        const int ar = with_ib ? L.act[comp * NN + j * N + i] : -1;
+        // with walls a box may take its own inverse without elastic rows
+        // (a box along a wall, or no structure at all): act is then absent
+        const int ar = (with_ib && L.act) ? L.act[comp * NN + j * N + i] : -1;
         if (ar >= 0) {
           const double* cw = L.win + ((size_t)comp * L.maxact + ar) * IBMG_WS;
           for (int dy = -L.reach; dy <= L.reach; ++dy)
@@ -560,7 +562,7 @@ __device__ void assemble_box(const LevelView<double>& L, int bx, int by, bool wi
         if ((col = box_local(2, i, j, bx, by, n, N)) >= 0) row[col] += L.invh;
         if ((col = box_local(2, i, jm, bx, by, n, N)) >= 0) row[col] -= L.invh;
       }
-      const int ar = with_ib ? L.act[comp * NN + j * N + i] : -1;
+      const int ar = (with_ib && L.act) ? L.act[comp * NN + j * N + i] : -1;
       if (ar >= 0) {
         const double* cw = L.win + ((size_t)comp * L.maxact + ar) * IBMG_WS;
         for (int dy = -L.reach; dy <= L.reach; ++dy)

@@ -523,7 +523,7 @@ __device__ void small_sweep(const LevelView<T>& L, const T* __restrict__ b, T* _
           box_dof(lane, bx, by, NB, N, comp, i, j);
           g = (size_t)comp * NN + (size_t)j * N + i;
           T y = r[g];
-          if (ibx >= 0 && comp < 2) y -= L.yib[g];   // zero off the active rows
+          if (ibx >= 0 && comp < 2 && L.yib) y -= L.yib[g];   // zero off the active rows
           res[wave][lane] = (double)y;
         }
       }

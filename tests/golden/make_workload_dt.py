@@ -8,7 +8,10 @@ Sec. 4.1 of the paper, read for nodal springs) and the workload's
 dt = factor * dt_exp.  The time step is an input of the solve; the GPU path
 reads it from this file and never computes it.
 
-Usage: python tests/golden/make_workload_dt.py [c1 c2 c3 c4 c5]
+For the walled test problem ("cavity") it stores alpha_exp of the thick
+annulus at N = 32, 64, 128 (Table 1's quantity, from the oracle).
+
+Usage: python tests/golden/make_workload_dt.py [c1 c2 c3 c4 c5 cavity]
 """
 import json
 import os
@@ -58,6 +61,9 @@ def main(which):
         data["c4"] = [entry(w) for w in ibgen.config_c4()]
     if "c5" in which:
         data["c5"] = [entry(ibgen.config_c5())]
+    if "cavity" in which:   # the walled test problem: alpha_exp of Table 1 (Sec. 4.1)
+        from oracle import cavity
+        data["cavity"] = [dict(N=N, alpha_exp=cavity.alpha_exp(N)) for N in (32, 64, 128)]
     with open(OUT, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     print("wrote", OUT, sorted(data))

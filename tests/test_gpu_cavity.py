@@ -208,3 +208,39 @@ def test_cavity_mg_solver_matches_oracle(ratio):
         xg = tnp(x)
         assert np.linalg.norm(bo - lv[0].A @ xg) / np.linalg.norm(bo) <= 1e-6
     s.close()
+
+
+@pytest.mark.parametrize("box,with_points", [(1, False), (4, True)])
+def test_cavity_without_elastic_rows(box, with_points):
+    """Walls and no elastic rows (no points, or points with K = 0): the boxes
+    along the walls still take their own inverses.  Box blocks, a V-cycle,
+    the lid right-hand side and a solve against the oracle's Stokes-only
+    walled problem."""
+    from paper_1311_5614_amd import ibmg
+    N, levels = 32, (4 if box == 1 else 3)
+    X, offs, M1, M2 = __import__("ibgen").annulus(N)
+    cfg = ibmg.Config(N=N, levels=levels, K=0.0, rho=0.0, box=box, nu1=1, nu2=1, maxit=100, rtol=1e-10,
+                      colours=2, tail_max=1, delta=ibmg.IBMG_DELTA_COS4, domain=ibmg.IBMG_CAVITY)
+    s = ibmg.Solver(cfg, offs if with_points else None, DEV)
+    s.setup(1.0, tdev(X) if with_points else None)
+    lv = cavity.hierarchy(N, levels, 0.0, None)
+    sm = smoother.BoxSmoother(lv[0].A, N, box)
+    for bx in range(N // box):
+        for by in (0, 1, N // box - 1):
+            A = tnp(s.box_matrix(0, bx, by))
+            Ao = sm.box_matrix(bx, by)
+            assert np.max(np.abs(A - Ao)) < 1e-12 * np.max(np.abs(Ao)), (bx, by)
+    V = mg.VCycle(lv, box, 1, 1, "colour2")
+    r = _zero_walls(np.random.default_rng(55).standard_normal(3 * N * N), N)
+    r[2 * N * N:] -= r[2 * N * N:].mean()
+    assert rel(tnp(s.vcycle(tdev(r))), V(r)) < 1e-11
+    z = torch.zeros(N, N, dtype=torch.float64, device=DEV)
+    b = s.rhs(z, z)
+    bo = cavity.rhs(N, None, 0.0)
+    assert rel(tnp(b), bo) < 1e-13
+    x = torch.zeros(3 * N * N, dtype=torch.float64, device=DEV)
+    st = s.solve(b, x)
+    res = krylov.fgmres(lv[0].A, bo, V, rtol=1e-10, maxit=100)
+    assert st["converged"] == 1 and abs(st["iters"] - res.iters) <= 1
+    assert np.linalg.norm(bo - lv[0].A @ tnp(x)) / np.linalg.norm(bo) <= 1e-10
+    s.close()

@@ -221,3 +221,14 @@ def test_table2_counts_single_cell():
         for ratio, want in zip(c["ratios"], want_row):
             got = _gmres_count(64, 1, nu, float(ratio))
             assert abs(got - want) <= 2, (nu, ratio, got, want)
+
+
+def test_input_generator_annulus_matches_oracle():
+    """The GPU tests and the benchmark take the annulus from the input
+    generator; it is the oracle's geometry."""
+    import ibgen
+    for N in (32, 64):
+        X, offs, M1, M2 = ibgen.annulus(N)
+        a = cavity.annulus(N)
+        assert (M1, M2) == (a.M1, a.M2) and np.array_equal(offs, a.fiber_offsets)
+        assert np.max(np.abs(X - a.X)) < 1e-15
