@@ -232,3 +232,45 @@ def test_input_generator_annulus_matches_oracle():
         a = cavity.annulus(N)
         assert (M1, M2) == (a.M1, a.M2) and np.array_equal(offs, a.fiber_offsets)
         assert np.max(np.abs(X - a.X)) < 1e-15
+
+
+def _spectral_radius(ratio, tol=1e-6):
+    """Largest eigenvalue magnitude of the V-cycle iteration matrix
+    I - M A (Sec. 5.2) on the cavity at h = 2^-5, single-cell boxes in the
+    paper's order, V(1,1), with the constant-pressure direction projected
+    out (its eigenvalue 1 is the pressure's free constant), by Arnoldi."""
+    import scipy.sparse.linalg as spla
+    lv, mg = _cavity_levels(32, 1, float(ratio))
+    V = mg.VCycle(lv, 1, 1, 1, "paper")
+    A = lv[0].A
+    n = A.shape[0]
+    q = np.zeros(n)
+    q[2 * 32 * 32:] = 1.0 / 32
+
+    def mv(x):
+        x = x - q * (q @ x)
+        y = x - V(A @ x)
+        return y - q * (q @ y)
+
+    op = spla.LinearOperator((n, n), matvec=mv, dtype=float)
+    ev = spla.eigs(op, k=4, which="LM", return_eigenvectors=False, tol=tol,
+                   v0=np.random.default_rng(3).standard_normal(n))
+    return float(np.max(np.abs(ev)))
+
+
+@pytest.mark.parametrize("ratio", [10, 100])
+def test_mg_spectral_radius_stiff(ratio):
+    """Sec. 5.2: spectral radius 0.30 at relative stiffness 10 and 0.85 at
+    100 (the slow mode), to the printed digits."""
+    want = _counts()["spectrum"][str(ratio)]
+    got = _spectral_radius(ratio, tol=1e-3)
+    assert abs(got - want) <= 0.006, (ratio, got, want)
+
+
+@pytest.mark.skipif(not os.environ.get("IBMG_FULL_TABLES"), reason="minutes of CPU; set IBMG_FULL_TABLES=1")
+@pytest.mark.parametrize("ratio", [0, 1])
+def test_mg_spectral_radius_mild(ratio):
+    """Sec. 5.2: 0.24 without elasticity and 0.22 at relative stiffness 1."""
+    want = _counts()["spectrum"][str(ratio)]
+    got = _spectral_radius(ratio)
+    assert abs(got - want) <= 0.006, (ratio, got, want)
