@@ -164,12 +164,13 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
     const int groups = (cnt + B - 1) / B;
     const int nper = (B > 1 && groups > kBoxWaveTarget) ? groups / kBoxWaveTarget : 1;
     const int waves = (groups + nper - 1) / nper;
-    const int grid = (waves + kBoxWavesMax - 1) / kBoxWavesMax;
+    constexpr int W1 = kBoxWavesOne;
+    const int grid = (waves + (B == 4 ? kBoxWavesMax : W1) - 1) / (B == 4 ? kBoxWavesMax : W1);
     if (L.n == 4) {
       if (B == 4) k_box<T, 4, kBoxWavesMax, 4><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt, nper);
-      else k_box<T, 4, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt, nper);
-    } else if (L.n == 2) k_box<T, 2, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt, nper);
-    else k_box<T, 1, kBoxWavesMax><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, r, w, colour, cnt, nper);
+      else k_box<T, 4, W1><<<grid, 64 * W1, 0, s>>>(V, r, w, colour, cnt, nper);
+    } else if (L.n == 2) k_box<T, 2, W1><<<grid, 64 * W1, 0, s>>>(V, r, w, colour, cnt, nper);
+    else k_box<T, 1, W1><<<grid, 64 * W1, 0, s>>>(V, r, w, colour, cnt, nper);
   } else {
     if (L.n == 4) k_box<T, 4, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt, 1);
     else if (L.n == 2) k_box<T, 2, 1><<<cnt, 64, 0, s>>>(V, r, w, colour, cnt, 1);
@@ -190,12 +191,13 @@ template <typename T> void launch_phase_fused(hipStream_t s, const LevelView<T>&
     const int groups = (cnt + B - 1) / B;
     const int nper = (B > 1 && groups > kBoxWaveTarget) ? groups / kBoxWaveTarget : 1;
     const int waves = (groups + nper - 1) / nper;
-    const int grid = (waves + kBoxWavesMax - 1) / kBoxWavesMax;
+    constexpr int W1 = kBoxWavesOne;
+    const int grid = (waves + (B == 4 ? kBoxWavesMax : W1) - 1) / (B == 4 ? kBoxWavesMax : W1);
     if (L.n == 4) {
       if (B == 4) k_box<T, 4, kBoxWavesMax, 4, true><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, b, w, colour, cnt, nper);
-      else k_box<T, 4, kBoxWavesMax, 1, true><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, b, w, colour, cnt, nper);
+      else k_box<T, 4, W1, 1, true><<<grid, 64 * W1, 0, s>>>(V, b, w, colour, cnt, nper);
     } else {
-      k_box<T, 2, kBoxWavesMax, 1, true><<<grid, 64 * kBoxWavesMax, 0, s>>>(V, b, w, colour, cnt, nper);
+      k_box<T, 2, W1, 1, true><<<grid, 64 * W1, 0, s>>>(V, b, w, colour, cnt, nper);
     }
   } else {
     if (L.n == 4) k_box<T, 4, 1, 1, true><<<cnt, 64, 0, s>>>(V, b, w, colour, cnt, 1);
