@@ -457,7 +457,16 @@ def c3_schedule():
     return autotune.load()["c3"]["1024"]
 
 
-C3_FORMS = ("chosen", "plain", "chosen_zero_start", "chosen_fp32")
+C3_FORMS = ("chosen", "plain", "chosen_prev_start", "chosen_zero_start", "chosen_fp32")
+
+
+def c3_start(form):
+    """Initial iterate of a form: "extrap" (w^n plus the previous step's
+    increment, through the solver's guard: ibmg_guess_step), "prev" (w^n) or
+    "zero"."""
+    if form in ("chosen", "chosen_fp32"):
+        return c3_schedule().get("start", "prev")
+    return {"chosen_prev_start": "prev", "chosen_zero_start": "zero"}.get(form, "zero")
 
 
 def c3_config(form):
@@ -470,6 +479,8 @@ def c3_config(form):
     import ibgen
     if form == "chosen_zero_start":
         return dataclasses.replace(c3_config("chosen"), guess=ibmg.IBMG_GUESS_ZERO)
+    if form == "chosen_prev_start":
+        return dataclasses.replace(c3_config("chosen"), guess=ibmg.IBMG_GUESS_PREV)
     if form == "chosen_fp32":
         return dataclasses.replace(c3_config("chosen"), prec=ibmg.IBMG_FP32)
     w = ibgen.config_c3()
@@ -485,51 +496,62 @@ def c3_config(form):
                        omega=sch.get("omega", 1.0), orth=sch.get("orth", ibmg.IBMG_ORTH_CGS2))
 
 
-def describe(cfg):
+def describe(cfg, start=None):
     from paper_1311_5614_amd import ibmg
     rs = f"FGMRES({cfg.restart}), cap {cfg.maxit}" if cfg.restart else f"FGMRES, cap {cfg.maxit}"
     order = (f"{cfg.colours} colours on levels 0-{cfg.colours_from - 1}, checkerboard below" if cfg.colours_from
              else f"{cfg.colours} colours")
-    start = "previous step's solution" if cfg.guess == ibmg.IBMG_GUESS_PREV else "zero"
+    if start == "extrap":
+        start = "previous step's solution plus its increment (guarded extrapolation)"
+    else:
+        start = "previous step's solution" if cfg.guess == ibmg.IBMG_GUESS_PREV else "zero"
     orth = "delayed CGS2" if cfg.orth == ibmg.IBMG_ORTH_DCGS2 else "CGS2"
     return (f"{'FP32' if cfg.prec == ibmg.IBMG_FP32 else 'FP64'} V({cfg.nu1},{cfg.nu2}) V-cycle, {cfg.levels} levels, "
             f"{cfg.box}x{cfg.box} boxes, {order}, box weight {cfg.omega:g}, tail {cfg.tail_max or 32}, {rs}, "
             f"FP64 Krylov ({orth}), initial iterate {start}")
 
 
-def timed_trajectory(s, w, dt, dev, steps, warmup, repeats):
+def timed_trajectory(s, w, dt, dev, steps, warmup, repeats, net=None):
     """`warmup` untimed steps, then `repeats` runs of `steps` steps, each from
     the workload's initial state (u = v = p = 0, X^0), bracketed by device
-    synchronisations.  Returns the per-run seconds and the per-step stats of
-    every run."""
+    synchronisations.  net: a network handle whose trajectory state serves
+    the extrapolated start (ibmg_guess_step, reset with the state).  Returns
+    the per-run seconds and the per-step stats of every run."""
     import torch
+    from paper_1311_5614_amd import ibmg
     t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
     X0 = t(w.X)
     z = torch.zeros(w.N, w.N, dtype=torch.float64, device=dev)
     u, v, p, X = z.clone(), z.clone(), z.clone(), X0.clone()
+    step = (lambda: s.step(dt, u, v, p, X)) if net is None else \
+        (lambda: s.guess_step(net, ibmg.IBMG_GUESS_EXTRAP, dt, u, v, p, X))
+    if net is not None:
+        net.reset()
     for _ in range(warmup):
-        s.step(dt, u, v, p, X)
+        step()
     times, stats = [], []
     for _ in range(repeats):
         u.zero_(); v.zero_(); p.zero_(); X.copy_(X0)
+        if net is not None:
+            net.reset()
         torch.cuda.synchronize()
         run = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            run.append(s.step(dt, u, v, p, X))
+            run.append(step())
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         stats.append(run)
     return times, stats
 
 
-def form_summary(cfg, times, stats, steps):
+def form_summary(cfg, times, stats, steps, start=None):
     import statistics
     med = statistics.median(times)
     its = [st["iters"] for run in stats for st in run]
     res = [st["rel_resid_true"] for run in stats for st in run]
     conv = [st["converged"] for run in stats for st in run]
-    return {"schedule": describe(cfg), "rate": steps / med, "ms_per_step": 1e3 * med / steps,
+    return {"schedule": describe(cfg, start), "rate": steps / med, "ms_per_step": 1e3 * med / steps,
             "runs_s": [round(x, 4) for x in times], "iters_mean": sum(its) / len(its), "iters_max": max(its),
             "steps_timed": len(its), "converged": sum(conv), "missed_rtol": len(its) - sum(conv),
             "rel_resid_max": max(res), "fallbacks": sum(st["fallback"] for run in stats for st in run)}
@@ -690,9 +712,13 @@ def run_c3(args, dev):
     res, solvers = {}, {}
     for form in forms:
         cfg = c3_config(form)
+        start = c3_start(form)
         s = ibmg.Solver(cfg, w.fiber_offsets, dev)
-        times, stats = timed_trajectory(s, w, dt, dev, args.steps, args.warmup, args.repeats)
-        res[form] = form_summary(cfg, times, stats, args.steps)
+        net = ibmg.Cnn(w.N, 1, dev) if start == "extrap" else None
+        times, stats = timed_trajectory(s, w, dt, dev, args.steps, args.warmup, args.repeats, net)
+        if net is not None:
+            net.close()
+        res[form] = form_summary(cfg, times, stats, args.steps, start)
         r = res[form]
         print(f"[bench] c3 {form}: {r['rate']:.3f} steps/s (runs {r['runs_s']} s), iters mean "
               f"{r['iters_mean']:.1f} max {r['iters_max']}, missed rtol {r['missed_rtol']}/{r['steps_timed']}",
@@ -717,7 +743,7 @@ def run_c3(args, dev):
         "vs_baseline": None, "dtype": "f64+f32" if cfg.prec == ibmg.IBMG_FP32 else "f64", "data": "synthetic",
         "config": {"workload": (f"1024x1024 periodic grid, 8 elastic rings x 2048 points (16384), K 1e6, "
                                 f"dt 500 x explicit limit, {cfg.levels} levels, rtol 1e-8; chosen form: "
-                                f"{describe(cfg)}"),
+                                f"{describe(cfg, c3_start(chosen))}"),
                    "grid": w.N, "points": w.M, "rings": 8, "K": w.K, "dt_factor": w.dt_factor,
                    "repeats": args.repeats, "timing": "median of the repeats"},
         "forms": res,

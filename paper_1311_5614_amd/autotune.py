@@ -97,10 +97,12 @@ def candidates_c3(w):
     the coarsest solve spread over the grid (tail 1), over box orders (four
     colours on every level, on the two finest only, or the checkerboard
     throughout) and sweeps.  FP32 V-cycles are tried on the best of these in
-    the second stage."""
-    for (col, cf), nu, om in itertools.product(((4, 2), (4, 3), (2, 0)), ((2, 2), (3, 3), (2, 1)), (1.0, 0.8)):
+    the second stage.  FGMRES delays its second Gram-Schmidt projection
+    (orth 1), as the benchmark's chosen form does.  (V(3,3) stalled on a
+    calibration step in every order and weight; it is no longer tried.)"""
+    for (col, cf), nu, om in itertools.product(((4, 2), (4, 3), (2, 0)), ((2, 2), (2, 1), (1, 1)), (1.0, 0.8)):
         yield dict(box=4, levels=w.levels, tail_max=1, nu1=nu[0], nu2=nu[1], colours=col, colours_from=cf, prec=0,
-                   maxit=C3_CAP, restart=C3_BASIS, omega=om, guess=1)
+                   maxit=C3_CAP, restart=C3_BASIS, omega=om, guess=1, orth=1)
 
 
 def candidates(w, boxes=(4,)):
@@ -131,7 +133,7 @@ def time_schedule(w, dt, sch, steps, dev):
     cfg = ibmg.Config(N=w.N, levels=sch["levels"], K=w.K, box=sch["box"], nu1=sch["nu1"], nu2=sch["nu2"],
                       maxit=sch.get("maxit", MAXIT), restart=sch.get("restart", 0), rtol=w.rtol, prec=sch["prec"],
                       colours=sch["colours"], colours_from=sch.get("colours_from", 0), tail_max=sch["tail_max"],
-                      omega=sch.get("omega", 1.0), guess=sch.get("guess", 0))
+                      omega=sch.get("omega", 1.0), guess=sch.get("guess", 0), orth=sch.get("orth", 0))
     s = ibmg.Solver(cfg, w.fiber_offsets, dev)
     t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
     gu = t(w.g_u) if w.g_u is not None else None
