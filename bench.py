@@ -631,7 +631,7 @@ def finish_cpu_leg(p, cores, iters_per_step, timeout_s=900):
             "iter_s": d["iter_s"]}
 
 
-def c3_roofline(s, cfg, w, dt, dev, iters_mean, reps=BOX_REPS):
+def c3_roofline(s, cfg, w, dt, dev, iters_mean, reps=BOX_REPS, nvec=None):
     """HIP-event timing of the hot kernels of the chosen form on the state the
     timed runs left (setup at the current positions, the last solve's Krylov
     basis): the box relaxation and the residual pass of one colour phase on
@@ -645,7 +645,8 @@ def c3_roofline(s, cfg, w, dt, dev, iters_mean, reps=BOX_REPS):
     X = torch.as_tensor(w.X, dtype=torch.float64, device=dev).contiguous()
     s.setup(dt, X)
     basis = cfg.restart or cfg.maxit
-    nvec = max(1, min(int(round(iters_mean / 2)) + 1, basis - 1))
+    if not nvec:   # the mean basis size of the timed solves (a counter run may fix it)
+        nvec = max(1, min(int(round(iters_mean / 2)) + 1, basis - 1))
     sweeps = (cfg.nu1 + cfg.nu2) * cfg.colours * iters_mean        # finest-level phases per step
     cand = {
         "k_box": (ibmg.IBMG_KERNEL_BOX, 0, 0, sweeps, "box relaxation of one colour phase, finest level"),
@@ -732,7 +733,7 @@ def run_c3(args, dev):
     chosen = "chosen" if "chosen" in res else forms[0]
     rc = res[chosen]
     s, cfg = solvers[chosen]
-    roof = c3_roofline(s, cfg, w, dt, dev, rc["iters_mean"])
+    roof = c3_roofline(s, cfg, w, dt, dev, rc["iters_mean"], nvec=args.roofline_nvec)
     for f, (sv, _) in solvers.items():
         sv.close()
     del solvers
@@ -1203,6 +1204,8 @@ def main():
     ap.add_argument("--no-probe", action="store_true", help="skip the 4096x4096 bandwidth probe")
     ap.add_argument("--probe-only", action="store_true", help="run only the 4096x4096 bandwidth probe")
     ap.add_argument("--probe-n", type=int, default=PROBE_N, help="grid of the bandwidth probe")
+    ap.add_argument("--roofline-nvec", type=int, default=0,
+                    help="basis size of the Gram-Schmidt roofline launches (default: from the timed solves)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy a device buffer of this many MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
