@@ -61,6 +61,10 @@ void layout(ibmg_handle* h) {
       take(cur, B.win, 2 * (size_t)B.maxact * IBMG_WS * sizeof(double));
       if (h->prec == IBMG_FP32) take(cur, B.winf, 2 * (size_t)B.maxact * IBMG_WS * sizeof(float));
       take(cur, B.yib, 2 * NN * sizeof(double));
+      if (l < h->levels - 1 && phase_fusable(h->ncol_l[l], h->n)) {
+        take(cur, B.crow, 8 * (size_t)B.maxact * sizeof(int));
+        take(cur, B.ncrow, 8 * sizeof(int));
+      }
     }
     if (l < h->levels - 1) {
       const size_t nbox = (size_t)B.nb * B.nb;
@@ -344,6 +348,11 @@ int setup_launch(ibmg_handle* h, double dt, const double* X) {
       // elastic rows by face: zero off this step's active rows
       const size_t ny = 2 * (size_t)B.N * B.N;
       k_fill<double><<<nblk(ny), 256, 0, s>>>(h->p<double>(B.yib), ny, 0.0);
+      // one-launch four-colour levels: each colour's phase evaluates only
+      // the elastic rows of its own boxes
+      if (B.crow.bytes)
+        launch_colour_rows(s, B.N, h->n, B.nb, h->p<int>(B.rows), h->p<int>(B.nact), B.maxact, h->p<int>(B.crow),
+                           h->p<int>(B.ncrow));
     }
   }
   for (int l = 0; l + 1 < Lv; ++l) {

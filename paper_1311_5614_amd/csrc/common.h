@@ -46,6 +46,9 @@ struct LevelView {
   const int* rows;// [2][maxact] face of each active row
   const int* nact;// [2] active rows per component
   T* yib;         // [2][N^2] (M_l w) on the active rows, zero elsewhere; formed before each colour phase
+  const int* crow;   // levels whose four-colour phases run as one launch: [4][2][maxact] the active rows
+                     // (indices into rows) lying in boxes of each colour, or null
+  const int* ncrow;  // [4][2] their counts
   const int* ib_index;  // [nb^2] index of the box among boxes with elastic rows, or -1
   const T* ainv_plain;  // [ndof * ndof] inverse of the plain box block, column-major
   const double* ainv_ib;// [n_ib][ndof * ndof] inverses of boxes with elastic rows, column-major

@@ -28,6 +28,7 @@ struct LevelBufs {
   Buf act, rows, nact;       // active elastic rows of this level
   Buf win, winf;             // FP64 windows and their FP32 copy
   Buf yib;                   // elastic rows evaluated before a colour phase (V-cycle precision)
+  Buf crow, ncrow;           // one-launch four-colour levels: active rows in the boxes of each colour
   Buf ib_index, ib_boxes, boxflag, info;
   Buf ainv_plain, ainv_plain_f, ainv_ib;
   int max_ib = 0;
@@ -124,6 +125,10 @@ inline LevelView<T> view(const ibmg_handle* h, int l) {
     v.rows = h->p<int>(B.rows);
     v.nact = h->p<int>(B.nact);
     v.yib = h->p<T>(B.yib);
+    if (B.crow.bytes) {
+      v.crow = h->p<int>(B.crow);
+      v.ncrow = h->p<int>(B.ncrow);
+    }
     v.win = sizeof(T) == sizeof(float) ? reinterpret_cast<const T*>(h->p<float>(B.winf))
                                        : reinterpret_cast<const T*>(h->p<double>(B.win));
   }

@@ -430,6 +430,30 @@ k_win_coarse(int Nc, const int* __restrict__ act_f, const double* __restrict__ w
   if (bad) atomicOr(flags, 2);
 }
 
+// Per-colour lists of the active rows (four colours): a face lies in the
+// box that holds it and, on a box edge across its normal, also in the
+// neighbour before it (periodic index); the two boxes differ in colour, so
+// each list holds a row at most once.  The order within a list depends on
+// the atomics; each row is evaluated on its own, so the results do not.
+__global__ void __launch_bounds__(256)
+k_colour_rows(int N, int n, int nb, const int* __restrict__ rows, const int* __restrict__ nact, int maxact,
+              int* __restrict__ crow, int* __restrict__ ncrow) {
+  const int comp = blockIdx.y;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= min(nact[comp], maxact)) return;
+  const int f = rows[comp * maxact + r];
+  const int i = f % N, j = f / N;
+  const int a = comp == 0 ? i : j, t = comp == 0 ? j : i;   // along the normal, along the tangent
+  const int ba[2] = {a / n, (a / n + nb - 1) % nb};
+  const int nba = (a % n == 0) ? 2 : 1;
+  for (int q = 0; q < nba; ++q) {
+    const int bx = comp == 0 ? ba[q] : t / n, by = comp == 0 ? t / n : ba[q];
+    const int c = (bx & 1) | ((by & 1) << 1);
+    const int slot = atomicAdd(&ncrow[c * 2 + comp], 1);
+    crow[(size_t)(c * 2 + comp) * maxact + slot] = r;
+  }
+}
+
 // ---------------------------------------------------------------- boxes with elastic rows
 // A box takes its own inverse if one of its faces has elastic rows (act
 // given) or, with walls, if it touches a wall (its block differs from the
@@ -730,6 +754,12 @@ void launch_windows_coarse(hipStream_t s, int Nc, const int* act_f, const double
                            int walls) {
   dim3 g((unsigned)((maxact + 3) / 4), 2);
   k_win_coarse<<<g, 256, 0, s>>>(Nc, act_f, win_f, maxact_f, reach_f, rows, nact, maxact, reach, win, flags, walls);
+}
+
+void launch_colour_rows(hipStream_t s, int N, int n, int nb, const int* rows, const int* nact, int maxact, int* crow,
+                        int* ncrow) {
+  k_fill_i32<<<1, 256, 0, s>>>(ncrow, 8, 0);
+  k_colour_rows<<<dim3((unsigned)((maxact + 255) / 256), 2), 256, 0, s>>>(N, n, nb, rows, nact, maxact, crow, ncrow);
 }
 
 void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int walls, int* flag,

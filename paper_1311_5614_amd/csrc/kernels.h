@@ -78,6 +78,9 @@ void launch_windows_coarse(hipStream_t s, int Nc, const int* act_f, const double
                            int walls = 0);
 void launch_box_classes(hipStream_t s, int N, int n, int nb, int ncol, const int* act, int walls, int* flag,
                         int* ib_index, int* ib_boxes, int* info);
+// per-colour lists of the active rows of a four-colour level (LevelView::crow)
+void launch_colour_rows(hipStream_t s, int N, int n, int nb, const int* rows, const int* nact, int maxact, int* crow,
+                        int* ncrow);
 // Box inverses of every non-coarsest level in one launch: level l owns blocks
 // first[l] .. first[l + 1] - 1, the first of them its plain block and the
 // others its boxes with elastic rows (ib_boxes[l]).

@@ -73,13 +73,18 @@ __device__ inline T ib_row(const LevelView<T>& L, const T* __restrict__ w, int c
 
 // Rows of one component, nblk workgroups striding over the active rows (the
 // count is read on the device, so a captured launch stays valid when the
-// active set changes).
+// active set changes).  colour >= 0 (mode 0, levels with per-colour row
+// lists): only the rows in boxes of that colour, the only ones its phase
+// reads.
 template <typename T>
 __device__ inline void ib_rows_body(const LevelView<T>& L, const T* __restrict__ w, T* __restrict__ out, int mode,
-                                    int blk, int comp, int nblk) {
+                                    int blk, int comp, int nblk, int colour = -1) {
   const int lane = threadIdx.x & 15, NN = L.N * L.N;
-  const int nrows = min(L.nact[comp], L.maxact);
-  for (int row = (blk * 256 + threadIdx.x) >> 4; row < nrows; row += nblk * 16) {   // uniform over 16 lanes
+  const bool sub = colour >= 0 && L.crow;
+  const int* list = sub ? L.crow + (size_t)(colour * 2 + comp) * L.maxact : nullptr;
+  const int nrows = min(sub ? L.ncrow[colour * 2 + comp] : L.nact[comp], L.maxact);
+  for (int q = (blk * 256 + threadIdx.x) >> 4; q < nrows; q += nblk * 16) {   // uniform over 16 lanes
+    const int row = sub ? list[q] : q;
     int f;
     const T acc = ib_row(L, w, comp, row, lane, f);
     if (lane != 0) continue;
@@ -249,10 +254,16 @@ __device__ inline void box_body_n(const LevelView<T>& L, const T* __restrict__ r
         if (ibx[b] >= 0) {
           const double* A = L.ainv_ib + (size_t)ibx[b] * ND * ND;
           double z = 0.0;
-          // unrolled by eight, not fully: the register pressure of 56 loads in
-          // flight would halve the waves resident per SIMD
+          if constexpr (B == 1) {
+            // one box per wave: unrolled by eight, not fully (the register
+            // pressure of 56 loads in flight would halve the waves resident
+            // per SIMD)
 #pragma unroll 8
-          for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[b][c];
+            for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[b][c];
+          } else {
+#pragma unroll
+            for (int c = 0; c < ND; ++c) z += A[c * ND + lane] * res[b][c];
+          }
           w[g[b]] = wv[b] + L.omega * (T)z;
         } else if constexpr (LI) {
           T z = T(0);

@@ -26,8 +26,9 @@ k_residual(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ w, T* 
   residual_body<T>(L, b, w, r, xcd_remap(blockIdx.x, gridDim.x));
 }
 template <typename T>
-__global__ void __launch_bounds__(256) k_ib_rows(LevelView<T> L, const T* __restrict__ w, T* __restrict__ out, int mode) {
-  ib_rows_body<T>(L, w, out, mode, blockIdx.x, blockIdx.y, gridDim.x);
+__global__ void __launch_bounds__(256)
+k_ib_rows(LevelView<T> L, const T* __restrict__ w, T* __restrict__ out, int mode, int colour) {
+  ib_rows_body<T>(L, w, out, mode, blockIdx.x, blockIdx.y, gridDim.x, colour);
 }
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -137,7 +138,7 @@ namespace ibmg {
 template <typename T> void launch_residual(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r,
                                            bool ib) {
   k_residual<T><<<nblk(3 * (size_t)L.N * L.N), 256, 0, s>>>(L, b, w, r);
-  if (ib) k_ib_rows<T><<<dim3(ib_blocks(L.rowhint), 2), 256, 0, s>>>(L, w, r, b ? 2 : 1);
+  if (ib) k_ib_rows<T><<<dim3(ib_blocks(L.rowhint), 2), 256, 0, s>>>(L, w, r, b ? 2 : 1, -1);
 }
 template <typename T> void launch_res(hipStream_t s, const LevelView<T>& L, const T* b, const T* w, T* r, bool ib) {
   const int nres = (int)nblk(3 * (size_t)L.N * L.N);
@@ -183,7 +184,7 @@ template <typename T> void launch_box(hipStream_t s, const LevelView<T>& L, cons
 template <typename T> void launch_phase_fused(hipStream_t s, const LevelView<T>& L, const T* b, T* w, int colour,
                                               bool ib, bool ib_rows) {
   LevelView<T> V = L;
-  if (ib && ib_rows && L.act) k_ib_rows<T><<<dim3(ib_blocks(L.rowhint), 2), 256, 0, s>>>(L, w, nullptr, 0);
+  if (ib && ib_rows && L.act) k_ib_rows<T><<<dim3(ib_blocks(L.rowhint), 2), 256, 0, s>>>(L, w, nullptr, 0, colour);
   if (!ib) V.ib_index = nullptr;
   const int cnt = colour_count(L.ncol, L.nb);
   if (cnt >= kBoxWavesMax * 512) {
