@@ -647,10 +647,14 @@ def c3_roofline(s, cfg, w, dt, dev, iters_mean, reps=BOX_REPS, nvec=None):
     basis = cfg.restart or cfg.maxit
     if not nvec:   # the mean basis size of the timed solves (a counter run may fix it)
         nvec = max(1, min(int(round(iters_mean / 2)) + 1, basis - 1))
-    sweeps = (cfg.nu1 + cfg.nu2) * cfg.colours * iters_mean        # finest-level phases per step
+    phases = (cfg.nu1 + cfg.nu2) * cfg.colours                      # finest-level colour phases per V-cycle
+    fused = cfg.colours == 4 and cfg.box in (2, 4)                   # one-launch phases (they form their residual)
+    # finest-level residual passes per V-cycle: one per phase but the first (from zero) plus the one before
+    # the restriction; with one-launch phases only the latter
+    res_per_v = 1 if fused else phases
     cand = {
-        "k_box": (ibmg.IBMG_KERNEL_BOX, 0, 0, sweeps, "box relaxation of one colour phase, finest level"),
-        "k_res_ib": (ibmg.IBMG_KERNEL_RES, 0, 0, sweeps, "residual pass of one colour phase, finest level"),
+        "k_box": (ibmg.IBMG_KERNEL_BOX, 0, 0, phases * iters_mean, "box relaxation of one colour phase, finest level"),
+        "k_res_ib": (ibmg.IBMG_KERNEL_RES, 0, 0, res_per_v * iters_mean, "residual pass, finest level"),
     }
     if cfg.orth == ibmg.IBMG_ORTH_DCGS2:     # one product pass and one update pass per iteration
         cand["k_multidot2"] = (ibmg.IBMG_KERNEL_DOT2, 0, nvec, iters_mean,
