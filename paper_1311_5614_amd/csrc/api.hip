@@ -1045,8 +1045,10 @@ int ibmg_kernel_bench(ibmg_handle* h, int kernel, int level, int arg, int reps, 
       const int rc = replay_time(
           h, reps, [&](hipStream_t s) { launch_multidot(s, V, n0, arg, V + (size_t)arg * n0, n0, part, kDotBlocks); },
           avg_us);
-      // the arg basis vectors once, the new vector once per group of eight
-      *bytes = ((double)arg + (arg + 7) / 8) * n0 * sizeof(double);
+      // the arg basis vectors and the new vector once (the kernel reads the
+      // new vector again for each group of eight basis vectors; those reads
+      // hit L2 and are not counted)
+      *bytes = ((double)arg + 1.0) * n0 * sizeof(double);
       return rc;
     }
     case IBMG_KERNEL_UPDATE: {
@@ -1072,8 +1074,10 @@ int ibmg_kernel_bench(ibmg_handle* h, int kernel, int level, int arg, int reps, 
                              kDotBlocks);
           },
           avg_us);
-      // the arg + 1 basis vectors once, the two vectors once per group of sixteen
-      *bytes = ((double)(arg + 1) + 2.0 * ((arg + 1 + 15) / 16)) * n0 * sizeof(double);
+      // the arg + 1 basis vectors and the two vectors once (the kernel reads
+      // the two again for each group of sixteen; those reads hit L2 and are
+      // not counted: HBM reads measured 1.0 x this at 60 vectors)
+      *bytes = ((double)(arg + 1) + 2.0) * n0 * sizeof(double);
       return rc;
     }
     case IBMG_KERNEL_UPDATE2: {
