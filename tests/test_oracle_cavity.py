@@ -274,3 +274,15 @@ def test_mg_spectral_radius_mild(ratio):
     want = _counts()["spectrum"][str(ratio)]
     got = _spectral_radius(ratio)
     assert abs(got - want) <= 0.006, (ratio, got, want)
+
+
+@pytest.mark.parametrize("box", [2, 4, 8, 16])
+def test_fig6_big_box_growth(box):
+    """Sec. 6.1: MG-GMRES iterations grow from relative stiffness 0 to 1000 by
+    factors of about 10, 6, 4, 3 for boxes of 2, 4, 8, 16 cells (h = 2^-5,
+    V(1,1), the paper's order).  The factor is read from the text to one
+    digit: it must round to the printed value within 0.5."""
+    want = _counts()["fig6_growth"][str(box)]
+    lo = _gmres_count(32, box, (1, 1), 0.0)
+    hi = _gmres_count(32, box, (1, 1), 1000.0)
+    assert abs(hi / lo - want) <= 0.5, (box, lo, hi, hi / lo)
