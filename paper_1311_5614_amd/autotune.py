@@ -95,12 +95,13 @@ def classes(workload):
 def candidates_c3(w):
     """The eight-ring trajectory: FP64 V-cycles of 4 x 4 boxes down to 16^2,
     the coarsest solve spread over the grid (tail 1), over box orders (four
-    colours on every level, on the two finest only, or the checkerboard
-    throughout) and sweeps.  FP32 V-cycles are tried on the best of these in
+    colours on every level, on the two or three finest only, or the
+    checkerboard throughout) and sweeps.  FP32 V-cycles are tried on the best of these in
     the second stage.  FGMRES delays its second Gram-Schmidt projection
     (orth 1), as the benchmark's chosen form does.  (V(3,3) stalled on a
     calibration step in every order and weight; it is no longer tried.)"""
-    for (col, cf), nu, om in itertools.product(((4, 2), (4, 3), (2, 0)), ((2, 2), (2, 1), (1, 1)), (1.0, 0.8)):
+    for (col, cf), nu, om in itertools.product(((4, 0), (4, 2), (4, 3), (2, 0)), ((2, 2), (2, 1), (1, 1)),
+                                              (1.0, 0.8)):
         yield dict(box=4, levels=w.levels, tail_max=1, nu1=nu[0], nu2=nu[1], colours=col, colours_from=cf, prec=0,
                    maxit=C3_CAP, restart=C3_BASIS, omega=om, guess=1, orth=1)
 
