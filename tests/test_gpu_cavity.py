@@ -244,3 +244,78 @@ def test_cavity_without_elastic_rows(box, with_points):
     assert st["converged"] == 1 and abs(st["iters"] - res.iters) <= 1
     assert np.linalg.norm(bo - lv[0].A @ tnp(x)) / np.linalg.norm(bo) <= 1e-10
     s.close()
+
+
+def _bordered_solve(A, b, N):
+    """x of A x = b with the pressure's mean fixed (the one null vector)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n = A.shape[0]
+    e = np.zeros(n)
+    e[2 * N * N:] = 1.0
+    B = sp.bmat([[A, sp.csr_matrix(e[:, None])], [sp.csr_matrix(e[None, :]), None]], format="csc")
+    return spla.spsolve(B, np.concatenate([b, [0.0]]))[:n]
+
+
+def test_cavity_time_steps_and_explicit_limit():
+    """Time steps on the walled problem with the structure lagged (Sec. 2.3,
+    steady Stokes as in Sec. 7): two implicit steps (the elastic operator
+    dt S K L S* in the system) and three explicit steps (the force at X^n on
+    the right-hand side, Stokes alone in the system) against the oracle's
+    direct solves, then the explicit stability limit of Table 1 in practice:
+    200 steps at 0.95 dt_exp stay bounded and 200 steps at 1.1 dt_exp blow
+    up, dt_exp = alpha_exp / gamma with the oracle's alpha_exp."""
+    from paper_1311_5614_amd import ibmg
+    from oracle import ib
+    N, levels, dt = 32, 3, 1.0 / 40
+    a = cavity.annulus(N)
+    aexp = _alpha_exp(N)
+    gamma = 10.0 * aexp / dt
+    dte = aexp / gamma
+    K = cavity.nodal_stiffness(a, gamma)
+    z = np.zeros((N, N))
+
+    def oracle_step(X, step_dt, implicit):
+        b = cavity.lid_rhs(N, 1.0)
+        fu, fv = ib.spread(X, ib.fiber_force(X, a.fiber_offsets, K), N, ib.DELTA_COS4)
+        b[:N * N] += np.where(cavity.wall_u(N), 0.0, fu).ravel()
+        b[N * N:2 * N * N] += np.where(cavity.wall_v(N), 0.0, fv).ravel()
+        Xa = cavity.Annulus(X, a.fiber_offsets, a.M1, a.M2, a.ds1, a.ds2)
+        A = cavity.hierarchy(N, 1, gamma * step_dt if implicit else 0.0, Xa)[0].A
+        x = _bordered_solve(A, b, N)
+        u, v = x[:N * N].reshape(N, N), x[N * N:2 * N * N].reshape(N, N)
+        return u, X + step_dt * ib.interp(X, u, v, ib.DELTA_COS4)
+
+    for scheme, step_dt, nsteps in ((ibmg.IBMG_IMPLICIT, dt, 2), (ibmg.IBMG_EXPLICIT, 0.95 * dte, 3)):
+        cfg = ibmg.Config(N=N, levels=levels, K=gamma, rho=0.0, box=4, nu1=1, nu2=1, maxit=200, rtol=1e-11,
+                          colours=2, tail_max=1, delta=ibmg.IBMG_DELTA_COS4, domain=ibmg.IBMG_CAVITY,
+                          scheme=scheme)
+        s = ibmg.Solver(cfg, a.fiber_offsets, DEV)
+        u, v, p, X = tdev(z), tdev(z), tdev(z), tdev(a.X)
+        Xo = a.X.copy()
+        for _ in range(nsteps):
+            st = s.step(step_dt, u, v, p, X)
+            uo, Xo = oracle_step(Xo, step_dt, scheme == ibmg.IBMG_IMPLICIT)
+            assert st["converged"] == 1
+            assert rel(tnp(u), uo) < 1e-9 and rel(tnp(X), Xo) < 1e-12, scheme
+        s.close()
+
+    cfg = ibmg.Config(N=N, levels=levels, K=gamma, rho=0.0, box=4, nu1=1, nu2=1, maxit=200, rtol=1e-8,
+                      colours=2, tail_max=1, delta=ibmg.IBMG_DELTA_COS4, domain=ibmg.IBMG_CAVITY,
+                      scheme=ibmg.IBMG_EXPLICIT, guess=ibmg.IBMG_GUESS_PREV)
+    s = ibmg.Solver(cfg, a.fiber_offsets, DEV)
+
+    def run(fac, n):
+        uu, vv, pp, XX = tdev(z), tdev(z), tdev(z), tdev(a.X)
+        try:
+            for _ in range(n):
+                s.step(fac * dte, uu, vv, pp, XX)
+        except ibmg.IBMGError:        # a non-finite iterate: the explicit run has blown up
+            return float("inf")
+        d = float((XX - tdev(a.X)).abs().max()) * N
+        return d if np.isfinite(d) else float("inf")
+    stable, unstable = run(0.95, 200), run(1.1, 200)
+    print(f"cavity explicit method: max displacement {stable:.3g} cells at 0.95 dt_exp, "
+          f"{unstable:.3g} cells at 1.1 dt_exp (200 steps)")
+    assert stable < 5.0 and unstable > 1e3
+    s.close()
