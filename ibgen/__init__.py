@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "Workload", "seed_for", "ellipse", "rings", "fourier_force",
     "config_c1", "config_c2_cases", "config_c3", "config_c4", "config_c5",
-    "small_case", "cnn_init",
+    "small_case", "cnn_init", "sphere_rings",
 ]
 
 
@@ -247,3 +247,26 @@ def cnn_init(seed: int, layers=((5, 32), (32, 32), (32, 32), (32, 32), (32, 32),
             W = rng.standard_normal(co * ci * 9) * np.sqrt(2.0 / (9 * ci))
         parts += [W, np.zeros(co)]
     return np.concatenate(parts).astype(np.float32)
+
+
+def sphere_rings(N: int, seed: int = 0, r: float = 0.22, spacing: float = 1.0,
+                 stretch=(1.15, 0.9, 0.95), centre=(0.5, 0.5, 0.5), jitter: float = 0.05):
+    """Three-dimensional structure for the periodic unit cube: closed
+    latitude rings on a stretched sphere (an ellipsoid with semi-axes
+    r * stretch), rings `spacing` h apart in polar arc length, points about
+    `spacing` h apart along each ring, each ring turned by a random phase and
+    every point moved by up to jitter * h.  Returns (X (M, 3), fibre offsets)."""
+    rng = np.random.default_rng(seed_for(6, seed))
+    h = 1.0 / N
+    n_lat = max(1, int(round(np.pi * r / (spacing * h))) - 1)
+    pts, offs = [], [0]
+    for i in range(n_lat):
+        th = np.pi * (i + 1) / (n_lat + 1)
+        m = max(8, int(round(2.0 * np.pi * r * np.sin(th) / (spacing * h))))
+        ph = 2.0 * np.pi * np.arange(m) / m + rng.uniform(0.0, 2.0 * np.pi)
+        ring = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.full(m, np.cos(th))], axis=1)
+        ring = np.asarray(centre) + r * np.asarray(stretch) * ring
+        ring += rng.uniform(-jitter * h, jitter * h, size=ring.shape)
+        pts.append(ring)
+        offs.append(offs[-1] + m)
+    return np.concatenate(pts), np.asarray(offs, dtype=np.int32)
