@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libibmg.so")
-SOURCES = ["api.hip", "batch.hip", "cnn.hip", "ib_setup.hip", "mg.hip", "dense.hip", "krylov.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "batch.hip", "cnn.hip", "ib_setup.hip", "mg.hip", "dense.hip", "krylov.hip", "noalloc.hip", "d3.hip"]
 ARCH = "gfx950"
 
 

@@ -47,6 +47,12 @@ EXPORTS = [
     "ibmg_guess_set_increment",
 ]
 
+EXPORTS3 = [
+    "ibmg3_create", "ibmg3_workspace_bytes", "ibmg3_bind_workspace", "ibmg3_destroy", "ibmg3_setup",
+    "ibmg3_apply", "ibmg3_restrict", "ibmg3_prolong_add", "ibmg3_box_matrix", "ibmg3_smooth", "ibmg3_vcycle",
+    "ibmg3_rhs", "ibmg3_solve", "ibmg3_step", "ibmg3_box_counts",
+]
+
 
 class ibmg_problem(C.Structure):
     _fields_ = [("N", C.c_int32), ("rho", C.c_double), ("mu", C.c_double),
@@ -71,6 +77,17 @@ class ibmg_stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ibmg3_problem(C.Structure):
+    _fields_ = [("N", C.c_int32), ("rho", C.c_double), ("mu", C.c_double), ("M", C.c_int32),
+                ("nfib", C.c_int32), ("fiber_offsets", C.POINTER(C.c_int32)), ("K", C.c_double),
+                ("delta", C.c_int32)]
+
+
+class ibmg3_opts(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("box", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("maxit", C.c_int32), ("rtol", C.c_double), ("omega", C.c_double)]
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:
@@ -131,6 +148,23 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ibmg_guess_get_increment": [vp, vp],
         "ibmg_guess_set_increment": [vp, vp],
     }
+    sig.update({
+        "ibmg3_create": [C.POINTER(vp), C.POINTER(ibmg3_problem), C.POINTER(ibmg3_opts), vp],
+        "ibmg3_workspace_bytes": [vp, C.POINTER(sz)],
+        "ibmg3_bind_workspace": [vp, vp, sz],
+        "ibmg3_destroy": [vp],
+        "ibmg3_setup": [vp, dbl, vp],
+        "ibmg3_apply": [vp, i32, vp, vp],
+        "ibmg3_restrict": [vp, i32, vp, vp],
+        "ibmg3_prolong_add": [vp, i32, vp, vp],
+        "ibmg3_box_matrix": [vp, i32, i32, i32, i32, vp],
+        "ibmg3_smooth": [vp, i32, vp, vp, i32],
+        "ibmg3_vcycle": [vp, vp, vp],
+        "ibmg3_rhs": [vp, vp, vp, vp],
+        "ibmg3_solve": [vp, vp, vp, C.POINTER(ibmg_stats)],
+        "ibmg3_step": [vp, dbl, vp, vp, vp, C.POINTER(ibmg_stats)],
+        "ibmg3_box_counts": [vp, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+    })
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
@@ -533,3 +567,117 @@ class Cnn:
         _check(lib().ibmg_cnn_loss_grad(self.h, _ptr(in5), _ptr(dw3), C.byref(loss),
                                         g.ctypes.data_as(C.POINTER(C.c_float))), "ibmg_cnn_loss_grad")
         return loss.value, g
+
+
+@dataclass
+class Config3:
+    """Problem and options of the three-dimensional solver (include/ibmg3.h)."""
+    N: int
+    levels: int
+    K: float = 0.0
+    rho: float = 1.0
+    mu: float = 1.0
+    delta: int = IBMG_DELTA_IB4
+    box: int = 4
+    nu1: int = 1
+    nu2: int = 1
+    maxit: int = 100
+    rtol: float = 1e-8
+    omega: float = 1.0
+
+
+class Solver3:
+    """An ibmg3 handle plus its torch-owned workspace on `device`."""
+
+    def __init__(self, cfg: Config3, fiber_offsets, device="cuda:0", stream=None):
+        L = lib()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        offs = [int(x) for x in (fiber_offsets if fiber_offsets is not None else [0])]
+        self.M = offs[-1] if len(offs) > 1 else 0
+        self._offs = (C.c_int32 * len(offs))(*offs)
+        prob = ibmg3_problem(cfg.N, cfg.rho, cfg.mu, self.M, max(0, len(offs) - 1),
+                             C.cast(self._offs, C.POINTER(C.c_int32)), cfg.K, cfg.delta)
+        opts = ibmg3_opts(cfg.levels, cfg.box, cfg.nu1, cfg.nu2, cfg.maxit, cfg.rtol, cfg.omega)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.ibmg3_create(C.byref(h), C.byref(prob), C.byref(opts), C.c_void_p(self.stream.cuda_stream)),
+               "ibmg3_create")
+        self.h = h
+        nbytes = C.c_size_t()
+        _check(L.ibmg3_workspace_bytes(h, C.byref(nbytes)), "ibmg3_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        _check(L.ibmg3_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value),
+               "ibmg3_bind_workspace")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ibmg3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def n(self, level=0):
+        Nl = self.cfg.N >> level
+        return 4 * Nl ** 3
+
+    def setup(self, dt, X):
+        return _check(lib().ibmg3_setup(self.h, float(dt), _ptr(X)), "ibmg3_setup")
+
+    def apply(self, level, x):
+        y = torch.empty(self.n(level), dtype=torch.float64, device=self.device)
+        _check(lib().ibmg3_apply(self.h, level, _ptr(x), _ptr(y)), "ibmg3_apply")
+        return y
+
+    def restrict(self, level, rf):
+        rc = torch.empty(self.n(level + 1), dtype=torch.float64, device=self.device)
+        _check(lib().ibmg3_restrict(self.h, level, _ptr(rf), _ptr(rc)), "ibmg3_restrict")
+        return rc
+
+    def prolong_add(self, level, ec, wf):
+        _check(lib().ibmg3_prolong_add(self.h, level, _ptr(ec), _ptr(wf)), "ibmg3_prolong_add")
+        return wf
+
+    def box_matrix(self, level, bx, by, bz):
+        n = self.cfg.box
+        nd = 3 * (n + 1) * n * n + n ** 3
+        out = torch.empty(nd, nd, dtype=torch.float64, device=self.device)
+        _check(lib().ibmg3_box_matrix(self.h, level, bx, by, bz, _ptr(out)), "ibmg3_box_matrix")
+        return out
+
+    def smooth(self, level, b, w, sweeps=1):
+        _check(lib().ibmg3_smooth(self.h, level, _ptr(b), _ptr(w), sweeps), "ibmg3_smooth")
+        return w
+
+    def vcycle(self, r):
+        z = torch.empty_like(r)
+        _check(lib().ibmg3_vcycle(self.h, _ptr(r), _ptr(z)), "ibmg3_vcycle")
+        return z
+
+    def rhs(self, uvw, X=None):
+        b = torch.empty(self.n(0), dtype=torch.float64, device=self.device)
+        _check(lib().ibmg3_rhs(self.h, _ptr(uvw), _ptr(X), _ptr(b)), "ibmg3_rhs")
+        return b
+
+    def solve(self, b, x):
+        st = ibmg_stats()
+        code = _check(lib().ibmg3_solve(self.h, _ptr(b), _ptr(x), C.byref(st)), "ibmg3_solve")
+        d = st.as_dict()
+        d["status"] = code
+        return d
+
+    def step(self, dt, uvw, p, X):
+        st = ibmg_stats()
+        code = _check(lib().ibmg3_step(self.h, float(dt), _ptr(uvw), _ptr(p), _ptr(X), C.byref(st)), "ibmg3_step")
+        d = st.as_dict()
+        d["status"] = code
+        return d
+
+    def box_counts(self, level):
+        own, total = C.c_int32(), C.c_int32()
+        _check(lib().ibmg3_box_counts(self.h, level, C.byref(own), C.byref(total)), "ibmg3_box_counts")
+        return own.value, total.value

@@ -195,3 +195,84 @@ def test_cnn_create_validates_without_gpu():
     assert L.ibmg_cnn_create(C.byref(h), 48, 4, None) == -2
     assert L.ibmg_cnn_create(C.byref(h), 8, 4, None) == -2
     assert L.ibmg_cnn_create(C.byref(h), 64, 0, None) == -1
+
+
+HEADER3 = os.path.join(ROOT, "include", "ibmg3.h")
+
+
+def test_three_dimensional_abi_exports_and_layout():
+    """include/ibmg3.h: every declared symbol is exported and bound, and the
+    ctypes structs match the C layout."""
+    ibmg, L = _lib()
+    syms = sorted(set(re.findall(r"^int\s+(ibmg3_\w+)\s*\(", open(HEADER3).read(), re.M)))
+    assert syms == sorted(ibmg.EXPORTS3)
+    out = subprocess.run(["nm", "-D", "--defined-only", ibmg.LIB_PATH], capture_output=True, text=True).stdout
+    for s in syms:
+        assert hasattr(L, s) and re.search(rf"\bT {s}$", out, re.M), s
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "ibmg3.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibmg3_problem), sizeof(ibmg3_opts),
+         offsetof(ibmg3_problem, fiber_offsets), offsetof(ibmg3_problem, K), offsetof(ibmg3_problem, delta),
+         offsetof(ibmg3_opts, rtol), offsetof(ibmg3_opts, omega));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        got = list(map(int, subprocess.run([exe], capture_output=True, text=True).stdout.split()))
+    P, O = ibmg.ibmg3_problem, ibmg.ibmg3_opts
+    assert got == [C.sizeof(P), C.sizeof(O), P.fiber_offsets.offset, P.K.offset, P.delta.offset, O.rtol.offset,
+                   O.omega.offset]
+
+
+def _create3(N=32, levels=4, box=4, offs=(0, 40, 80), **kw):
+    ibmg, L = _lib()
+    o = (C.c_int32 * len(offs))(*offs)
+    prob = ibmg.ibmg3_problem(N, kw.get("rho", 1.0), kw.get("mu", 1.0), offs[-1], len(offs) - 1,
+                              C.cast(o, C.POINTER(C.c_int32)), kw.get("K", 1e3), kw.get("delta", 0))
+    opts = ibmg.ibmg3_opts(levels, box, kw.get("nu1", 1), kw.get("nu2", 1), kw.get("maxit", 100),
+                           kw.get("rtol", 1e-8), kw.get("omega", 1.0))
+    h = C.c_void_p()
+    rc = L.ibmg3_create(C.byref(h), C.byref(prob), C.byref(opts), None)
+    return rc, h, L
+
+
+def test_three_dimensional_create_validation_and_workspace():
+    """Shapes the 3-D handle accepts and rejects (no device work): N a power
+    of two in 8..128, box 2 or 4 with an even number of boxes per side on
+    every smoothed level, a coarsest grid of 2 to 8 cells, fibres of at least
+    3 points; the workspace grows with the grid and holds one 304 x 304
+    inverse per box of the smoothed levels with structure."""
+    rc, h, L = _create3()
+    assert rc == 0
+    nb = C.c_size_t()
+    assert L.ibmg3_workspace_bytes(h, C.byref(nb)) == 0
+    boxes = 8 ** 3 + 4 ** 3 + 2 ** 3      # the three smoothed levels of 32^3 with 4^3 boxes
+    assert nb.value > boxes * 304 * 304 * 8
+    L.ibmg3_destroy(h)
+    rc, h, L = _create3(K=0.0)
+    nb0 = C.c_size_t()
+    L.ibmg3_workspace_bytes(h, C.byref(nb0))
+    assert nb0.value < nb.value
+    L.ibmg3_destroy(h)
+    invalid = (dict(N=24), dict(N=4, levels=2), dict(box=3),
+               dict(levels=2), dict(levels=3),      # coarsest 16 and 8 cells (at most 4)
+               dict(levels=5),                      # level 4 smoothed with one box per side
+               dict(levels=6), dict(offs=(0, 2)), dict(offs=(0, 40, 30)), dict(rho=0.0), dict(omega=1.5),
+               dict(maxit=0), dict(nu1=0, nu2=0), dict(delta=3))
+    for kw in invalid:
+        rc, h, L = _create3(**kw)
+        assert rc == -1, kw
+    valid = (dict(levels=4), dict(N=64, levels=5), dict(N=16, levels=3), dict(N=8, levels=2),
+             dict(N=16, levels=3, box=2), dict(N=8, levels=2, box=2), dict(N=8, levels=2, box=4),
+             dict(N=16, levels=4, box=2))
+    for kw in valid:
+        rc, h, L = _create3(**kw)
+        assert rc == 0, kw
+        L.ibmg3_destroy(h)

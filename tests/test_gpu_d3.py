@@ -1,0 +1,196 @@
+"""GPU parity of the three-dimensional form (include/ibmg3.h) against the
+oracle (oracle/d3.py), element by element on the same seeded inputs: the
+level operators with their Galerkin elasticity blocks on every level, the
+face and pressure transfers, the box blocks (boxes that meet the structure
+and plain ones, 44 and 304 unknowns), checkerboard sweeps, V-cycles, the
+FGMRES solve and one implicit step.  Cases: 16^3 with 2^3 and 4^3 boxes,
+the structure in the middle and wrapped across the periodic corner, no
+structure, and 32^3 with 4^3 boxes (the size the benchmark's 3-D line
+uses).  Tolerances: 1e-12 relative for operator applications and
+transfers, 1e-10 for sweeps and V-cycles (dense box inverses formed by
+Gauss-Jordan on the GPU against LU solves in the oracle), iteration counts
+within one and the solution at rtol in the oracle's operator."""
+import numpy as np
+import pytest
+import torch
+
+import ibgen
+from gpu_common import DEV, rel, tdev, tnp
+
+pytestmark = pytest.mark.gpu
+
+from oracle import d3, krylov  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_5614_amd import ibmg  # noqa: F401  (raises if the library is missing)
+
+
+_CACHE = {}
+
+
+def case(N=16, box=2, K=1e3, dt=0.01, centre=(0.5, 0.5, 0.5), levels=3):
+    """GPU solver (set up) and oracle hierarchy + V-cycle of one problem."""
+    key = (N, box, K, dt, centre, levels)
+    if key in _CACHE:
+        return _CACHE[key]
+    from paper_1311_5614_amd import ibmg
+    X, offs = ibgen.sphere_rings(N, centre=centre)
+    cfg = ibmg.Config3(N=N, levels=levels, K=K, box=box, nu1=1, nu2=1, maxit=100, rtol=1e-10)
+    s = ibmg.Solver3(cfg, offs if K else None, DEV)
+    s.setup(dt, tdev(X) if K else None)
+    lv = d3.hierarchy(N, levels, 1.0, 1.0, dt, X if K else None, offs, K)
+    V = d3.VCycle(lv, box, 1, 1)
+    _CACHE[key] = (s, lv, V, X, offs)
+    return _CACHE[key]
+
+
+CASES = [dict(N=16, box=2), dict(N=16, box=4), dict(N=16, box=2, centre=(0.05, 0.95, 0.02)),
+         dict(N=16, box=4, K=0.0)]
+
+
+def _zero_mean_p(x, N):
+    x = np.array(x, float)
+    x[3 * N ** 3:] -= x[3 * N ** 3:].mean()
+    return x
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_d3_operator_every_level(kw):
+    s, lv, V, X, offs = case(**kw)
+    rng = np.random.default_rng(11)
+    for l, L in enumerate(lv):
+        x = rng.standard_normal(L.A.shape[0])
+        y = tnp(s.apply(l, tdev(x)))
+        print(f"level {l} N {L.N}: rel {rel(y, L.A @ x):.2e}")
+        assert rel(y, L.A @ x) < 1e-12, l
+
+
+@pytest.mark.parametrize("kw", CASES[:1])
+def test_d3_transfers(kw):
+    s, lv, V, X, offs = case(**kw)
+    rng = np.random.default_rng(12)
+    for l in range(len(lv) - 1):
+        f = rng.standard_normal(lv[l].A.shape[0])
+        assert rel(tnp(s.restrict(l, tdev(f))), lv[l].R @ f) < 1e-13
+        c = rng.standard_normal(lv[l + 1].A.shape[0])
+        w = rng.standard_normal(lv[l].A.shape[0])
+        assert rel(tnp(s.prolong_add(l, tdev(c), tdev(w))), w + lv[l].P @ c) < 1e-13
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_d3_box_matrices(kw):
+    """Every box of every smoothed level against the oracle's extracted block
+    (own boxes include the elastic entries; the plain ones share one)."""
+    s, lv, V, X, offs = case(**kw)
+    for l, sm in enumerate(V.smoothers):
+        own, total = s.box_counts(l)
+        assert total == sm.nb ** 3
+        worst = 0.0
+        for q, b in enumerate(sm.boxes):
+            if q % 3 and kw.get("K", 1e3) == 0.0:
+                continue
+            Ag = tnp(s.box_matrix(l, *b))
+            Ao = sm.box_matrix(b)
+            worst = max(worst, np.max(np.abs(Ag - Ao)) / np.max(np.abs(Ao)))
+        print(f"level {l}: {own} own of {total} boxes, worst rel {worst:.2e}")
+        assert worst < 1e-12
+        if kw.get("K", 1e3) != 0.0:
+            assert 0 < own <= total and (l > 0 or own < total)
+        else:
+            assert own == 0
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_d3_smooth_and_vcycle(kw):
+    s, lv, V, X, offs = case(**kw)
+    N = kw["N"]
+    rng = np.random.default_rng(13)
+    for l, sm in enumerate(V.smoothers):
+        b = rng.standard_normal(lv[l].A.shape[0])
+        w = rng.standard_normal(lv[l].A.shape[0])
+        wg = tnp(s.smooth(l, tdev(b), tdev(w), 2))
+        wo = sm.sweep(sm.sweep(w, b), b)
+        print(f"sweeps level {l}: rel {rel(wg, wo):.2e}")
+        assert rel(wg, wo) < 1e-10, l
+    r = _zero_mean_p(rng.standard_normal(lv[0].A.shape[0]), N)
+    zg = tnp(s.vcycle(tdev(r)))
+    zo = V(r)
+    print(f"V-cycle: rel {rel(zg, zo):.2e}")
+    assert rel(zg, zo) < 1e-10
+
+
+@pytest.mark.parametrize("kw", CASES[:3])
+def test_d3_fgmres_matches_oracle(kw):
+    s, lv, V, X, offs = case(**kw)
+    N = kw["N"]
+    rng = np.random.default_rng(14)
+    b = _zero_mean_p(rng.standard_normal(lv[0].A.shape[0]), N)
+    x = torch.zeros(4 * N ** 3, dtype=torch.float64, device=DEV)
+    st = s.solve(tdev(b), x)
+    res = krylov.fgmres(lv[0].A, b, V, rtol=1e-10, maxit=100)
+    xg = tnp(x)
+    print(f"FGMRES: gpu {st['iters']} oracle {res.iters}")
+    assert st["converged"] == 1 and res.converged and abs(st["iters"] - res.iters) <= 1
+    assert np.linalg.norm(b - lv[0].A @ xg) <= 1e-10 * np.linalg.norm(b)
+    if st["iters"] == res.iters:
+        assert np.linalg.norm(_zero_mean_p(xg, N) - _zero_mean_p(res.x, N)) < 1e-8 * np.linalg.norm(res.x)
+
+
+def test_d3_step_matches_oracle():
+    """Two implicit steps from rest (the structure's force drives the flow):
+    velocity, pressure (zero mean) and the moved points against the oracle's
+    steps."""
+    from paper_1311_5614_amd import ibmg
+    N, levels, dt, K = 16, 3, 0.01, 1e3
+    X, offs = ibgen.sphere_rings(N)
+    cfg = ibmg.Config3(N=N, levels=levels, K=K, box=2, nu1=1, nu2=1, maxit=100, rtol=1e-11)
+    s = ibmg.Solver3(cfg, offs, DEV)
+    n3 = N ** 3
+    uvw = torch.zeros(3 * n3, dtype=torch.float64, device=DEV)
+    p = torch.zeros(n3, dtype=torch.float64, device=DEV)
+    Xg = tdev(X)
+    uo = [np.zeros(n3)] * 3
+    Xo = X.copy()
+    for _ in range(2):
+        st = s.step(dt, uvw, p, Xg)
+        uo, po, Xo, res = d3.step(uo, Xo, offs, N, levels, 1.0, 1.0, dt, K, n=2, rtol=1e-11)
+        assert st["converged"] == 1 and res.converged
+        assert rel(tnp(uvw), np.concatenate(uo)) < 1e-8
+        pg = tnp(p)
+        assert rel(pg - pg.mean(), po - po.mean()) < 1e-8
+        assert rel(tnp(Xg) - X, Xo - X) < 1e-8
+    assert float(np.abs(Xo - X).max()) > 1e-6      # the structure moved
+    s.close()
+
+
+def test_d3_rhs_matches_oracle():
+    from paper_1311_5614_amd import ibmg
+    s, lv, V, X, offs = case(N=16, box=2)
+    N = 16
+    rng = np.random.default_rng(15)
+    u = rng.standard_normal(3 * N ** 3)
+    b = tnp(s.rhs(tdev(u), tdev(X)))
+    bo = d3.rhs(N, 1.0 / 0.01, [u[:N ** 3], u[N ** 3:2 * N ** 3], u[2 * N ** 3:]], X, offs, 1e3)
+    assert rel(b, bo) < 1e-13
+    with pytest.raises(ibmg.IBMGError):
+        s.rhs(tdev(u), None)
+
+
+def test_d3_32_cubed_vcycle_and_operator():
+    """32^3 with 4^3 boxes (304 unknowns each), four levels: the level-0
+    operator, one V-cycle and the box counts against the oracle."""
+    s, lv, V, X, offs = case(N=32, box=4, K=1e3, dt=0.01, levels=4)
+    rng = np.random.default_rng(16)
+    x = rng.standard_normal(lv[0].A.shape[0])
+    assert rel(tnp(s.apply(0, tdev(x))), lv[0].A @ x) < 1e-12
+    r = _zero_mean_p(rng.standard_normal(lv[0].A.shape[0]), 32)
+    zg = tnp(s.vcycle(tdev(r)))
+    assert rel(zg, V(r)) < 1e-10
+    for l, sm in enumerate(V.smoothers):
+        own, total = s.box_counts(l)
+        print(f"32^3 level {l}: {own} of {total} boxes own")
+        assert total == sm.nb ** 3
