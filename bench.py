@@ -22,7 +22,9 @@ the same workload, and (unless --no-extras) the 256x256 stiffness sweep and
 the 64-problem batch as extra keys.
 
 Other workloads: --workload c2 (256x256 sweep, forms concurrent / plain /
-fp32 / tuned), c4 (64-problem batch), c5 (512x512 learned warm start), c1.
+fp32 / tuned), c4 (64-problem batch), c5 (512x512 learned warm start), c1,
+cavity (the walled test problem), mgsolver, efficiency, d3 (the
+three-dimensional form).
 
 python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload c3|c2|c4|c5|c1]
 """
@@ -1079,6 +1081,64 @@ def cavity_efficiency(dev, alpha_exp, N=32, dt=1.0 / 40, steps=40, probe=200):
             "rows": rows, "explicit_stability_probe": stab}
 
 
+def run_d3(args, dev, steps=5, only=None):
+    """The three-dimensional form (include/ibmg3.h) on the periodic unit
+    cube: closed latitude rings on a stretched sphere (ibgen.sphere_rings,
+    about 0.6 k points at 32^3, 2.5 k at 64^3), rho = mu = 1, dt = 0.01,
+    dt K = 10 and 100, MG-FGMRES V(1,1) with checkerboard boxes of 2^3 cells
+    (44 unknowns) and 4^3 cells (304 unknowns, the paper's 750 KB block),
+    rtol 1e-8, implicit steps from rest.  Per row: ms per step (setup with
+    the box inverses, right-hand side, solve, point update), the setup alone,
+    FGMRES iterations per step and the boxes with own inverses on level 0."""
+    import numpy as np
+    import torch
+    from paper_1311_5614_amd import ibmg
+    import ibgen
+    rows = []
+    for N in (32, 64):
+        X, offs = ibgen.sphere_rings(N)
+        for box in (2, 4):
+            levels = int(np.log2(N // (2 if box == 2 else 4))) + 1
+            for alpha in (10.0, 100.0):
+                if only is not None and (N, box, alpha) != only:
+                    continue
+                dt = 0.01
+                cfg = ibmg.Config3(N=N, levels=levels, K=alpha / dt, box=box, nu1=1, nu2=1, maxit=200, rtol=1e-8)
+                s = ibmg.Solver3(cfg, offs, dev)
+                n3 = N ** 3
+                uvw = torch.zeros(3 * n3, dtype=torch.float64, device=dev)
+                p = torch.zeros(n3, dtype=torch.float64, device=dev)
+                Xg = torch.as_tensor(X, dtype=torch.float64, device=dev).contiguous()
+                s.step(dt, uvw, p, Xg)
+                torch.cuda.synchronize()
+                its, conv, ms = [], 0, []
+                for _ in range(steps):
+                    t0 = time.perf_counter()
+                    st = s.step(dt, uvw, p, Xg)
+                    torch.cuda.synchronize()
+                    ms.append(1e3 * (time.perf_counter() - t0))
+                    its.append(st["iters"])
+                    conv += int(st["converged"])
+                t0 = time.perf_counter()
+                s.setup(dt, Xg)
+                torch.cuda.synchronize()
+                setup_ms = 1e3 * (time.perf_counter() - t0)
+                own, total = s.box_counts(0)
+                row = {"N": N, "box": box, "unknowns_per_box": 3 * (box + 1) * box * box + box ** 3,
+                       "levels": levels, "dt_K": alpha, "points": int(offs[-1]), "ms_per_step": float(np.median(ms)),
+                       "setup_ms": setup_ms, "iters_mean": sum(its) / steps, "converged": f"{conv}/{steps}",
+                       "own_boxes_level0": own, "boxes_level0": total}
+                rows.append(row)
+                print(f"[bench] 3-D {N}^3 box {box} dtK {alpha:g}: {row['ms_per_step']:.1f} ms/step "
+                      f"(setup {setup_ms:.1f} ms), {row['iters_mean']:.1f} its, {conv}/{steps} converged, "
+                      f"{own}/{total} own boxes", file=sys.stderr, flush=True)
+                s.close()
+                del s
+                torch.cuda.empty_cache()
+    return {"workload": "sphere rings in the periodic unit cube, implicit steps from rest, MG-FGMRES V(1,1), "
+                        "checkerboard boxes, rtol 1e-8", "rows": rows}
+
+
 PROBE_N = 4096   # bandwidth probe: plain V(2,2) with no structure on this grid
 
 
@@ -1287,6 +1347,7 @@ def main():
     ap.add_argument("--probe-n", type=int, default=PROBE_N, help="grid of the bandwidth probe")
     ap.add_argument("--roofline-nvec", type=int, default=0,
                     help="basis size of the Gram-Schmidt roofline launches (default: from the timed solves)")
+    ap.add_argument("--d3-case", default="", help="d3: one row only, N,box,dtK (e.g. 64,4,100)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy a device buffer of this many MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -1323,6 +1384,13 @@ def main():
         return
     if args.workload == "cavity":
         print(json.dumps({"cavity": run_cavity(args, dev)}))
+        return
+    if args.workload == "d3":
+        only = None
+        if args.d3_case:
+            a, b, c = args.d3_case.split(",")
+            only = (int(a), int(b), float(c))
+        print(json.dumps({"d3": run_d3(args, dev, steps=args.steps or 5, only=only)}))
         return
     args.steps = args.steps or 20
     if args.workload == "c3":

@@ -41,7 +41,6 @@ constexpr int kW = 5;                 // window entries per axis on every level
 constexpr int kBoxThreads = 256;      // box products
 constexpr int kGjThreads = 1024;      // box inverses
 constexpr int kMaxNd = 3 * 5 * 16 + 64;   // 304: unknowns of an n = 4 box
-constexpr int kListCap = 2048;        // points staged per pass of a box assembly
 
 struct Win {
   int base[3];
@@ -62,6 +61,10 @@ struct Lv3 {
   const int* bin_pts;      // [3 M]
   const int* act;          // [3 N^3] active faces (component * N^3 + face), ascending
   const int* nact;         // [1]
+  const int* act_index;    // [3 N^3] index of a face in act, or -1
+  const int* coff;         // [3 N^3 + 1] CSR of S_l by active face: offsets
+  const int* cpt;          // point of each entry (ascending within a face)
+  const double* cw;        // weight S_l(face, point) of each entry
   double* y;               // [3 N^3] elastic rows, zero off the active faces
 };
 
@@ -211,28 +214,18 @@ __global__ void __launch_bounds__(256) k3_bin_count(int M, int N, const Win* __r
   atomicAdd(&cnt[k], 1);
 }
 
+// Stable placement: a (point, component) goes to its bin at the rank it has
+// among the entries of the same key with a smaller index (so each bin lists
+// its points in ascending order, independent of scheduling).
 __global__ void __launch_bounds__(256) k3_bin_fill(int M, const int* __restrict__ key, const int* __restrict__ start,
-                                                   int* __restrict__ cursor, int* __restrict__ pts) {
+                                                   int* __restrict__ pts) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * M) return;
-  const int k = key[t];
-  pts[start[k] + atomicAdd(&cursor[k], 1)] = t / 3;
-}
-
-// Points of one bin in ascending order (the fill order depends on atomics).
-__global__ void __launch_bounds__(256) k3_bin_sort(int nbins, const int* __restrict__ start, int* __restrict__ pts) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
-  const int s = start[b], e = start[b + 1];
-  for (int i = s + 1; i < e; ++i) {
-    const int v = pts[i];
-    int j = i - 1;
-    while (j >= s && pts[j] > v) {
-      pts[j + 1] = pts[j];
-      --j;
-    }
-    pts[j + 1] = v;
-  }
+  const int m3 = 3 * M;
+  const int k = t < m3 ? key[t] : -1;
+  int rank = 0;
+  const int lim = min(m3, (blockIdx.x + 1) * blockDim.x);
+  for (int u = 0; u < lim; ++u) rank += (u < t && key[u] == k) ? 1 : 0;
+  if (t < m3) pts[start[k] + rank] = t / 3;
 }
 
 // Faces any S window reaches (per component): flag = 1.
@@ -293,9 +286,60 @@ __global__ void __launch_bounds__(1024) k3_scan_add(int* __restrict__ out, int n
 }
 
 __global__ void __launch_bounds__(256) k3_compact(const int* __restrict__ flag, const int* __restrict__ pos, int n,
-                                                  int* __restrict__ list) {
+                                                  int* __restrict__ list, int* __restrict__ index) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && flag[i]) list[pos[i]] = i;
+  if (i >= n) return;
+  if (flag[i]) list[pos[i]] = i;
+  index[i] = flag[i] ? pos[i] : -1;
+}
+
+__device__ inline int wave_incl_scan(int v, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(v, off);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// CSR of S_l by active face, built once per setup from the bins, one wave
+// per face: lane l takes the window offsets l and l + 64 (of 125), pass 0
+// counts the entries of each face, pass 1 writes them at the lane's prefix
+// (so the order is fixed: by lane, offset, then ascending point in a bin).
+template <int kPass>
+__global__ void __launch_bounds__(256) k3_csr(Lv3 L, int* __restrict__ count, const int* __restrict__ off,
+                                              int* __restrict__ cpt, double* __restrict__ cw) {
+  const int lane = threadIdx.x & 63;
+  const int q = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (q >= *L.nact) return;   // uniform per wave
+  const int N = L.N, N3 = N * N * N;
+  const int x = L.act[q], c = x / N3, g = x - c * N3;
+  const int i = g % N, j = (g / N) % N, k = g / (N * N);
+  int n = 0;
+  for (int pass = 0; pass < (kPass ? 2 : 1); ++pass) {
+    int w0 = 0;
+    if (pass == 1) w0 = off[q] + wave_incl_scan(n, lane) - n;
+    int m = 0;
+    for (int o = lane; o < kW * kW * kW; o += 64) {
+      const int ox = o % kW, oy = (o / kW) % kW, oz = o / (kW * kW);
+      const int b = c * N3 + (pmod(k - oz, N) * N + pmod(j - oy, N)) * N + pmod(i - ox, N);
+      for (int u = L.bin_start[b]; u < L.bin_start[b + 1]; ++u) {
+        const int p = L.bin_pts[u];
+        const Win& w = L.S[3 * p + c];
+        const double v = w.w[0][ox] * w.w[1][oy] * w.w[2][oz];
+        if (v == 0.0) continue;
+        if (pass == 1) {
+          cpt[w0 + m] = p;
+          cw[w0 + m] = v;
+        }
+        ++m;
+      }
+    }
+    n = m;
+  }
+  if (!kPass) {
+    const int tot = wave_incl_scan(n, lane);
+    if (lane == 63) count[q] = tot;
+  }
 }
 
 // ---------------------------------------------------------------- elastic rows
@@ -332,25 +376,19 @@ __global__ void __launch_bounds__(256) k3_force(Lv3 L, double coef, const double
   L.F[t] = coef * (U[3 * L.prev[p] + c] - 2.0 * U[t] + U[3 * L.next[p] + c]);
 }
 
-// y[c][face] = sum over points of S_l(face, p) F[p, c], active faces only.
+// y[c][face] = sum over points of S_l(face, p) F[p, c], active faces only;
+// one wave per face, lanes strided over its CSR entries, a fixed reduction
+// tree across lanes.
 __global__ void __launch_bounds__(256) k3_spread(Lv3 L, double* __restrict__ y) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= *L.nact) return;
-  const int N = L.N, N3 = N * N * N;
-  const int x = L.act[q], c = x / N3, g = x - c * N3;
-  const int i = g % N, j = (g / N) % N, k = g / (N * N);
+  const int lane = threadIdx.x & 63;
+  const int q = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (q >= *L.nact) return;   // uniform per wave
+  const int N3 = L.N * L.N * L.N;
+  const int x = L.act[q], c = x / N3;
   double s = 0.0;
-  for (int oz = 0; oz < kW; ++oz)
-    for (int oy = 0; oy < kW; ++oy)
-      for (int ox = 0; ox < kW; ++ox) {
-        const int b = c * N3 + (pmod(k - oz, N) * N + pmod(j - oy, N)) * N + pmod(i - ox, N);
-        for (int u = L.bin_start[b]; u < L.bin_start[b + 1]; ++u) {
-          const int p = L.bin_pts[u];
-          const Win& w = L.S[3 * p + c];
-          s += w.w[0][ox] * w.w[1][oy] * w.w[2][oz] * L.F[3 * p + c];
-        }
-      }
-  y[x] = s;
+  for (int u = L.coff[q] + lane; u < L.coff[q + 1]; u += 64) s += L.cw[u] * L.F[3 * L.cpt[u] + c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) y[x] = s;
 }
 
 // r = b - A x (b != null) or r = A x, every unknown of the level; the elastic
@@ -449,15 +487,28 @@ __global__ void __launch_bounds__(256) k3_prolong_add(int Nf, const double* __re
 
 // ---------------------------------------------------------------- box blocks
 
+// sum over the CSR entries (p, S_l(a, p)) of active face a (index ia) of
+// S_l(a, p) (J_prev(b) - 2 J_p(b) + J_next(b)): the elastic entry (a, b) of
+// component c without the factor -dt K.
+__device__ double elastic_entry(const Lv3& L, int c, int ia, int gb) {
+  const int N = L.N;
+  const int bi = gb % N, bj = (gb / N) % N, bk = gb / (N * N);
+  double s = 0.0;
+  for (int u = L.coff[ia]; u < L.coff[ia + 1]; ++u) {
+    const int p = L.cpt[u];
+    const double jb = wval(L.J[3 * L.prev[p] + c], bi, bj, bk, N) - 2.0 * wval(L.J[3 * p + c], bi, bj, bk, N) +
+                      wval(L.J[3 * L.next[p] + c], bi, bj, bk, N);
+    s += L.cw[u] * jb;
+  }
+  return s;
+}
+
 // Block of box `boxes[blockIdx.x]` (with the elastic part when with_ib),
 // written transposed: out[col][row] = A[row][col].  The elastic entries of a
 // velocity row a and column b of component c are coef sum_p S_p(a)
-// (J_prev(b) - 2 J_p(b) + J_next(b)), over the points whose S window meets
-// the box, in ascending point order.
+// (J_prev(b) - 2 J_p(b) + J_next(b)) over the CSR entries of row a.
 __global__ void __launch_bounds__(kGjThreads) k3_box_assemble(Lv3 L, const int* __restrict__ boxes, int with_ib,
                                                               double* __restrict__ out, size_t stride) {
-  __shared__ int list[kListCap];
-  __shared__ int scan[kGjThreads];
   const int nd = L.nd, n = L.n, N = L.N, nb = L.nb;
   const int box = boxes ? boxes[blockIdx.x] : 0;
   const int bx = box % nb, by = (box / nb) % nb, bz = box / (nb * nb);
@@ -467,81 +518,90 @@ __global__ void __launch_bounds__(kGjThreads) k3_box_assemble(Lv3 L, const int* 
     B[t] = stokes_entry(L, box_dof(row, bx, by, bz, n, N), box_dof(col, bx, by, bz, n, N));
   }
   if (!with_ib || L.coef == 0.0 || L.M == 0) return;
-  __syncthreads();
-  const int nf = (n + 1) * n * n;
-  const int lo[3] = {bx * n, by * n, bz * n};
-  for (int base = 0; base < L.M; base += kListCap) {
-    // stage the points of this chunk whose S window (any component) meets the box, ascending
-    int cnt = 0;
-    for (int sub = 0; sub < kListCap && base + sub < L.M; sub += kGjThreads) {
-      const int p = base + sub + threadIdx.x;
-      int hit = 0;
-      if (sub + threadIdx.x < kListCap && p < L.M) {
-        for (int c = 0; c < 3 && !hit; ++c) {
-          const Win& w = L.S[3 * p + c];
-          bool in = true;
-          for (int d = 0; d < 3 && in; ++d) {
-            const int ext = d == c ? n + 1 : n;
-            // window covers [base, base + kW) mod N; box covers [lo, lo + ext) mod N
-            const int o = pmod(lo[d] - w.base[d], N);
-            in = o < kW || o + ext > N;   // overlap on the circle
-          }
-          hit = in;
-        }
-      }
-      scan[threadIdx.x] = hit;
-      __syncthreads();
-      for (int off = 1; off < kGjThreads; off <<= 1) {
-        const int a = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-        __syncthreads();
-        scan[threadIdx.x] += a;
-        __syncthreads();
-      }
-      if (hit) list[cnt + scan[threadIdx.x] - 1] = p;
-      cnt += scan[kGjThreads - 1];
-      __syncthreads();
-    }
-    for (int t = threadIdx.x; t < 3 * nf * nf; t += blockDim.x) {
-      const int c = t / (nf * nf), rem = t - c * nf * nf;
-      const int ra = rem / nf, cb = rem - ra * nf;
-      const int ga = box_dof(c * nf + ra, bx, by, bz, n, N) - c * N * N * N;
-      const int gb = box_dof(c * nf + cb, bx, by, bz, n, N) - c * N * N * N;
-      const int ai = ga % N, aj = (ga / N) % N, ak = ga / (N * N);
-      const int bi = gb % N, bj = (gb / N) % N, bk = gb / (N * N);
-      double s = 0.0;
-      for (int u = 0; u < cnt; ++u) {
-        const int p = list[u];
-        const double sa = wval(L.S[3 * p + c], ai, aj, ak, N);
-        if (sa == 0.0) continue;
-        const double jb = wval(L.J[3 * L.prev[p] + c], bi, bj, bk, N) - 2.0 * wval(L.J[3 * p + c], bi, bj, bk, N) +
-                          wval(L.J[3 * L.next[p] + c], bi, bj, bk, N);
-        s += sa * jb;
-      }
-      B[(size_t)(c * nf + cb) * nd + c * nf + ra] += L.coef * s;
-    }
-    __syncthreads();
+  __syncthreads();   // the Stokes pass above owns the entries in another order
+  const int nf = (n + 1) * n * n, N3 = N * N * N;
+  for (int t = threadIdx.x; t < 3 * nf * nf; t += blockDim.x) {
+    const int c = t / (nf * nf), rem = t - c * nf * nf;
+    const int ra = rem / nf, cb = rem - ra * nf;
+    const int ga = box_dof(c * nf + ra, bx, by, bz, n, N) - c * N3;
+    const int ia = L.act_index[c * N3 + ga];
+    if (ia < 0) continue;
+    const int gb = box_dof(c * nf + cb, bx, by, bz, n, N) - c * N3;
+    B[(size_t)(c * nf + cb) * nd + c * nf + ra] += L.coef * elastic_entry(L, c, ia, gb);
   }
 }
 
-// In-place Gauss-Jordan inverse of each nd x nd matrix (no pivoting: the
-// velocity block comes first and has a dominant positive diagonal, the
-// pressure pivots are then those of the box's Schur complement).
+// In-place Gauss-Jordan inverse of each nd x nd matrix, blocked by panels
+// of kPanel pivots (no pivoting: the velocity block comes first and has a
+// dominant positive diagonal, the pressure pivots are then those of the
+// box's Schur complement).  For the pivot block K and the rest R:
+//   D = A_KK^{-1};  A_KR <- D A_KR;  A_RR <- A_RR - A_RK A_KR;
+//   A_RK <- -A_RK D;  A_KK <- D,
+// so the matrix is read and written once per panel instead of once per pivot.
+constexpr int kPanel = 8;
+
 __global__ void __launch_bounds__(kGjThreads) k3_gj(double* __restrict__ mats, int nd, size_t stride) {
-  __shared__ double colk[kMaxNd], rowk[kMaxNd];
+  __shared__ double rowp[kPanel][kMaxNd];   // rows of K (then D A_KR)
+  __shared__ double colp[kMaxNd][kPanel];   // columns of K (A_RK, old)
+  __shared__ double dinv[kPanel][kPanel];
   double* A = mats + stride * blockIdx.x;
-  for (int k = 0; k < nd; ++k) {
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-      colk[i] = A[(size_t)i * nd + k];
-      rowk[i] = A[(size_t)k * nd + i];
+  const int tid = threadIdx.x;
+  for (int k0 = 0; k0 < nd; k0 += kPanel) {
+    const int pw = min(kPanel, nd - k0);
+    for (int t = tid; t < pw * nd; t += blockDim.x) {
+      const int s = t / nd, j = t - s * nd;
+      rowp[s][j] = A[(size_t)(k0 + s) * nd + j];
+      colp[j][s] = A[(size_t)j * nd + k0 + s];
     }
     __syncthreads();
-    const double inv = 1.0 / rowk[k];
-    for (int t = threadIdx.x; t < nd * nd; t += blockDim.x) {
+    if (tid == 0) {   // D = A_KK^{-1}, scalar Gauss-Jordan on the small block
+      for (int a = 0; a < pw; ++a)
+        for (int b = 0; b < pw; ++b) dinv[a][b] = rowp[a][k0 + b];
+      for (int k = 0; k < pw; ++k) {
+        const double inv = 1.0 / dinv[k][k];
+        for (int b = 0; b < pw; ++b)
+          if (b != k) dinv[k][b] *= inv;
+        for (int a = 0; a < pw; ++a) {
+          if (a == k) continue;
+          const double f = dinv[a][k];
+          for (int b = 0; b < pw; ++b)
+            if (b != k) dinv[a][b] -= f * dinv[k][b];
+          dinv[a][k] = -f * inv;
+        }
+        dinv[k][k] = inv;
+      }
+    }
+    __syncthreads();
+    // new pivot rows D A_KR (columns outside K), one column per thread
+    for (int j = tid; j < nd; j += blockDim.x) {
+      if (j >= k0 && j < k0 + pw) continue;
+      double v[kPanel];
+      for (int a = 0; a < pw; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < pw; ++b) s += dinv[a][b] * rowp[b][j];
+        v[a] = s;
+      }
+      for (int a = 0; a < pw; ++a) rowp[a][j] = v[a];
+    }
+    __syncthreads();
+    // rank-pw update of A_RR and the new blocks
+    for (int t = tid; t < nd * nd; t += blockDim.x) {
       const int i = t / nd, j = t - i * nd;
+      const bool ik = i >= k0 && i < k0 + pw, jk = j >= k0 && j < k0 + pw;
       double v;
-      if (i == k) v = j == k ? inv : rowk[j] * inv;
-      else if (j == k) v = -colk[i] * inv;
-      else v = A[t] - colk[i] * rowk[j] * inv;
+      if (ik && jk) {
+        v = dinv[i - k0][j - k0];
+      } else if (ik) {
+        v = rowp[i - k0][j];
+      } else if (jk) {
+        double s = 0.0;
+        for (int b = 0; b < pw; ++b) s += colp[i][b] * dinv[b][j - k0];
+        v = -s;
+      } else {
+        double s = A[t];
+        for (int b = 0; b < pw; ++b) s -= colp[i][b] * rowp[b][j];
+        v = s;
+      }
       A[t] = v;
     }
     __syncthreads();
@@ -550,30 +610,55 @@ __global__ void __launch_bounds__(kGjThreads) k3_gj(double* __restrict__ mats, i
 
 // w[box] += omega A_box^{-1} r[box] for the listed boxes: entry q of the
 // list is a box id (plain: shared inverse) or, own, the own index of a box.
+// Grid: (boxes / kB, row slices of 64).  In a workgroup each of the four
+// waves takes a quarter of the columns k for the slice's 64 rows (lane =
+// row), the four partial sums meet in LDS and are added in wave order.
+// Plain boxes go kShare to a workgroup so that each load of the shared
+// inverse (from L2) serves kShare boxes.
+constexpr int kShare = 4;
+
+template <int kB>
 __global__ void __launch_bounds__(kBoxThreads) k3_box_apply(Lv3 L, const double* __restrict__ r, double* __restrict__ w,
                                                             const int* __restrict__ list, int count,
                                                             const int* __restrict__ own_box,
                                                             const double* __restrict__ inv, size_t stride) {
-  __shared__ double rb[kMaxNd];
-  __shared__ int dof[kMaxNd];
-  const int q = blockIdx.x;
-  if (q >= count) return;
+  __shared__ double rb[kB][kMaxNd];
+  __shared__ double part[4][kB][64];
+  const int q0 = blockIdx.x * kB;
   const int nd = L.nd, n = L.n, nb = L.nb;
-  const int id = list[q];
-  const int box = own_box ? own_box[id] : id;
-  const double* Ai = inv + (own_box ? stride * id : 0);
-  const int bx = box % nb, by = (box / nb) % nb, bz = box / (nb * nb);
-  for (int t = threadIdx.x; t < nd; t += blockDim.x) {
-    const int g = box_dof(t, bx, by, bz, n, L.N);
-    dof[t] = g;
-    rb[t] = r[g];
+  const int nbx = min(kB, count - q0);
+  int bxs[kB], bys[kB], bzs[kB];
+  for (int u = 0; u < kB; ++u) {
+    const int id = list[q0 + min(u, nbx - 1)];
+    const int box = own_box ? own_box[id] : id;
+    bxs[u] = box % nb;
+    bys[u] = (box / nb) % nb;
+    bzs[u] = box / (nb * nb);
   }
+  for (int u = 0; u < kB; ++u)
+    for (int t = threadIdx.x; t < nd; t += blockDim.x)
+      rb[u][t] = u < nbx ? r[box_dof(t, bxs[u], bys[u], bzs[u], n, L.N)] : 0.0;
   __syncthreads();
-  for (int row = threadIdx.x; row < nd; row += blockDim.x) {
-    double z = 0.0;
-    for (int k = 0; k < nd; ++k) z += Ai[(size_t)k * nd + row] * rb[k];
-    w[dof[row]] += L.omega * z;
+  const double* Ai = inv + (own_box ? stride * list[q0] : 0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = blockIdx.y * 64 + lane;
+  const int kq = (nd + 3) / 4, k0 = wv * kq, k1 = min(nd, k0 + kq);
+  double z[kB];
+  for (int u = 0; u < kB; ++u) z[u] = 0.0;
+  if (row < nd) {
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
+      const double a = Ai[(size_t)k * nd + row];
+      for (int u = 0; u < kB; ++u) z[u] += a * rb[u][k];
+    }
   }
+  for (int u = 0; u < kB; ++u) part[wv][u][lane] = z[u];
+  __syncthreads();
+  if (wv == 0 && row < nd)
+    for (int u = 0; u < nbx; ++u) {
+      const double v = ((part[0][u][lane] + part[1][u][lane]) + part[2][u][lane]) + part[3][u][lane];
+      w[box_dof(row, bxs[u], bys[u], bzs[u], n, L.N)] += L.omega * v;
+    }
 }
 
 // ---------------------------------------------------------------- coarsest level
@@ -591,19 +676,18 @@ __global__ void __launch_bounds__(256) k3_coarse_assemble(Lv3 L, double* __restr
   }
   for (int col = 0; col < nu; ++col) a[col] = stokes_entry(L, row, col);
   if (row >= 3 * N3) a[nu] = 1.0;
-  if (row >= 3 * N3 || L.coef == 0.0) return;
-  const int c = row / N3, g = row - c * N3;
-  const int ai = g % N, aj = (g / N) % N, ak = g / (N * N);
-  for (int p = 0; p < L.M; ++p) {
-    const double sa = wval(L.S[3 * p + c], ai, aj, ak, N);
-    if (sa == 0.0) continue;
-    for (int cb = 0; cb < N3; ++cb) {
-      const int bi = cb % N, bj = (cb / N) % N, bk = cb / (N * N);
-      const double jb = wval(L.J[3 * L.prev[p] + c], bi, bj, bk, N) - 2.0 * wval(L.J[3 * p + c], bi, bj, bk, N) +
-                        wval(L.J[3 * L.next[p] + c], bi, bj, bk, N);
-      a[c * N3 + cb] += L.coef * sa * jb;
-    }
-  }
+}
+
+// Elastic entries of the coarsest matrix, one thread per (component, row,
+// column) of the velocity blocks (after k3_coarse_assemble).
+__global__ void __launch_bounds__(256) k3_coarse_elastic(Lv3 L, double* __restrict__ aug, int nr) {
+  const int N3 = L.N * L.N * L.N;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * N3 * N3) return;
+  const int c = t / (N3 * N3), rem = t - c * N3 * N3, ga = rem / N3, gb = rem - ga * N3;
+  const int ia = L.act_index[c * N3 + ga];
+  if (ia < 0) return;
+  aug[(size_t)(c * N3 + ga) * 2 * nr + c * N3 + gb] += L.coef * elastic_entry(L, c, ia, gb);
 }
 
 // ---------------------------------------------------------------- step pieces
@@ -659,9 +743,10 @@ __global__ void __launch_bounds__(256) k3_finite(const double* __restrict__ x, s
 struct Lvl3Bufs {
   int N = 0, nb = 0;
   Buf w, b, r, y;
-  Buf S, J, key, cnt, start, cursor, pts, flag, pos, act, nact;
+  Buf S, J, key, cnt, start, pts, flag, pos, act, nact, act_index, ccount, coff, cpt, cw;
   Buf boxflag, lists, own_box, inv_plain, inv_own;
   int n_own = 0, max_own = 0;
+  int nact_h = 0;                        // active faces (host copy, sets launch sizes)
   int lo[2] = {0, 0}, lc[2] = {0, 0};   // own lists: offset and count per colour
   int po[2] = {0, 0}, pc[2] = {0, 0};   // plain lists
 };
@@ -717,12 +802,17 @@ void layout(ibmg3_handle* h) {
       take(cur, B.key, 3 * M * sizeof(int));
       take(cur, B.cnt, (3 * N3 + 1) * sizeof(int));
       take(cur, B.start, (3 * N3 + 1) * sizeof(int));
-      take(cur, B.cursor, 3 * N3 * sizeof(int));
       take(cur, B.pts, 3 * M * sizeof(int));
       take(cur, B.flag, (3 * N3 + 1) * sizeof(int));
       take(cur, B.pos, (3 * N3 + 1) * sizeof(int));
       take(cur, B.act, 3 * N3 * sizeof(int));
       take(cur, B.nact, 4 * sizeof(int));
+      take(cur, B.act_index, 3 * N3 * sizeof(int));
+      take(cur, B.ccount, (3 * N3 + 1) * sizeof(int));
+      take(cur, B.coff, (3 * N3 + 1) * sizeof(int));
+      const size_t ent = 3 * M * kW * kW * kW;   // every window entry of every point and component
+      take(cur, B.cpt, ent * sizeof(int));
+      take(cur, B.cw, ent * sizeof(double));
     }
     if (l < h->levels - 1) {
       B.nb = B.N / h->n;
@@ -795,6 +885,10 @@ Lv3 view(const ibmg3_handle* h, int l) {
     v.bin_pts = h->p<int>(B.pts);
     v.act = h->p<int>(B.act);
     v.nact = h->p<int>(B.nact);
+    v.act_index = h->p<int>(B.act_index);
+    v.coff = h->p<int>(B.coff);
+    v.cpt = h->p<int>(B.cpt);
+    v.cw = h->p<double>(B.cw);
     v.y = h->p<double>(B.y);
   }
   return v;
@@ -821,8 +915,7 @@ void elastic_rows(ibmg3_handle* h, int l, const double* x) {
   const int m3 = 3 * h->M;
   k3_gather<<<nblk(m3), 256, 0, s>>>(v, x);
   k3_force<<<nblk(m3), 256, 0, s>>>(v, v.coef, v.U);
-  const size_t N3 = (size_t)v.N * v.N * v.N;
-  k3_spread<<<nblk(3 * N3), 256, 0, s>>>(v, v.y);
+  if (h->L[l].nact_h > 0) k3_spread<<<nblk((size_t)h->L[l].nact_h * 64), 256, 0, s>>>(v, v.y);
 }
 
 void residual(ibmg3_handle* h, int l, const double* b, const double* x, double* r) {
@@ -840,12 +933,14 @@ void sweep(ibmg3_handle* h, int l, const double* b, double* w) {
   const int* lists = h->p<int>(B.lists);
   for (int c = 0; c < 2; ++c) {
     residual(h, l, b, w, r);
+    const unsigned slices = (unsigned)((h->nd + 63) / 64);
     if (B.lc[c] > 0)
-      k3_box_apply<<<B.lc[c], kBoxThreads, 0, s>>>(v, r, w, lists + B.lo[c], B.lc[c], h->p<int>(B.own_box),
-                                                   h->p<double>(B.inv_own), (size_t)h->nd * h->nd);
+      k3_box_apply<1><<<dim3(B.lc[c], slices), kBoxThreads, 0, s>>>(v, r, w, lists + B.lo[c], B.lc[c],
+                                                                    h->p<int>(B.own_box), h->p<double>(B.inv_own),
+                                                                    (size_t)h->nd * h->nd);
     if (B.pc[c] > 0)
-      k3_box_apply<<<B.pc[c], kBoxThreads, 0, s>>>(v, r, w, lists + B.po[c], B.pc[c], nullptr,
-                                                   h->p<double>(B.inv_plain), 0);
+      k3_box_apply<kShare><<<dim3((B.pc[c] + kShare - 1) / kShare, slices), kBoxThreads, 0, s>>>(
+          v, r, w, lists + B.po[c], B.pc[c], nullptr, h->p<double>(B.inv_plain), 0);
   }
 }
 
@@ -894,17 +989,25 @@ int build_level(ibmg3_handle* h, int l) {
       k3_win_coarse<<<nblk(m3), 256, 0, s>>>(h->M, h->p<Win>(h->L[l - 1].S), h->p<Win>(h->L[l - 1].J),
                                             h->p<Win>(B.S), h->p<Win>(B.J));
     fill<int>(s, h->p<int>(B.cnt), 3 * N3 + 1, 0);
-    fill<int>(s, h->p<int>(B.cursor), 3 * N3, 0);
     k3_bin_count<<<nblk(m3), 256, 0, s>>>(h->M, N, h->p<Win>(B.S), h->p<int>(B.cnt), h->p<int>(B.key));
     scan(h, h->p<int>(B.cnt), (int)(3 * N3 + 1), h->p<int>(B.start));
-    k3_bin_fill<<<nblk(m3), 256, 0, s>>>(h->M, h->p<int>(B.key), h->p<int>(B.start), h->p<int>(B.cursor),
-                                         h->p<int>(B.pts));
-    k3_bin_sort<<<nblk(3 * N3), 256, 0, s>>>((int)(3 * N3), h->p<int>(B.start), h->p<int>(B.pts));
+    k3_bin_fill<<<nblk(m3), 256, 0, s>>>(h->M, h->p<int>(B.key), h->p<int>(B.start), h->p<int>(B.pts));
     fill<int>(s, h->p<int>(B.flag), 3 * N3 + 1, 0);
     k3_active_flag<<<nblk((size_t)m3 * kW * kW * kW), 256, 0, s>>>(h->M, N, h->p<Win>(B.S), h->p<int>(B.flag));
     scan(h, h->p<int>(B.flag), (int)(3 * N3 + 1), h->p<int>(B.pos));
-    k3_compact<<<nblk(3 * N3), 256, 0, s>>>(h->p<int>(B.flag), h->p<int>(B.pos), (int)(3 * N3), h->p<int>(B.act));
+    k3_compact<<<nblk(3 * N3), 256, 0, s>>>(h->p<int>(B.flag), h->p<int>(B.pos), (int)(3 * N3), h->p<int>(B.act),
+                                            h->p<int>(B.act_index));
     IBMG_HIP(hipMemcpyAsync(h->p<int>(B.nact), h->p<int>(h->total), sizeof(int), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipMemcpyAsync(&B.nact_h, h->p<int>(h->total), sizeof(int), hipMemcpyDeviceToHost, s));
+    IBMG_HIP(hipStreamSynchronize(s));
+    if (B.nact_h > 0) {
+      Lv3 v = view(h, l);
+      const unsigned blocks = nblk((size_t)B.nact_h * 64);
+      fill<int>(s, h->p<int>(B.ccount), 3 * N3 + 1, 0);
+      k3_csr<0><<<blocks, 256, 0, s>>>(v, h->p<int>(B.ccount), nullptr, nullptr, nullptr);
+      scan(h, h->p<int>(B.ccount), (int)(3 * N3 + 1), h->p<int>(B.coff));
+      k3_csr<1><<<blocks, 256, 0, s>>>(v, nullptr, h->p<int>(B.coff), h->p<int>(B.cpt), h->p<double>(B.cw));
+    }
     fill<double>(s, h->p<double>(B.y), 3 * N3, 0.0);
   }
   if (l == h->levels - 1) return IBMG_OK;
@@ -993,6 +1096,10 @@ int do_setup(ibmg3_handle* h, double dt, const double* X) {
   }
   Lv3 vc = view(h, h->levels - 1);
   k3_coarse_assemble<<<nblk(h->nr), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
+  if (has_ib(h)) {
+    const size_t N3c = (size_t)vc.N * vc.N * vc.N;
+    k3_coarse_elastic<<<nblk(3 * N3c * N3c), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
+  }
   if (ibmg::coarse_factor(s, h->p<double>(h->aug), h->nr, h->p<double>(h->cm), h->p<int>(h->cpiv), nullptr,
                           h->p<int>(h->crowpos), h->p<int>(h->cused), h->p<double>(h->cY),
                           h->p<double>(h->cainv)) != 0)
@@ -1091,7 +1198,7 @@ const double* spread_nodal_force(ibmg3_handle* h, const double* X) {
   double* y = h->p<double>(h->yfine);
   fill<double>(s, y, 3 * N3, 0.0);
   k3_nodal_force<<<nblk(3 * (size_t)h->M), 256, 0, s>>>(h->M, h->K, v.prev, v.next, X, v.F);
-  k3_spread<<<nblk(3 * N3), 256, 0, s>>>(v, y);
+  if (h->L[0].nact_h > 0) k3_spread<<<nblk((size_t)h->L[0].nact_h * 64), 256, 0, s>>>(v, y);
   return y;
 }
 
