@@ -584,25 +584,33 @@ __global__ void __launch_bounds__(kGjThreads) k3_gj(double* __restrict__ mats, i
       for (int a = 0; a < pw; ++a) rowp[a][j] = v[a];
     }
     __syncthreads();
-    // rank-pw update of A_RR and the new blocks
-    for (int t = tid; t < nd * nd; t += blockDim.x) {
-      const int i = t / nd, j = t - i * nd;
-      const bool ik = i >= k0 && i < k0 + pw, jk = j >= k0 && j < k0 + pw;
-      double v;
-      if (ik && jk) {
-        v = dinv[i - k0][j - k0];
-      } else if (ik) {
-        v = rowp[i - k0][j];
-      } else if (jk) {
-        double s = 0.0;
-        for (int b = 0; b < pw; ++b) s += colp[i][b] * dinv[b][j - k0];
-        v = -s;
-      } else {
-        double s = A[t];
-        for (int b = 0; b < pw; ++b) s -= colp[i][b] * rowp[b][j];
-        v = s;
+    // rank-pw update of A_RR and the new blocks: thread (g, j) owns column j
+    // for rows g, g + ng, ...; its column of the panel rows sits in
+    // registers, the panel column entry colp[i][.] is the same for the lanes
+    // of a wave (an LDS broadcast), and the lanes' A accesses are contiguous.
+    const int ng = blockDim.x / nd;
+    const int g = tid / nd, j = tid - g * nd;
+    if (g < ng) {
+      const bool jk = j >= k0 && j < k0 + pw;
+      double rj[kPanel];
+      for (int b = 0; b < kPanel; ++b) rj[b] = b < pw ? (jk ? dinv[b][j - k0] : rowp[b][j]) : 0.0;
+      for (int i = g; i < nd; i += ng) {
+        const size_t t = (size_t)i * nd + j;
+        const bool ik = i >= k0 && i < k0 + pw;
+        double v;
+        if (ik) {
+          v = rj[i - k0];
+        } else if (jk) {
+          double s = 0.0;
+          for (int b = 0; b < pw; ++b) s += colp[i][b] * rj[b];
+          v = -s;
+        } else {
+          double s = A[t];
+          for (int b = 0; b < pw; ++b) s -= colp[i][b] * rj[b];
+          v = s;
+        }
+        A[t] = v;
       }
-      A[t] = v;
     }
     __syncthreads();
   }
@@ -754,6 +762,7 @@ struct Lvl3Bufs {
 struct ibmg3_handle {
   int N = 0, M = 0, nfib = 0, kind = 0, levels = 0, n = 4, nu1 = 1, nu2 = 1, maxit = 100;
   double rho = 1, mu = 1, K = 0, rtol = 1e-8, omega = 1.0, dt = 0.0;
+  double plain_dt = 0.0;   // dt of the shared plain-box inverses in the workspace (0: none)
   int nd = 0;
   std::vector<int> prev, next;
   hipStream_t stream = nullptr;
@@ -1063,8 +1072,10 @@ int build_level(ibmg3_handle* h, int l) {
   IBMG_HIP(hipStreamSynchronize(s));
   Lv3 v = view(h, l);
   const size_t nd2 = (size_t)h->nd * h->nd;
-  k3_box_assemble<<<1, kGjThreads, 0, s>>>(v, nullptr, 0, h->p<double>(B.inv_plain), nd2);
-  k3_gj<<<1, kGjThreads, 0, s>>>(h->p<double>(B.inv_plain), h->nd, nd2);
+  if (h->plain_dt != h->dt) {   // the plain block depends on rho / dt, mu and h only
+    k3_box_assemble<<<1, kGjThreads, 0, s>>>(v, nullptr, 0, h->p<double>(B.inv_plain), nd2);
+    k3_gj<<<1, kGjThreads, 0, s>>>(h->p<double>(B.inv_plain), h->nd, nd2);
+  }
   if (nown) {
     k3_box_assemble<<<nown, kGjThreads, 0, s>>>(v, h->p<int>(B.own_box), 1, h->p<double>(B.inv_own), nd2);
     k3_gj<<<nown, kGjThreads, 0, s>>>(h->p<double>(B.inv_own), h->nd, nd2);
@@ -1092,8 +1103,12 @@ int do_setup(ibmg3_handle* h, double dt, const double* X) {
   }
   for (int l = 0; l < h->levels; ++l) {
     const int rc = build_level(h, l);
-    if (rc) return rc;
+    if (rc) {
+      h->plain_dt = 0.0;
+      return rc;
+    }
   }
+  h->plain_dt = h->dt;
   Lv3 vc = view(h, h->levels - 1);
   k3_coarse_assemble<<<nblk(h->nr), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
   if (has_ib(h)) {
@@ -1288,6 +1303,7 @@ int ibmg3_bind_workspace(ibmg3_handle* h, void* dev, size_t bytes) {
   h->ws = (char*)dev;
   h->ws_bytes = bytes;
   h->ready = false;
+  h->plain_dt = 0.0;
   if (h->M > 0) {
     IBMG_HIP(hipMemcpyAsync(h->p<int>(h->prev_d), h->prev.data(), h->M * sizeof(int), hipMemcpyHostToDevice,
                             h->stream));
