@@ -494,6 +494,7 @@ __device__ double elastic_entry(const Lv3& L, int c, int ia, int gb) {
   const int N = L.N;
   const int bi = gb % N, bj = (gb / N) % N, bk = gb / (N * N);
   double s = 0.0;
+#pragma unroll 4
   for (int u = L.coff[ia]; u < L.coff[ia + 1]; ++u) {
     const int p = L.cpt[u];
     const double jb = wval(L.J[3 * L.prev[p] + c], bi, bj, bk, N) - 2.0 * wval(L.J[3 * p + c], bi, bj, bk, N) +
@@ -507,12 +508,9 @@ __device__ double elastic_entry(const Lv3& L, int c, int ia, int gb) {
 // written transposed: out[col][row] = A[row][col].  The elastic entries of a
 // velocity row a and column b of component c are coef sum_p S_p(a)
 // (J_prev(b) - 2 J_p(b) + J_next(b)) over the CSR entries of row a.
-__global__ void __launch_bounds__(kGjThreads) k3_box_assemble(Lv3 L, const int* __restrict__ boxes, int with_ib,
-                                                              double* __restrict__ out, size_t stride) {
+__device__ void box_assemble_body(const Lv3& L, int box, int with_ib, double* __restrict__ B) {
   const int nd = L.nd, n = L.n, N = L.N, nb = L.nb;
-  const int box = boxes ? boxes[blockIdx.x] : 0;
   const int bx = box % nb, by = (box / nb) % nb, bz = box / (nb * nb);
-  double* B = out + stride * blockIdx.x;
   for (int t = threadIdx.x; t < nd * nd; t += blockDim.x) {
     const int col = t / nd, row = t - col * nd;   // B[col][row] = A[row][col]
     B[t] = stokes_entry(L, box_dof(row, bx, by, bz, n, N), box_dof(col, bx, by, bz, n, N));
@@ -531,6 +529,33 @@ __global__ void __launch_bounds__(kGjThreads) k3_box_assemble(Lv3 L, const int* 
   }
 }
 
+__global__ void __launch_bounds__(kGjThreads) k3_box_assemble(Lv3 L, const int* __restrict__ boxes, int with_ib,
+                                                              double* __restrict__ out, size_t stride) {
+  box_assemble_body(L, boxes ? boxes[blockIdx.x] : 0, with_ib, out + stride * blockIdx.x);
+}
+
+// The boxes with own inverses of all smoothed levels in one launch (the
+// levels are independent): workgroup q takes box q - start[l] of level l.
+struct OwnJobs {
+  Lv3 v[IBMG_MAX_LEVELS];
+  int start[IBMG_MAX_LEVELS + 1];
+  int nlev;
+};
+
+__device__ inline int job_level(const OwnJobs& J, int q) {
+  int l = 0;
+  while (l + 1 < J.nlev && q >= J.start[l + 1]) ++l;
+  return l;
+}
+
+__global__ void __launch_bounds__(kGjThreads) k3_box_assemble_own(const OwnJobs* __restrict__ J,
+                                                                  int* const* __restrict__ own_box,
+                                                                  double* const* __restrict__ inv) {
+  const int q = blockIdx.x, l = job_level(*J, q), i = q - J->start[l];
+  const Lv3& L = J->v[l];
+  box_assemble_body(L, own_box[l][i], 1, inv[l] + (size_t)L.nd * L.nd * i);
+}
+
 // In-place Gauss-Jordan inverse of each nd x nd matrix, blocked by panels
 // of kPanel pivots (no pivoting: the velocity block comes first and has a
 // dominant positive diagonal, the pressure pivots are then those of the
@@ -540,11 +565,10 @@ __global__ void __launch_bounds__(kGjThreads) k3_box_assemble(Lv3 L, const int* 
 // so the matrix is read and written once per panel instead of once per pivot.
 constexpr int kPanel = 8;
 
-__global__ void __launch_bounds__(kGjThreads) k3_gj(double* __restrict__ mats, int nd, size_t stride) {
+__device__ void gj_body(double* __restrict__ A, int nd) {
   __shared__ double rowp[kPanel][kMaxNd];   // rows of K (then D A_KR)
   __shared__ double colp[kMaxNd][kPanel];   // columns of K (A_RK, old)
   __shared__ double dinv[kPanel][kPanel];
-  double* A = mats + stride * blockIdx.x;
   const int tid = threadIdx.x;
   for (int k0 = 0; k0 < nd; k0 += kPanel) {
     const int pw = min(kPanel, nd - k0);
@@ -554,22 +578,18 @@ __global__ void __launch_bounds__(kGjThreads) k3_gj(double* __restrict__ mats, i
       colp[j][s] = A[(size_t)j * nd + k0 + s];
     }
     __syncthreads();
-    if (tid == 0) {   // D = A_KK^{-1}, scalar Gauss-Jordan on the small block
-      for (int a = 0; a < pw; ++a)
-        for (int b = 0; b < pw; ++b) dinv[a][b] = rowp[a][k0 + b];
+    if (tid < 64) {   // D = A_KK^{-1}: wave 0, lane (a, b) holds entry (a, b) (identity outside pw)
+      const int a = tid >> 3, b = tid & 7;
+      double d = (a < pw && b < pw) ? rowp[a][k0 + b] : (a == b ? 1.0 : 0.0);
       for (int k = 0; k < pw; ++k) {
-        const double inv = 1.0 / dinv[k][k];
-        for (int b = 0; b < pw; ++b)
-          if (b != k) dinv[k][b] *= inv;
-        for (int a = 0; a < pw; ++a) {
-          if (a == k) continue;
-          const double f = dinv[a][k];
-          for (int b = 0; b < pw; ++b)
-            if (b != k) dinv[a][b] -= f * dinv[k][b];
-          dinv[a][k] = -f * inv;
-        }
-        dinv[k][k] = inv;
+        const double piv = __shfl(d, k * 8 + k);
+        const double rk = __shfl(d, k * 8 + b);   // entry (k, b)
+        const double ck = __shfl(d, a * 8 + k);   // entry (a, k)
+        const double inv = 1.0 / piv;
+        if (a == k) d = b == k ? inv : rk * inv;
+        else d = b == k ? -ck * inv : d - ck * rk * inv;
       }
+      if (a < pw && b < pw) dinv[a][b] = d;
     }
     __syncthreads();
     // new pivot rows D A_KR (columns outside K), one column per thread
@@ -594,26 +614,48 @@ __global__ void __launch_bounds__(kGjThreads) k3_gj(double* __restrict__ mats, i
       const bool jk = j >= k0 && j < k0 + pw;
       double rj[kPanel];
       for (int b = 0; b < kPanel; ++b) rj[b] = b < pw ? (jk ? dinv[b][j - k0] : rowp[b][j]) : 0.0;
-      for (int i = g; i < nd; i += ng) {
-        const size_t t = (size_t)i * nd + j;
-        const bool ik = i >= k0 && i < k0 + pw;
-        double v;
-        if (ik) {
-          v = rj[i - k0];
-        } else if (jk) {
-          double s = 0.0;
-          for (int b = 0; b < pw; ++b) s += colp[i][b] * rj[b];
-          v = -s;
-        } else {
-          double s = A[t];
-          for (int b = 0; b < pw; ++b) s -= colp[i][b] * rj[b];
-          v = s;
+      // rows four at a time: the four loads of A are issued before the
+      // first product, so each thread keeps four L2 requests in flight
+      for (int i0 = g; i0 < nd; i0 += 4 * ng) {
+        double a4[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r * ng;
+          a4[r] = i < nd ? A[(size_t)i * nd + j] : 0.0;
         }
-        A[t] = v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r * ng;
+          if (i >= nd) break;
+          const bool ik = i >= k0 && i < k0 + pw;
+          double v;
+          if (ik) {
+            v = rj[i - k0];
+          } else if (jk) {
+            double s = 0.0;
+            for (int b = 0; b < pw; ++b) s += colp[i][b] * rj[b];
+            v = -s;
+          } else {
+            double s = a4[r];
+            for (int b = 0; b < pw; ++b) s -= colp[i][b] * rj[b];
+            v = s;
+          }
+          A[(size_t)i * nd + j] = v;
+        }
       }
     }
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(kGjThreads) k3_gj(double* __restrict__ mats, int nd, size_t stride) {
+  gj_body(mats + stride * blockIdx.x, nd);
+}
+
+__global__ void __launch_bounds__(kGjThreads) k3_gj_own(const OwnJobs* __restrict__ J, double* const* __restrict__ inv) {
+  const int q = blockIdx.x, l = job_level(*J, q), i = q - J->start[l];
+  const int nd = J->v[l].nd;
+  gj_body(inv[l] + (size_t)nd * nd * i, nd);
 }
 
 // w[box] += omega A_box^{-1} r[box] for the listed boxes: entry q of the
@@ -773,6 +815,9 @@ struct ibmg3_handle {
   int nr = 0;
   Buf aug, cm, cpiv, crowpos, cused, cY, cainv;
   Buf V, Z, H, g, cs, sn, y, scal, partial, flags_d, bvec, xvec, yfine;
+  Buf jobs, jobptr;             // own-box jobs of all levels (device copies of the two below)
+  OwnJobs jobs_h{};             // host sources of the asynchronous copies (kept alive with the handle)
+  void* jobptr_h[2 * IBMG_MAX_LEVELS] = {};
   double* flags_h = nullptr;
   bool ready = false;
   template <typename T> T* p(const Buf& b) const { return reinterpret_cast<T*>(ws + b.off); }
@@ -866,6 +911,8 @@ void layout(ibmg3_handle* h) {
   take(cur, h->bvec, n0 * sizeof(double));
   take(cur, h->xvec, n0 * sizeof(double));
   take(cur, h->yfine, 3 * N30 * sizeof(double));
+  take(cur, h->jobs, sizeof(OwnJobs));
+  take(cur, h->jobptr, 2 * IBMG_MAX_LEVELS * sizeof(void*));
   h->need = cur + 256;
 }
 
@@ -1076,10 +1123,6 @@ int build_level(ibmg3_handle* h, int l) {
     k3_box_assemble<<<1, kGjThreads, 0, s>>>(v, nullptr, 0, h->p<double>(B.inv_plain), nd2);
     k3_gj<<<1, kGjThreads, 0, s>>>(h->p<double>(B.inv_plain), h->nd, nd2);
   }
-  if (nown) {
-    k3_box_assemble<<<nown, kGjThreads, 0, s>>>(v, h->p<int>(B.own_box), 1, h->p<double>(B.inv_own), nd2);
-    k3_gj<<<nown, kGjThreads, 0, s>>>(h->p<double>(B.inv_own), h->nd, nd2);
-  }
   return IBMG_OK;
 }
 
@@ -1109,6 +1152,29 @@ int do_setup(ibmg3_handle* h, double dt, const double* X) {
     }
   }
   h->plain_dt = h->dt;
+  // the boxes with own inverses of every smoothed level: one assembly and
+  // one Gauss-Jordan launch for all levels
+  {
+    OwnJobs& J = h->jobs_h;
+    int total = 0;
+    J.nlev = h->levels - 1;
+    for (int l = 0; l < J.nlev; ++l) {
+      J.v[l] = view(h, l);
+      J.start[l] = total;
+      total += h->L[l].n_own;
+      h->jobptr_h[l] = h->p<int>(h->L[l].own_box);
+      h->jobptr_h[IBMG_MAX_LEVELS + l] = h->p<double>(h->L[l].inv_own);
+    }
+    J.start[J.nlev] = total;
+    if (total > 0) {
+      IBMG_HIP(hipMemcpyAsync(h->p<OwnJobs>(h->jobs), &J, sizeof(OwnJobs), hipMemcpyHostToDevice, s));
+      IBMG_HIP(hipMemcpyAsync(h->p<void*>(h->jobptr), h->jobptr_h, sizeof(h->jobptr_h), hipMemcpyHostToDevice, s));
+      int* const* boxes = reinterpret_cast<int* const*>(h->p<void*>(h->jobptr));
+      double* const* invs = reinterpret_cast<double* const*>(h->p<void*>(h->jobptr) + IBMG_MAX_LEVELS);
+      k3_box_assemble_own<<<total, kGjThreads, 0, s>>>(h->p<OwnJobs>(h->jobs), boxes, invs);
+      k3_gj_own<<<total, kGjThreads, 0, s>>>(h->p<OwnJobs>(h->jobs), invs);
+    }
+  }
   Lv3 vc = view(h, h->levels - 1);
   k3_coarse_assemble<<<nblk(h->nr), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
   if (has_ib(h)) {
