@@ -344,28 +344,24 @@ __global__ void __launch_bounds__(256) k3_csr(Lv3 L, int* __restrict__ count, co
 
 // ---------------------------------------------------------------- elastic rows
 
-// U[p, c] = (J_l x_c)(p)
+// U[p, c] = (J_l x_c)(p): one wave per (point, component), lane l taking the
+// window entries l and l + 64 of 125, a fixed shuffle tree across lanes.
 __global__ void __launch_bounds__(256) k3_gather(Lv3 L, const double* __restrict__ x) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * L.M) return;
+  const int lane = threadIdx.x & 63;
+  const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (t >= 3 * L.M) return;   // uniform per wave
   const int c = t % 3, N = L.N;
-  const Win w = L.J[t];
+  const Win& w = L.J[t];
   const double* xc = x + (size_t)c * N * N * N;
   double s = 0.0;
-  for (int ez = 0; ez < kW; ++ez) {
-    const double wz = w.w[2][ez];
-    if (wz == 0.0) continue;
-    const int k = pmod(w.base[2] + ez, N);
-    for (int ey = 0; ey < kW; ++ey) {
-      const double wy = w.w[1][ey];
-      if (wy == 0.0) continue;
-      const int j = pmod(w.base[1] + ey, N);
-      double sx = 0.0;
-      for (int ex = 0; ex < kW; ++ex) sx += w.w[0][ex] * xc[(k * N + j) * N + pmod(w.base[0] + ex, N)];
-      s += wz * wy * sx;
-    }
+  for (int e = lane; e < kW * kW * kW; e += 64) {
+    const int ex = e % kW, ey = (e / kW) % kW, ez = e / (kW * kW);
+    const double wt = w.w[0][ex] * w.w[1][ey] * w.w[2][ez];
+    if (wt != 0.0)
+      s += wt * xc[(pmod(w.base[2] + ez, N) * N + pmod(w.base[1] + ey, N)) * N + pmod(w.base[0] + ex, N)];
   }
-  L.U[t] = s;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) L.U[t] = s;
 }
 
 // F[p, c] = coef (U[prev] - 2 U[p] + U[next])
@@ -969,7 +965,7 @@ void elastic_rows(ibmg3_handle* h, int l, const double* x) {
   hipStream_t s = h->stream;
   Lv3 v = view(h, l);
   const int m3 = 3 * h->M;
-  k3_gather<<<nblk(m3), 256, 0, s>>>(v, x);
+  k3_gather<<<nblk((size_t)m3 * 64), 256, 0, s>>>(v, x);
   k3_force<<<nblk(m3), 256, 0, s>>>(v, v.coef, v.U);
   if (h->L[l].nact_h > 0) k3_spread<<<nblk((size_t)h->L[l].nact_h * 64), 256, 0, s>>>(v, v.y);
 }
@@ -1493,7 +1489,7 @@ int ibmg3_step(ibmg3_handle* h, double dt, double* uvw, double* p, double* X, ib
   k3_copy<<<nblk(N3), 256, 0, s>>>(x + 3 * N3, p, N3);
   if (has_ib(h)) {
     Lv3 v = view(h, 0);
-    k3_gather<<<nblk(3 * (size_t)h->M), 256, 0, s>>>(v, uvw);
+    k3_gather<<<nblk(3 * (size_t)h->M * 64), 256, 0, s>>>(v, uvw);
     k3_move<<<nblk(3 * (size_t)h->M), 256, 0, s>>>(h->M, dt, v.U, X);
   }
   rc = sync(h);
