@@ -810,7 +810,7 @@ struct ibmg3_handle {
   Buf prev_d, next_d, U, F, bsum, total, bad;
   int nr = 0;
   Buf aug, cm, cpiv, crowpos, cused, cY, cainv;
-  Buf V, Z, H, g, cs, sn, y, scal, partial, flags_d, bvec, xvec, yfine;
+  Buf V, Z, H, g, cs, sn, y, hc, scal, partial, flags_d, bvec, xvec, yfine;
   Buf jobs, jobptr;             // own-box jobs of all levels (device copies of the two below)
   OwnJobs jobs_h{};             // host sources of the asynchronous copies (kept alive with the handle)
   void* jobptr_h[2 * IBMG_MAX_LEVELS] = {};
@@ -902,7 +902,9 @@ void layout(ibmg3_handle* h) {
   take(cur, h->sn, (m + 1) * sizeof(double));
   take(cur, h->y, (m + 1) * sizeof(double));
   take(cur, h->scal, 16 * sizeof(double));
-  take(cur, h->partial, (size_t)kDotBlocks * (m + 2) * sizeof(double));
+  take(cur, h->hc, 2 * (m + 2) * sizeof(double));
+  // product passes (two vectors per pass) and the update pass's per-workgroup norm shares
+  take(cur, h->partial, std::max((size_t)kDotBlocks * 2 * (m + 2), (size_t)nblk(n0)) * sizeof(double));
   take(cur, h->flags_d, 8 * sizeof(double));
   take(cur, h->bvec, n0 * sizeof(double));
   take(cur, h->xvec, n0 * sizeof(double));
@@ -1197,7 +1199,9 @@ int do_solve(ibmg3_handle* h, const double* b, double* x, ibmg_stats* st) {
   double* g = h->p<double>(h->g);
   double* scal = h->p<double>(h->scal);
   double* partial = h->p<double>(h->partial);
-  double* hc = h->p<double>(h->y);
+  double* hc = h->p<double>(h->hc);
+  double* cs = h->p<double>(h->cs);
+  double* sn = h->p<double>(h->sn);
   double* flags = h->p<double>(h->flags_d);
   double hs[4];
   st->iters = 0;
@@ -1237,22 +1241,27 @@ int do_solve(ibmg3_handle* h, const double* b, double* x, ibmg_stats* st) {
     double* colj = H + (size_t)j * ldh;
     vcycle_level(h, 0, vj, zj);
     residual(h, 0, nullptr, zj, vn);
-    // classical Gram-Schmidt, twice; the norm and the Givens step of column j
-    ibmg::launch_multidot(s, V, n0, j + 1, vn, n0, partial, kDotBlocks);
-    ibmg::launch_reduce(s, partial, kDotBlocks, j + 1, colj, 0);
-    ibmg::launch_update_acc(s, V, n0, j + 1, colj, vn, n0, nullptr);
-    ibmg::launch_multidot(s, V, n0, j + 1, vn, n0, partial, kDotBlocks);
-    ibmg::launch_reduce(s, partial, kDotBlocks, j + 1, hc, 0);
-    ibmg::launch_update_acc(s, V, n0, j + 1, hc, vn, n0, colj);
-    ibmg::launch_multidot(s, vn, 0, 1, vn, n0, partial, kDotBlocks);
-    ibmg::launch_reduce2(s, partial, kDotBlocks, colj + j + 1, scal + 1);
-    ibmg::launch_scale_givens(s, vn, n0, scal + 1, H, ldh, g, h->p<double>(h->cs), h->p<double>(h->sn), j, flags,
-                              target);
+    // delayed classical Gram-Schmidt (the low-synchronisation DCGS2 form of
+    // the 2-D solver): one pass forms the products of the basis with u_j and
+    // w, it completes u_j into v_j, column j - 1 and projects w; the
+    // stopping test uses column j before its delayed projection
+    ibmg::launch_multidot2(s, V, n0, j + 1, vj, vn, n0, partial, kDotBlocks);
+    ibmg::launch_reduce(s, partial, kDotBlocks, 2 * (j + 1), hc, 0);
+    ibmg::launch_dcgs2_coef(s, hc, hc + (j + 1), j - 1, H, ldh, cs, sn, g, scal + 2);
+    ibmg::launch_dcgs2_update(s, V, n0, j, hc, hc + (j + 1), scal + 2, n0, partial);
+    ibmg::launch_reduce2(s, partial, (int)nblk(n0), colj + j + 1, scal + 1);
+    ibmg::launch_scale_tentative(s, vn, n0, scal + 1, H, ldh, g, cs, sn, j, flags, target);
     if ((rc = read_doubles(h, flags, hs, 3))) return rc;
     k = j + 1;
     st->rel_resid_est = hs[0] / bnorm;
     if (hs[2] != 0.0) return IBMG_ENONFINITE;
     if (hs[1] != 0.0) break;
+  }
+  if (k > 0) {   // complete column k - 1 (second projection of u_k)
+    const int c = k - 1;
+    ibmg::launch_multidot(s, V, n0, c + 2, V + (size_t)(c + 1) * n0, n0, partial, kDotBlocks);
+    ibmg::launch_reduce(s, partial, kDotBlocks, c + 2, hc, 0);
+    ibmg::launch_dcgs2_coef(s, hc, nullptr, c, H, ldh, cs, sn, g, scal + 2);
   }
   ibmg::launch_backsolve(s, H, ldh, g, k, h->p<double>(h->y));
   ibmg::launch_update(s, Z, n0, k, h->p<double>(h->y), x, n0, 1.0);
