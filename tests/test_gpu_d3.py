@@ -128,9 +128,12 @@ def test_d3_fgmres_matches_oracle(kw):
     s, lv, V, X, offs = case(**kw)
     N = kw["N"]
     rng = np.random.default_rng(14)
-    b = _zero_mean_p(rng.standard_normal(lv[0].A.shape[0]), N)
+    z = np.zeros(3 * N ** 3)
+    bg = s.rhs(tdev(z), tdev(X))
+    b = d3.rhs(N, 1.0 / dt, [z[:N ** 3]] * 3, X, offs, K)
+    assert rel(tnp(bg), b) < 1e-13
     x = torch.zeros(4 * N ** 3, dtype=torch.float64, device=DEV)
-    st = s.solve(tdev(b), x)
+    st = s.solve(bg, x)
     res = krylov.fgmres(lv[0].A, b, V, rtol=1e-10, maxit=100)
     xg = tnp(x)
     print(f"FGMRES: gpu {st['iters']} oracle {res.iters}")
@@ -194,3 +197,42 @@ def test_d3_32_cubed_vcycle_and_operator():
         own, total = s.box_counts(l)
         print(f"32^3 level {l}: {own} of {total} boxes own")
         assert total == sm.nb ** 3
+
+
+def test_d3_64_cubed_first_step_matches_oracle():
+    """64^3 with 4^3 boxes, five levels, dt K = 10, the first step of the
+    benchmark problem from rest: the level-0 and level-1 operators and the
+    right-hand side (the spread elastic force) against the oracle's, then 40
+    MG-FGMRES iterations, whose true relative residual must equal the
+    oracle's after its 40 iterations on the same system
+    (tests/golden/d3_first_step_64.json, written by make_d3_first_step.py
+    from oracle/ alone; the oracle's V-cycle at this size takes minutes).
+    The GPU's Gram-Schmidt is the delayed form, the oracle's the classical
+    one: equal in exact arithmetic.  This solve is slow: both need several
+    hundred iterations to reach 1e-8 (the residual is about 6e-3 after 200)."""
+    import json
+    import os
+    from paper_1311_5614_amd import ibmg
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "d3_first_step_64.json")))
+    N, dt, K = g["N"], g["dt"], g["K"]
+    X, offs = ibgen.sphere_rings(N)
+    cfg = ibmg.Config3(N=N, levels=g["levels"], K=K, box=g["box"], nu1=1, nu2=1, maxit=g["maxit"], rtol=1e-8)
+    s = ibmg.Solver3(cfg, offs, DEV)
+    s.setup(dt, tdev(X))
+    lv = d3.hierarchy(N, 2, 1.0, 1.0, dt, X, offs, K)
+    rng = np.random.default_rng(17)
+    for l in range(2):
+        x = rng.standard_normal(lv[l].A.shape[0])
+        assert rel(tnp(s.apply(l, tdev(x))), lv[l].A @ x) < 1e-12, l
+    z = np.zeros(3 * N ** 3)
+    bg = s.rhs(tdev(z), tdev(X))
+    b = d3.rhs(N, 1.0 / dt, [z[:N ** 3]] * 3, X, offs, K)
+    assert rel(tnp(bg), b) < 1e-13
+    x = torch.zeros(4 * N ** 3, dtype=torch.float64, device=DEV)
+    st = s.solve(bg, x)
+    r = np.linalg.norm(b - lv[0].A @ tnp(x)) / np.linalg.norm(b)
+    print(f"64^3: {st['iters']} iterations, residual {r:.6e} (GPU {st['rel_resid_true']:.6e}), "
+          f"oracle {g['rel_resid_true']:.6e} after {g['iters']}")
+    assert st["iters"] == g["iters"] and not g["converged"]
+    assert abs(r - g["rel_resid_true"]) <= 1e-6 * g["rel_resid_true"]
+    s.close()
