@@ -1085,8 +1085,10 @@ def run_d3(args, dev, steps=5, only=None):
     """The three-dimensional form (include/ibmg3.h) on the periodic unit
     cube: closed latitude rings on a stretched sphere (ibgen.sphere_rings,
     about 0.6 k points at 32^3, 2.5 k at 64^3), rho = mu = 1, dt = 0.01,
-    dt K = 10 and 100, MG-FGMRES V(1,1) with checkerboard boxes of 2^3 cells
+    dt K = 10 and 100, MG-FGMRES with checkerboard boxes of 2^3 cells
     (44 unknowns) and 4^3 cells (304 unknowns, the paper's 750 KB block),
+    in two forms: the paper's undamped boxes with V(1,1), and V(2,1) with
+    box corrections weighted by 0.5 (this build's damping option),
     rtol 1e-8, FGMRES(500), implicit steps from rest.  Per row: the first
     step (from the stretched rings at rest, the hardest solve) on its own,
     then `steps` more: ms per step (setup with the box inverses,
@@ -1101,11 +1103,13 @@ def run_d3(args, dev, steps=5, only=None):
         X, offs = ibgen.sphere_rings(N)
         for box in (2, 4):
             levels = int(np.log2(N // (2 if box == 2 else 4))) + 1
-            for alpha in (10.0, 100.0):
+            for alpha, form in ((10.0, "paper"), (100.0, "paper"), (10.0, "damped"), (100.0, "damped")):
                 if only is not None and (N, box, alpha) != only:
                     continue
                 dt = 0.01
-                cfg = ibmg.Config3(N=N, levels=levels, K=alpha / dt, box=box, nu1=1, nu2=1, maxit=500, rtol=1e-8)
+                nu, omega = ((1, 1), 1.0) if form == "paper" else ((2, 1), 0.5)
+                cfg = ibmg.Config3(N=N, levels=levels, K=alpha / dt, box=box, nu1=nu[0], nu2=nu[1], maxit=500,
+                                   rtol=1e-8, omega=omega)
                 s = ibmg.Solver3(cfg, offs, dev)
                 n3 = N ** 3
                 uvw = torch.zeros(3 * n3, dtype=torch.float64, device=dev)
@@ -1132,12 +1136,13 @@ def run_d3(args, dev, steps=5, only=None):
                 torch.cuda.synchronize()
                 setup_ms = 1e3 * (time.perf_counter() - t0)
                 own, total = s.box_counts(0)
-                row = {"N": N, "box": box, "unknowns_per_box": 3 * (box + 1) * box * box + box ** 3,
+                row = {"N": N, "box": box, "form": form, "nu": list(nu), "omega": omega,
+                       "unknowns_per_box": 3 * (box + 1) * box * box + box ** 3,
                        "levels": levels, "dt_K": alpha, "points": int(offs[-1]), "ms_per_step": float(np.median(ms)),
                        "setup_ms": setup_ms, "iters_mean": sum(its) / steps, "converged": f"{conv}/{steps}",
                        "own_boxes_level0": own, "boxes_level0": total, "first_step": first}
                 rows.append(row)
-                print(f"[bench] 3-D {N}^3 box {box} dtK {alpha:g}: first step {first['ms']:.1f} ms, "
+                print(f"[bench] 3-D {N}^3 box {box} dtK {alpha:g} {form}: first step {first['ms']:.1f} ms, "
                       f"{first['iters']} its, converged {first['converged']}; then {row['ms_per_step']:.1f} ms/step "
                       f"(setup {setup_ms:.1f} ms), {row['iters_mean']:.1f} its, {conv}/{steps} converged, "
                       f"{own}/{total} own boxes", file=sys.stderr, flush=True)
