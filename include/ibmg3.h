@@ -27,7 +27,8 @@
  *     Jacobi within a colour, optional weight omega.
  *   - Coarsest level (Algorithm 1): exact solve of the system bordered by the
  *     pressure constant (zero-mean pressure).
- *   - FGMRES right-preconditioned by one V-cycle (Sec. 3.3).
+ *   - FGMRES right-preconditioned by one V-cycle (Sec. 3.3), classical
+ *     Gram-Schmidt applied twice in its delayed (low-synchronisation) form.
  *
  * Memory: every pointer argument is device memory owned by the caller; the
  * library allocates no device memory (the caller binds one workspace of

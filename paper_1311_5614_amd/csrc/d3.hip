@@ -9,8 +9,8 @@
 // weight rows, kept in unwrapped coordinates and wrapped on use.  The
 // elastic rows M_l x = S_l (-dt K L (J_l x)) are three passes: a gather per
 // (point, component), the fibre second difference, and a gather per active
-// face over the points binned by window base (ascending point order, so
-// every sum has a fixed order).
+// face over the face's entries of a CSR of S_l, built once per setup from
+// the points binned by window base (every sum has a fixed order).
 //
 // Box smoother: a box of n^3 cells has 3 (n + 1) n^2 + n^3 unknowns (304
 // for n = 4).  The block of a box that meets no structure is the same for
@@ -20,7 +20,7 @@
 // Gauss-Jordan inverse is the inverse stored column-major and the per-box
 // product reads it with consecutive threads on consecutive rows).  A colour
 // phase is a residual pass over the level (Jacobi within the colour) and
-// one box pass.
+// one box pass.  FGMRES uses the delayed Gram-Schmidt kernels of krylov.hip.
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <cmath>
