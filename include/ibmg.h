@@ -222,7 +222,10 @@ int ibmg_kernel_bench(ibmg_handle* h, int kernel, int level, int arg, int reps, 
  * weights, point-to-box binning, the elastic rows of M_0 as coefficient
  * windows and M_{l+1} = R M_l P as windows on every coarser level, box
  * inverses and the bordered coarsest inverse, for time step dt.
- * X: M x 2.  Synchronises.  Errors: EINVAL, ENOMEM, EHIP, ENONFINITE. */
+ * X: M x 2.  Synchronises.  Errors: EINVAL, ENOMEM, EHIP, ENONFINITE, and
+ * ESHAPE when an elastic coupling reaches beyond the coefficient window
+ * (fibre neighbours more than about one cell apart); the handle stays
+ * usable for a setup at other positions. */
 int ibmg_setup(ibmg_handle* h, double dt, const double* X);
 
 /* One implicit IB time step (Sec. 2.3.2): setup at X^n, right-hand side,

@@ -363,6 +363,31 @@ def test_errors_are_reported():
         s.vcycle(torch.zeros(3 * 1024, dtype=torch.float64, device=DEV))   # before setup
 
 
+def test_coupling_beyond_the_window_is_reported_and_recoverable():
+    """M_l is held in 11 x 11 coefficient windows per row (reach five cells
+    on the finest level).  A fibre whose neighbouring points lie farther
+    apart than the window can hold (eight points on a circle of radius 0.2
+    at 64^2: about ten cells apart) makes setup return ESHAPE rather than
+    drop couplings; the same handle then sets up and steps normally at
+    positions that fit (the same eight points on a circle of radius 0.01)."""
+    from paper_1311_5614_amd import ibmg
+    N, M = 64, 8
+    th = 2.0 * np.pi * np.arange(M) / M
+    far = np.stack([0.5 + 0.2 * np.cos(th), 0.5 + 0.2 * np.sin(th)], 1)
+    near = np.stack([0.5 + 0.01 * np.cos(th), 0.5 + 0.01 * np.sin(th)], 1)
+    s = ibmg.Solver(ibmg.Config(N=N, levels=4, K=1e3, box=4, nu1=2, nu2=2, maxit=200, rtol=1e-10),
+                    np.array([0, M], dtype=np.int32), DEV)
+    with pytest.raises(ibmg.IBMGError) as e:
+        s.setup(0.01, tdev(far))
+    assert e.value.code == ibmg.IBMG_ESHAPE
+    s.setup(0.01, tdev(near))
+    z = np.zeros((N, N))
+    u, v, p, X = tdev(z), tdev(z), tdev(z), tdev(near)
+    st = s.step(0.01, u, v, p, X)
+    assert st["converged"] == 1 and bool(torch.isfinite(X).all())
+    s.close()
+
+
 # ---------------------------------------------------------------- precision form: FP32 V-cycle
 
 def test_fp32_vcycle_error_statement():
