@@ -32,24 +32,24 @@ def _gpu():
 _CACHE = {}
 
 
-def case(N=16, box=2, K=1e3, dt=0.01, centre=(0.5, 0.5, 0.5), levels=3):
+def case(N=16, box=2, K=1e3, dt=0.01, centre=(0.5, 0.5, 0.5), levels=3, delta=0):
     """GPU solver (set up) and oracle hierarchy + V-cycle of one problem."""
-    key = (N, box, K, dt, centre, levels)
+    key = (N, box, K, dt, centre, levels, delta)
     if key in _CACHE:
         return _CACHE[key]
     from paper_1311_5614_amd import ibmg
     X, offs = ibgen.sphere_rings(N, centre=centre)
-    cfg = ibmg.Config3(N=N, levels=levels, K=K, box=box, nu1=1, nu2=1, maxit=100, rtol=1e-10)
+    cfg = ibmg.Config3(N=N, levels=levels, K=K, box=box, nu1=1, nu2=1, maxit=100, rtol=1e-10, delta=delta)
     s = ibmg.Solver3(cfg, offs if K else None, DEV)
     s.setup(dt, tdev(X) if K else None)
-    lv = d3.hierarchy(N, levels, 1.0, 1.0, dt, X if K else None, offs, K)
+    lv = d3.hierarchy(N, levels, 1.0, 1.0, dt, X if K else None, offs, K, kind=delta)
     V = d3.VCycle(lv, box, 1, 1)
     _CACHE[key] = (s, lv, V, X, offs)
     return _CACHE[key]
 
 
 CASES = [dict(N=16, box=2), dict(N=16, box=4), dict(N=16, box=2, centre=(0.05, 0.95, 0.02)),
-         dict(N=16, box=4, K=0.0)]
+         dict(N=16, box=4, K=0.0), dict(N=16, box=4, delta=1)]   # the last: cosine delta
 
 
 def _zero_mean_p(x, N):
@@ -123,7 +123,7 @@ def test_d3_smooth_and_vcycle(kw):
     assert rel(zg, zo) < 1e-10
 
 
-@pytest.mark.parametrize("kw", CASES[:3])
+@pytest.mark.parametrize("kw", CASES[:3] + CASES[4:])
 def test_d3_fgmres_matches_oracle(kw):
     s, lv, V, X, offs = case(**kw)
     N = kw["N"]
