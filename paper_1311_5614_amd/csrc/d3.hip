@@ -544,12 +544,42 @@ __device__ inline int job_level(const OwnJobs& J, int q) {
   return l;
 }
 
+// The Stokes part of every own box (one workgroup per box) ...
 __global__ void __launch_bounds__(kGjThreads) k3_box_assemble_own(const OwnJobs* __restrict__ J,
                                                                   int* const* __restrict__ own_box,
                                                                   double* const* __restrict__ inv) {
   const int q = blockIdx.x, l = job_level(*J, q), i = q - J->start[l];
   const Lv3& L = J->v[l];
-  box_assemble_body(L, own_box[l][i], 1, inv[l] + (size_t)L.nd * L.nd * i);
+  box_assemble_body(L, own_box[l][i], 0, inv[l] + (size_t)L.nd * L.nd * i);
+}
+
+// ... then the elastic entries, one workgroup per (box, component, 16 rows):
+// on the coarse levels a face's CSR row holds most of the points, and
+// splitting a box fifteen ways keeps those boxes from setting the launch's
+// length.  Each entry belongs to one workgroup (stored transposed as above).
+constexpr int kElRows = 16;
+
+__global__ void __launch_bounds__(256) k3_box_elastic_own(const OwnJobs* __restrict__ J,
+                                                          int* const* __restrict__ own_box,
+                                                          double* const* __restrict__ inv) {
+  const int q = blockIdx.x, l = job_level(*J, q), i = q - J->start[l];
+  const Lv3& L = J->v[l];
+  const int n = L.n, N = L.N, nb = L.nb, nd = L.nd, N3 = N * N * N;
+  const int nf = (n + 1) * n * n;
+  const int c = blockIdx.y / ((nf + kElRows - 1) / kElRows);
+  const int r0 = (blockIdx.y - c * ((nf + kElRows - 1) / kElRows)) * kElRows;
+  const int box = own_box[l][i];
+  const int bx = box % nb, by = (box / nb) % nb, bz = box / (nb * nb);
+  double* B = inv[l] + (size_t)nd * nd * i;
+  for (int t = threadIdx.x; t < kElRows * nf; t += blockDim.x) {
+    const int ra = r0 + t / nf, cb = t % nf;
+    if (ra >= nf) break;
+    const int ga = box_dof(c * nf + ra, bx, by, bz, n, N) - c * N3;
+    const int ia = L.act_index[c * N3 + ga];
+    if (ia < 0) continue;
+    const int gb = box_dof(c * nf + cb, bx, by, bz, n, N) - c * N3;
+    B[(size_t)(c * nf + cb) * nd + c * nf + ra] += L.coef * elastic_entry(L, c, ia, gb);
+  }
 }
 
 // In-place Gauss-Jordan inverse of each nd x nd matrix, blocked by panels
@@ -1170,6 +1200,9 @@ int do_setup(ibmg3_handle* h, double dt, const double* X) {
       int* const* boxes = reinterpret_cast<int* const*>(h->p<void*>(h->jobptr));
       double* const* invs = reinterpret_cast<double* const*>(h->p<void*>(h->jobptr) + IBMG_MAX_LEVELS);
       k3_box_assemble_own<<<total, kGjThreads, 0, s>>>(h->p<OwnJobs>(h->jobs), boxes, invs);
+      const int nf = (h->n + 1) * h->n * h->n;
+      k3_box_elastic_own<<<dim3(total, 3 * ((nf + kElRows - 1) / kElRows)), 256, 0, s>>>(h->p<OwnJobs>(h->jobs),
+                                                                                       boxes, invs);
       k3_gj_own<<<total, kGjThreads, 0, s>>>(h->p<OwnJobs>(h->jobs), invs);
     }
   }
