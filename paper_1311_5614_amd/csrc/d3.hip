@@ -219,12 +219,19 @@ __global__ void __launch_bounds__(256) k3_bin_count(int M, int N, const Win* __r
 // its points in ascending order, independent of scheduling).
 __global__ void __launch_bounds__(256) k3_bin_fill(int M, const int* __restrict__ key, const int* __restrict__ start,
                                                    int* __restrict__ pts) {
+  __shared__ int sk[1024];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int m3 = 3 * M;
   const int k = t < m3 ? key[t] : -1;
   int rank = 0;
-  const int lim = min(m3, (blockIdx.x + 1) * blockDim.x);
-  for (int u = 0; u < lim; ++u) rank += (u < t && key[u] == k) ? 1 : 0;
+  const int lim = min(m3, (blockIdx.x + 1) * blockDim.x);   // the same for the whole workgroup
+  for (int base = 0; base < lim; base += 1024) {   // the keys below lim, 1024 at a time through LDS
+    const int n = min(1024, lim - base);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sk[i] = key[base + i];
+    __syncthreads();
+    for (int u = 0; u < n; ++u) rank += (base + u < t && sk[u] == k) ? 1 : 0;
+  }
   if (t < m3) pts[start[k] + rank] = t / 3;
 }
 
@@ -754,16 +761,29 @@ __global__ void __launch_bounds__(256) k3_coarse_assemble(Lv3 L, double* __restr
   if (row >= 3 * N3) a[nu] = 1.0;
 }
 
-// Elastic entries of the coarsest matrix, one thread per (component, row,
-// column) of the velocity blocks (after k3_coarse_assemble).
+// Elastic entries of the coarsest matrix (after k3_coarse_assemble): one
+// wave per (component, row a), the lanes over the columns b, so that each
+// CSR entry of row a and its three interpolation windows are read once per
+// wave.
 __global__ void __launch_bounds__(256) k3_coarse_elastic(Lv3 L, double* __restrict__ aug, int nr) {
-  const int N3 = L.N * L.N * L.N;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * N3 * N3) return;
-  const int c = t / (N3 * N3), rem = t - c * N3 * N3, ga = rem / N3, gb = rem - ga * N3;
+  const int N = L.N, N3 = N * N * N;
+  const int lane = threadIdx.x & 63;
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= 3 * N3) return;   // uniform per wave
+  const int c = w / N3, ga = w - c * N3;
   const int ia = L.act_index[c * N3 + ga];
   if (ia < 0) return;
-  aug[(size_t)(c * N3 + ga) * 2 * nr + c * N3 + gb] += L.coef * elastic_entry(L, c, ia, gb);
+  for (int gb = lane; gb < N3; gb += 64) {
+    const int bi = gb % N, bj = (gb / N) % N, bk = gb / (N * N);
+    double s = 0.0;
+    for (int u = L.coff[ia]; u < L.coff[ia + 1]; ++u) {
+      const int p = L.cpt[u];
+      const double jb = wval(L.J[3 * L.prev[p] + c], bi, bj, bk, N) - 2.0 * wval(L.J[3 * p + c], bi, bj, bk, N) +
+                        wval(L.J[3 * L.next[p] + c], bi, bj, bk, N);
+      s += L.cw[u] * jb;
+    }
+    aug[(size_t)(c * N3 + ga) * 2 * nr + c * N3 + gb] += L.coef * s;
+  }
 }
 
 // ---------------------------------------------------------------- step pieces
@@ -1210,7 +1230,7 @@ int do_setup(ibmg3_handle* h, double dt, const double* X) {
   k3_coarse_assemble<<<nblk(h->nr), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
   if (has_ib(h)) {
     const size_t N3c = (size_t)vc.N * vc.N * vc.N;
-    k3_coarse_elastic<<<nblk(3 * N3c * N3c), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
+    k3_coarse_elastic<<<nblk(3 * N3c * 64), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
   }
   if (ibmg::coarse_factor(s, h->p<double>(h->aug), h->nr, h->p<double>(h->cm), h->p<int>(h->cpiv), nullptr,
                           h->p<int>(h->crowpos), h->p<int>(h->cused), h->p<double>(h->cY),
