@@ -761,28 +761,47 @@ __global__ void __launch_bounds__(256) k3_coarse_assemble(Lv3 L, double* __restr
   if (row >= 3 * N3) a[nu] = 1.0;
 }
 
-// Elastic entries of the coarsest matrix (after k3_coarse_assemble): one
-// wave per (component, row a), the lanes over the columns b, so that each
-// CSR entry of row a and its three interpolation windows are read once per
-// wave.
-__global__ void __launch_bounds__(256) k3_coarse_elastic(Lv3 L, double* __restrict__ aug, int nr) {
-  const int N = L.N, N3 = N * N * N;
-  const int lane = threadIdx.x & 63;
-  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (w >= 3 * N3) return;   // uniform per wave
-  const int c = w / N3, ga = w - c * N3;
+// Elastic entries of the coarsest matrix (after k3_coarse_assemble), NC^3
+// cells (NC = 2 or 4): one wave per (component, row a), the lanes strided
+// over the CSR entries of row a.  A lane tabulates the per-axis weights of
+// its entry's three interpolation windows over the NC coordinates once and
+// accumulates every column; the columns are then summed across the lanes by
+// a fixed shuffle tree.
+template <int NC>
+__global__ void __launch_bounds__(64) k3_coarse_elastic(Lv3 L, double* __restrict__ aug, int nr) {
+  constexpr int N3 = NC * NC * NC;
+  const int lane = threadIdx.x;
+  const int c = blockIdx.x / N3, ga = blockIdx.x - c * N3;
   const int ia = L.act_index[c * N3 + ga];
   if (ia < 0) return;
-  for (int gb = lane; gb < N3; gb += 64) {
-    const int bi = gb % N, bj = (gb / N) % N, bk = gb / (N * N);
-    double s = 0.0;
-    for (int u = L.coff[ia]; u < L.coff[ia + 1]; ++u) {
-      const int p = L.cpt[u];
-      const double jb = wval(L.J[3 * L.prev[p] + c], bi, bj, bk, N) - 2.0 * wval(L.J[3 * p + c], bi, bj, bk, N) +
-                        wval(L.J[3 * L.next[p] + c], bi, bj, bk, N);
-      s += L.cw[u] * jb;
+  double acc[N3];
+#pragma unroll
+  for (int b = 0; b < N3; ++b) acc[b] = 0.0;
+  for (int u = L.coff[ia] + lane; u < L.coff[ia + 1]; u += 64) {
+    const int p = L.cpt[u];
+    const double wa = L.cw[u];
+    const int qs[3] = {L.prev[p], p, L.next[p]};
+    double tab[3][3][NC];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const Win& Jw = L.J[3 * qs[m] + c];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int x = 0; x < NC; ++x) tab[m][d][x] = wsum(Jw, d, x, NC);
     }
-    aug[(size_t)(c * N3 + ga) * 2 * nr + c * N3 + gb] += L.coef * s;
+#pragma unroll
+    for (int b = 0; b < N3; ++b) {
+      const int bi = b % NC, bj = (b / NC) % NC, bk = b / (NC * NC);
+      acc[b] += wa * (tab[0][0][bi] * tab[0][1][bj] * tab[0][2][bk] - 2.0 * tab[1][0][bi] * tab[1][1][bj] * tab[1][2][bk] +
+                      tab[2][0][bi] * tab[2][1][bj] * tab[2][2][bk]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < N3; ++b) {
+    double v = acc[b];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) aug[(size_t)(c * N3 + ga) * 2 * nr + c * N3 + b] += L.coef * v;
   }
 }
 
@@ -1230,7 +1249,8 @@ int do_setup(ibmg3_handle* h, double dt, const double* X) {
   k3_coarse_assemble<<<nblk(h->nr), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
   if (has_ib(h)) {
     const size_t N3c = (size_t)vc.N * vc.N * vc.N;
-    k3_coarse_elastic<<<nblk(3 * N3c * 64), 256, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
+    if (vc.N == 4) k3_coarse_elastic<4><<<(unsigned)(3 * N3c), 64, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
+    else k3_coarse_elastic<2><<<(unsigned)(3 * N3c), 64, 0, s>>>(vc, h->p<double>(h->aug), h->nr);
   }
   if (ibmg::coarse_factor(s, h->p<double>(h->aug), h->nr, h->p<double>(h->cm), h->p<int>(h->cpiv), nullptr,
                           h->p<int>(h->crowpos), h->p<int>(h->cused), h->p<double>(h->cY),

@@ -49,7 +49,8 @@ def case(N=16, box=2, K=1e3, dt=0.01, centre=(0.5, 0.5, 0.5), levels=3, delta=0)
 
 
 CASES = [dict(N=16, box=2), dict(N=16, box=4), dict(N=16, box=2, centre=(0.05, 0.95, 0.02)),
-         dict(N=16, box=4, K=0.0), dict(N=16, box=4, delta=1)]   # the last: cosine delta
+         dict(N=16, box=4, K=0.0), dict(N=16, box=4, delta=1),   # cosine delta
+         dict(N=16, box=2, levels=4)]                               # coarsest grid of 2^3 cells
 
 
 def _zero_mean_p(x, N):
