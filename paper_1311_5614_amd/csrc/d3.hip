@@ -248,6 +248,19 @@ __global__ void __launch_bounds__(256) k3_active_flag(int M, int N, const Win* _
   flag[c * N * N * N + g] = 1;
 }
 
+// Box classes: 1 if a velocity unknown of the box is an active face (the box
+// gets its own inverse), else 0; one thread per box.
+__global__ void __launch_bounds__(256) k3_box_flags(int N, int n, int nb, const int* __restrict__ act,
+                                                    int* __restrict__ boxflag) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb * nb * nb) return;
+  const int bx = b % nb, by = (b / nb) % nb, bz = b / (nb * nb);
+  const int nf = (n + 1) * n * n;
+  int hit = 0;   // box_dof of a velocity unknown is also its index in act (component * N^3 + face)
+  for (int t = 0; t < 3 * nf && !hit; ++t) hit = act[box_dof(t, bx, by, bz, n, N)];
+  boxflag[b] = hit ? 1 : 0;
+}
+
 // Exclusive scan in three launches: per-1024 block, block sums, add.
 __global__ void __launch_bounds__(1024) k3_scan_block(const int* __restrict__ in, int n, int* __restrict__ out,
                                                       int* __restrict__ bsum) {
@@ -1139,24 +1152,9 @@ int build_level(ibmg3_handle* h, int l) {
   const int nbox = nb * nb * nb;
   std::vector<int> flag(nbox, 0);
   if (has_ib(h)) {
-    std::vector<int> act(3 * N3 + 1);
-    IBMG_HIP(hipMemcpyAsync(act.data(), h->p<int>(B.flag), 3 * N3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    k3_box_flags<<<nblk(nbox), 256, 0, s>>>(N, h->n, nb, h->p<int>(B.flag), h->p<int>(B.boxflag));
+    IBMG_HIP(hipMemcpyAsync(flag.data(), h->p<int>(B.boxflag), nbox * sizeof(int), hipMemcpyDeviceToHost, s));
     IBMG_HIP(hipStreamSynchronize(s));
-    const int n = h->n;
-    for (int bz = 0; bz < nb; ++bz)
-      for (int by = 0; by < nb; ++by)
-        for (int bx = 0; bx < nb; ++bx) {
-          int hit = 0;
-          for (int c = 0; c < 3 && !hit; ++c)
-            for (int k = 0; k <= n && !hit; ++k)
-              for (int j = 0; j <= n && !hit; ++j)
-                for (int i = 0; i <= n && !hit; ++i) {
-                  if ((c != 0 && i == n) || (c != 1 && j == n) || (c != 2 && k == n)) continue;
-                  const int g = ((bz * n + k) % N * N + (by * n + j) % N) * N + (bx * n + i) % N;
-                  hit = act[c * N3 + g];
-                }
-          flag[(bz * nb + by) * nb + bx] = hit;
-        }
   }
   std::vector<int> lists, own_box;
   int nown = 0;
