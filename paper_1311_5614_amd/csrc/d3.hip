@@ -38,7 +38,7 @@ namespace {
 using ibmg::nblk;
 
 constexpr int kW = 5;                 // window entries per axis on every level
-constexpr int kBoxThreads = 256;      // box products
+constexpr int kBoxThreads = 512;      // box products: eight waves split the columns
 constexpr int kGjThreads = 1024;      // box inverses
 constexpr int kMaxNd = 3 * 5 * 16 + 64;   // 304: unknowns of an n = 4 box
 
@@ -706,9 +706,9 @@ __global__ void __launch_bounds__(kGjThreads) k3_gj_own(const OwnJobs* __restric
 
 // w[box] += omega A_box^{-1} r[box] for the listed boxes: entry q of the
 // list is a box id (plain: shared inverse) or, own, the own index of a box.
-// Grid: (boxes / kB, row slices of 64).  In a workgroup each of the four
-// waves takes a quarter of the columns k for the slice's 64 rows (lane =
-// row), the four partial sums meet in LDS and are added in wave order.
+// Grid: (boxes / kB, row slices of 64).  In a workgroup each of the eight
+// waves takes an eighth of the columns k for the slice's 64 rows (lane =
+// row), the partial sums meet in LDS and are added in wave order.
 // Plain boxes go kShare to a workgroup so that each load of the shared
 // inverse (from L2) serves kShare boxes.
 constexpr int kShare = 4;
@@ -719,7 +719,7 @@ __global__ void __launch_bounds__(kBoxThreads) k3_box_apply(Lv3 L, const double*
                                                             const int* __restrict__ own_box,
                                                             const double* __restrict__ inv, size_t stride) {
   __shared__ double rb[kB][kMaxNd];
-  __shared__ double part[4][kB][64];
+  __shared__ double part[kBoxThreads / 64][kB][64];
   const int q0 = blockIdx.x * kB;
   const int nd = L.nd, n = L.n, nb = L.nb;
   const int nbx = min(kB, count - q0);
@@ -738,7 +738,8 @@ __global__ void __launch_bounds__(kBoxThreads) k3_box_apply(Lv3 L, const double*
   const double* Ai = inv + (own_box ? stride * list[q0] : 0);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = blockIdx.y * 64 + lane;
-  const int kq = (nd + 3) / 4, k0 = wv * kq, k1 = min(nd, k0 + kq);
+  constexpr int kWaves = kBoxThreads / 64;
+  const int kq = (nd + kWaves - 1) / kWaves, k0 = wv * kq, k1 = min(nd, k0 + kq);
   double z[kB];
   for (int u = 0; u < kB; ++u) z[u] = 0.0;
   if (row < nd) {
@@ -752,7 +753,8 @@ __global__ void __launch_bounds__(kBoxThreads) k3_box_apply(Lv3 L, const double*
   __syncthreads();
   if (wv == 0 && row < nd)
     for (int u = 0; u < nbx; ++u) {
-      const double v = ((part[0][u][lane] + part[1][u][lane]) + part[2][u][lane]) + part[3][u][lane];
+      double v = part[0][u][lane];
+      for (int q = 1; q < kWaves; ++q) v += part[q][u][lane];   // wave order
       w[box_dof(row, bxs[u], bys[u], bzs[u], n, L.N)] += L.omega * v;
     }
 }
